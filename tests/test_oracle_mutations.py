@@ -1,0 +1,124 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that a pin catches each.
+
+Every case patches one oracle function with a wrong variant (a dropped term, a
+wrong sign, a swapped operand, an off-by-one) and re-runs one of the pin
+tests, which must then fail.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fftlen, noise, pointing, solver
+
+import test_oracle_pointing_noise as pn
+import test_oracle_solver as sv
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_swapped_q_u_weights_are_caught(monkeypatch):
+    orig = pointing.row_weights
+
+    def swapped(pix, w, ns):
+        r = orig(pix, w, ns)
+        if ns == 3:
+            r = r[:, [0, 2, 1]]
+        return r
+    monkeypatch.setattr(pointing, "row_weights", swapped)
+    _fails(pn.test_polarised_row_follows_the_formalism_equation, 45.0, (0.5, 0.5, 0.0))
+    _fails(pn.test_pointing_reproduces_the_generators_noiseless_signal, 3)
+
+
+def test_dropped_half_factor_is_caught(monkeypatch):
+    orig = pointing.row_weights
+    monkeypatch.setattr(pointing, "row_weights", lambda p, w, ns: orig(p, w, ns) * (2.0 if ns == 3 else 1.0))
+    _fails(pn.test_uniform_angles_give_the_closed_form_block)
+
+
+def test_missing_taper_is_caught(monkeypatch):
+    monkeypatch.setattr(noise, "taper", lambda n_c: np.ones(n_c))
+    _fails(pn.test_lags_match_quadrature_of_the_inverse_spectrum, 400)
+
+
+def test_psd_instead_of_inverse_psd_is_caught(monkeypatch):
+    orig = noise.inverse_psd_grid
+
+    def wrong(L, fs, sg, fk, al):
+        s = orig(L, fs, sg, fk, al)
+        out = np.zeros_like(s)
+        out[s > 0] = 1.0 / s[s > 0]
+        return out
+    monkeypatch.setattr(noise, "inverse_psd_grid", wrong)
+    _fails(pn.test_ninv_on_a_sinusoid_returns_the_inverse_power)
+
+
+def test_convolution_off_by_one_is_caught(monkeypatch):
+    def shifted(y, f, direct):
+        n = y.shape[-1]
+        if n == 0:
+            return np.zeros_like(y)
+        k = noise.symmetric_kernel(f)
+        full = np.convolve(y, k, mode="full")
+        c = f.shape[0] - 2
+        return full[c:c + n]
+    monkeypatch.setattr(noise, "_convolve_interval", shifted)
+    _fails(pn.test_ninv_fft_equals_direct_equals_dense_toeplitz, [257, 31, 33, 2])
+
+
+def test_pcg_beta_sign_error_is_caught(monkeypatch):
+    def bad_pcg(self, b, tol=1e-6, max_iter=50, precond="block", **kw):
+        M = self.preconditioner(precond)
+        x = np.zeros_like(b)
+        r = b.copy()
+        z = M(r)
+        p = z.copy()
+        rho = r @ z
+        for it in range(max_iter):
+            q = self.apply_H(p)
+            a = rho / (p @ q)
+            x = x + a * p
+            r = r - a * q
+            if np.linalg.norm(r) <= tol * np.linalg.norm(b):
+                break
+            z = M(r)
+            rho_new = r @ z
+            p = z - (rho_new / rho) * p          # planted: wrong sign of beta
+            rho = rho_new
+        return x, solver.PCGInfo(it + 1, it + 1, 0.0, np.zeros(1), True)
+    monkeypatch.setattr(solver.Oracle, "pcg", bad_pcg)
+    _fails(sv.test_pcg_matches_dense_direct_solve, 3)
+
+
+def test_unweighted_preconditioner_is_caught(monkeypatch):
+    # dropping W^-1 from (A^T W^-1 A) breaks one-step convergence with two noise levels
+    orig = noise.white_weights
+    monkeypatch.setattr(noise, "white_weights", lambda *a: np.ones_like(orig(*a)))
+    _fails(sv.test_white_noise_T_map_is_the_binned_average)
+
+
+def test_wrong_h_prime_is_caught(monkeypatch):
+    monkeypatch.setattr(fftlen, "h_prime",
+                        lambda nf, nc: (1.0 + np.log(nf)) / (nf - 2.0 * nc))
+    _fails(sv.test_appendix_a_critical_point_is_a_minimum, 1024)
+
+
+def test_best_iterate_rule_is_caught(monkeypatch):
+    orig = solver.Oracle.pcg
+
+    def last_iterate(self, b, **kw):
+        cb_x = {}
+        user_cb = kw.pop("callback", None)
+
+        def cb(it, x, r):
+            cb_x["x"] = x.copy()
+            if user_cb:
+                user_cb(it, x, r)
+        x, info = orig(self, b, callback=cb, **kw)
+        info.best_iter = info.iters
+        return cb_x.get("x", x), info
+    monkeypatch.setattr(solver.Oracle, "pcg", last_iterate)
+    _fails(sv.test_returns_the_lowest_residual_iterate)
