@@ -1,0 +1,197 @@
+/*
+ * mm.h -- C ABI of the MI355X maximum-likelihood map-maker (libmm.so).
+ *
+ * The library solves the map-making normal equations of the MADmap paper
+ * (Cantalupo et al., arXiv:0906.1775, Algorithm section, eq. pcgSystem):
+ *
+ *     H m = b,   H = P^T N^-1 P,   b = P^T N^-1 d,
+ *
+ * by preconditioned conjugate gradients (Implementation section).  P is the
+ * sparse pointing matrix of the Formalism section (the paper calls it A):
+ * one unit weight per sample for temperature, or the three weights
+ * (1/2, sin(2a_t)/2, cos(2a_t)/2) of (I, Q, U) for an ideal polarimeter.
+ * N^-1 is block diagonal with one banded Toeplitz block per stationary
+ * interval, (N^-1)_{t,t'} = f(|t - t'|) for |t - t'| < n_c (Weighting
+ * section), applied by overlap-save FFTs.  The preconditioner is the
+ * white-noise block inverse (P^T W^-1 P)^-1 with W^-1 = diag(N^-1), or the
+ * point-Jacobi diag(P^T P)^-1 (Implementation section).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device (HBM) pointers on the current HIP device;
+ *     all others are host pointers.  The caller owns every buffer it passes;
+ *     the library owns only the plan and what the plan allocates.
+ *   - `stream` is a hipStream_t (passed as void*); NULL means the default
+ *     stream.  Work is enqueued on it; entry points that must read results
+ *     on the host (plan creation, mm_solve) synchronise that stream.
+ *   - Maps cross the boundary in global pixel layout, float64,
+ *     [n_rhs][n_pix][n_stokes] (Stokes fastest).  Pixels never observed are
+ *     written as 0.
+ *   - Time-ordered data (TOD) cross the boundary as [n_rhs][n_samples] of
+ *     float32 (MM_F32) or float64 (MM_F64).
+ *   - Every entry point returns an mm_status_t and never throws; on failure
+ *     mm_last_error() gives a message for the calling thread.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_plan_s* mm_plan_t;
+
+typedef enum {
+  MM_OK = 0,
+  MM_EINVAL = 1,        /* invalid argument or descriptor */
+  MM_ENOMEM = 2,        /* device allocation failed */
+  MM_EDEVICE = 3,       /* HIP runtime or kernel error */
+  MM_ENOTCONV = 4,      /* solve ended at max_iter above tol (best iterate still written) */
+  MM_ESINGULAR = 5,     /* a preconditioner block is singular or ill-conditioned */
+  MM_EUNSUPPORTED = 6   /* valid request this build does not implement */
+} mm_status_t;
+
+/* precision of the CG iterations */
+enum { MM_FP64 = 0,     /* gather, filter and scatter in float64 */
+       MM_MIXED = 1 };  /* TOD filtering and scatter in float32 with compensated pixel
+                           sums; dot products, scalars, preconditioner in float64 */
+
+/* preconditioner */
+enum { MM_PRECOND_BLOCK = 0,   /* (P^T W^-1 P)^-1, 1x1 or 3x3 per pixel */
+       MM_PRECOND_JACOBI = 1,  /* diag(P^T P)^-1 */
+       MM_PRECOND_NONE = 2 };
+
+/* element type of a TOD buffer */
+enum { MM_F32 = 0, MM_F64 = 1 };
+
+typedef struct {
+  int32_t n_stokes;             /* 1 (T) or 3 (I, Q, U) */
+  int64_t n_pix;                /* global pixel count; pointing indices lie in [-1, n_pix) */
+  int64_t n_samples;            /* n_t, at most 2^31 - 1 */
+  int32_t n_intervals;          /* stationary intervals n_b >= 1 */
+  const int64_t* iv_start;      /* host [n_intervals + 1]: iv_start[0] = 0, non-decreasing,
+                                   iv_start[n_intervals] = n_samples */
+  const int32_t* iv_filter;     /* host [n_intervals]: noise filter of each interval */
+  int32_t n_filters;            /* >= 1 */
+  const double* filter_params;  /* host [n_filters][3] = (sigma, f_knee, alpha) of
+                                   p(f) = sigma^2 (1 + (f_knee/f)^alpha); may be NULL
+                                   when filter_lags is given */
+  const double* filter_lags;    /* host [n_filters][n_c] explicit f(tau), or NULL */
+  double f_samp;                /* sampling frequency in Hz (used with filter_params) */
+  int32_t n_c;                  /* correlation length: f(tau) = 0 for tau >= n_c; >= 1 */
+  int32_t n_f;                  /* overlap-save FFT length: 0 = library default (the
+                                   paper's rule capped at the largest on-chip length),
+                                   > 0 = forced power of two with n_f > 2 n_c */
+  int32_t lag_dft_len;          /* L_K, frequencies on which 1/p is sampled to build f
+                                   from filter_params; 0 = 2^20; power of two >= 4 n_c */
+  int32_t precision;            /* MM_FP64 or MM_MIXED */
+  int32_t precond;              /* MM_PRECOND_* */
+  int32_t n_rhs;                /* right-hand sides solved together, 1 .. 64 */
+} mm_desc_t;
+
+typedef struct {
+  int64_t n_obs;                /* observed pixels (the unknowns are n_obs * n_stokes per RHS) */
+  int64_t n_valid;              /* samples with a pixel (pointing index >= 0) */
+  int32_t n_f;                  /* FFT length the iterations use */
+  int32_t n_chunks;             /* overlap-save transforms per TOD pass and RHS */
+  int32_t n_singular;           /* preconditioner blocks flagged singular */
+  int64_t device_bytes;         /* device memory held by the plan */
+} mm_plan_info_t;
+
+/*
+ * Build a plan: validate the descriptor, range-check the pointing, compact
+ * the observed pixels (Implementation section, observed index scheme), sort
+ * samples by pixel for the pixel-major scatter, build the noise filters
+ * (lags f(tau) and overlap-save spectra) and the preconditioner.
+ *   d_pix: device int32 [n_samples], pixel of each sample, -1 = no pixel
+ *          (excised sample; its row of P is zero).
+ *   d_w:   device float32 [n_samples][2] = (sin 2a_t, cos 2a_t); required
+ *          when n_stokes == 3, ignored (may be NULL) when n_stokes == 1.
+ *          d_w must stay allocated and unchanged until mm_plan_destroy.
+ * Errors: MM_EINVAL (descriptor, pixel out of range), MM_ENOMEM, MM_EDEVICE,
+ * MM_EUNSUPPORTED (forced n_f longer than the on-chip transforms).  A
+ * singular preconditioner block does not fail the plan; it is counted in
+ * mm_plan_info_t.n_singular and makes mm_solve return MM_ESINGULAR.
+ */
+mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w,
+                           void* stream, mm_plan_t* out_plan);
+mm_status_t mm_plan_destroy(mm_plan_t plan);
+mm_status_t mm_plan_get_info(mm_plan_t plan, mm_plan_info_t* info);
+
+/* Hit count of every global pixel: device int32 [n_pix] (exact integers). */
+mm_status_t mm_hits(mm_plan_t plan, int32_t* d_hits, void* stream);
+
+/* The plan's lags f(tau): host float64 [n_filters][n_c] (synchronises). */
+mm_status_t mm_filter_lags(mm_plan_t plan, double* lags_out, void* stream);
+
+/* y = P x: device map [n_rhs][n_pix][n_stokes] float64 -> TOD [n_rhs][n_samples]
+ * of tod_dtype (unpointing, Formalism section). */
+mm_status_t mm_unpoint(mm_plan_t plan, const double* d_x, void* d_y, int32_t tod_dtype,
+                       void* stream);
+
+/* x = P^T y: TOD [n_rhs][n_samples] of tod_dtype -> map (pointing / scatter-add). */
+mm_status_t mm_point(mm_plan_t plan, const void* d_y, int32_t tod_dtype, double* d_x,
+                     void* stream);
+
+/* y_out = N^-1 y_in per interval (Weighting section), in the plan's precision
+ * (float64 for MM_FP64, float32 arithmetic for MM_MIXED).  TOD buffers
+ * [n_rhs][n_samples] of tod_dtype; y_out must not overlap y_in. */
+mm_status_t mm_weight(mm_plan_t plan, const void* d_y_in, void* d_y_out, int32_t tod_dtype,
+                      void* stream);
+
+/* y = H x = P^T N^-1 P x for maps [n_rhs][n_pix][n_stokes] (one CG operator application). */
+mm_status_t mm_apply_A(mm_plan_t plan, const double* d_x, double* d_y, void* stream);
+
+/* b = P^T N^-1 d (right-hand side, one pass over the TOD). */
+mm_status_t mm_rhs(mm_plan_t plan, const void* d_tod, int32_t tod_dtype, double* d_b,
+                   void* stream);
+
+typedef struct {
+  double tol;                   /* stop when ||r||_2 / ||b||_2 <= tol (paper default 1e-6) */
+  int32_t max_iter;             /* at most this many H applications (paper default 50) */
+  int32_t fixed_iters;          /* > 0: run exactly this many iterations, ignore tol */
+  int32_t check_every;          /* iterations between host convergence checks (>= 1) */
+  int32_t use_graph;            /* capture each block of check_every iterations in a hipGraph */
+  int32_t true_residual;        /* recompute ||b - H x_best|| / ||b|| in float64 at exit */
+  const double* d_x0;           /* optional initial map [n_rhs][n_pix][n_stokes]; NULL = 0 */
+} mm_solve_opts_t;
+
+typedef struct {
+  int32_t* iters;               /* [n_rhs] H applications performed per RHS */
+  int32_t* best_iter;           /* [n_rhs] iteration of the returned iterate (0 = x0) */
+  double* best_rel_res;         /* [n_rhs] its recurrence relative residual */
+  double* true_rel_res;         /* [n_rhs] float64 ||b - H x||/||b|| of the returned map, or NaN */
+  double* history;              /* [n_rhs][max_iter + 1] relative residual per iteration
+                                   (entry 0 = start); may be NULL */
+} mm_solve_info_t;
+
+/* Fill opts with the paper's defaults (tol 1e-6, max_iter 50, check_every 8, graph on). */
+void mm_solve_opts_default(mm_solve_opts_t* opts);
+
+/*
+ * Solve H m = b for every RHS with PCG; writes to d_x the iterate with the
+ * lowest relative residual seen (Implementation section).  Each RHS stops at
+ * its own tol.  Returns MM_ENOTCONV (with the best iterate written) if any RHS
+ * ends at max_iter above tol, MM_ESINGULAR if the plan flagged a singular
+ * preconditioner block.  info may be NULL; its arrays are optional.
+ */
+mm_status_t mm_solve(mm_plan_t plan, const void* d_tod, int32_t tod_dtype, double* d_x,
+                     const mm_solve_opts_t* opts, mm_solve_info_t* info, void* stream);
+
+/* FFT length by the paper's halving rule (Weighting section, eq. FFTcomplexityFunction):
+ * start at the smallest power of two >= longest, halve while h'(n_f/2) >= 0 and
+ * n_f/2 > 2 n_c.  Returns 0 for invalid arguments. */
+int32_t mm_fft_length_rule(int32_t n_c, int64_t longest);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* mm_last_error(void);
+
+/* Library version string. */
+const char* mm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MM_H */

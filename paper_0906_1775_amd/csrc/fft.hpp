@@ -1,0 +1,254 @@
+// Workgroup-resident complex FFT for gfx950 (device code).
+//
+// A workgroup of NT threads transforms N = 2^LOGN complex points.  Each
+// thread keeps E = N / NT points in registers; the transform is a sequence of
+// Stockham autosort passes (radix 2^LOGE, plus one shorter pass when LOGE
+// does not divide LOGN).  A pass runs the radix-R butterflies of one thread
+// entirely in registers; between passes the points are re-distributed
+// through LDS (all at once when N complex points fit, else real parts then
+// imaginary parts through an N-scalar buffer).  LDS indices are padded by one
+// element per 128-byte row so the strided writes of the early passes spread
+// over the banks.
+//
+// Pass with radix R and span Ns (product of the radices before it), for
+// butterfly b in [0, N/R) and element r in [0, R):
+//   input  index  b + r N/R,
+//   twiddle       exp(-2 pi i (b mod Ns) r / (Ns R)),
+//   output index  (b / Ns) Ns R + (b mod Ns) + r Ns.
+// Thread t owns butterflies b = t + i NT.  After the last pass the output of
+// (b, r) is point b + r N/R_last, i.e. the natural order, strided.
+//
+// Twiddles come from a table tw2[k] = exp(-2 pi i k / (2N)), k < N, built in
+// float64 and rounded once to T; the same table serves the real-to-complex
+// packing of the overlap-save filter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// cos(2 pi k / 32), k in [0, 32) (correctly rounded decimal expansions for k <= 8)
+__host__ __device__ constexpr double cos32_first_octant(int k) {
+  return k == 0 ? 1.0
+       : k == 1 ? 0.9807852804032304491261822
+       : k == 2 ? 0.9238795325112867561281832
+       : k == 3 ? 0.8314696123025452370787884
+       : k == 4 ? 0.7071067811865475244008444
+       : k == 5 ? 0.5555702330196022247428308
+       : k == 6 ? 0.38268343236508977172846
+       : k == 7 ? 0.1950903220161282678482849
+       : 0.0;
+}
+__host__ __device__ constexpr double cos32(int k) {
+  return k <= 8 ? cos32_first_octant(k)
+       : (k <= 16 ? -cos32_first_octant(16 - k)
+       : (k <= 24 ? -cos32_first_octant(k - 16) : cos32_first_octant(32 - k)));
+}
+__host__ __device__ constexpr double sin32(int k) { return cos32((k + 24) & 31); }
+
+// z * exp(-2 pi i j / len), len a power of two <= 32, j < len; branches fold at compile time
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle_const(cx<T> z, int j, int len) {
+  const int k = j * (32 / len);  // angle = 2 pi k / 32
+  if (k == 0) return z;
+  if (k == 8) return {z.im, -z.re};                         // * (-i)
+  if (k == 16) return {-z.re, -z.im};                       // * (-1)
+  if (k == 24) return {-z.im, z.re};                        // * (+i)
+  const T c = (T)cos32(k), s = (T)sin32(k);                 // w = c - i s
+  if (k == 4) { const T h = c; return {h * (z.re + z.im), h * (z.im - z.re)}; }
+  if (k == 12) { const T h = s; return {h * (z.im - z.re), -h * (z.re + z.im)}; }
+  return {z.re * c + z.im * s, z.im * c - z.re * s};
+}
+
+__host__ __device__ constexpr int bitrev(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// In-register forward DFT of R = 2^LOGR points: radix-2 decimation in
+// frequency, then the bit-reversal permutation (free register renaming).
+template <typename T, int LOGR>
+__device__ __forceinline__ void dft_reg(cx<T>* v) {
+  constexpr int R = 1 << LOGR;
+#pragma unroll
+  for (int len = R; len >= 2; len >>= 1) {
+    const int half = len >> 1;
+#pragma unroll
+    for (int blk = 0; blk < R; blk += len) {
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const cx<T> a = v[blk + j], b = v[blk + j + half];
+        v[blk + j] = cadd(a, b);
+        v[blk + j + half] = twiddle_const(csub(a, b), j, len);
+      }
+    }
+  }
+  cx<T> tmp[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) tmp[k] = v[bitrev(k, LOGR)];
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = tmp[k];
+}
+
+// exp(-2 pi i idx / N) from tw2[k] = exp(-2 pi i k / (2N)), idx < N
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle_N(const cx<T>* __restrict__ tw2, int idx, int N) {
+  const int k = 2 * idx;
+  if (k < N) return tw2[k];
+  const cx<T> w = tw2[k - N];
+  return {-w.re, -w.im};
+}
+
+template <typename T, int LOGN, int NT_, int LOGE>
+struct BlockFFT {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int NT = NT_;
+  static constexpr int E = 1 << LOGE;
+  static_assert(N == NT * E, "N must equal threads * points per thread");
+  static constexpr int P = LOGN / LOGE;
+  static constexpr int REM = LOGN % LOGE;
+  static constexpr int NP = P + (REM ? 1 : 0);
+  // forward sequence: the short pass first; inverse sequence: the short pass last,
+  // so the last forward pass and the first inverse pass share one data layout
+  static constexpr int flog(int p) { return (REM && p == 0) ? REM : LOGE; }
+  static constexpr int ilog(int p) { return (REM && p == NP - 1) ? REM : LOGE; }
+
+  static constexpr int kLdsLimit = 160 * 1024;
+  static constexpr int cx_pad_log = (sizeof(T) == 4) ? 4 : 3;  // 128 B / (2 sizeof T)
+  static constexpr int sc_pad_log = (sizeof(T) == 4) ? 5 : 4;  // 128 B / sizeof T
+  static constexpr int cx_bytes = (N + (N >> cx_pad_log)) * 2 * (int)sizeof(T);
+  static constexpr int sc_bytes = (N + (N >> sc_pad_log)) * (int)sizeof(T);
+  static constexpr bool SPLIT = cx_bytes > kLdsLimit;
+  static constexpr int LDS_BYTES = SPLIT ? sc_bytes : cx_bytes;
+  static_assert(LDS_BYTES <= kLdsLimit, "transform does not fit in LDS");
+
+  __device__ static __forceinline__ int cpad(int i) { return i + (i >> cx_pad_log); }
+  __device__ static __forceinline__ int spad(int i) { return i + (i >> sc_pad_log); }
+
+  // output position of element (i, r) of thread t after a pass (LOGR, LOGNS)
+  template <int LOGR, int LOGNS>
+  __device__ static __forceinline__ int out_index(int t, int i, int r) {
+    const int b = t + i * NT;
+    return ((b >> LOGNS) << (LOGNS + LOGR)) + (b & ((1 << LOGNS) - 1)) + (r << LOGNS);
+  }
+  // input position of element (i, r) of thread t for a pass of radix 2^LOGR
+  template <int LOGR>
+  __device__ static __forceinline__ int in_index(int t, int i, int r) {
+    return t + i * NT + (r << (LOGN - LOGR));
+  }
+
+  // butterflies of one pass, in registers
+  template <int LOGR, int LOGNS>
+  __device__ static __forceinline__ void butterflies(cx<T>* v, const cx<T>* __restrict__ tw2, int t) {
+    constexpr int R = 1 << LOGR;
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (LOGNS > 0) {
+        const int j = (t + i * NT) & ((1 << LOGNS) - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int idx = (j * r) << (LOGN - LOGNS - LOGR);
+          v[i * R + r] = cmul(v[i * R + r], twiddle_N(tw2, idx, N));
+        }
+      }
+      dft_reg<T, LOGR>(v + i * R);
+    }
+  }
+
+  // redistribute: element (i, r) of a pass (LOGR, LOGNS) goes to the slot of the next pass (LOGR2)
+  template <int LOGR, int LOGNS, int LOGR2>
+  __device__ static __forceinline__ void exchange(cx<T>* v, void* lds_raw, int t) {
+    constexpr int R = 1 << LOGR, NB = E / R;
+    constexpr int R2 = 1 << LOGR2, NB2 = E / R2;
+    if constexpr (!SPLIT) {
+      cx<T>* lds = reinterpret_cast<cx<T>*>(lds_raw);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[cpad(out_index<LOGR, LOGNS>(t, i, r))] = v[i * R + r];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NB2; ++i)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds[cpad(in_index<LOGR2>(t, i, r))];
+    } else {
+      T* lds = reinterpret_cast<T*>(lds_raw);
+      T tmp[E];
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            lds[spad(out_index<LOGR, LOGNS>(t, i, r))] = part ? v[i * R + r].im : v[i * R + r].re;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB2; ++i)
+#pragma unroll
+          for (int r = 0; r < R2; ++r) tmp[i * R2 + r] = lds[spad(in_index<LOGR2>(t, i, r))];
+        if (part == 0) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e].re = tmp[e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e].im = tmp[e];
+        }
+      }
+    }
+  }
+
+  // pass p of a sequence (FWD: forward order of radices, else inverse order)
+  template <bool FWD, int p, int LOGNS>
+  __device__ static __forceinline__ void run_from(cx<T>* v, void* lds, const cx<T>* __restrict__ tw2,
+                                                  int t) {
+    constexpr int LR = FWD ? flog(p) : ilog(p);
+    butterflies<LR, LOGNS>(v, tw2, t);
+    if constexpr (p + 1 < NP) {
+      constexpr int LR2 = FWD ? flog(p + 1) : ilog(p + 1);
+      exchange<LR, LOGNS, LR2>(v, lds, t);
+      run_from<FWD, p + 1, LOGNS + LR>(v, lds, tw2, t);
+    }
+  }
+
+  // Input: point (i, r) of thread t holds x[in_index<first radix>(t, i, r)].
+  // Output: point (i, r) holds X[t + i NT + r N / R_last] (forward DFT, no scaling).
+  __device__ static __forceinline__ void forward(cx<T>* v, void* lds, const cx<T>* __restrict__ tw2,
+                                                 int t) {
+    run_from<true, 0, 0>(v, lds, tw2, t);
+  }
+  // Same transform with the radix order reversed (first pass = forward's last radix).
+  __device__ static __forceinline__ void forward_rev(cx<T>* v, void* lds, const cx<T>* __restrict__ tw2,
+                                                     int t) {
+    run_from<false, 0, 0>(v, lds, tw2, t);
+  }
+
+  static constexpr int first_log_fwd() { return flog(0); }
+  static constexpr int last_log_fwd() { return flog(NP - 1); }
+  static constexpr int first_log_rev() { return ilog(0); }
+  static constexpr int last_log_rev() { return ilog(NP - 1); }
+};
+
+}  // namespace mm

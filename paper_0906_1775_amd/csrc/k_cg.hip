@@ -1,0 +1,413 @@
+// Preconditioned conjugate-gradient vector kernels and the block
+// preconditioner (Implementation section of the MADmap paper).
+//
+// All pixel-domain vectors are float64 [R][n_obs][ns].  Dot products are
+// formed as kDotBlocks partial sums per RHS (fixed grid => fixed summation
+// order => bitwise repeatable) and folded by the scalar kernels, which keep
+// every CG scalar on the device (CgState), so an iteration needs no host
+// round trip.
+//
+// Iteration (per RHS, while active), matching the textbook PCG order:
+//   q = H p;  alpha = rho / (p.q);  x += alpha p;  r -= alpha q;
+//   rel = ||r|| / ||b||;  keep x if rel is the lowest so far;  stop if rel <= tol;
+//   z = M r;  rho' = r.z;  beta = rho'/rho;  p = z + beta p.
+#include "mm_internal.h"
+
+namespace mm {
+
+static dim3 grid_for(int64_t n) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  return dim3((unsigned)nb);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  }
+  __syncthreads();
+  return s;   // valid in thread 0
+}
+
+// sum of the kDotBlocks partials of RHS r by one wavefront (fixed order)
+__device__ __forceinline__ double fold_partials(const double* __restrict__ part, int r) {
+  const int lane = threadIdx.x & 63;
+  double v = 0.0;
+  for (int i = lane; i < kDotBlocks; i += 64) v += part[(int64_t)r * kDotBlocks + i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------- dots
+__global__ __launch_bounds__(kDotThreads) void k_dot(const double* __restrict__ x,
+                                                     const double* __restrict__ y, int64_t nu,
+                                                     double* __restrict__ partial) {
+  __shared__ double sh[kDotThreads / 64];
+  const int r = blockIdx.y;
+  const double* xr = x + (int64_t)r * nu;
+  const double* yr = y + (int64_t)r * nu;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i < nu;
+       i += (int64_t)kDotBlocks * kDotThreads)
+    acc += xr[i] * yr[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)r * kDotBlocks + blockIdx.x] = s;
+}
+
+hipError_t launch_dot(const double* x, const double* y, int64_t nu, int n_rhs, double* partial,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(kDotBlocks, n_rhs), dim3(kDotThreads), 0, s, x, y, nu, partial);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scalars
+__global__ void k_cg_init(CgState* st, const double* __restrict__ pbb, const double* __restrict__ prr,
+                          const double* __restrict__ prz, double tol, int fixed,
+                          double* __restrict__ history, int hist_stride) {
+  const int r = blockIdx.x;
+  const double bb = fold_partials(pbb, r);
+  const double rr = fold_partials(prr, r);
+  const double rz = fold_partials(prz, r);
+  if (threadIdx.x != 0) return;
+  CgState s;
+  s.bnorm = sqrt(bb);
+  s.rel = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+  s.rho = rz;
+  s.alpha = 0.0;
+  s.beta = 0.0;
+  s.best_rel = s.rel;
+  s.tol = tol;
+  s.iter = 0;
+  s.best_iter = 0;
+  s.fixed = fixed;
+  s.active = (s.bnorm > 0.0) && (fixed || !(s.rel <= tol)) ? 1 : 0;
+  s.copy_best = 0;
+  s.pad = 0;
+  st[r] = s;
+  if (history) history[(int64_t)r * hist_stride] = s.rel;
+}
+
+hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* partial_rr,
+                          const double* partial_rz, double tol, int fixed, int n_rhs,
+                          double* history, int hist_stride, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(n_rhs), dim3(64), 0, s, st, partial_bb, partial_rr, partial_rz,
+                     tol, fixed, history, hist_stride);
+  return hipGetLastError();
+}
+
+__global__ void k_cg_alpha(CgState* st, const double* __restrict__ ppq) {
+  const int r = blockIdx.x;
+  const double pq = fold_partials(ppq, r);
+  if (threadIdx.x != 0) return;
+  CgState& s = st[r];
+  if (!s.active) { s.alpha = 0.0; return; }
+  if (!(pq > 0.0) || !isfinite(pq)) {   // breakdown: H not positive definite on p
+    s.alpha = 0.0;
+    s.active = 0;
+    return;
+  }
+  s.alpha = s.rho / pq;
+}
+
+hipError_t launch_cg_alpha(CgState* st, const double* partial_pq, int n_rhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(n_rhs), dim3(64), 0, s, st, partial_pq);
+  return hipGetLastError();
+}
+
+template <int NS>
+__device__ __forceinline__ void precond_apply(const double* __restrict__ m, const double* r, double* z) {
+  if (NS == 1) {
+    z[0] = m[0] * r[0];
+  } else {
+    z[0] = m[0] * r[0] + m[1] * r[1] + m[2] * r[2];
+    z[1] = m[1] * r[0] + m[3] * r[1] + m[4] * r[2];
+    z[2] = m[2] * r[0] + m[4] * r[1] + m[5] * r[2];
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(kDotThreads) void k_cg_update(
+    double* __restrict__ x, const double* __restrict__ p, double* __restrict__ rv,
+    const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ minv,
+    const CgState* __restrict__ st, int64_t n_obs, double* __restrict__ prz,
+    double* __restrict__ prr) {
+  __shared__ double sh[kDotThreads / 64];
+  constexpr int NM = NS == 1 ? 1 : 6;
+  const int r = blockIdx.y;
+  const bool active = st[r].active != 0;
+  const double alpha = st[r].alpha;
+  const int64_t off = (int64_t)r * n_obs * NS;
+  double arz = 0.0, arr = 0.0;
+  if (active) {
+    for (int64_t o = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; o < n_obs;
+         o += (int64_t)kDotBlocks * kDotThreads) {
+      const int64_t b = off + o * NS;
+      double rr[NS], zz[NS];
+#pragma unroll
+      for (int c = 0; c < NS; ++c) {
+        x[b + c] += alpha * p[b + c];
+        rr[c] = rv[b + c] - alpha * q[b + c];
+        rv[b + c] = rr[c];
+      }
+      precond_apply<NS>(minv + o * NM, rr, zz);
+#pragma unroll
+      for (int c = 0; c < NS; ++c) {
+        z[b + c] = zz[c];
+        arz += rr[c] * zz[c];
+        arr += rr[c] * rr[c];
+      }
+    }
+  }
+  const double s1 = block_sum(arz, sh);
+  const double s2 = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    prz[(int64_t)r * kDotBlocks + blockIdx.x] = s1;
+    prr[(int64_t)r * kDotBlocks + blockIdx.x] = s2;
+  }
+}
+
+hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
+                            double* z, const double* minv, const CgState* st, int64_t n_obs,
+                            int n_rhs, double* partial_rz, double* partial_rr, hipStream_t s) {
+  const dim3 g(kDotBlocks, n_rhs), b(kDotThreads);
+  if (ns == 1)
+    hipLaunchKernelGGL(k_cg_update<1>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, partial_rz, partial_rr);
+  else
+    hipLaunchKernelGGL(k_cg_update<3>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, partial_rz, partial_rr);
+  return hipGetLastError();
+}
+
+__global__ void k_cg_finalize(CgState* st, const double* __restrict__ prz,
+                              const double* __restrict__ prr, double* __restrict__ history,
+                              int hist_stride) {
+  const int r = blockIdx.x;
+  const double rz = fold_partials(prz, r);
+  const double rr = fold_partials(prr, r);
+  if (threadIdx.x != 0) return;
+  CgState s = st[r];
+  if (!s.active) {
+    s.copy_best = 0;
+    st[r] = s;
+    return;
+  }
+  s.iter += 1;
+  s.rel = sqrt(rr) / s.bnorm;
+  if (history) history[(int64_t)r * hist_stride + s.iter] = s.rel;
+  if (s.rel < s.best_rel) {
+    s.best_rel = s.rel;
+    s.best_iter = s.iter;
+    s.copy_best = 1;
+  } else {
+    s.copy_best = 0;
+  }
+  if (!s.fixed && s.rel <= s.tol) s.active = 0;
+  s.beta = rz / s.rho;
+  s.rho = rz;
+  st[r] = s;
+}
+
+hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
+                              int n_rhs, double* history, int hist_stride, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_finalize, dim3(n_rhs), dim3(64), 0, s, st, partial_rz, partial_rr,
+                     history, hist_stride);
+  return hipGetLastError();
+}
+
+__global__ void k_cg_copy_best(const double* __restrict__ x, double* __restrict__ xbest,
+                               const CgState* __restrict__ st, int64_t nu) {
+  const int r = blockIdx.y;
+  if (!st[r].copy_best) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride)
+    xbest[(int64_t)r * nu + i] = x[(int64_t)r * nu + i];
+}
+
+hipError_t launch_cg_copy_best(const double* x, double* xbest, const CgState* st, int64_t nu,
+                               int n_rhs, hipStream_t s) {
+  dim3 g = grid_for(nu);
+  g.y = n_rhs;
+  hipLaunchKernelGGL(k_cg_copy_best, g, dim3(256), 0, s, x, xbest, st, nu);
+  return hipGetLastError();
+}
+
+__global__ void k_cg_update_p(double* __restrict__ p, const double* __restrict__ z,
+                              const CgState* __restrict__ st, int64_t nu) {
+  const int r = blockIdx.y;
+  if (!st[r].active) return;
+  const double beta = st[r].beta;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
+    const int64_t j = (int64_t)r * nu + i;
+    p[j] = z[j] + beta * p[j];
+  }
+}
+
+hipError_t launch_cg_update_p(double* p, const double* z, const CgState* st, int64_t nu,
+                              int n_rhs, hipStream_t s) {
+  dim3 g = grid_for(nu);
+  g.y = n_rhs;
+  hipLaunchKernelGGL(k_cg_update_p, g, dim3(256), 0, s, p, z, st, nu);
+  return hipGetLastError();
+}
+
+template <int NS>
+__global__ void k_apply_precond(const double* __restrict__ minv, const double* __restrict__ r,
+                                double* __restrict__ z, int64_t n_obs, int n_rhs) {
+  constexpr int NM = NS == 1 ? 1 : 6;
+  const int64_t n = n_obs * n_rhs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t o = i % n_obs;
+    double rr[NS], zz[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) rr[c] = r[i * NS + c];
+    precond_apply<NS>(minv + o * NM, rr, zz);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) z[i * NS + c] = zz[c];
+  }
+}
+
+hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
+                                int64_t n_obs, int n_rhs, hipStream_t s) {
+  const dim3 g = grid_for(n_obs * n_rhs);
+  if (ns == 1) hipLaunchKernelGGL(k_apply_precond<1>, g, dim3(256), 0, s, minv, r, z, n_obs, n_rhs);
+  else hipLaunchKernelGGL(k_apply_precond<3>, g, dim3(256), 0, s, minv, r, z, n_obs, n_rhs);
+  return hipGetLastError();
+}
+
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b,
+                        int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    y[i] = a * x[i] + b * y[i];
+}
+
+hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby, grid_for(n), dim3(256), 0, s, y, x, a, b, n);
+  return hipGetLastError();
+}
+
+__global__ void k_sub(double* __restrict__ out, const double* __restrict__ a,
+                      const double* __restrict__ b, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = a[i] - b[i];
+}
+
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub, grid_for(n), dim3(256), 0, s, out, a, b, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- preconditioner
+// kind 0: block (P^T W^-1 P)^-1 with W^-1 = diag(N^-1) = f_b(0) of each sample's interval;
+// kind 1: point Jacobi diag(P^T P)^-1;  kind 2: identity.
+template <int NS>
+__global__ void k_precond_build(int kind, const int64_t* __restrict__ pix_ptr,
+                                const int32_t* __restrict__ perm, const float2* __restrict__ w_pm,
+                                const int64_t* __restrict__ iv_start, int n_iv,
+                                const int32_t* __restrict__ iv_filter,
+                                const double* __restrict__ lags, int n_c, int64_t n_obs,
+                                double* __restrict__ minv, int32_t* __restrict__ singular) {
+  constexpr int NM = NS == 1 ? 1 : 6;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n_obs; o += stride) {
+    double* m = minv + o * NM;
+    int32_t bad = 0;
+    if (kind == 2) {
+      m[0] = 1.0;
+      if (NS == 3) { m[1] = 0.0; m[2] = 0.0; m[3] = 1.0; m[4] = 0.0; m[5] = 1.0; }
+      singular[o] = 0;
+      continue;
+    }
+    double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = pix_ptr[o]; k < pix_ptr[o + 1]; ++k) {
+      double wgt = 1.0;
+      if (kind == 0) {
+        const int64_t t = perm[k];
+        int lo = 0, hi = n_iv;   // last interval with iv_start <= t
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (iv_start[mid] <= t) lo = mid; else hi = mid;
+        }
+        wgt = lags[(int64_t)iv_filter[lo] * n_c];
+      }
+      if (NS == 1) {
+        B[0] += wgt;
+      } else {
+        const float2 sc = w_pm[k];
+        const double a0 = 0.5, a1 = 0.5 * (double)sc.x, a2 = 0.5 * (double)sc.y;
+        B[0] += wgt * a0 * a0;
+        B[1] += wgt * a0 * a1;
+        B[2] += wgt * a0 * a2;
+        B[3] += wgt * a1 * a1;
+        B[4] += wgt * a1 * a2;
+        B[5] += wgt * a2 * a2;
+      }
+    }
+    if (NS == 1) {
+      bad = !(B[0] > 0.0);
+      m[0] = bad ? 0.0 : 1.0 / B[0];
+    } else if (kind == 1) {
+      bad = !(B[0] > 0.0 && B[3] > 0.0 && B[5] > 0.0);
+      m[0] = bad ? 0.0 : 1.0 / B[0];
+      m[3] = bad ? 0.0 : 1.0 / B[3];
+      m[5] = bad ? 0.0 : 1.0 / B[5];
+      m[1] = m[2] = m[4] = 0.0;
+    } else {
+      // symmetric 3x3 inverse by cofactors
+      const double a = B[0], b = B[1], c = B[2], d = B[3], e = B[4], f = B[5];
+      const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+      const double c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+      const double det = a * c00 + b * c01 + c * c02;
+      bad = !(det > 1e-10 * a * d * f) || !isfinite(det);
+      const double id = bad ? 0.0 : 1.0 / det;
+      m[0] = c00 * id; m[1] = c01 * id; m[2] = c02 * id;
+      m[3] = c11 * id; m[4] = c12 * id; m[5] = c22 * id;
+    }
+    singular[o] = bad;
+  }
+}
+
+hipError_t launch_precond_build(int ns, int kind, const int64_t* pix_ptr, const int32_t* perm,
+                                const float* w_pm, const int64_t* iv_start, int n_iv,
+                                const int32_t* iv_filter, const double* lags, int n_c,
+                                int64_t n_obs, double* minv, int32_t* singular, hipStream_t s) {
+  if (n_obs == 0) return hipSuccess;
+  const dim3 g = grid_for(n_obs);
+  if (ns == 1)
+    hipLaunchKernelGGL(k_precond_build<1>, g, dim3(256), 0, s, kind, pix_ptr, perm,
+                       (const float2*)w_pm, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular);
+  else
+    hipLaunchKernelGGL(k_precond_build<3>, g, dim3(256), 0, s, kind, pix_ptr, perm,
+                       (const float2*)w_pm, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void k_count_nonzero(const int32_t* __restrict__ flags, int64_t n,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[1024 / 64];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += flags[i] != 0 ? 1.0 : 0.0;
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_count_nonzero(const int32_t* flags, int64_t n, double* partial, double* out,
+                                hipStream_t s) {
+  (void)partial;
+  hipLaunchKernelGGL(k_count_nonzero, dim3(1), dim3(1024), 0, s, flags, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace mm

@@ -1,0 +1,322 @@
+// Plan-time pointing preparation: pixel range check, stable sort of samples
+// by pixel, observed-pixel compaction and the pixel-major layout.
+//
+// The paper keeps three pixel index schemes (Implementation section, pixel
+// indexing) and re-indexes with binary searches every time the pointing is
+// rebuilt.  Here the pointing stays resident, so the re-indexing happens once:
+// a stable least-significant-digit radix sort (8-bit digits) orders the
+// samples by pixel; the first sample of each run of equal pixels opens an
+// observed pixel, which gives the observed ids, the pixel-major CSR offsets,
+// hit counts and the time-major observed index used by the gather.
+//
+// Sort tile: 256 threads x 16 rounds = 4096 keys.  Within a round, lanes of a
+// wavefront holding the same digit find each other with eight ballots; the
+// per-wave counts in LDS order the four waves; rounds run in key order, so
+// the sort is stable and every output position is computed, not raced for.
+#include "mm_internal.h"
+
+namespace mm {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+static dim3 grid_for(int64_t n, int threads = 256) {
+  int64_t nb = (n + threads - 1) / threads;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  return dim3((unsigned)nb);
+}
+
+__global__ void k_check_pix(const int32_t* __restrict__ pix, int64_t n, int64_t n_pix,
+                            int32_t* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t p = pix[i];
+    bad |= (p < -1) || ((int64_t)p >= n_pix);
+  }
+  if (bad) flag[0] = 1;   // every writer stores the same value
+}
+
+hipError_t launch_check_pix(const int32_t* pix, int64_t n, int64_t n_pix, int32_t* flag,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_pix, grid_for(n), dim3(256), 0, s, pix, n, n_pix, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scan (uint32)
+// block scan of 4096 items; writes per-block totals
+__global__ __launch_bounds__(kScanThreads) void k_scan_block(const uint32_t* __restrict__ in,
+                                                             uint32_t* __restrict__ out, int64_t n,
+                                                             uint32_t* __restrict__ block_sums,
+                                                             int exclusive) {
+  __shared__ uint32_t sh[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    v[i] = idx < n ? in[idx] : 0u;
+    sum += v[i];
+  }
+  sh[tid] = sum;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 256 thread sums
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t x = tid >= off ? sh[tid - off] : 0u;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  uint32_t run = tid > 0 ? sh[tid - 1] : 0u;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    const uint32_t x = v[i];
+    if (exclusive) {
+      if (idx < n) out[idx] = run;
+      run += x;
+    } else {
+      run += x;
+      if (idx < n) out[idx] = run;
+    }
+  }
+  if (tid == kScanThreads - 1) block_sums[blockIdx.x] = sh[kScanThreads - 1];
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n,
+                           const uint32_t* __restrict__ block_offsets) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += block_offsets[i / kScanBlock];
+}
+
+size_t scan_scratch_bytes(int64_t n) {
+  size_t total = 0;
+  int64_t m = n;
+  while (m > 1) {
+    const int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+    total += (size_t)(nb + 1) * sizeof(uint32_t);
+    if (nb == 1) break;
+    m = nb;
+  }
+  return total + 64;
+}
+
+static hipError_t scan_impl(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch,
+                            int exclusive, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  uint32_t* sums = scratch;
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, sums,
+                     exclusive);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nb == 1) return e;
+  // exclusive scan of the block totals, in place, then add
+  e = scan_impl(sums, sums, nb, scratch + nb + 1, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_inclusive(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
+                                 hipStream_t s) {
+  return scan_impl(in, out, n, (uint32_t*)scratch, 0, s);
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ void k_sort_init(const int32_t* __restrict__ pix, int64_t n, uint32_t n_pix,
+                            uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t p = pix[i];
+    keys[i] = p >= 0 ? (uint32_t)p : n_pix;
+    vals[i] = (int32_t)i;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             int64_t n, int shift, int64_t n_tiles,
+                                                             uint32_t* __restrict__ counts) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int i = 0; i < kSortRounds; ++i) {
+    const int64_t idx = base + (int64_t)i * kSortThreads + tid;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  counts[(int64_t)tid * n_tiles + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n, int shift,
+    int64_t n_tiles, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
+    int32_t* __restrict__ vals_out) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  base[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  for (int i = 0; i < kSortRounds; ++i) {
+#pragma unroll
+    for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t idx = tile0 + (int64_t)i * kSortThreads + tid;
+    const bool valid = idx < n;
+    const uint32_t key = valid ? keys_in[idx] : 0u;
+    const int32_t val = valid ? vals_in[idx] : 0;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][tid];
+    base[tid] += add;
+    __syncthreads();
+  }
+}
+
+size_t sort_scratch_bytes(int64_t n) {
+  const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+  const int64_t m = 256 * n_tiles;
+  return (size_t)n * 8 * 2                      // two key/value buffers
+         + (size_t)m * sizeof(uint32_t)          // digit counts / offsets
+         + scan_scratch_bytes(m) + 256;
+}
+
+hipError_t launch_sort_by_pixel(const int32_t* pix, int64_t n, int64_t n_pix, uint32_t* keys_out,
+                                int32_t* vals_out, void* scratch, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+  const int64_t m = 256 * n_tiles;
+  char* p = (char*)scratch;
+  uint32_t* ka = (uint32_t*)p; p += (size_t)n * 4;
+  int32_t* va = (int32_t*)p;   p += (size_t)n * 4;
+  uint32_t* kb = (uint32_t*)p; p += (size_t)n * 4;
+  int32_t* vb = (int32_t*)p;   p += (size_t)n * 4;
+  uint32_t* counts = (uint32_t*)p; p += (size_t)m * 4;
+  uint32_t* scan_tmp = (uint32_t*)p;
+
+  int bits = 0;
+  while (bits < 32 && (((uint64_t)n_pix) >> bits) != 0) ++bits;   // keys lie in [0, n_pix]
+  int passes = (bits + 7) / 8;
+  if (passes == 0) passes = 1;
+
+  hipLaunchKernelGGL(k_sort_init, grid_for(n), dim3(256), 0, s, pix, n, (uint32_t)n_pix, ka, va);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint32_t *kin = ka, *kout = kb;
+  int32_t *vin = va, *vout = vb;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = 8 * ps;
+    const bool last = ps == passes - 1;
+    uint32_t* ko = last ? keys_out : kout;
+    int32_t* vo = last ? vals_out : vout;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin, n,
+                       shift, n_tiles, counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_impl(counts, counts, m, scan_tmp, 1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin,
+                       vin, n, shift, n_tiles, counts, ko, vo);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    uint32_t* tk = kin; kin = kout; kout = tk;
+    int32_t* tv = vin; vin = vout; vout = tv;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------- observed layout
+__global__ void k_segment_flags(const uint32_t* __restrict__ keys, int64_t n, uint32_t n_pix,
+                                uint32_t* __restrict__ flags) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = keys[i];
+    flags[i] = (k < n_pix && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+  }
+}
+
+__global__ void k_find_nvalid(const uint32_t* __restrict__ keys, int64_t n, uint32_t n_pix,
+                              int64_t* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (keys[i] < n_pix && (i == n - 1 || keys[i + 1] >= n_pix)) out[0] = i + 1;   // unique writer
+  }
+}
+
+hipError_t launch_find_nvalid(const uint32_t* keys, int64_t n, uint32_t n_pix, int64_t* out,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_find_nvalid, grid_for(n), dim3(256), 0, s, keys, n, n_pix, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_flags(const uint32_t* keys, int64_t n, uint32_t n_pix, uint32_t* flags,
+                                hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segment_flags, grid_for(n), dim3(256), 0, s, keys, n, n_pix, flags);
+  return hipGetLastError();
+}
+
+// seg_id = inclusive scan of the segment flags (observed id + 1 for valid samples)
+__global__ void k_build_layout(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals,
+                               const uint32_t* __restrict__ seg_id, int64_t n, uint32_t n_pix,
+                               const float2* __restrict__ w, int ns, int64_t* __restrict__ pix_ptr,
+                               int32_t* __restrict__ obs2glob, int32_t* __restrict__ pix_obs,
+                               float2* __restrict__ w_pm, int32_t* __restrict__ perm) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = keys[i];
+    const int32_t v = vals[i];
+    if (k < n_pix) {
+      const int32_t o = (int32_t)seg_id[i] - 1;
+      if (i == 0 || keys[i - 1] != k) {
+        pix_ptr[o] = i;
+        obs2glob[o] = (int32_t)k;
+      }
+      pix_obs[v] = o;
+      perm[i] = v;
+      if (ns == 3) w_pm[i] = w[v];
+    } else {
+      pix_obs[v] = -1;
+    }
+  }
+}
+
+hipError_t launch_build_layout(const uint32_t* keys, const int32_t* vals, const uint32_t* seg_id,
+                               int64_t n, uint32_t n_pix, const float* w, int ns, int64_t* pix_ptr,
+                               int32_t* obs2glob, int32_t* pix_obs, float* w_pm, int32_t* perm,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_layout, grid_for(n), dim3(256), 0, s, keys, vals, seg_id, n, n_pix,
+                     (const float2*)w, ns, pix_ptr, obs2glob, pix_obs, (float2*)w_pm, perm);
+  return hipGetLastError();
+}
+
+}  // namespace mm

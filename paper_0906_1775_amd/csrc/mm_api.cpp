@@ -1,0 +1,782 @@
+// C ABI of the map-maker: plan construction, operator entry points and the
+// PCG driver.  See include/mm.h for the contract of every entry point.
+#include "mm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mm_internal.h"
+
+using namespace mm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+  mm_status_t status;
+};
+
+[[noreturn]] void fail(mm_status_t st, const std::string& msg) {
+  g_last_error = msg;
+  throw Failure{st};
+}
+
+void hipchk(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      fail(MM_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    fail(MM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+template <typename F>
+mm_status_t guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return MM_OK;
+  } catch (const Failure& x) {
+    return x.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MM_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected exception";
+    return MM_EDEVICE;
+  }
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+// transform length the plan prefers when the descriptor leaves n_f open
+constexpr int kPreferredMaxLogN = 13;   // n_f = 2^14
+constexpr int kMinLogN = 6;
+
+int32_t fft_length_rule(int32_t n_c, int64_t longest) {
+  if (n_c < 1 || longest < 1) return 0;
+  auto hprime_sign = [&](double nf) { return nf - 2.0 * n_c * (1.0 + std::log(nf)); };
+  int64_t nf = 1;
+  while (nf < longest) nf <<= 1;
+  if (nf <= 2 * (int64_t)n_c) {
+    nf = 1;
+    while (nf <= 2 * (int64_t)n_c) nf <<= 1;
+  } else if (hprime_sign((double)nf) > 0) {
+    for (;;) {
+      const int64_t half = nf / 2;
+      if (half <= 2 * (int64_t)n_c || hprime_sign((double)half) < 0) break;
+      nf = half;
+    }
+  }
+  return nf > (int64_t(1) << 30) ? 0 : (int32_t)nf;
+}
+
+struct FilterSetup {
+  bool ready = false;
+  bool fp64 = true;
+  int logn = 0;
+  int N = 0, nf = 0, m = 0;
+  void* tw2 = nullptr;
+  void* spec = nullptr;
+  OlsChunk* chunks = nullptr;
+  int n_chunks = 0;
+};
+
+}  // namespace
+
+struct mm_plan_s {
+  // descriptor
+  int ns = 1;
+  int64_t n_pix = 0, n_t = 0;
+  int n_iv = 0, n_filt = 0, n_c = 0;
+  int precision = MM_FP64, precond = MM_PRECOND_BLOCK, R = 1;
+  int nf_req = 0;
+  int64_t lag_len = 0;
+  double f_samp = 0;
+  std::vector<int64_t> iv_start;
+  std::vector<int32_t> iv_filter;
+  std::vector<double> params;
+  std::vector<double> lags_host;
+  int device = 0;
+  hipStream_t own = nullptr;    // stream of mm_solve and its graphs
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+
+  // pointing
+  int64_t n_obs = 0, n_valid = 0;
+  const float* w = nullptr;     // caller's (sin, cos) pairs, time-major
+  int32_t* pix_obs = nullptr;
+  int32_t* perm = nullptr;
+  float* w_pm = nullptr;
+  int64_t* pix_ptr = nullptr;
+  int32_t* obs2glob = nullptr;
+  int scatter_group = 8;
+
+  // noise
+  double* lags = nullptr;
+  int64_t* d_iv_start = nullptr;
+  int32_t* d_iv_filter = nullptr;
+  FilterSetup fs_main, fs64;
+
+  // preconditioner
+  double* minv = nullptr;
+  int n_singular = 0;
+
+  // work
+  void* y1 = nullptr;            // [R][n_t] of the iteration precision
+  void* y2 = nullptr;
+  double* y64a = nullptr;        // [n_t] float64 (true residual in mixed mode)
+  double* y64b = nullptr;
+  double *vx = nullptr, *vp = nullptr, *vr = nullptr, *vz = nullptr, *vq = nullptr,
+         *vxb = nullptr, *vb = nullptr;   // [R][n_obs][ns]
+  double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
+  CgState* st = nullptr;
+  CgState* st_host = nullptr;
+  double* hist = nullptr;
+  int hist_cap = 0;
+
+  // cached graph of check_every iterations
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
+  const double* graph_hist = nullptr;
+
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+
+  template <typename T>
+  T* alloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    const size_t b = (size_t)count * sizeof(T);
+    hipchk(hipMalloc(&p, b), "hipMalloc");
+    allocs.push_back(p);
+    bytes += (int64_t)b;
+    return (T*)p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+      allocs.erase(it);
+      hipFree(p);
+    }
+  }
+  ~mm_plan_s() {
+    if (graph) hipGraphExecDestroy(graph);
+    for (void* p : allocs) hipFree(p);
+    if (st_host) hipHostFree(st_host);
+    if (ev_in) hipEventDestroy(ev_in);
+    if (ev_out) hipEventDestroy(ev_out);
+    if (own) hipStreamDestroy(own);
+  }
+
+  int64_t nu() const { return n_obs * ns; }
+  bool main_fp64() const { return precision == MM_FP64; }
+};
+
+namespace {
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
+  const int maxlog = ols_max_logn(fp64);
+  int64_t nf;
+  if (P->nf_req > 0 && !(secondary && ilog2(P->nf_req) - 1 > maxlog)) {
+    nf = P->nf_req;
+  } else {
+    int64_t longest = 1;
+    for (int b = 0; b < P->n_iv; ++b)
+      longest = std::max<int64_t>(longest, P->iv_start[b + 1] - P->iv_start[b]);
+    nf = fft_length_rule(P->n_c, longest);
+    nf = std::min<int64_t>(nf, int64_t(1) << (kPreferredMaxLogN + 1));
+    if (nf <= 2 * (int64_t)P->n_c) {
+      nf = 1;
+      while (nf <= 2 * (int64_t)P->n_c) nf <<= 1;
+    }
+    nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
+  }
+  const int logn = ilog2(nf) - 1;
+  if (logn > maxlog)
+    fail(MM_EUNSUPPORTED, "FFT length " + std::to_string(nf) + " exceeds the on-chip transform limit " +
+                              std::to_string(int64_t(1) << (maxlog + 1)) +
+                              (fp64 ? " for float64" : " for float32"));
+  if (logn < kMinLogN) fail(MM_EUNSUPPORTED, "FFT length below 128");
+  fs.fp64 = fp64;
+  fs.logn = logn;
+  fs.N = 1 << logn;
+  fs.nf = (int)nf;
+  fs.m = fs.nf - 2 * P->n_c;
+  if (fs.m <= 0) fail(MM_EINVAL, "n_f must exceed 2 n_c");
+
+  std::vector<OlsChunk> ch;
+  for (int b = 0; b < P->n_iv; ++b) {
+    const int64_t a = P->iv_start[b], e = P->iv_start[b + 1];
+    for (int64_t o = a; o < e; o += fs.m) ch.push_back(OlsChunk{o, a, e, P->iv_filter[b], 0});
+  }
+  if (ch.size() > (size_t)0x7fffffff) fail(MM_EUNSUPPORTED, "too many overlap-save chunks");
+  fs.n_chunks = (int)ch.size();
+  fs.chunks = P->alloc<OlsChunk>((int64_t)ch.size());
+  if (!ch.empty())
+    hipchk(hipMemcpyAsync(fs.chunks, ch.data(), ch.size() * sizeof(OlsChunk), hipMemcpyHostToDevice, s),
+           "chunk table upload");
+  const int esz = fp64 ? 8 : 4;
+  fs.tw2 = P->alloc<char>((int64_t)fs.N * 2 * esz);
+  hipchk(launch_tw2_table(fs.tw2, logn, fp64, s), "twiddle table");
+  fs.spec = P->alloc<char>((int64_t)P->n_filt * (fs.N + 1) * esz);
+  double* ctab = P->alloc<double>((int64_t)fs.nf);
+  hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, ctab, s), "filter spectra");
+  hipchk(hipStreamSynchronize(s), "filter setup");
+  P->release(ctab);
+  fs.ready = true;
+}
+
+// y_out = N^-1 y_in with the transforms of fs; in_f64 = element type of y_in;
+// y_out has the element type of fs
+void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, void* y_out, int R,
+            hipStream_t s) {
+  hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, fs.spec, fs.tw2,
+                    P->n_t, P->n_c, fs.m, R, s),
+         "overlap-save filter");
+}
+
+// out = P^T N^-1 P in (observed layout), R right-hand sides, precision of fs
+void apply_H_obs(mm_plan_s* P, const FilterSetup& fs, const double* in, double* out, void* ya, void* yb,
+                 int R, hipStream_t s) {
+  hipchk(launch_gather(fs.fp64, P->ns, P->pix_obs, P->w, in, ya, P->n_t, P->n_obs, R, s), "gather");
+  weight(P, fs, ya, fs.fp64, yb, R, s);
+  hipchk(launch_scatter(fs.fp64, P->ns, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, yb, out,
+                        P->n_obs, P->n_t, R, s),
+         "scatter");
+}
+
+void rhs_obs(mm_plan_s* P, const FilterSetup& fs, const void* tod, bool tod_f64, double* out, void* yb,
+             int R, hipStream_t s) {
+  weight(P, fs, tod, tod_f64, yb, R, s);
+  hipchk(launch_scatter(fs.fp64, P->ns, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, yb, out,
+                        P->n_obs, P->n_t, R, s),
+         "scatter");
+}
+
+void ensure_fp64_path(mm_plan_s* P, hipStream_t s) {
+  if (P->main_fp64()) return;
+  if (!P->fs64.ready) build_filter(P, P->fs64, true, s, true);
+  if (!P->y64a) {
+    P->y64a = P->alloc<double>(P->n_t);
+    P->y64b = P->alloc<double>(P->n_t);
+  }
+}
+
+void check_tod_dtype(int32_t dt) {
+  if (dt != MM_F32 && dt != MM_F64) fail(MM_EINVAL, "tod_dtype must be MM_F32 or MM_F64");
+}
+
+void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const float* d_w, hipStream_t s) {
+  if (!d) fail(MM_EINVAL, "descriptor is NULL");
+  if (d->n_stokes != 1 && d->n_stokes != 3) fail(MM_EINVAL, "n_stokes must be 1 or 3");
+  if (d->n_pix < 1 || d->n_pix >= (int64_t(1) << 31) - 1) fail(MM_EINVAL, "n_pix must be in [1, 2^31 - 1)");
+  if (d->n_samples < 0 || d->n_samples > (int64_t(1) << 31) - 1)
+    fail(MM_EINVAL, "n_samples must be in [0, 2^31 - 1]");
+  if (d->n_intervals < 1 || !d->iv_start || !d->iv_filter) fail(MM_EINVAL, "interval table missing");
+  if (d->n_filters < 1) fail(MM_EINVAL, "n_filters must be >= 1");
+  if (d->n_c < 1) fail(MM_EINVAL, "n_c must be >= 1");
+  if (!d->filter_params && !d->filter_lags) fail(MM_EINVAL, "give filter_params or filter_lags");
+  if (d->precision != MM_FP64 && d->precision != MM_MIXED) fail(MM_EINVAL, "precision must be MM_FP64 or MM_MIXED");
+  if (d->precond < MM_PRECOND_BLOCK || d->precond > MM_PRECOND_NONE) fail(MM_EINVAL, "unknown preconditioner");
+  if (d->n_rhs < 1 || d->n_rhs > 64) fail(MM_EINVAL, "n_rhs must be in [1, 64]");
+  if (d->n_samples > 0 && !d_pix) fail(MM_EINVAL, "d_pix is NULL");
+  if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
+  if (d->n_f != 0 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
+    fail(MM_EINVAL, "n_f must be 0 or a power of two above 2 n_c");
+
+  P->ns = d->n_stokes;
+  P->n_pix = d->n_pix;
+  P->n_t = d->n_samples;
+  P->n_iv = d->n_intervals;
+  P->n_filt = d->n_filters;
+  P->n_c = d->n_c;
+  P->precision = d->precision;
+  P->precond = d->precond;
+  P->R = d->n_rhs;
+  P->nf_req = d->n_f;
+  P->f_samp = d->f_samp;
+  P->w = d_w;
+  P->iv_start.assign(d->iv_start, d->iv_start + d->n_intervals + 1);
+  P->iv_filter.assign(d->iv_filter, d->iv_filter + d->n_intervals);
+  if (P->iv_start[0] != 0 || P->iv_start[P->n_iv] != P->n_t)
+    fail(MM_EINVAL, "intervals must start at 0 and end at n_samples");
+  for (int b = 0; b < P->n_iv; ++b) {
+    if (P->iv_start[b + 1] < P->iv_start[b]) fail(MM_EINVAL, "iv_start must be non-decreasing");
+    if (P->iv_filter[b] < 0 || P->iv_filter[b] >= P->n_filt) fail(MM_EINVAL, "iv_filter out of range");
+  }
+  int ncp = 1 << std::max(kMinLogN, ilog2(P->n_c));
+  P->lag_len = d->lag_dft_len ? d->lag_dft_len : (1 << 20);
+  if (d->filter_params) {
+    if (!(d->f_samp > 0)) fail(MM_EINVAL, "f_samp must be positive");
+    if (!is_pow2(P->lag_len) || P->lag_len < 4 * (int64_t)ncp)
+      fail(MM_EINVAL, "lag_dft_len must be a power of two >= 4 n_c");
+    if (ncp > (1 << ols_max_logn(true))) fail(MM_EUNSUPPORTED, "n_c too large for the lag construction");
+    P->params.assign(d->filter_params, d->filter_params + 3 * (size_t)P->n_filt);
+    for (int f = 0; f < P->n_filt; ++f) {
+      const double sg = P->params[3 * f], fk = P->params[3 * f + 1], al = P->params[3 * f + 2];
+      if (!(sg > 0) || !(fk >= 0) || !(al > 0) || !std::isfinite(sg) || !std::isfinite(fk) || !std::isfinite(al))
+        fail(MM_EINVAL, "filter parameters need sigma > 0, f_knee >= 0, alpha > 0");
+    }
+  }
+
+  hipchk(hipGetDevice(&P->device), "hipGetDevice");
+  hipchk(hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking), "stream");
+  hipchk(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming), "event");
+  hipchk(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming), "event");
+  hipchk(hipHostMalloc((void**)&P->st_host, sizeof(CgState) * P->R, hipHostMallocDefault), "pinned state");
+
+  const int64_t n = P->n_t;
+  // ---- pointing: range check, sort by pixel, observed layout
+  {
+    int32_t* flag = P->alloc<int32_t>(1);
+    hipchk(launch_fill_i32(flag, 0, 1, s), "fill");
+    hipchk(launch_check_pix(d_pix, n, P->n_pix, flag, s), "pixel check");
+    int32_t hflag = 0;
+    hipchk(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "pixel check copy");
+    hipchk(hipStreamSynchronize(s), "pixel check");
+    P->release(flag);
+    if (hflag) fail(MM_EINVAL, "pointing index outside [-1, n_pix)");
+  }
+  P->pix_obs = P->alloc<int32_t>(n);
+  if (n > 0) {
+    char* scratch = P->alloc<char>((int64_t)sort_scratch_bytes(n));
+    uint32_t* keys = P->alloc<uint32_t>(n);
+    int32_t* vals = P->alloc<int32_t>(n);
+    hipchk(launch_sort_by_pixel(d_pix, n, P->n_pix, keys, vals, scratch, s), "pixel sort");
+    P->release(scratch);
+    uint32_t* flags = P->alloc<uint32_t>(n);
+    uint32_t* seg = P->alloc<uint32_t>(n);
+    char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(n));
+    int64_t* nvalid_d = P->alloc<int64_t>(1);
+    hipchk(launch_segment_flags(keys, n, (uint32_t)P->n_pix, flags, s), "segment flags");
+    hipchk(launch_scan_inclusive(flags, seg, n, sscr, s), "segment scan");
+    hipchk(hipMemsetAsync(nvalid_d, 0, sizeof(int64_t), s), "memset");
+    hipchk(launch_find_nvalid(keys, n, (uint32_t)P->n_pix, nvalid_d, s), "valid count");
+    uint32_t nobs_h = 0;
+    int64_t nvalid_h = 0;
+    hipchk(hipMemcpyAsync(&nobs_h, seg + (n - 1), 4, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(&nvalid_h, nvalid_d, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipStreamSynchronize(s), "observed count");
+    P->n_obs = nobs_h;
+    P->n_valid = nvalid_h;
+    P->pix_ptr = P->alloc<int64_t>(P->n_obs + 1);
+    P->obs2glob = P->alloc<int32_t>(P->n_obs);
+    P->perm = P->alloc<int32_t>(P->n_valid);
+    if (P->ns == 3) P->w_pm = P->alloc<float>(2 * P->n_valid);
+    hipchk(launch_build_layout(keys, vals, seg, n, (uint32_t)P->n_pix, d_w, P->ns, P->pix_ptr,
+                               P->obs2glob, P->pix_obs, P->w_pm, P->perm, s),
+           "pointing layout");
+    hipchk(hipMemcpyAsync(P->pix_ptr + P->n_obs, &P->n_valid, 8, hipMemcpyHostToDevice, s), "copy");
+    hipchk(hipStreamSynchronize(s), "pointing layout");
+    P->release(keys);
+    P->release(vals);
+    P->release(flags);
+    P->release(seg);
+    P->release(sscr);
+    P->release(nvalid_d);
+  } else {
+    P->pix_ptr = P->alloc<int64_t>(1);
+    hipchk(hipMemsetAsync(P->pix_ptr, 0, 8, s), "memset");
+    P->obs2glob = P->alloc<int32_t>(1);
+    P->perm = P->alloc<int32_t>(1);
+  }
+  {
+    const double avg = P->n_obs > 0 ? (double)P->n_valid / (double)P->n_obs : 1.0;
+    int g = 4;
+    while (g < 64 && g * 4 < avg) g *= 2;
+    P->scatter_group = g;
+  }
+
+  // ---- noise filters
+  P->lags = P->alloc<double>((int64_t)P->n_filt * P->n_c);
+  if (d->filter_lags) {
+    hipchk(hipMemcpyAsync(P->lags, d->filter_lags, sizeof(double) * P->n_filt * P->n_c,
+                          hipMemcpyHostToDevice, s),
+           "lag upload");
+  } else {
+    double* dparams = P->alloc<double>(3 * (int64_t)P->n_filt);
+    hipchk(hipMemcpyAsync(dparams, P->params.data(), sizeof(double) * 3 * P->n_filt,
+                          hipMemcpyHostToDevice, s),
+           "parameter upload");
+    const int batch = std::max(1, std::min(P->n_filt, 16));
+    const size_t sb = lags_scratch_bytes(P->n_c, P->lag_len, batch);
+    char* scr = P->alloc<char>((int64_t)sb);
+    hipchk(launch_lags(dparams, P->n_filt, P->f_samp, P->n_c, P->lag_len, P->lags, scr, sb, s),
+           "lag construction");
+    hipchk(hipStreamSynchronize(s), "lag construction");
+    P->release(scr);
+    P->release(dparams);
+  }
+  P->lags_host.resize((size_t)P->n_filt * P->n_c);
+  hipchk(hipMemcpyAsync(P->lags_host.data(), P->lags, sizeof(double) * P->lags_host.size(),
+                        hipMemcpyDeviceToHost, s),
+         "lag download");
+  hipchk(hipStreamSynchronize(s), "lags");
+  build_filter(P, P->fs_main, P->main_fp64(), s);
+
+  // ---- preconditioner
+  P->d_iv_start = P->alloc<int64_t>(P->n_iv + 1);
+  P->d_iv_filter = P->alloc<int32_t>(P->n_iv);
+  hipchk(hipMemcpyAsync(P->d_iv_start, P->iv_start.data(), 8 * (P->n_iv + 1), hipMemcpyHostToDevice, s), "copy");
+  hipchk(hipMemcpyAsync(P->d_iv_filter, P->iv_filter.data(), 4 * P->n_iv, hipMemcpyHostToDevice, s), "copy");
+  const int nm = P->ns == 1 ? 1 : 6;
+  P->minv = P->alloc<double>(P->n_obs * nm);
+  {
+    int32_t* sing = P->alloc<int32_t>(P->n_obs);
+    double* cnt = P->alloc<double>(1);
+    hipchk(launch_precond_build(P->ns, P->precond, P->pix_ptr, P->perm, P->w_pm, P->d_iv_start, P->n_iv,
+                                P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
+           "preconditioner");
+    hipchk(launch_count_nonzero(sing, P->n_obs, nullptr, cnt, s), "singular count");
+    double hc = 0;
+    hipchk(hipMemcpyAsync(&hc, cnt, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipStreamSynchronize(s), "preconditioner");
+    P->n_singular = (int)hc;
+    P->release(sing);
+    P->release(cnt);
+  }
+
+  // ---- work buffers
+  const int tsz = P->main_fp64() ? 8 : 4;
+  P->y1 = P->alloc<char>((int64_t)P->R * n * tsz);
+  P->y2 = P->alloc<char>((int64_t)P->R * n * tsz);
+  const int64_t vn = (int64_t)P->R * P->nu();
+  P->vx = P->alloc<double>(vn);
+  P->vp = P->alloc<double>(vn);
+  P->vr = P->alloc<double>(vn);
+  P->vz = P->alloc<double>(vn);
+  P->vq = P->alloc<double>(vn);
+  P->vxb = P->alloc<double>(vn);
+  P->vb = P->alloc<double>(vn);
+  P->part1 = P->alloc<double>((int64_t)P->R * kDotBlocks);
+  P->part2 = P->alloc<double>((int64_t)P->R * kDotBlocks);
+  P->part3 = P->alloc<double>((int64_t)P->R * kDotBlocks);
+  P->st = P->alloc<CgState>(P->R);
+}
+
+// queue one PCG iteration for every RHS
+void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
+  const int R = P->R;
+  apply_H_obs(P, P->fs_main, P->vp, P->vq, P->y1, P->y2, R, s);
+  hipchk(launch_dot(P->vp, P->vq, P->nu(), R, P->part1, s), "dot");
+  hipchk(launch_cg_alpha(P->st, P->part1, R, s), "alpha");
+  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, R,
+                          P->part2, P->part3, s),
+         "update");
+  hipchk(launch_cg_finalize(P->st, P->part2, P->part3, R, P->hist, P->hist_cap, s), "finalize");
+  hipchk(launch_cg_copy_best(P->vx, P->vxb, P->st, P->nu(), R, s), "copy best");
+  hipchk(launch_cg_update_p(P->vp, P->vz, P->st, P->nu(), R, s), "update p");
+}
+
+void solve_impl(mm_plan_s* P, const void* d_tod, int32_t tod_dtype, double* d_x,
+                const mm_solve_opts_t* o_in, mm_solve_info_t* info, hipStream_t caller,
+                mm_status_t* result) {
+  check_tod_dtype(tod_dtype);
+  mm_solve_opts_t o;
+  mm_solve_opts_default(&o);
+  if (o_in) o = *o_in;
+  if (!d_x) fail(MM_EINVAL, "d_x is NULL");
+  if (!d_tod && P->n_t > 0) fail(MM_EINVAL, "d_tod is NULL");
+  if (o.fixed_iters < 0 || o.max_iter < 0) fail(MM_EINVAL, "iteration counts must be >= 0");
+  if (!(o.tol >= 0)) fail(MM_EINVAL, "tol must be >= 0");
+  if (o.check_every < 1) o.check_every = 1;
+  const bool fixed = o.fixed_iters > 0;
+  const int n_max = fixed ? o.fixed_iters : o.max_iter;
+  const int R = P->R;
+  const int64_t nu = P->nu();
+  const bool tod64 = tod_dtype == MM_F64;
+  hipStream_t s = P->own;
+
+  // order the plan stream after the caller's work
+  hipchk(hipEventRecord(P->ev_in, caller), "event");
+  hipchk(hipStreamWaitEvent(s, P->ev_in, 0), "event wait");
+
+  if (P->hist_cap < n_max + 1) {
+    if (P->hist) P->release(P->hist);
+    P->hist_cap = n_max + 1;
+    P->hist = P->alloc<double>((int64_t)R * P->hist_cap);
+  }
+
+  rhs_obs(P, P->fs_main, d_tod, tod64, P->vb, P->y2, R, s);
+  if (o.d_x0) {
+    hipchk(launch_to_observed(o.d_x0, P->vx, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "x0");
+    apply_H_obs(P, P->fs_main, P->vx, P->vq, P->y1, P->y2, R, s);
+    hipchk(launch_sub(P->vr, P->vb, P->vq, (int64_t)R * nu, s), "residual");
+  } else {
+    hipchk(launch_fill_f64(P->vx, 0.0, (int64_t)R * nu, s), "fill");
+    hipchk(hipMemcpyAsync(P->vr, P->vb, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+  }
+  hipchk(hipMemcpyAsync(P->vxb, P->vx, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+  hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, R, s), "precondition");
+  hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+  hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
+  hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
+  hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
+  hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, o.tol, fixed ? 1 : 0, R, P->hist,
+                        P->hist_cap, s),
+         "init");
+
+  auto all_done = [&]() {
+    hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
+    hipchk(hipStreamSynchronize(s), "solve");
+    for (int r = 0; r < R; ++r)
+      if (P->st_host[r].active) return false;
+    return true;
+  };
+
+  int done = 0;
+  bool finished = all_done();
+  const int k = std::min(o.check_every, std::max(1, n_max));
+  while (!finished && done < n_max) {
+    const int step = std::min(k, n_max - done);
+    if (o.use_graph && step == k && k > 0) {
+      if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
+        if (P->graph) {
+          hipGraphExecDestroy(P->graph);
+          P->graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+          for (int i = 0; i < k; ++i) enqueue_iteration(P, s);
+        } catch (...) {
+          hipStreamEndCapture(s, &g);
+          if (g) hipGraphDestroy(g);
+          throw;
+        }
+        hipchk(hipStreamEndCapture(s, &g), "end capture");
+        hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
+        hipGraphDestroy(g);
+        P->graph_k = k;
+        P->graph_hist = P->hist;
+      }
+      hipchk(hipGraphLaunch(P->graph, s), "graph launch");
+    } else {
+      for (int i = 0; i < step; ++i) enqueue_iteration(P, s);
+    }
+    done += step;
+    finished = all_done();
+  }
+
+  hipchk(launch_to_global(P->vxb, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "map output");
+
+  std::vector<double> tres(R, std::nan(""));
+  if (o.true_residual && P->n_obs > 0) {
+    // ||b - H x|| / ||b|| in float64, one RHS at a time
+    if (!P->main_fp64()) ensure_fp64_path(P, s);
+    const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
+    void* ya = P->main_fp64() ? P->y1 : (void*)P->y64a;
+    void* yb = P->main_fp64() ? P->y2 : (void*)P->y64b;
+    const int esz = tod64 ? 8 : 4;
+    std::vector<double> hb(kDotBlocks), hr(kDotBlocks);
+    for (int r = 0; r < R; ++r) {
+      const void* tod_r = (const char*)d_tod + (size_t)r * P->n_t * esz;
+      rhs_obs(P, f64, tod_r, tod64, P->vr, yb, 1, s);                       // b (float64)
+      apply_H_obs(P, f64, P->vxb + (int64_t)r * nu, P->vq, ya, yb, 1, s);   // H x
+      hipchk(launch_sub(P->vz, P->vr, P->vq, nu, s), "residual");
+      hipchk(launch_dot(P->vr, P->vr, nu, 1, P->part1, s), "dot");
+      hipchk(launch_dot(P->vz, P->vz, nu, 1, P->part2, s), "dot");
+      hipchk(hipMemcpyAsync(hb.data(), P->part1, 8 * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipMemcpyAsync(hr.data(), P->part2, 8 * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipStreamSynchronize(s), "true residual");
+      double bb = 0, rr = 0;
+      for (int i = 0; i < kDotBlocks; ++i) {
+        bb += hb[i];
+        rr += hr[i];
+      }
+      tres[r] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    }
+  }
+
+  hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
+  std::vector<double> hh;
+  if (info && info->history) {
+    hh.resize((size_t)R * P->hist_cap);
+    hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+  }
+  hipchk(hipStreamSynchronize(s), "solve end");
+  hipchk(hipEventRecord(P->ev_out, s), "event");
+  hipchk(hipStreamWaitEvent(caller, P->ev_out, 0), "event wait");
+
+  bool notconv = false;
+  for (int r = 0; r < R; ++r) {
+    const CgState& c = P->st_host[r];
+    if (!fixed && c.bnorm > 0 && !(c.rel <= o.tol) && !(c.best_rel <= o.tol)) notconv = true;
+    if (info) {
+      if (info->iters) info->iters[r] = c.iter;
+      if (info->best_iter) info->best_iter[r] = c.best_iter;
+      if (info->best_rel_res) info->best_rel_res[r] = c.best_rel;
+      if (info->true_rel_res) info->true_rel_res[r] = tres[r];
+      if (info->history) {
+        for (int i = 0; i <= n_max; ++i)
+          info->history[(size_t)r * (n_max + 1) + i] = i <= c.iter ? hh[(size_t)r * P->hist_cap + i] : std::nan("");
+      }
+    }
+  }
+  if (P->n_singular > 0) {
+    g_last_error = std::to_string(P->n_singular) + " singular preconditioner block(s)";
+    *result = MM_ESINGULAR;
+  } else if (notconv) {
+    g_last_error = "tolerance not reached within max_iter";
+    *result = MM_ENOTCONV;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void mm_solve_opts_default(mm_solve_opts_t* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->max_iter = 50;
+  o->fixed_iters = 0;
+  o->check_every = 8;
+  o->use_graph = 1;
+  o->true_residual = 0;
+  o->d_x0 = nullptr;
+}
+
+mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* stream,
+                           mm_plan_t* out_plan) {
+  if (!out_plan) {
+    g_last_error = "out_plan is NULL";
+    return MM_EINVAL;
+  }
+  *out_plan = nullptr;
+  mm_plan_s* P = nullptr;
+  const mm_status_t st = guarded([&] {
+    P = new mm_plan_s();
+    build_plan(P, desc, d_pix, d_w, as_stream(stream));
+  });
+  if (st != MM_OK) {
+    delete P;
+    return st;
+  }
+  *out_plan = P;
+  return MM_OK;
+}
+
+mm_status_t mm_plan_destroy(mm_plan_t plan) {
+  return guarded([&] { delete plan; });
+}
+
+mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
+  return guarded([&] {
+    if (!P || !info) fail(MM_EINVAL, "NULL argument");
+    info->n_obs = P->n_obs;
+    info->n_valid = P->n_valid;
+    info->n_f = P->fs_main.nf;
+    info->n_chunks = P->fs_main.n_chunks;
+    info->n_singular = P->n_singular;
+    info->device_bytes = P->bytes;
+  });
+}
+
+mm_status_t mm_hits(mm_plan_t P, int32_t* d_hits, void* stream) {
+  return guarded([&] {
+    if (!P || !d_hits) fail(MM_EINVAL, "NULL argument");
+    hipchk(launch_hits(P->pix_ptr, P->obs2glob, d_hits, P->n_obs, P->n_pix, as_stream(stream)), "hits");
+  });
+}
+
+mm_status_t mm_filter_lags(mm_plan_t P, double* lags_out, void* stream) {
+  (void)stream;
+  return guarded([&] {
+    if (!P || !lags_out) fail(MM_EINVAL, "NULL argument");
+    std::memcpy(lags_out, P->lags_host.data(), sizeof(double) * P->lags_host.size());
+  });
+}
+
+mm_status_t mm_unpoint(mm_plan_t P, const double* d_x, void* d_y, int32_t tod_dtype, void* stream) {
+  return guarded([&] {
+    if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
+    check_tod_dtype(tod_dtype);
+    hipStream_t s = as_stream(stream);
+    hipchk(launch_to_observed(d_x, P->vq, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+    hipchk(launch_gather(tod_dtype == MM_F64, P->ns, P->pix_obs, P->w, P->vq, d_y, P->n_t, P->n_obs, P->R, s),
+           "gather");
+  });
+}
+
+mm_status_t mm_point(mm_plan_t P, const void* d_y, int32_t tod_dtype, double* d_x, void* stream) {
+  return guarded([&] {
+    if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
+    check_tod_dtype(tod_dtype);
+    hipStream_t s = as_stream(stream);
+    hipchk(launch_scatter(tod_dtype == MM_F64, P->ns, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, d_y,
+                          P->vq, P->n_obs, P->n_t, P->R, s),
+           "scatter");
+    hipchk(launch_to_global(P->vq, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+  });
+}
+
+mm_status_t mm_weight(mm_plan_t P, const void* d_y_in, void* d_y_out, int32_t tod_dtype, void* stream) {
+  return guarded([&] {
+    if (!P || ((!d_y_in || !d_y_out) && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
+    check_tod_dtype(tod_dtype);
+    if (d_y_in == d_y_out && P->n_t > 0) fail(MM_EINVAL, "y_out must not alias y_in");
+    hipStream_t s = as_stream(stream);
+    const bool in64 = tod_dtype == MM_F64;
+    const bool t64 = P->main_fp64();
+    if (in64 == t64) {
+      weight(P, P->fs_main, d_y_in, in64, d_y_out, P->R, s);
+    } else {
+      weight(P, P->fs_main, d_y_in, in64, P->y2, P->R, s);
+      hipchk(launch_convert(t64, in64, P->y2, d_y_out, (int64_t)P->R * P->n_t, s), "convert");
+    }
+  });
+}
+
+mm_status_t mm_apply_A(mm_plan_t P, const double* d_x, double* d_y, void* stream) {
+  return guarded([&] {
+    if (!P || !d_x || !d_y) fail(MM_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    hipchk(launch_to_observed(d_x, P->vz, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+    apply_H_obs(P, P->fs_main, P->vz, P->vq, P->y1, P->y2, P->R, s);
+    hipchk(launch_to_global(P->vq, d_y, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+  });
+}
+
+mm_status_t mm_rhs(mm_plan_t P, const void* d_tod, int32_t tod_dtype, double* d_b, void* stream) {
+  return guarded([&] {
+    if (!P || !d_b || (!d_tod && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
+    check_tod_dtype(tod_dtype);
+    hipStream_t s = as_stream(stream);
+    rhs_obs(P, P->fs_main, d_tod, tod_dtype == MM_F64, P->vq, P->y2, P->R, s);
+    hipchk(launch_to_global(P->vq, d_b, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+  });
+}
+
+mm_status_t mm_solve(mm_plan_t P, const void* d_tod, int32_t tod_dtype, double* d_x,
+                     const mm_solve_opts_t* opts, mm_solve_info_t* info, void* stream) {
+  mm_status_t result = MM_OK;
+  const mm_status_t st = guarded([&] {
+    if (!P) fail(MM_EINVAL, "plan is NULL");
+    solve_impl(P, d_tod, tod_dtype, d_x, opts, info, as_stream(stream), &result);
+  });
+  return st != MM_OK ? st : result;
+}
+
+int32_t mm_fft_length_rule(int32_t n_c, int64_t longest) { return fft_length_rule(n_c, longest); }
+
+const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+const char* mm_version(void) { return "mm 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+// One overlap-save transform: outputs [out_start, min(out_start + m, iv_hi)) of
+// the interval [iv_lo, iv_hi); the transform input starts n_c samples earlier.
+struct OlsChunk {
+  int64_t out_start;
+  int64_t iv_lo;
+  int64_t iv_hi;
+  int32_t filter;
+  int32_t pad;
+};
+
+// Per-RHS conjugate-gradient scalars, resident in device memory.
+struct CgState {
+  double rho;        // r . z
+  double alpha;
+  double beta;
+  double bnorm;      // ||b||_2
+  double rel;        // ||r||_2 / ||b||_2 of the current iterate
+  double best_rel;   // lowest relative residual so far
+  double tol;
+  int32_t iter;      // iterations performed while active
+  int32_t best_iter;
+  int32_t active;    // 1 while the RHS still iterates
+  int32_t copy_best; // set when the current iterate became the best
+  int32_t fixed;     // 1 = ignore tol
+  int32_t pad;
+};
+
+constexpr int kDotBlocks = 256;     // partial sums per dot product (fixed => deterministic)
+constexpr int kDotThreads = 256;
+
+// ---------------------------------------------------------------- filter (k_filter.hip)
+int ols_max_logn(bool fp64);
+hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s);
+hipError_t launch_lags(const double* params /*dev [nf][3]*/, int n_filters, double f_samp, int n_c,
+                       int64_t lag_len, double* lags /*dev [nf][n_c]*/, void* scratch,
+                       size_t scratch_bytes, hipStream_t s);
+size_t lags_scratch_bytes(int n_c, int64_t lag_len, int filters_per_batch);
+hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, bool fp64,
+                          void* spec /*[nf][N+1]*/, double* ctab /*scratch, 2N doubles*/,
+                          hipStream_t s);
+// y_out[r][t] = (N^-1 y_in)[r][t]; compute type T (fp64 flag); input type in_f64; output type T
+hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* y_out,
+                      const OlsChunk* chunks, int n_chunks, const void* spec, const void* tw2,
+                      int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s);
+
+// ---------------------------------------------------------------- pointing (k_pointing.hip)
+hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
+                         const double* p, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
+                         hipStream_t s);
+hipError_t launch_scatter(bool in_f64, int ns, int group, const int64_t* pix_ptr,
+                          const int32_t* perm, const float* w_pm, const void* y, double* q,
+                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s);
+hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, int64_t n,
+                          hipStream_t s);
+hipError_t launch_to_observed(const double* glob, double* obs, const int32_t* obs2glob,
+                              int64_t n_obs, int64_t n_pix, int ns, int n_rhs, hipStream_t s);
+hipError_t launch_to_global(const double* obs, double* glob, const int32_t* obs2glob,
+                            int64_t n_obs, int64_t n_pix, int ns, int n_rhs, hipStream_t s);
+hipError_t launch_hits(const int64_t* pix_ptr, const int32_t* obs2glob, int32_t* hits,
+                       int64_t n_obs, int64_t n_pix, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- plan (k_sort.hip)
+// flag[0] = 1 if any pix is < -1 or >= n_pix
+hipError_t launch_check_pix(const int32_t* pix, int64_t n, int64_t n_pix, int32_t* flag,
+                            hipStream_t s);
+size_t sort_scratch_bytes(int64_t n);
+// Stable sort of sample ids by pixel; excised samples (pix = -1) go last.
+// keys_out[i] = pixel of the i-th sample in pixel-major order, vals_out[i] = its sample id.
+hipError_t launch_sort_by_pixel(const int32_t* pix, int64_t n, int64_t n_pix, uint32_t* keys_out,
+                                int32_t* vals_out, void* scratch, hipStream_t s);
+size_t scan_scratch_bytes(int64_t n);
+// inclusive scan of uint32 values
+hipError_t launch_scan_inclusive(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
+                                 hipStream_t s);
+// flags[i] = 1 where a new pixel segment starts (i < n_valid)
+hipError_t launch_segment_flags(const uint32_t* keys, int64_t n, uint32_t n_pix, uint32_t* flags,
+                                hipStream_t s);
+// out[0] = number of sorted keys below n_pix (out[0] must be 0 beforehand)
+hipError_t launch_find_nvalid(const uint32_t* keys, int64_t n, uint32_t n_pix, int64_t* out,
+                              hipStream_t s);
+// pix_ptr, obs2glob, pix_obs, w_pm, perm from the sorted order
+hipError_t launch_build_layout(const uint32_t* keys, const int32_t* vals, const uint32_t* seg_id,
+                               int64_t n, uint32_t n_pix, const float* w, int ns, int64_t* pix_ptr,
+                               int32_t* obs2glob, int32_t* pix_obs, float* w_pm, int32_t* perm,
+                               hipStream_t s);
+
+// ---------------------------------------------------------------- CG (k_cg.hip)
+hipError_t launch_precond_build(int ns, int kind, const int64_t* pix_ptr, const int32_t* perm,
+                                const float* w_pm, const int64_t* iv_start, int n_iv,
+                                const int32_t* iv_filter, const double* lags, int n_c,
+                                int64_t n_obs, double* minv, int32_t* singular, hipStream_t s);
+hipError_t launch_count_nonzero(const int32_t* flags, int64_t n, double* partial, double* out,
+                                hipStream_t s);
+hipError_t launch_dot(const double* x, const double* y, int64_t nu, int n_rhs, double* partial,
+                      hipStream_t s);
+hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* partial_rr,
+                          const double* partial_rz, double tol, int fixed, int n_rhs,
+                          double* history, int hist_stride, hipStream_t s);
+hipError_t launch_cg_alpha(CgState* st, const double* partial_pq, int n_rhs, hipStream_t s);
+hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
+                            double* z, const double* minv, const CgState* st, int64_t n_obs,
+                            int n_rhs, double* partial_rz, double* partial_rr, hipStream_t s);
+hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
+                              int n_rhs, double* history, int hist_stride, hipStream_t s);
+hipError_t launch_cg_copy_best(const double* x, double* xbest, const CgState* st, int64_t nu,
+                               int n_rhs, hipStream_t s);
+hipError_t launch_cg_update_p(double* p, const double* z, const CgState* st, int64_t nu,
+                              int n_rhs, hipStream_t s);
+hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
+                                int64_t n_obs, int n_rhs, hipStream_t s);
+hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+
+}  // namespace mm

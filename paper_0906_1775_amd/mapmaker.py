@@ -1,0 +1,198 @@
+"""Torch-facing wrapper of libmm: device tensors in, device tensors out.
+
+Every computation runs in the HIP library; this module only checks tensor
+shapes and dtypes, passes pointers and the current stream, and converts
+results.  Maps are float64 tensors [n_rhs, n_pix, n_stokes]; TOD tensors are
+float32 or float64 [n_rhs, n_samples].
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp64": L.MM_FP64, "mixed": L.MM_MIXED}
+_PRECOND = {"block": L.MM_PRECOND_BLOCK, "jacobi": L.MM_PRECOND_JACOBI, "none": L.MM_PRECOND_NONE}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _tod_dtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return L.MM_F32
+    if t.dtype == torch.float64:
+        return L.MM_F64
+    raise TypeError("TOD must be float32 or float64")
+
+
+def fft_length_rule(n_c: int, longest: int) -> int:
+    return int(L.load().mm_fft_length_rule(int(n_c), int(longest)))
+
+
+class MapMaker:
+    """A plan of the map-making operators for one pointing and noise model."""
+
+    def __init__(self, pix: torch.Tensor, w: Optional[torch.Tensor], n_pix: int, n_stokes: int,
+                 iv_start, iv_filter, filter_params=None, filter_lags=None, f_samp: float = 0.0,
+                 n_c: int = 1, n_f: int = 0, lag_dft_len: int = 0, precision: str = "fp64",
+                 precond: str = "block", n_rhs: int = 1):
+        self._lib = L.load()
+        if not pix.is_cuda or pix.dtype != torch.int32 or not pix.is_contiguous():
+            raise ValueError("pix must be a contiguous int32 CUDA tensor")
+        if n_stokes == 3:
+            if w is None or not w.is_cuda or w.dtype != torch.float32 or not w.is_contiguous() \
+                    or tuple(w.shape) != (pix.shape[0], 2):
+                raise ValueError("w must be a contiguous float32 CUDA tensor [n_samples, 2]")
+        self.pix, self.w = pix, w            # the plan reads w until it is destroyed
+        self.n_pix, self.n_stokes, self.n_rhs = int(n_pix), int(n_stokes), int(n_rhs)
+        self.n_samples = int(pix.shape[0])
+        self.n_c = int(n_c)
+        self._iv_start = np.ascontiguousarray(iv_start, dtype=np.int64)
+        self._iv_filter = np.ascontiguousarray(iv_filter, dtype=np.int32)
+        self._params = None if filter_params is None else np.ascontiguousarray(filter_params, np.float64)
+        self._lags = None if filter_lags is None else np.ascontiguousarray(filter_lags, np.float64)
+        n_filters = (self._params if self._params is not None else self._lags).shape[0]
+        self.n_filters = int(n_filters)
+        d = L.MMDesc()
+        d.n_stokes = self.n_stokes
+        d.n_pix = self.n_pix
+        d.n_samples = self.n_samples
+        d.n_intervals = int(self._iv_filter.shape[0])
+        d.iv_start = self._iv_start.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        d.iv_filter = self._iv_filter.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.n_filters = self.n_filters
+        d.filter_params = None if self._params is None else \
+            self._params.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.filter_lags = None if self._lags is None else \
+            self._lags.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.f_samp = float(f_samp)
+        d.n_c = self.n_c
+        d.n_f = int(n_f)
+        d.lag_dft_len = int(lag_dft_len)
+        d.precision = _PREC[precision]
+        d.precond = _PRECOND[precond]
+        d.n_rhs = self.n_rhs
+        self.precision = precision
+        h = ctypes.c_void_p()
+        L.check(self._lib.mm_plan_create(ctypes.byref(d), _ptr(pix), _ptr(w), _stream(), ctypes.byref(h)),
+                self._lib)
+        self._h = h
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = L.MMPlanInfo()
+        L.check(self._lib.mm_plan_get_info(self._h, ctypes.byref(i)), self._lib)
+        return dict(n_obs=i.n_obs, n_valid=i.n_valid, n_f=i.n_f, n_chunks=i.n_chunks,
+                    n_singular=i.n_singular, device_bytes=i.device_bytes)
+
+    # ------------------------------------------------------------------ helpers
+    def _map_like(self) -> torch.Tensor:
+        return torch.empty((self.n_rhs, self.n_pix, self.n_stokes), dtype=torch.float64, device=self.pix.device)
+
+    def _check_map(self, x: torch.Tensor):
+        if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous() or \
+                tuple(x.shape) != (self.n_rhs, self.n_pix, self.n_stokes):
+            raise ValueError(f"map must be contiguous float64 CUDA [{self.n_rhs}, {self.n_pix}, {self.n_stokes}]")
+
+    def _check_tod(self, y: torch.Tensor):
+        if not y.is_cuda or not y.is_contiguous() or tuple(y.shape) != (self.n_rhs, self.n_samples):
+            raise ValueError(f"TOD must be contiguous CUDA [{self.n_rhs}, {self.n_samples}]")
+        return _tod_dtype(y)
+
+    # ------------------------------------------------------------------ operators
+    def hits(self) -> torch.Tensor:
+        h = torch.empty(self.n_pix, dtype=torch.int32, device=self.pix.device)
+        L.check(self._lib.mm_hits(self._h, _ptr(h), _stream()), self._lib)
+        return h
+
+    def lags(self) -> np.ndarray:
+        out = np.zeros((self.n_filters, self.n_c))
+        L.check(self._lib.mm_filter_lags(self._h, out.ctypes.data_as(ctypes.c_void_p), _stream()), self._lib)
+        return out
+
+    def unpoint(self, x: torch.Tensor, dtype=torch.float64) -> torch.Tensor:
+        self._check_map(x)
+        y = torch.empty((self.n_rhs, self.n_samples), dtype=dtype, device=x.device)
+        L.check(self._lib.mm_unpoint(self._h, _ptr(x), _ptr(y), _tod_dtype(y), _stream()), self._lib)
+        return y
+
+    def point(self, y: torch.Tensor) -> torch.Tensor:
+        dt = self._check_tod(y)
+        x = self._map_like()
+        L.check(self._lib.mm_point(self._h, _ptr(y), dt, _ptr(x), _stream()), self._lib)
+        return x
+
+    def weight(self, y: torch.Tensor) -> torch.Tensor:
+        dt = self._check_tod(y)
+        out = torch.empty_like(y)
+        L.check(self._lib.mm_weight(self._h, _ptr(y), _ptr(out), dt, _stream()), self._lib)
+        return out
+
+    def apply_A(self, x: torch.Tensor) -> torch.Tensor:
+        self._check_map(x)
+        y = self._map_like()
+        L.check(self._lib.mm_apply_A(self._h, _ptr(x), _ptr(y), _stream()), self._lib)
+        return y
+
+    def rhs(self, tod: torch.Tensor) -> torch.Tensor:
+        dt = self._check_tod(tod)
+        b = self._map_like()
+        L.check(self._lib.mm_rhs(self._h, _ptr(tod), dt, _ptr(b), _stream()), self._lib)
+        return b
+
+    def solve(self, tod: torch.Tensor, tol: float = 1e-6, max_iter: int = 50, fixed_iters: int = 0,
+              check_every: int = 8, use_graph: bool = True, true_residual: bool = False,
+              x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+              raise_on_notconv: bool = False):
+        """PCG solve; returns (map [n_rhs, n_pix, n_stokes], info dict)."""
+        dt = self._check_tod(tod)
+        if x0 is not None:
+            self._check_map(x0)
+        x = out if out is not None else self._map_like()
+        self._check_map(x)
+        o = L.MMSolveOpts()
+        self._lib.mm_solve_opts_default(ctypes.byref(o))
+        o.tol, o.max_iter, o.fixed_iters = float(tol), int(max_iter), int(fixed_iters)
+        o.check_every, o.use_graph, o.true_residual = int(check_every), int(bool(use_graph)), int(bool(true_residual))
+        o.d_x0 = None if x0 is None else x0.data_ptr()
+        R = self.n_rhs
+        n_hist = (fixed_iters if fixed_iters > 0 else max_iter) + 1
+        iters = (ctypes.c_int32 * R)()
+        best = (ctypes.c_int32 * R)()
+        best_rel = (ctypes.c_double * R)()
+        true_rel = (ctypes.c_double * R)()
+        hist = np.zeros((R, n_hist))
+        inf = L.MMSolveInfo()
+        inf.iters = ctypes.cast(iters, ctypes.POINTER(ctypes.c_int32))
+        inf.best_iter = ctypes.cast(best, ctypes.POINTER(ctypes.c_int32))
+        inf.best_rel_res = ctypes.cast(best_rel, ctypes.POINTER(ctypes.c_double))
+        inf.true_rel_res = ctypes.cast(true_rel, ctypes.POINTER(ctypes.c_double))
+        inf.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st = self._lib.mm_solve(self._h, _ptr(tod), dt, _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())
+        allow = () if raise_on_notconv else (L.MM_ENOTCONV,)
+        L.check(st, self._lib, allow=allow)
+        info = dict(status=L.STATUS_NAMES[st], iters=list(iters), best_iter=list(best),
+                    best_rel_res=list(best_rel), true_rel_res=list(true_rel), history=hist)
+        return x, info

@@ -1,0 +1,182 @@
+"""Solve parity: HIP PCG (through the C ABI) vs the FP64 CPU oracle's PCG.
+
+Protocol: (i) fixed iteration count k on both sides, maps within 1e-10
+relative (float64 path); (ii) both converged to 1e-12, maps within 1e-10;
+(iii) mixed precision converged to 1e-8, map within 1e-5 of the converged
+FP64 oracle map.  The lowest-residual return rule, multi-RHS batching,
+warm starts, hipGraph capture and determinism are checked on the same data.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_helpers import oracle_for, plan_for, rel_err, tod_tensor
+from test_gpu_operators import L_K, prob_t, prob_tqu, with_excised
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    p = prob_t(n_rhs=3)
+    return p, oracle_for(p, L_K)
+
+
+@pytest.fixture(scope="module")
+def TQU():
+    p = with_excised(prob_tqu(n_rhs=1, tod_dtype=np.float32))
+    return p, oracle_for(p, L_K)
+
+
+@pytest.fixture(scope="module")
+def C1():
+    p = synth.make_problem("c1")
+    return p, oracle_for(p)
+
+
+def _oracle_map(o, d, **kw):
+    x, info = o.pcg(o.rhs(d), **kw)
+    return o.to_global(x), info
+
+
+@pytest.mark.parametrize("which", ["T", "TQU", "C1"])
+@pytest.mark.parametrize("precond", ["block", "jacobi"])
+def test_fixed_iterations_fp64(which, precond, T, TQU, C1):
+    p, o = {"T": T, "TQU": TQU, "C1": C1}[which]
+    k = 12
+    mm = plan_for(p, n_rhs=1, lag_dft_len=0 if which == "C1" else L_K, precond=precond)
+    m, info = mm.solve(tod_tensor(p, rows=slice(0, 1)), fixed_iters=k)
+    ref, rinfo = _oracle_map(o, p.tod[0], fixed_iters=k, precond=precond)
+    assert rel_err(m.cpu().numpy()[0], ref) <= 1e-10
+    assert info["iters"][0] == k
+    assert info["best_iter"][0] == rinfo.best_iter
+    assert np.allclose(info["history"][0], rinfo.history, rtol=1e-8, atol=0)
+
+
+@pytest.mark.parametrize("which", ["T", "TQU", "C1"])
+def test_converged_fp64(which, T, TQU, C1):
+    p, o = {"T": T, "TQU": TQU, "C1": C1}[which]
+    mm = plan_for(p, n_rhs=1, lag_dft_len=0 if which == "C1" else L_K)
+    m, info = mm.solve(tod_tensor(p, rows=slice(0, 1)), tol=1e-12, max_iter=500, true_residual=True)
+    ref, rinfo = _oracle_map(o, p.tod[0], tol=1e-12, max_iter=500)
+    assert info["status"] == "MM_OK"
+    assert rel_err(m.cpu().numpy()[0], ref) <= 1e-10
+    assert abs(info["iters"][0] - rinfo.iters) <= 1
+    assert info["true_rel_res"][0] < 1e-11
+
+
+@pytest.mark.parametrize("which", ["T", "TQU", "C1"])
+def test_converged_mixed(which, T, TQU, C1):
+    p, o = {"T": T, "TQU": TQU, "C1": C1}[which]
+    d = p.tod[0].astype(np.float32)
+    mm = plan_for(p, n_rhs=1, precision="mixed", lag_dft_len=0 if which == "C1" else L_K)
+    m, info = mm.solve(torch.from_numpy(d[None, :].copy()).cuda(), tol=1e-8, max_iter=500,
+                       true_residual=True)
+    ref, _ = _oracle_map(o, d.astype(np.float64), tol=1e-13, max_iter=1000)
+    err = rel_err(m.cpu().numpy()[0], ref)
+    print(f"mixed {which}: iters {info['iters'][0]} map error vs FP64 oracle {err:.3e} "
+          f"true residual {info['true_rel_res'][0]:.3e}")
+    assert err <= 1e-5
+
+
+def test_unobserved_pixels_are_zero(TQU):
+    p, o = TQU
+    mm = plan_for(p, n_rhs=1, lag_dft_len=L_K)
+    m, _ = mm.solve(tod_tensor(p), fixed_iters=3)
+    m = m.cpu().numpy()[0]
+    assert np.all(m[o.hits == 0] == 0)
+
+
+def test_multi_rhs_equals_single(T):
+    p, o = T
+    k = 10
+    mm3 = plan_for(p, n_rhs=3, lag_dft_len=L_K)
+    m3, i3 = mm3.solve(tod_tensor(p), fixed_iters=k)
+    m3 = m3.cpu().numpy()
+    for r in range(3):
+        ref, _ = _oracle_map(o, p.tod[r], fixed_iters=k)
+        assert rel_err(m3[r], ref) <= 1e-10
+    mm1 = plan_for(p, n_rhs=1, lag_dft_len=L_K)
+    m1, _ = mm1.solve(tod_tensor(p, rows=slice(1, 2)), fixed_iters=k)
+    assert np.array_equal(m1.cpu().numpy()[0], m3[1])
+
+
+def test_multi_rhs_stop_independently(T):
+    p, o = T
+    tod = tod_tensor(p).clone()
+    tod[2] *= 0.0      # zero RHS: nothing to iterate
+    mm = plan_for(p, n_rhs=3, lag_dft_len=L_K)
+    m, info = mm.solve(tod, tol=1e-9, max_iter=300)
+    assert info["iters"][2] == 0
+    assert np.all(m.cpu().numpy()[2] == 0)
+    for r in range(2):
+        ref, rinfo = _oracle_map(o, p.tod[r], tol=1e-9, max_iter=300)
+        assert abs(info["iters"][r] - rinfo.iters) <= 1
+        assert rel_err(m.cpu().numpy()[r], ref) <= 1e-7
+
+
+def test_graph_and_plain_launches_agree_bitwise(TQU):
+    p, _ = TQU
+    mm = plan_for(p, n_rhs=1, lag_dft_len=L_K)
+    d = tod_tensor(p)
+    a, ia = mm.solve(d, fixed_iters=13, check_every=4, use_graph=True)
+    b, ib = mm.solve(d, fixed_iters=13, check_every=4, use_graph=False)
+    c, ic = mm.solve(d, fixed_iters=13, check_every=4, use_graph=True)   # graph replay
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert np.array_equal(ia["history"], ib["history"])
+
+
+def test_warm_start(T):
+    p, o = T
+    mm = plan_for(p, n_rhs=1, lag_dft_len=L_K)
+    x0 = np.random.default_rng(3).standard_normal((1, p.n_pix, 1)) * (o.hits > 0)[None, :, None]
+    m, info = mm.solve(tod_tensor(p, rows=slice(0, 1)), fixed_iters=6,
+                       x0=torch.from_numpy(x0).cuda())
+    xr, rinfo = o.pcg(o.rhs(p.tod[0]), fixed_iters=6, x0=o.to_observed(x0[0]))
+    assert rel_err(m.cpu().numpy()[0], o.to_global(xr)) <= 1e-10
+    assert info["best_iter"][0] == rinfo.best_iter
+
+
+def test_noiseless_tod_recovers_the_sky():
+    p = synth.make_custom(3, grid=(10, 10), det_lens=(6000, 6000), n_c=50, f_samp=20.0,
+                          filters=((1.0, 0.4, 1.5),), noiseless=True, seed=41)
+    mm = plan_for(p, lag_dft_len=L_K)
+    m, info = mm.solve(tod_tensor(p), tol=1e-13, max_iter=500)
+    hits = mm.hits().cpu().numpy() > 0
+    assert np.max(np.abs(m.cpu().numpy()[0][hits] - p.sky[hits])) < 1e-9
+
+
+def test_white_noise_converges_in_one_iteration():
+    p = synth.make_custom(3, grid=(10, 10), det_lens=(5000, 4000), n_c=20, f_samp=20.0,
+                          filters=((1.0, 0.0, 1.5), (0.6, 0.0, 1.5)), seed=42)
+    mm = plan_for(p, lag_dft_len=L_K)
+    m, info = mm.solve(tod_tensor(p), tol=1e-12, max_iter=20)
+    assert info["iters"][0] == 1
+
+
+def test_c2_fixed_iterations_fp64_full_size():
+    p = synth.make_problem("c2")
+    o = oracle_for(p)
+    k = 6
+    mm = plan_for(p)
+    m, info = mm.solve(tod_tensor(p), fixed_iters=k)
+    ref, rinfo = _oracle_map(o, p.tod[0].astype(np.float64), fixed_iters=k)
+    assert rel_err(m.cpu().numpy()[0], ref) <= 1e-10
+    hits = mm.hits().cpu().numpy()
+    assert np.array_equal(hits, o.hits.astype(np.int32))
+
+
+def test_c2_mixed_solve_residual_under_the_oracle_operator():
+    p = synth.make_problem("c2")
+    o = oracle_for(p)
+    mm = plan_for(p, precision="mixed")
+    m, info = mm.solve(tod_tensor(p), tol=1e-8, max_iter=400, true_residual=True)
+    x = o.to_observed(m.cpu().numpy()[0])
+    b = o.rhs(p.tod[0].astype(np.float64))
+    res = np.linalg.norm(b - o.apply_H(x)) / np.linalg.norm(b)
+    print(f"C2 mixed: iters {info['iters'][0]} GPU true residual {info['true_rel_res'][0]:.3e} "
+          f"oracle residual {res:.3e}")
+    assert res < 1e-5
+    assert abs(res - info["true_rel_res"][0]) <= 1e-3 * res + 1e-12
