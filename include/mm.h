@@ -98,6 +98,8 @@ typedef struct {
   int32_t n_chunks;             /* overlap-save transforms per TOD pass and RHS */
   int32_t n_singular;           /* preconditioner blocks flagged singular */
   int64_t device_bytes;         /* device memory held by the plan */
+  int64_t n_sliced;             /* entries of the sliced pixel-major pointing (>= n_valid;
+                                   the excess is padding to the widest pixel of each slice) */
 } mm_plan_info_t;
 
 /*
@@ -156,29 +158,64 @@ typedef struct {
   int32_t use_graph;            /* capture each block of check_every iterations in a hipGraph */
   int32_t true_residual;        /* recompute ||b - H x_best|| / ||b|| in float64 at exit */
   const double* d_x0;           /* optional initial map [n_rhs][n_pix][n_stokes]; NULL = 0 */
+  int32_t refine;               /* MM_MIXED only: 1 = float64 residual correction (the float32-
+                                   operator PCG solves for corrections of the float64 residual
+                                   b - H x, recomputed with the float64 filter after each inner
+                                   solve; the map then reaches float64 accuracy); 0 = plain
+                                   mixed iterations.  Ignored with fixed_iters. */
 } mm_solve_opts_t;
 
 typedef struct {
   int32_t* iters;               /* [n_rhs] H applications performed per RHS */
   int32_t* best_iter;           /* [n_rhs] iteration of the returned iterate (0 = x0) */
   double* best_rel_res;         /* [n_rhs] its recurrence relative residual */
-  double* true_rel_res;         /* [n_rhs] float64 ||b - H x||/||b|| of the returned map, or NaN */
-  double* history;              /* [n_rhs][max_iter + 1] relative residual per iteration
-                                   (entry 0 = start); may be NULL */
+  double* true_rel_res;         /* [n_rhs] float64 ||b - H x||/||b|| of the returned map, or NaN
+                                   (always set with refine; with true_residual otherwise) */
+  double* history;              /* [n_rhs][n + 1], n = fixed_iters if > 0 else max_iter:
+                                   relative residual per iteration (entry 0 = start, NaN after
+                                   the last iteration); with refine, inner residuals scaled to
+                                   ||b|| and the float64 residual at each correction; may be NULL */
 } mm_solve_info_t;
 
-/* Fill opts with the paper's defaults (tol 1e-6, max_iter 50, check_every 8, graph on). */
+/* Fill opts with the paper's defaults (tol 1e-6, max_iter 50) and check_every 8, graph on,
+ * refine on. */
 void mm_solve_opts_default(mm_solve_opts_t* opts);
 
 /*
  * Solve H m = b for every RHS with PCG; writes to d_x the iterate with the
- * lowest relative residual seen (Implementation section).  Each RHS stops at
+ * lowest relative residual seen (Implementation section).  best_rel_res
+ * (and the tol test) use the recurrence residual, or with refine the float64
+ * residual of the accumulated map.  Each RHS stops at
  * its own tol.  Returns MM_ENOTCONV (with the best iterate written) if any RHS
  * ends at max_iter above tol, MM_ESINGULAR if the plan flagged a singular
  * preconditioner block.  info may be NULL; its arrays are optional.
  */
 mm_status_t mm_solve(mm_plan_t plan, const void* d_tod, int32_t tod_dtype, double* d_x,
                      const mm_solve_opts_t* opts, mm_solve_info_t* info, void* stream);
+
+/*
+ * Same solve with the right-hand side given as a map: H m = b for
+ * d_b [n_rhs][n_pix][n_stokes] float64 (unobserved pixels ignored).  H is
+ * symmetric (Algorithm section), so this is also the adjoint solve of a map
+ * loss: lambda = H^-1 dL/dm.
+ */
+mm_status_t mm_solve_rhs(mm_plan_t plan, const double* d_b, double* d_x,
+                         const mm_solve_opts_t* opts, mm_solve_info_t* info, void* stream);
+
+/*
+ * Gradient of a map loss with respect to the noise parameters.  For
+ * m = H^-1 P^T N^-1 d and lambda = H^-1 dL/dm, dL/dtheta = u^T (dN^-1/dtheta) v
+ * with u = P lambda and v = d - P m, where dN^-1/dtheta is the banded Toeplitz
+ * operator whose lags are the theta-derivative of f(tau) (the lag construction
+ * of the plan differentiated under the inverse DFT), restricted to the intervals
+ * of each filter.
+ *   d_u, d_v: TOD [n_rhs][n_samples] of tod_dtype.
+ *   grad_out: host float64 [n_rhs][n_filters][3] = dL/d(sigma, f_knee, alpha).
+ * Computed in float64 whatever the plan's precision; synchronises.  Returns
+ * MM_EUNSUPPORTED for plans built from explicit lags.
+ */
+mm_status_t mm_noise_gradient(mm_plan_t plan, const void* d_u, const void* d_v, int32_t tod_dtype,
+                              double* grad_out, void* stream);
 
 /* FFT length by the paper's halving rule (Weighting section, eq. FFTcomplexityFunction):
  * start at the smallest power of two >= longest, halve while h'(n_f/2) >= 0 and

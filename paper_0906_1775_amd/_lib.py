@@ -18,7 +18,8 @@ MM_F32, MM_F64 = 0, 1
 
 EXPORTED = ["mm_plan_create", "mm_plan_destroy", "mm_plan_get_info", "mm_hits", "mm_filter_lags",
             "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A", "mm_rhs", "mm_solve_opts_default",
-            "mm_solve", "mm_fft_length_rule", "mm_last_error", "mm_version"]
+            "mm_solve", "mm_solve_rhs", "mm_noise_gradient", "mm_fft_length_rule", "mm_last_error",
+            "mm_version"]
 
 
 class MMDesc(ctypes.Structure):
@@ -33,13 +34,13 @@ class MMDesc(ctypes.Structure):
 
 class MMPlanInfo(ctypes.Structure):
     _fields_ = [("n_obs", c_int64), ("n_valid", c_int64), ("n_f", c_int32), ("n_chunks", c_int32),
-                ("n_singular", c_int32), ("device_bytes", c_int64)]
+                ("n_singular", c_int32), ("device_bytes", c_int64), ("n_sliced", c_int64)]
 
 
 class MMSolveOpts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("max_iter", c_int32), ("fixed_iters", c_int32),
                 ("check_every", c_int32), ("use_graph", c_int32), ("true_residual", c_int32),
-                ("d_x0", c_void_p)]
+                ("d_x0", c_void_p), ("refine", c_int32)]
 
 
 class MMSolveInfo(ctypes.Structure):
@@ -79,12 +80,15 @@ def load(path: str = LIB_PATH):
     lib.mm_solve_opts_default.argtypes = [POINTER(MMSolveOpts)]
     lib.mm_solve_opts_default.restype = None
     lib.mm_solve.argtypes = [P, P, c_int32, P, POINTER(MMSolveOpts), POINTER(MMSolveInfo), P]
+    lib.mm_solve_rhs.argtypes = [P, P, P, POINTER(MMSolveOpts), POINTER(MMSolveInfo), P]
+    lib.mm_noise_gradient.argtypes = [P, P, P, c_int32, P, P]
     lib.mm_fft_length_rule.argtypes = [c_int32, c_int64]
     lib.mm_fft_length_rule.restype = c_int32
     lib.mm_last_error.restype = c_char_p
     lib.mm_version.restype = c_char_p
     for name in ("mm_plan_create", "mm_plan_destroy", "mm_plan_get_info", "mm_hits", "mm_filter_lags",
-                 "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A", "mm_rhs", "mm_solve"):
+                 "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A", "mm_rhs", "mm_solve",
+                 "mm_solve_rhs", "mm_noise_gradient"):
         getattr(lib, name).restype = c_int32
     _LIB = lib
     return lib

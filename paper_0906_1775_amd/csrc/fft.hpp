@@ -18,9 +18,12 @@
 // Thread t owns butterflies b = t + i NT.  After the last pass the output of
 // (b, r) is point b + r N/R_last, i.e. the natural order, strided.
 //
-// Twiddles come from a table tw2[k] = exp(-2 pi i k / (2N)), k < N, built in
-// float64 and rounded once to T; the same table serves the real-to-complex
-// packing of the overlap-save filter.
+// Twiddles come from per-pass tables built once in float64 and rounded to T:
+// pass p with radix R and span Ns owns Ns rows of R entries,
+// row j = exp(-2 pi i j r / (Ns R)), r < R, so a thread reads its R-1 factors
+// as one contiguous row.  The forward and the radix-reversed sequences have
+// their own tables (tw_offset).  A second table tw2[k] = exp(-2 pi i k/(2N)),
+// k < N, serves the real-to-complex packing of the overlap-save filter.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -110,28 +113,23 @@ __device__ __forceinline__ void dft_reg(cx<T>* v) {
   for (int k = 0; k < R; ++k) v[k] = tmp[k];
 }
 
-// exp(-2 pi i idx / N) from tw2[k] = exp(-2 pi i k / (2N)), idx < N
-template <typename T>
-__device__ __forceinline__ cx<T> twiddle_N(const cx<T>* __restrict__ tw2, int idx, int N) {
-  const int k = 2 * idx;
-  if (k < N) return tw2[k];
-  const cx<T> w = tw2[k - N];
-  return {-w.re, -w.im};
-}
-
-template <typename T, int LOGN, int NT_, int LOGE>
+// LOGR: log2 of the largest radix (default: one butterfly of E points per thread
+// per pass); with LOGR < LOGE each thread runs E / R butterflies per pass.
+template <typename T, int LOGN, int NT_, int LOGE, int LOGR_ = LOGE>
 struct BlockFFT {
   static constexpr int N = 1 << LOGN;
   static constexpr int NT = NT_;
   static constexpr int E = 1 << LOGE;
+  static constexpr int LOGRMAX = LOGR_;
   static_assert(N == NT * E, "N must equal threads * points per thread");
-  static constexpr int P = LOGN / LOGE;
-  static constexpr int REM = LOGN % LOGE;
+  static_assert(LOGR_ <= LOGE, "radix larger than the points of a thread");
+  static constexpr int P = LOGN / LOGR_;
+  static constexpr int REM = LOGN % LOGR_;
   static constexpr int NP = P + (REM ? 1 : 0);
   // forward sequence: the short pass first; inverse sequence: the short pass last,
   // so the last forward pass and the first inverse pass share one data layout
-  static constexpr int flog(int p) { return (REM && p == 0) ? REM : LOGE; }
-  static constexpr int ilog(int p) { return (REM && p == NP - 1) ? REM : LOGE; }
+  static constexpr int flog(int p) { return (REM && p == 0) ? REM : LOGR_; }
+  static constexpr int ilog(int p) { return (REM && p == NP - 1) ? REM : LOGR_; }
 
   static constexpr int kLdsLimit = 160 * 1024;
   static constexpr int cx_pad_log = (sizeof(T) == 4) ? 4 : 3;  // 128 B / (2 sizeof T)
@@ -157,20 +155,40 @@ struct BlockFFT {
     return t + i * NT + (r << (LOGN - LOGR));
   }
 
-  // butterflies of one pass, in registers
+  // ---- per-pass twiddle tables
+  static constexpr int log_radix(bool fwd, int p) { return fwd ? flog(p) : ilog(p); }
+  static constexpr int log_span(bool fwd, int p) {
+    int s = 0;
+    for (int q = 0; q < p; ++q) s += log_radix(fwd, q);
+    return s;
+  }
+  static constexpr int tw_count(bool fwd, int p) {
+    return log_span(fwd, p) == 0 ? 0 : (1 << (log_span(fwd, p) + log_radix(fwd, p)));
+  }
+  static constexpr int tw_total_seq(bool fwd) {
+    int o = 0;
+    for (int q = 0; q < NP; ++q) o += tw_count(fwd, q);
+    return o;
+  }
+  static constexpr int tw_offset(bool fwd, int p) {
+    int o = fwd ? 0 : tw_total_seq(true);
+    for (int q = 0; q < p; ++q) o += tw_count(fwd, q);
+    return o;
+  }
+  static constexpr int tw_total() { return tw_total_seq(true) + tw_total_seq(false); }
+
+  // butterflies of one pass, in registers; ptab = this pass's table (rows of R factors)
   template <int LOGR, int LOGNS>
-  __device__ static __forceinline__ void butterflies(cx<T>* v, const cx<T>* __restrict__ tw2, int t) {
+  __device__ static __forceinline__ void butterflies(cx<T>* v, const cx<T>* __restrict__ ptab, int t) {
     constexpr int R = 1 << LOGR;
     constexpr int NB = E / R;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       if (LOGNS > 0) {
         const int j = (t + i * NT) & ((1 << LOGNS) - 1);
+        const cx<T>* __restrict__ w = ptab + (j << LOGR);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const int idx = (j * r) << (LOGN - LOGNS - LOGR);
-          v[i * R + r] = cmul(v[i * R + r], twiddle_N(tw2, idx, N));
-        }
+        for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], w[r]);
       }
       dft_reg<T, LOGR>(v + i * R);
     }
@@ -195,7 +213,8 @@ struct BlockFFT {
         for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds[cpad(in_index<LOGR2>(t, i, r))];
     } else {
       T* lds = reinterpret_cast<T*>(lds_raw);
-      T tmp[E];
+      // real parts, then imaginary parts; a component can be overwritten as soon as
+      // the whole workgroup has stored it
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
         __syncthreads();
@@ -208,41 +227,38 @@ struct BlockFFT {
 #pragma unroll
         for (int i = 0; i < NB2; ++i)
 #pragma unroll
-          for (int r = 0; r < R2; ++r) tmp[i * R2 + r] = lds[spad(in_index<LOGR2>(t, i, r))];
-        if (part == 0) {
-#pragma unroll
-          for (int e = 0; e < E; ++e) v[e].re = tmp[e];
-        } else {
-#pragma unroll
-          for (int e = 0; e < E; ++e) v[e].im = tmp[e];
-        }
+          for (int r = 0; r < R2; ++r) {
+            const T x = lds[spad(in_index<LOGR2>(t, i, r))];
+            if (part) v[i * R2 + r].im = x; else v[i * R2 + r].re = x;
+          }
       }
     }
   }
 
   // pass p of a sequence (FWD: forward order of radices, else inverse order)
   template <bool FWD, int p, int LOGNS>
-  __device__ static __forceinline__ void run_from(cx<T>* v, void* lds, const cx<T>* __restrict__ tw2,
+  __device__ static __forceinline__ void run_from(cx<T>* v, void* lds, const cx<T>* __restrict__ ptw,
                                                   int t) {
     constexpr int LR = FWD ? flog(p) : ilog(p);
-    butterflies<LR, LOGNS>(v, tw2, t);
+    butterflies<LR, LOGNS>(v, ptw + tw_offset(FWD, p), t);
     if constexpr (p + 1 < NP) {
       constexpr int LR2 = FWD ? flog(p + 1) : ilog(p + 1);
       exchange<LR, LOGNS, LR2>(v, lds, t);
-      run_from<FWD, p + 1, LOGNS + LR>(v, lds, tw2, t);
+      run_from<FWD, p + 1, LOGNS + LR>(v, lds, ptw, t);
     }
   }
 
   // Input: point (i, r) of thread t holds x[in_index<first radix>(t, i, r)].
   // Output: point (i, r) holds X[t + i NT + r N / R_last] (forward DFT, no scaling).
-  __device__ static __forceinline__ void forward(cx<T>* v, void* lds, const cx<T>* __restrict__ tw2,
+  // ptw: the per-pass twiddle tables of this shape (tw_total() entries).
+  __device__ static __forceinline__ void forward(cx<T>* v, void* lds, const cx<T>* __restrict__ ptw,
                                                  int t) {
-    run_from<true, 0, 0>(v, lds, tw2, t);
+    run_from<true, 0, 0>(v, lds, ptw, t);
   }
   // Same transform with the radix order reversed (first pass = forward's last radix).
-  __device__ static __forceinline__ void forward_rev(cx<T>* v, void* lds, const cx<T>* __restrict__ tw2,
+  __device__ static __forceinline__ void forward_rev(cx<T>* v, void* lds, const cx<T>* __restrict__ ptw,
                                                      int t) {
-    run_from<false, 0, 0>(v, lds, tw2, t);
+    run_from<false, 0, 0>(v, lds, ptw, t);
   }
 
   static constexpr int first_log_fwd() { return flog(0); }

@@ -90,7 +90,7 @@ __global__ void k_cg_init(CgState* st, const double* __restrict__ pbb, const dou
   s.fixed = fixed;
   s.active = (s.bnorm > 0.0) && (fixed || !(s.rel <= tol)) ? 1 : 0;
   s.copy_best = 0;
-  s.pad = 0;
+  s.breakdown = 0;
   st[r] = s;
   if (history) history[(int64_t)r * hist_stride] = s.rel;
 }
@@ -100,25 +100,6 @@ hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* p
                           double* history, int hist_stride, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, dim3(n_rhs), dim3(64), 0, s, st, partial_bb, partial_rr, partial_rz,
                      tol, fixed, history, hist_stride);
-  return hipGetLastError();
-}
-
-__global__ void k_cg_alpha(CgState* st, const double* __restrict__ ppq) {
-  const int r = blockIdx.x;
-  const double pq = fold_partials(ppq, r);
-  if (threadIdx.x != 0) return;
-  CgState& s = st[r];
-  if (!s.active) { s.alpha = 0.0; return; }
-  if (!(pq > 0.0) || !isfinite(pq)) {   // breakdown: H not positive definite on p
-    s.alpha = 0.0;
-    s.active = 0;
-    return;
-  }
-  s.alpha = s.rho / pq;
-}
-
-hipError_t launch_cg_alpha(CgState* st, const double* partial_pq, int n_rhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(n_rhs), dim3(64), 0, s, st, partial_pq);
   return hipGetLastError();
 }
 
@@ -133,21 +114,43 @@ __device__ __forceinline__ void precond_apply(const double* __restrict__ m, cons
   }
 }
 
+// Each block folds the p.q partial sums of the scatter in the same fixed
+// order, so every block derives the same alpha; block 0 records it.
 template <int NS>
 __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     double* __restrict__ x, const double* __restrict__ p, double* __restrict__ rv,
     const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ minv,
-    const CgState* __restrict__ st, int64_t n_obs, double* __restrict__ prz,
-    double* __restrict__ prr) {
+    CgState* __restrict__ st, int64_t n_obs, const double* __restrict__ pq_part, int n_pq,
+    double* __restrict__ prz, double* __restrict__ prr) {
   __shared__ double sh[kDotThreads / 64];
+  __shared__ double s_alpha;
   constexpr int NM = NS == 1 ? 1 : 6;
   const int r = blockIdx.y;
-  const bool active = st[r].active != 0;
-  const double alpha = st[r].alpha;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int i = tid; i < n_pq; i += kDotThreads) acc += pq_part[(int64_t)r * n_pq + i];
+  const double pq = block_sum(acc, sh);
+  const bool was_active = st[r].active != 0;
+  if (tid == 0) {
+    double alpha = 0.0;
+    bool brk = false;
+    if (was_active) {
+      if (pq > 0.0 && isfinite(pq)) alpha = st[r].rho / pq;
+      else brk = true;
+    }
+    s_alpha = alpha;
+    if (blockIdx.x == 0) {
+      st[r].alpha = alpha;            // read by no other block of this kernel
+      st[r].breakdown = brk ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const double alpha = s_alpha;
+  const bool active = was_active && alpha != 0.0;
   const int64_t off = (int64_t)r * n_obs * NS;
   double arz = 0.0, arr = 0.0;
   if (active) {
-    for (int64_t o = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; o < n_obs;
+    for (int64_t o = (int64_t)blockIdx.x * kDotThreads + tid; o < n_obs;
          o += (int64_t)kDotBlocks * kDotThreads) {
       const int64_t b = off + o * NS;
       double rr[NS], zz[NS];
@@ -168,20 +171,23 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
   }
   const double s1 = block_sum(arz, sh);
   const double s2 = block_sum(arr, sh);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     prz[(int64_t)r * kDotBlocks + blockIdx.x] = s1;
     prr[(int64_t)r * kDotBlocks + blockIdx.x] = s2;
   }
 }
 
 hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
-                            double* z, const double* minv, const CgState* st, int64_t n_obs,
-                            int n_rhs, double* partial_rz, double* partial_rr, hipStream_t s) {
+                            double* z, const double* minv, CgState* st, int64_t n_obs,
+                            int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
+                            double* partial_rr, hipStream_t s) {
   const dim3 g(kDotBlocks, n_rhs), b(kDotThreads);
   if (ns == 1)
-    hipLaunchKernelGGL(k_cg_update<1>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, partial_rz, partial_rr);
+    hipLaunchKernelGGL(k_cg_update<1>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, pq_part, n_pq,
+                       partial_rz, partial_rr);
   else
-    hipLaunchKernelGGL(k_cg_update<3>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, partial_rz, partial_rr);
+    hipLaunchKernelGGL(k_cg_update<3>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, pq_part, n_pq,
+                       partial_rz, partial_rr);
   return hipGetLastError();
 }
 
@@ -193,8 +199,9 @@ __global__ void k_cg_finalize(CgState* st, const double* __restrict__ prz,
   const double rr = fold_partials(prr, r);
   if (threadIdx.x != 0) return;
   CgState s = st[r];
-  if (!s.active) {
+  if (!s.active || s.breakdown) {   // stopped, or p.q <= 0: no step was taken
     s.copy_best = 0;
+    s.active = 0;
     st[r] = s;
     return;
   }
@@ -221,40 +228,27 @@ hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const doubl
   return hipGetLastError();
 }
 
-__global__ void k_cg_copy_best(const double* __restrict__ x, double* __restrict__ xbest,
-                               const CgState* __restrict__ st, int64_t nu) {
+__global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z,
+                          const double* __restrict__ x, double* __restrict__ xbest,
+                          const CgState* __restrict__ st, int64_t nu) {
   const int r = blockIdx.y;
-  if (!st[r].copy_best) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride)
-    xbest[(int64_t)r * nu + i] = x[(int64_t)r * nu + i];
-}
-
-hipError_t launch_cg_copy_best(const double* x, double* xbest, const CgState* st, int64_t nu,
-                               int n_rhs, hipStream_t s) {
-  dim3 g = grid_for(nu);
-  g.y = n_rhs;
-  hipLaunchKernelGGL(k_cg_copy_best, g, dim3(256), 0, s, x, xbest, st, nu);
-  return hipGetLastError();
-}
-
-__global__ void k_cg_update_p(double* __restrict__ p, const double* __restrict__ z,
-                              const CgState* __restrict__ st, int64_t nu) {
-  const int r = blockIdx.y;
-  if (!st[r].active) return;
+  const bool upd = st[r].active != 0;
+  const bool best = st[r].copy_best != 0;
+  if (!upd && !best) return;
   const double beta = st[r].beta;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
     const int64_t j = (int64_t)r * nu + i;
-    p[j] = z[j] + beta * p[j];
+    if (best) xbest[j] = x[j];
+    if (upd) p[j] = z[j] + beta * p[j];
   }
 }
 
-hipError_t launch_cg_update_p(double* p, const double* z, const CgState* st, int64_t nu,
-                              int n_rhs, hipStream_t s) {
+hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
+                          const CgState* st, int64_t nu, int n_rhs, hipStream_t s) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
-  hipLaunchKernelGGL(k_cg_update_p, g, dim3(256), 0, s, p, z, st, nu);
+  hipLaunchKernelGGL(k_cg_next, g, dim3(256), 0, s, p, z, x, xbest, st, nu);
   return hipGetLastError();
 }
 
@@ -312,50 +306,55 @@ hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, 
 // ---------------------------------------------------------------- preconditioner
 // kind 0: block (P^T W^-1 P)^-1 with W^-1 = diag(N^-1) = f_b(0) of each sample's interval;
 // kind 1: point Jacobi diag(P^T P)^-1;  kind 2: identity.
-template <int NS>
-__global__ void k_precond_build(int kind, const int64_t* __restrict__ pix_ptr,
-                                const int32_t* __restrict__ perm, const float2* __restrict__ w_pm,
-                                const int64_t* __restrict__ iv_start, int n_iv,
-                                const int32_t* __restrict__ iv_filter,
-                                const double* __restrict__ lags, int n_c, int64_t n_obs,
-                                double* __restrict__ minv, int32_t* __restrict__ singular) {
+// A group of G lanes owns a pixel: lanes stride over its samples, the six
+// block entries are reduced across the group, and lane 0 inverts in float64.
+template <int NS, int G>
+__global__ __launch_bounds__(256) void k_precond_build(
+    int kind, const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm,
+    const float2* __restrict__ w_pm, const int64_t* __restrict__ iv_start, int n_iv,
+    const int32_t* __restrict__ iv_filter, const double* __restrict__ lags, int n_c, int64_t n_obs,
+    double* __restrict__ minv, int32_t* __restrict__ singular) {
   constexpr int NM = NS == 1 ? 1 : 6;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n_obs; o += stride) {
+  constexpr int GPB = 256 / G;
+  const int lane = threadIdx.x % G;
+  const int64_t stride = (int64_t)gridDim.x * GPB;
+  for (int64_t o = (int64_t)blockIdx.x * GPB + threadIdx.x / G; o < n_obs; o += stride) {
+    double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (kind != 2) {
+      for (int64_t k = pix_ptr[o] + lane; k < pix_ptr[o + 1]; k += G) {
+        double wgt = 1.0;
+        if (kind == 0) {
+          const int64_t t = perm[k];
+          int lo = 0, hi = n_iv;   // last interval with iv_start <= t
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (iv_start[mid] <= t) lo = mid; else hi = mid;
+          }
+          wgt = lags[(int64_t)iv_filter[lo] * n_c];
+        }
+        if (NS == 1) {
+          B[0] += wgt;
+        } else {
+          const float2 sc = w_pm[k];
+          const double a0 = 0.5, a1 = 0.5 * (double)sc.x, a2 = 0.5 * (double)sc.y;
+          B[0] += wgt * a0 * a0;
+          B[1] += wgt * a0 * a1;
+          B[2] += wgt * a0 * a2;
+          B[3] += wgt * a1 * a1;
+          B[4] += wgt * a1 * a2;
+          B[5] += wgt * a2 * a2;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < (NS == 1 ? 1 : 6); ++c) B[c] = group_sum<G>(B[c]);
+    }
+    if (lane != 0) continue;
     double* m = minv + o * NM;
     int32_t bad = 0;
     if (kind == 2) {
       m[0] = 1.0;
       if (NS == 3) { m[1] = 0.0; m[2] = 0.0; m[3] = 1.0; m[4] = 0.0; m[5] = 1.0; }
-      singular[o] = 0;
-      continue;
-    }
-    double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t k = pix_ptr[o]; k < pix_ptr[o + 1]; ++k) {
-      double wgt = 1.0;
-      if (kind == 0) {
-        const int64_t t = perm[k];
-        int lo = 0, hi = n_iv;   // last interval with iv_start <= t
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (iv_start[mid] <= t) lo = mid; else hi = mid;
-        }
-        wgt = lags[(int64_t)iv_filter[lo] * n_c];
-      }
-      if (NS == 1) {
-        B[0] += wgt;
-      } else {
-        const float2 sc = w_pm[k];
-        const double a0 = 0.5, a1 = 0.5 * (double)sc.x, a2 = 0.5 * (double)sc.y;
-        B[0] += wgt * a0 * a0;
-        B[1] += wgt * a0 * a1;
-        B[2] += wgt * a0 * a2;
-        B[3] += wgt * a1 * a1;
-        B[4] += wgt * a1 * a2;
-        B[5] += wgt * a2 * a2;
-      }
-    }
-    if (NS == 1) {
+    } else if (NS == 1) {
       bad = !(B[0] > 0.0);
       m[0] = bad ? 0.0 : 1.0 / B[0];
     } else if (kind == 1) {
@@ -379,18 +378,50 @@ __global__ void k_precond_build(int kind, const int64_t* __restrict__ pix_ptr,
   }
 }
 
-hipError_t launch_precond_build(int ns, int kind, const int64_t* pix_ptr, const int32_t* perm,
+template <int NS>
+static hipError_t precond_g(int group, dim3 g, hipStream_t s, int kind, const int64_t* pp,
+                            const int32_t* perm, const float2* w, const int64_t* ivs, int n_iv,
+                            const int32_t* ivf, const double* lags, int n_c, int64_t n_obs,
+                            double* minv, int32_t* sing) {
+  const dim3 b(256);
+  switch (group) {
+#define MM_PCB(G) case G: hipLaunchKernelGGL((k_precond_build<NS, G>), g, b, 0, s, kind, pp, perm, w, ivs, n_iv, ivf, lags, n_c, n_obs, minv, sing); break;
+    MM_PCB(4) MM_PCB(8) MM_PCB(16) MM_PCB(32) MM_PCB(64)
+#undef MM_PCB
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_build(int ns, int kind, int group, const int64_t* pix_ptr, const int32_t* perm,
                                 const float* w_pm, const int64_t* iv_start, int n_iv,
                                 const int32_t* iv_filter, const double* lags, int n_c,
                                 int64_t n_obs, double* minv, int32_t* singular, hipStream_t s) {
   if (n_obs == 0) return hipSuccess;
-  const dim3 g = grid_for(n_obs);
-  if (ns == 1)
-    hipLaunchKernelGGL(k_precond_build<1>, g, dim3(256), 0, s, kind, pix_ptr, perm,
-                       (const float2*)w_pm, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular);
-  else
-    hipLaunchKernelGGL(k_precond_build<3>, g, dim3(256), 0, s, kind, pix_ptr, perm,
-                       (const float2*)w_pm, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular);
+  int64_t nb = (n_obs * group + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  const dim3 g((unsigned)nb);
+  const float2* w = (const float2*)w_pm;
+  return ns == 1 ? precond_g<1>(group, g, s, kind, pix_ptr, perm, w, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular)
+                 : precond_g<3>(group, g, s, kind, pix_ptr, perm, w, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular);
+}
+
+__global__ __launch_bounds__(256) void k_interval_dots(const double* __restrict__ u,
+                                                       const double* __restrict__ v,
+                                                       const int64_t* __restrict__ iv_start,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[256 / 64];
+  const int64_t a = iv_start[blockIdx.x], e = iv_start[blockIdx.x + 1];
+  double acc = 0.0;
+  for (int64_t t = a + threadIdx.x; t < e; t += 256) acc += u[t] * v[t];
+  const double sum = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = sum;
+}
+
+hipError_t launch_interval_dots(const double* u, const double* v, const int64_t* iv_start, int n_iv,
+                                double* out, hipStream_t s) {
+  if (n_iv == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_interval_dots, dim3((unsigned)n_iv), dim3(256), 0, s, u, v, iv_start, out);
   return hipGetLastError();
 }
 

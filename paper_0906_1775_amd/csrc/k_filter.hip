@@ -22,19 +22,21 @@ namespace mm {
 
 // ---------------------------------------------------------------- transform shapes
 // (threads, log2 points per thread) of the workgroup transform of 2^LOGN points
+// and the log2 of the largest radix
 template <int LOGN> struct Shape;
-template <> struct Shape<6> { static constexpr int NT = 16, LOGE = 2; };
-template <> struct Shape<7> { static constexpr int NT = 32, LOGE = 2; };
-template <> struct Shape<8> { static constexpr int NT = 64, LOGE = 2; };
-template <> struct Shape<9> { static constexpr int NT = 64, LOGE = 3; };
-template <> struct Shape<10> { static constexpr int NT = 128, LOGE = 3; };
-template <> struct Shape<11> { static constexpr int NT = 256, LOGE = 3; };
-template <> struct Shape<12> { static constexpr int NT = 256, LOGE = 4; };
-template <> struct Shape<13> { static constexpr int NT = 512, LOGE = 4; };
-template <> struct Shape<14> { static constexpr int NT = 1024, LOGE = 4; };
+template <> struct Shape<6> { static constexpr int NT = 16, LOGE = 2, LOGR = 2; };
+template <> struct Shape<7> { static constexpr int NT = 32, LOGE = 2, LOGR = 2; };
+template <> struct Shape<8> { static constexpr int NT = 64, LOGE = 2, LOGR = 2; };
+template <> struct Shape<9> { static constexpr int NT = 64, LOGE = 3, LOGR = 3; };
+template <> struct Shape<10> { static constexpr int NT = 128, LOGE = 3, LOGR = 3; };
+template <> struct Shape<11> { static constexpr int NT = 256, LOGE = 3, LOGR = 3; };
+template <> struct Shape<12> { static constexpr int NT = 256, LOGE = 4, LOGR = 4; };
+template <> struct Shape<13> { static constexpr int NT = 512, LOGE = 4, LOGR = 4; };
+template <> struct Shape<14> { static constexpr int NT = 1024, LOGE = 4, LOGR = 4; };
+template <> struct Shape<15> { static constexpr int NT = 1024, LOGE = 5, LOGR = 4; };
 
 constexpr int kMinLogN = 6;
-constexpr int kMaxLogNF32 = 14;   // n_f = 2^15
+constexpr int kMaxLogNF32 = 15;   // n_f = 2^16
 constexpr int kMaxLogNF64 = 14;   // n_f = 2^15
 
 int ols_max_logn(bool fp64) { return fp64 ? kMaxLogNF64 : kMaxLogNF32; }
@@ -59,21 +61,92 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s) {
   return hipGetLastError();
 }
 
-// 1/p(nu_j) on the L-point grid, Hermitian-extended: s_j = s_{L-j}
+template <typename T, int LOGN>
+using ShapeFFT = BlockFFT<T, LOGN, Shape<LOGN>::NT, Shape<LOGN>::LOGE, Shape<LOGN>::LOGR>;
+
+// per-pass twiddle rows: entry (j, r) of pass p = exp(-2 pi i j r / (Ns R))
+template <typename T, int LOGN>
+__global__ void k_pass_tw(cx<T>* tab) {
+  using F = ShapeFFT<T, LOGN>;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= F::tw_total()) return;
+  for (int sq = 0; sq < 2; ++sq) {
+    const bool fwd = sq == 0;
+    for (int p = 0; p < F::NP; ++p) {
+      const int o = F::tw_offset(fwd, p), c = F::tw_count(fwd, p);
+      if (e >= o && e < o + c) {
+        const int lr = F::log_radix(fwd, p), ls = F::log_span(fwd, p);
+        const int j = (e - o) >> lr, r = (e - o) & ((1 << lr) - 1);
+        const double frac = (double)((int64_t)j * r) / (double)(1 << (lr + ls));
+        double sn, cs;
+        sincospi(2.0 * frac, &sn, &cs);
+        tab[e] = {(T)cs, (T)(-sn)};
+        return;
+      }
+    }
+  }
+}
+
+template <typename T, int LOGN>
+static int pass_tw_total_t() { return ShapeFFT<T, LOGN>::tw_total(); }
+
+int pass_twiddle_count(int logn, bool fp64) {
+#define MM_PTC(L) case L: return fp64 ? pass_tw_total_t<double, L>() : pass_tw_total_t<float, L>();
+  switch (logn) {
+    MM_PTC(6) MM_PTC(7) MM_PTC(8) MM_PTC(9) MM_PTC(10) MM_PTC(11) MM_PTC(12) MM_PTC(13) MM_PTC(14)
+    case 15: return fp64 ? -1 : pass_tw_total_t<float, 15>();
+    default: return -1;
+  }
+#undef MM_PTC
+}
+
+template <typename T, int LOGN>
+static hipError_t pass_tw_launch(void* tab, hipStream_t s) {
+  const int n = ShapeFFT<T, LOGN>::tw_total();
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_pass_tw<T, LOGN>), dim3((n + 255) / 256), dim3(256), 0, s, (cx<T>*)tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s) {
+#define MM_PTL(L) case L: return fp64 ? pass_tw_launch<double, L>(tab, s) : pass_tw_launch<float, L>(tab, s);
+  switch (logn) {
+    MM_PTL(6) MM_PTL(7) MM_PTL(8) MM_PTL(9) MM_PTL(10) MM_PTL(11) MM_PTL(12) MM_PTL(13) MM_PTL(14)
+    case 15: return fp64 ? hipErrorInvalidValue : pass_tw_launch<float, 15>(tab, s);
+    default: return hipErrorInvalidValue;
+  }
+#undef MM_PTL
+}
+
+// 1/p(nu_j) on the L-point grid, Hermitian-extended: s_j = s_{L-j}; mode 1-3
+// give its derivative with respect to sigma, f_knee, alpha.  With
+// x = (f_knee/nu)^alpha:  ds/dsigma = -2 s/sigma,  ds/df_knee = -s^2 sigma^2 alpha x/f_knee,
+// ds/dalpha = -s^2 sigma^2 x ln(f_knee/nu); the nu = 0 value (0 or 1/sigma^2)
+// does not depend on f_knee or alpha.
 __device__ __forceinline__ double inv_psd(int64_t j, int64_t L, double f_samp, double sigma,
-                                          double fknee, double alpha) {
+                                          double fknee, double alpha, int mode) {
   if (j > L / 2) j = L - j;
-  if (j == 0) return fknee > 0.0 ? 0.0 : 1.0 / (sigma * sigma);
+  if (j == 0) {
+    const double s0 = fknee > 0.0 ? 0.0 : 1.0 / (sigma * sigma);
+    return mode == 0 ? s0 : (mode == 1 ? -2.0 * s0 / sigma : 0.0);
+  }
   const double nu = (double)j * (f_samp / (double)L);
-  return 1.0 / (sigma * sigma * (1.0 + pow(fknee / nu, alpha)));
+  const double x = pow(fknee / nu, alpha);
+  const double s = 1.0 / (sigma * sigma * (1.0 + x));
+  switch (mode) {
+    case 0: return s;
+    case 1: return -2.0 * s / sigma;
+    case 2: return fknee > 0.0 ? -s * s * sigma * sigma * alpha * x / fknee : 0.0;
+    default: return fknee > 0.0 ? -s * s * sigma * sigma * x * log(fknee / nu) : 0.0;
+  }
 }
 
 // step 1: grid (R, filters in batch); one n_c'-point transform per (r, filter)
 template <int LOGN>
 __global__ __launch_bounds__(Shape<LOGN>::NT) void k_lag_step1(
     const double* __restrict__ params, int f0, double f_samp, int64_t L, int n_c,
-    const cx<double>* __restrict__ tw2, cx<double>* __restrict__ G) {
-  using F = BlockFFT<double, LOGN, Shape<LOGN>::NT, Shape<LOGN>::LOGE>;
+    const cx<double>* __restrict__ ptw, cx<double>* __restrict__ G, int mode) {
+  using F = ShapeFFT<double, LOGN>;
   __shared__ __align__(16) char lds[F::LDS_BYTES];
   constexpr int N = F::N, E = F::E;
   const int t = threadIdx.x;
@@ -88,9 +161,9 @@ __global__ __launch_bounds__(Shape<LOGN>::NT) void k_lag_step1(
 #pragma unroll
     for (int rr = 0; rr < R0; ++rr) {
       const int q = F::template in_index<L0>(t, i, rr);
-      v[i * R0 + rr] = {inv_psd(r + R * (int64_t)q, L, f_samp, sg, fk, al), 0.0};
+      v[i * R0 + rr] = {inv_psd(r + R * (int64_t)q, L, f_samp, sg, fk, al, mode), 0.0};
     }
-  F::forward(v, lds, tw2, t);
+  F::forward(v, lds, ptw, t);
   constexpr int LL = F::last_log_fwd(), RL = 1 << LL;
   cx<double>* out = G + ((int64_t)blockIdx.y * R + r) * n_c;
 #pragma unroll
@@ -126,50 +199,54 @@ static int ceil_log2(int64_t x) {
   return l;
 }
 
+static size_t lag_tw_bytes(int logn) {
+  const int n = pass_twiddle_count(logn, true);
+  return ((size_t)(n > 0 ? n : 1) * sizeof(cx<double>) + 255) & ~(size_t)255;
+}
+
 size_t lags_scratch_bytes(int n_c, int64_t lag_len, int filters_per_batch) {
   const int logn = ceil_log2(n_c) < kMinLogN ? kMinLogN : ceil_log2(n_c);
   const int64_t R = lag_len >> logn;
-  return (size_t)(1 << logn) * 16                                 // twiddles
-         + (size_t)filters_per_batch * R * n_c * sizeof(cx<double>);
+  return lag_tw_bytes(logn) + (size_t)filters_per_batch * R * n_c * sizeof(cx<double>);
 }
 
 template <int LOGN>
 static hipError_t lag_step1(dim3 g, hipStream_t s, const double* params, int f0, double fs,
-                            int64_t L, int n_c, const cx<double>* tw2, cx<double>* G) {
+                            int64_t L, int n_c, const cx<double>* ptw, cx<double>* G, int mode) {
   hipLaunchKernelGGL(k_lag_step1<LOGN>, g, dim3(Shape<LOGN>::NT), 0, s, params, f0, fs, L, n_c,
-                     tw2, G);
+                     ptw, G, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_lags(const double* params, int n_filters, double f_samp, int n_c,
                        int64_t lag_len, double* lags, void* scratch, size_t scratch_bytes,
-                       hipStream_t s) {
+                       hipStream_t s, int mode) {
   int logn = ceil_log2(n_c);
   if (logn < kMinLogN) logn = kMinLogN;
   if (logn > kMaxLogNF64) return hipErrorInvalidValue;
   const int64_t R = lag_len >> logn;
   if (R < 2 || (R << logn) != lag_len) return hipErrorInvalidValue;
-  cx<double>* tw2 = (cx<double>*)scratch;
-  cx<double>* G = (cx<double>*)((char*)scratch + (size_t)(1 << logn) * 16);
+  cx<double>* ptw = (cx<double>*)scratch;   // per-pass twiddle tables of the transform
+  cx<double>* G = (cx<double>*)((char*)scratch + lag_tw_bytes(logn));
   const size_t per_filter = (size_t)R * n_c * sizeof(cx<double>);
-  const size_t avail = scratch_bytes - (size_t)(1 << logn) * 16;
+  if (scratch_bytes < lag_tw_bytes(logn) + per_filter) return hipErrorInvalidValue;
+  const size_t avail = scratch_bytes - lag_tw_bytes(logn);
   int batch = (int)(avail / per_filter);
-  if (batch < 1) return hipErrorInvalidValue;
-  hipError_t e = launch_tw2_table(tw2, logn, true, s);
+  hipError_t e = launch_pass_twiddles(ptw, logn, true, s);
   if (e != hipSuccess) return e;
   for (int f0 = 0; f0 < n_filters; f0 += batch) {
     const int nb = (n_filters - f0) < batch ? (n_filters - f0) : batch;
     const dim3 g1((unsigned)R, (unsigned)nb);
     switch (logn) {
-      case 6: e = lag_step1<6>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 7: e = lag_step1<7>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 8: e = lag_step1<8>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 9: e = lag_step1<9>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 10: e = lag_step1<10>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 11: e = lag_step1<11>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 12: e = lag_step1<12>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 13: e = lag_step1<13>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
-      case 14: e = lag_step1<14>(g1, s, params, f0, f_samp, lag_len, n_c, tw2, G); break;
+      case 6: e = lag_step1<6>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 7: e = lag_step1<7>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 8: e = lag_step1<8>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 9: e = lag_step1<9>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 10: e = lag_step1<10>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 11: e = lag_step1<11>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 12: e = lag_step1<12>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 13: e = lag_step1<13>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
+      case 14: e = lag_step1<14>(g1, s, params, f0, f_samp, lag_len, n_c, ptw, G, mode); break;
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -181,101 +258,14 @@ hipError_t launch_lags(const double* params, int n_filters, double f_samp, int n
   return hipSuccess;
 }
 
-// ---------------------------------------------------------------- spectra
-__global__ void k_cos_table(double* ctab, int nf) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < nf) ctab[j] = cospi(2.0 * (double)j / (double)nf);
-}
-
-// spec[f][k] = F_k / (4N), F_k = f(0) + 2 sum_{tau=1}^{n_c-1} f(tau) cos(2 pi k tau / n_f), k <= N
-template <typename T>
-__global__ void k_spectrum(const double* __restrict__ lags, int n_c, int N,
-                           const double* __restrict__ ctab, T* __restrict__ spec) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > N) return;
-  const double* f = lags + (int64_t)blockIdx.y * n_c;
-  const int nf = 2 * N;
-  double acc = 0.0;
-  int idx = 0;
-  for (int tau = 1; tau < n_c; ++tau) {
-    idx += k;
-    if (idx >= nf) idx -= nf;
-    acc += f[tau] * ctab[idx];
-  }
-  const double F = f[0] + 2.0 * acc;
-  spec[(int64_t)blockIdx.y * (N + 1) + k] = (T)(F / (4.0 * (double)N));
-}
-
-hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, bool fp64,
-                          void* spec, double* ctab, hipStream_t s) {
-  const int N = 1 << logn, nf = 2 * N;
-  hipLaunchKernelGGL(k_cos_table, dim3((nf + 255) / 256), dim3(256), 0, s, ctab, nf);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const dim3 g((unsigned)((N + 1 + 255) / 256), (unsigned)n_filters);
-  if (fp64)
-    hipLaunchKernelGGL(k_spectrum<double>, g, dim3(256), 0, s, lags, n_c, N, ctab, (double*)spec);
-  else
-    hipLaunchKernelGGL(k_spectrum<float>, g, dim3(256), 0, s, lags, n_c, N, ctab, (float*)spec);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- overlap-save transform
-// One workgroup per (chunk, RHS).  The n_f = 2N real window u is packed as N
-// complex points z_k = u_{2k} + i u_{2k+1}; after the forward transform Z, the
-// spectrum of u is X_k = E_k + W^k O_k, X_{k+N} = E_k - W^k O_k with
-// E = (Z_k + conj Z_{N-k})/2, O = (Z_k - conj Z_{N-k})/(2i), W = e^{-2 pi i/(2N)}.
-// Multiplying by the filter symbol F and folding back gives the packed
-// spectrum of the output, Z'_k = (Y_k + Y_{k+N})/2 + i W^{-k} (Y_k - Y_{k+N})/2,
-// Y = F X.  The table spec holds F/(4N), which absorbs both halvings and the
-// 1/N of the inverse transform; the inverse is conj(FFT(conj Z')).
-template <typename T, typename Tin, int LOGN>
-__global__ __launch_bounds__(Shape<LOGN>::NT) void k_ols(
-    const Tin* __restrict__ yin, T* __restrict__ yout, const OlsChunk* __restrict__ chunks,
-    const T* __restrict__ spec, const cx<T>* __restrict__ tw2, int64_t n_t, int n_c, int m) {
-  using F = BlockFFT<T, LOGN, Shape<LOGN>::NT, Shape<LOGN>::LOGE>;
-  __shared__ __align__(16) char lds[F::LDS_BYTES];
+// ---------------------------------------------------------------- pairing helper
+// After a forward transform the thread holds Z_k at k = t + i NT + r N/R_last.
+// For each of its points, call fn(k, Z_k, Z_{N-k}) -> new value of the point,
+// with Z_{N-k} fetched from the owner thread through LDS.
+template <typename F, typename T, typename Fn>
+__device__ __forceinline__ void with_partner(cx<T>* v, void* lds, int t, Fn fn) {
   constexpr int N = F::N, E = F::E, NT = F::NT;
-  const int t = threadIdx.x;
-  const OlsChunk ch = chunks[blockIdx.x];
-  const int64_t roff = (int64_t)blockIdx.y * n_t;
-  const int64_t s0 = ch.out_start - n_c;
-  const int64_t lo = ch.iv_lo, hi = ch.iv_hi;
-  const Tin* __restrict__ src = yin + roff;
-
-  cx<T> v[E];
-  constexpr int L0 = F::first_log_fwd(), R0 = 1 << L0;
-#pragma unroll
-  for (int i = 0; i < E / R0; ++i)
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int k = F::template in_index<L0>(t, i, r);
-      const int64_t j = s0 + 2 * (int64_t)k;
-      const T a = (j >= lo && j < hi) ? (T)src[j] : (T)0;
-      const T b = (j + 1 >= lo && j + 1 < hi) ? (T)src[j + 1] : (T)0;
-      v[i * R0 + r] = {a, b};
-    }
-
-  F::forward(v, lds, tw2, t);
-
-  // pair Z_k with Z_{N-k} through LDS and apply the filter symbol
   constexpr int LL = F::last_log_fwd(), RL = 1 << LL, NBL = E / RL;
-  const T* __restrict__ S = spec + (int64_t)ch.filter * (N + 1);
-  auto symbol = [&](int k, cx<T> A, cx<T> partner) -> cx<T> {
-    const cx<T> B = cconj(partner);
-    const cx<T> Ev = cadd(A, B);
-    const cx<T> D = csub(A, B);
-    const cx<T> O = {D.im, -D.re};            // -i (A - B)
-    const cx<T> W = tw2[k];                    // e^{-2 pi i k / (2N)}
-    const cx<T> WO = cmul(W, O);
-    const T sa = S[k], sb = S[N - k];
-    const cx<T> Y = cscale(cadd(Ev, WO), sa);
-    const cx<T> Yp = cscale(csub(Ev, WO), sb);
-    const cx<T> sum = cadd(Y, Yp);
-    const cx<T> dif = csub(Y, Yp);
-    const cx<T> Wd = cmul(cconj(W), dif);      // W^{-k} (Y - Y')
-    return {sum.re - Wd.im, -(sum.im + Wd.re)};  // conj(sum + i Wd)
-  };
   if constexpr (!F::SPLIT) {
     cx<T>* l = reinterpret_cast<cx<T>*>(lds);
     __syncthreads();
@@ -289,7 +279,7 @@ __global__ __launch_bounds__(Shape<LOGN>::NT) void k_ols(
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int k = t + i * NT + r * (N >> LL);
-        v[i * RL + r] = symbol(k, v[i * RL + r], l[F::cpad((N - k) & (N - 1))]);
+        v[i * RL + r] = fn(k, v[i * RL + r], l[F::cpad((N - k) & (N - 1))]);
       }
   } else {
     T* l = reinterpret_cast<T*>(lds);
@@ -319,42 +309,253 @@ __global__ __launch_bounds__(Shape<LOGN>::NT) void k_ols(
       for (int r = 0; r < RL; ++r) {
         const int k = t + i * NT + r * (N >> LL);
         const cx<T> partner = {pre[i * RL + r], l[F::spad((N - k) & (N - 1))]};
-        v[i * RL + r] = symbol(k, v[i * RL + r], partner);
+        v[i * RL + r] = fn(k, v[i * RL + r], partner);
+      }
+  }
+}
+
+// ---------------------------------------------------------------- spectra
+// Symbol of the circulant that embeds one filter's band:
+//   F_k = f(0) + 2 sum_{tau=1}^{n_c-1} f(tau) cos(2 pi k tau / n_f),  k = 0 .. N,
+// i.e. the DFT of the real, even first column c (c_i = f(|i|) circularly).  c is
+// packed as N complex points, transformed in float64 by one workgroup, and the
+// real spectrum recovered with X_k = E_k + W^k O_k (X_N = E_0 - O_0).  The
+// table keeps F/(4N) in the filter's working precision.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(Shape<LOGN>::NT) void k_spectrum_fft(
+    const double* __restrict__ lags, int n_c, T* __restrict__ spec,
+    const cx<double>* __restrict__ ptw, const cx<double>* __restrict__ tw2) {
+  using F = ShapeFFT<double, LOGN>;
+  __shared__ __align__(16) char lds[F::LDS_BYTES];
+  constexpr int N = F::N, E = F::E;
+  const int nf = 2 * N;
+  const int t = threadIdx.x;
+  const double* __restrict__ f = lags + (int64_t)blockIdx.x * n_c;
+  T* __restrict__ out = spec + (int64_t)blockIdx.x * (N + 1);
+  auto col = [&](int i) -> double {
+    if (i < n_c) return f[i];
+    const int j = nf - i;
+    return j < n_c ? f[j] : 0.0;
+  };
+  cx<double> v[E];
+  constexpr int L0 = F::first_log_fwd(), R0 = 1 << L0;
+#pragma unroll
+  for (int i = 0; i < E / R0; ++i)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int k = F::template in_index<L0>(t, i, r);
+      v[i * R0 + r] = {col(2 * k), col(2 * k + 1)};
+    }
+  F::forward(v, lds, ptw, t);
+  const double scale = 1.0 / (4.0 * (double)N);
+  with_partner<F>(v, lds, t, [&](int k, cx<double> A, cx<double> Bp) {
+    const cx<double> B = cconj(Bp);
+    const cx<double> Ev = cadd(A, B);                       // 2 E_k
+    const cx<double> D = csub(A, B);
+    const cx<double> O = {D.im, -D.re};                     // 2 O_k
+    const cx<double> X = cadd(Ev, cmul(tw2[k], O));         // 2 X_k
+    out[k] = (T)(0.5 * X.re * scale);
+    if (k == 0) out[N] = (T)(0.5 * (Ev.re - O.re) * scale);
+    return A;
+  });
+}
+
+// Direct-sum form of the same symbol, for transform lengths beyond the largest
+// float64 workgroup transform: cos(2 pi k tau / n_f) from a float64 table of n_f
+// entries indexed by (k tau) mod n_f.
+__global__ void k_cos_table(double* ctab, int nf) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nf) ctab[j] = cospi(2.0 * (double)j / (double)nf);
+}
+
+template <typename T>
+__global__ void k_spectrum_direct(const double* __restrict__ lags, int n_c, int N,
+                                  const double* __restrict__ ctab, T* __restrict__ spec) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > N) return;
+  const double* f = lags + (int64_t)blockIdx.y * n_c;
+  const int nf = 2 * N;
+  double acc = 0.0;
+  int idx = 0;
+  for (int tau = 1; tau < n_c; ++tau) {
+    idx += k;
+    if (idx >= nf) idx -= nf;
+    acc += f[tau] * ctab[idx];
+  }
+  spec[(int64_t)blockIdx.y * (N + 1) + k] = (T)((f[0] + 2.0 * acc) / (4.0 * (double)N));
+}
+
+template <typename T, int LOGN>
+static hipError_t spectrum_launch(const double* lags, int n_filters, int n_c, void* spec,
+                                  const void* ptw, const void* tw2, hipStream_t s) {
+  hipLaunchKernelGGL((k_spectrum_fft<T, LOGN>), dim3((unsigned)n_filters), dim3(Shape<LOGN>::NT), 0, s,
+                     lags, n_c, (T*)spec, (const cx<double>*)ptw, (const cx<double>*)tw2);
+  return hipGetLastError();
+}
+
+size_t spectra_scratch_bytes(int logn) {
+  if (logn > kMaxLogNF64) return (size_t)(2 << logn) * sizeof(double) + 256;   // cosine table
+  const int n = pass_twiddle_count(logn, true);
+  return (size_t)(n > 0 ? n : 1) * sizeof(cx<double>) + (size_t)(1 << logn) * sizeof(cx<double>) + 256;
+}
+
+hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, bool fp64,
+                          void* spec, void* scratch, hipStream_t s) {
+  if (n_filters == 0) return hipSuccess;
+  if (logn > kMaxLogNF64) {
+    const int N = 1 << logn, nf = 2 * N;
+    double* ctab = (double*)scratch;
+    hipLaunchKernelGGL(k_cos_table, dim3((nf + 255) / 256), dim3(256), 0, s, ctab, nf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g((unsigned)((N + 1 + 255) / 256), (unsigned)n_filters);
+    if (fp64)
+      hipLaunchKernelGGL(k_spectrum_direct<double>, g, dim3(256), 0, s, lags, n_c, N, ctab, (double*)spec);
+    else
+      hipLaunchKernelGGL(k_spectrum_direct<float>, g, dim3(256), 0, s, lags, n_c, N, ctab, (float*)spec);
+    return hipGetLastError();
+  }
+  // float64 twiddles for the spectrum transform, whatever the filter's precision
+  cx<double>* ptw = (cx<double>*)scratch;
+  const int n = pass_twiddle_count(logn, true);
+  if (n < 0) return hipErrorInvalidValue;
+  cx<double>* tw2 = ptw + (n > 0 ? n : 1);
+  hipError_t e = launch_pass_twiddles(ptw, logn, true, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_tw2_table(tw2, logn, true, s)) != hipSuccess) return e;
+#define MM_SPC(L) \
+  case L: return fp64 ? spectrum_launch<double, L>(lags, n_filters, n_c, spec, ptw, tw2, s) \
+                      : spectrum_launch<float, L>(lags, n_filters, n_c, spec, ptw, tw2, s);
+  switch (logn) {
+    MM_SPC(6) MM_SPC(7) MM_SPC(8) MM_SPC(9) MM_SPC(10) MM_SPC(11) MM_SPC(12) MM_SPC(13) MM_SPC(14)
+    default: return hipErrorInvalidValue;
+  }
+#undef MM_SPC
+}
+
+// ---------------------------------------------------------------- overlap-save transform
+// One workgroup per (chunk, RHS).  The n_f = 2N real window u is packed as N
+// complex points z_k = u_{2k} + i u_{2k+1}; after the forward transform Z, the
+// spectrum of u is X_k = E_k + W^k O_k, X_{k+N} = E_k - W^k O_k with
+// E = (Z_k + conj Z_{N-k})/2, O = (Z_k - conj Z_{N-k})/(2i), W = e^{-2 pi i/(2N)}.
+// Multiplying by the filter symbol F and folding back gives the packed
+// spectrum of the output, Z'_k = (Y_k + Y_{k+N})/2 + i W^{-k} (Y_k - Y_{k+N})/2,
+// Y = F X.  The table spec holds F/(4N), which absorbs both halvings and the
+// 1/N of the inverse transform; the inverse is conj(FFT(conj Z')).
+template <typename V> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
+template <typename T, typename Tin, int LOGN>
+__global__ __launch_bounds__(Shape<LOGN>::NT) void k_ols(
+    const Tin* __restrict__ yin, T* __restrict__ yout, const OlsChunk* __restrict__ chunks,
+    const T* __restrict__ spec, const cx<T>* __restrict__ ptw, const cx<T>* __restrict__ tw2,
+    int64_t n_t, int n_c, int m) {
+  using F = ShapeFFT<T, LOGN>;
+  using PI = typename Pair<Tin>::type;
+  using PO = typename Pair<T>::type;
+  __shared__ __align__(16) char lds[F::LDS_BYTES];
+  constexpr int N = F::N, E = F::E, NT = F::NT;
+  const int t = threadIdx.x;
+  const OlsChunk ch = chunks[blockIdx.x];
+  const int64_t roff = (int64_t)blockIdx.y * n_t;
+  const int64_t s0 = ch.out_start - n_c;
+  const int64_t lo = ch.iv_lo, hi = ch.iv_hi;
+  const Tin* __restrict__ src = yin + roff;
+
+  cx<T> v[E];
+  constexpr int L0 = F::first_log_fwd(), R0 = 1 << L0;
+  const bool in_inside = s0 >= lo && s0 + 2 * N <= hi &&
+                         ((reinterpret_cast<uintptr_t>(src + s0) & (sizeof(PI) - 1)) == 0);
+  if (in_inside) {
+    const PI* __restrict__ src2 = reinterpret_cast<const PI*>(src + s0);
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const PI x = src2[F::template in_index<L0>(t, i, r)];
+        v[i * R0 + r] = {(T)x.x, (T)x.y};
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int k = F::template in_index<L0>(t, i, r);
+        const int64_t j = s0 + 2 * (int64_t)k;
+        const T a = (j >= lo && j < hi) ? (T)src[j] : (T)0;
+        const T b = (j + 1 >= lo && j + 1 < hi) ? (T)src[j + 1] : (T)0;
+        v[i * R0 + r] = {a, b};
       }
   }
 
-  F::forward_rev(v, lds, tw2, t);
+  F::forward(v, lds, ptw, t);
+
+  // pair Z_k with Z_{N-k} through LDS and apply the filter symbol
+  const T* __restrict__ S = spec + (int64_t)ch.filter * (N + 1);
+  with_partner<F>(v, lds, t, [&](int k, cx<T> A, cx<T> partner) -> cx<T> {
+    const cx<T> B = cconj(partner);
+    const cx<T> Ev = cadd(A, B);
+    const cx<T> D = csub(A, B);
+    const cx<T> O = {D.im, -D.re};            // -i (A - B)
+    const cx<T> W = tw2[k];                    // e^{-2 pi i k / (2N)}
+    const cx<T> WO = cmul(W, O);
+    const T sa = S[k], sb = S[N - k];
+    const cx<T> Y = cscale(cadd(Ev, WO), sa);
+    const cx<T> Yp = cscale(csub(Ev, WO), sb);
+    const cx<T> sum = cadd(Y, Yp);
+    const cx<T> dif = csub(Y, Yp);
+    const cx<T> Wd = cmul(cconj(W), dif);      // W^{-k} (Y - Y')
+    return {sum.re - Wd.im, -(sum.im + Wd.re)};  // conj(sum + i Wd)
+  });
+
+  F::forward_rev(v, lds, ptw, t);
 
   constexpr int LZ = F::last_log_rev(), RZ = 1 << LZ;
   T* __restrict__ dst = yout + roff;
+  const bool out_inside = ((n_c & 1) == 0) && s0 + n_c + m <= hi &&
+                          ((reinterpret_cast<uintptr_t>(dst + s0) & (sizeof(PO) - 1)) == 0);
+  if (out_inside) {
+    PO* __restrict__ dst2 = reinterpret_cast<PO*>(dst + s0);
+    const int j0 = n_c >> 1, j1 = (n_c + m) >> 1;
 #pragma unroll
-  for (int i = 0; i < E / RZ; ++i)
+    for (int i = 0; i < E / RZ; ++i)
 #pragma unroll
-    for (int r = 0; r < RZ; ++r) {
-      const int j = t + i * NT + r * (N >> LZ);
-      const int pos = 2 * j;
-      const cx<T> z = v[i * RZ + r];
-      if (pos >= n_c && pos < n_c + m && s0 + pos < hi) dst[s0 + pos] = z.re;
-      if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -z.im;
-    }
+      for (int r = 0; r < RZ; ++r) {
+        const int j = t + i * NT + r * (N >> LZ);
+        const cx<T> z = v[i * RZ + r];
+        if (j >= j0 && j < j1) dst2[j] = PO{z.re, -z.im};
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E / RZ; ++i)
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) {
+        const int j = t + i * NT + r * (N >> LZ);
+        const int pos = 2 * j;
+        const cx<T> z = v[i * RZ + r];
+        if (pos >= n_c && pos < n_c + m && s0 + pos < hi) dst[s0 + pos] = z.re;
+        if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -z.im;
+      }
+  }
 }
 
 template <typename T, typename Tin, int LOGN>
 static hipError_t ols_launch(const void* y_in, void* y_out, const OlsChunk* chunks, int n_chunks,
-                             const void* spec, const void* tw2, int64_t n_t, int n_c, int m,
-                             int n_rhs, hipStream_t s) {
+                             const void* spec, const void* ptw, const void* tw2, int64_t n_t, int n_c,
+                             int m, int n_rhs, hipStream_t s) {
   hipLaunchKernelGGL((k_ols<T, Tin, LOGN>), dim3((unsigned)n_chunks, (unsigned)n_rhs),
                      dim3(Shape<LOGN>::NT), 0, s, (const Tin*)y_in, (T*)y_out, chunks,
-                     (const T*)spec, (const cx<T>*)tw2, n_t, n_c, m);
+                     (const T*)spec, (const cx<T>*)ptw, (const cx<T>*)tw2, n_t, n_c, m);
   return hipGetLastError();
 }
 
 template <typename T, typename Tin>
 static hipError_t ols_dispatch(int logn, const void* y_in, void* y_out, const OlsChunk* chunks,
-                               int n_chunks, const void* spec, const void* tw2, int64_t n_t,
-                               int n_c, int m, int n_rhs, hipStream_t s) {
+                               int n_chunks, const void* spec, const void* ptw, const void* tw2,
+                               int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s) {
 #define MM_OLS_CASE(L) \
-  case L: return ols_launch<T, Tin, L>(y_in, y_out, chunks, n_chunks, spec, tw2, n_t, n_c, m, n_rhs, s);
+  case L: return ols_launch<T, Tin, L>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s);
   switch (logn) {
     MM_OLS_CASE(6)
     MM_OLS_CASE(7)
@@ -368,22 +569,26 @@ static hipError_t ols_dispatch(int logn, const void* y_in, void* y_out, const Ol
     default: break;
   }
 #undef MM_OLS_CASE
+  if constexpr (sizeof(T) == 4) {
+    if (logn == 15)
+      return ols_launch<T, Tin, 15>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s);
+  }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* y_out,
-                      const OlsChunk* chunks, int n_chunks, const void* spec, const void* tw2,
-                      int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s) {
+                      const OlsChunk* chunks, int n_chunks, const void* spec, const void* ptw,
+                      const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s) {
   if (n_chunks == 0 || n_rhs == 0) return hipSuccess;
   if (fp64) {
-    return in_f64 ? ols_dispatch<double, double>(logn, y_in, y_out, chunks, n_chunks, spec, tw2,
+    return in_f64 ? ols_dispatch<double, double>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
                                                  n_t, n_c, m, n_rhs, s)
-                  : ols_dispatch<double, float>(logn, y_in, y_out, chunks, n_chunks, spec, tw2,
+                  : ols_dispatch<double, float>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
                                                 n_t, n_c, m, n_rhs, s);
   }
-  return in_f64 ? ols_dispatch<float, double>(logn, y_in, y_out, chunks, n_chunks, spec, tw2, n_t,
+  return in_f64 ? ols_dispatch<float, double>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t,
                                               n_c, m, n_rhs, s)
-                : ols_dispatch<float, float>(logn, y_in, y_out, chunks, n_chunks, spec, tw2, n_t,
+                : ols_dispatch<float, float>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t,
                                              n_c, m, n_rhs, s);
 }
 

@@ -6,11 +6,14 @@
 // samples are zero.
 //
 // Gather streams the time-ordered pointing (observed pixel id, sin/cos pair)
-// coalesced and reads the map through the caches.  Scatter walks the
-// pixel-major copy of the pointing built by the plan: a group of G lanes owns
-// one pixel, strides over that pixel's samples and reduces across the group
-// with cross-lane shuffles, so every pixel sum is formed in a fixed order by
-// one group and no atomics are needed.  Maps are float64 [R][n_obs][ns].
+// coalesced and reads the map through the caches.  Scatter walks a sliced,
+// pixel-major copy of the pointing built by the plan: one lane (of each of
+// four wavefronts) owns one pixel, so every pixel sum is formed in a fixed
+// order and no atomics are needed.  The scatter can also return
+// the per-block partial sums of p.q for the CG step length.  Maps are float64
+// [R][n_obs][ns].
+#include <algorithm>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -80,81 +83,155 @@ template <> struct Acc<float> {
   __device__ double value() const { return (double)s + (double)c; }
 };
 
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, G);
-  return v;
+// Sliced layout of the pixel-major pointing: slice s holds the 64 observed
+// pixels 64s .. 64s+63; entry (j, L) at sell_off[s] + 64 j + L is the j-th
+// sample (in time order) of pixel 64s + L, or -1 past that pixel's hits.  One
+// wavefront walks one slice with one lane per pixel, so each step reads 64
+// consecutive entries and, for a raster scan, neighbouring TOD samples.
+__global__ void k_sell_widths(const int64_t* __restrict__ pix_ptr, int64_t n_obs,
+                              uint32_t* __restrict__ slice_len) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_sl = (n_obs + 63) / 64;
+  if (s >= n_sl) return;
+  int64_t w = 0;
+  for (int64_t o = s * 64; o < n_obs && o < s * 64 + 64; ++o) w = max(w, pix_ptr[o + 1] - pix_ptr[o]);
+  slice_len[s] = (uint32_t)min(w * 64, (int64_t)0xFFFFFFFF);   // saturates; the host rejects it
 }
 
-template <typename Ty, int NS, int G>
-__global__ void k_scatter(const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm,
-                          const float2* __restrict__ w_pm, const Ty* __restrict__ y,
-                          double* __restrict__ q, int64_t n_obs, int64_t n_t, int n_rhs) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t o = gid / G;
-  const int lane = (int)(gid % G);
-  const bool ok = o < n_obs;   // whole groups share o, so shuffles stay within live lanes
-  const int64_t k0 = ok ? pix_ptr[o] : 0, k1 = ok ? pix_ptr[o + 1] : 0;
-  for (int r = 0; r < n_rhs; ++r) {
-    const Ty* __restrict__ yr = y + (int64_t)r * n_t;
-    Acc<Ty> a0, a1, a2;
-    for (int64_t k = k0 + lane; k < k1; k += G) {
-      const Ty v = yr[perm[k]];
-      if (NS == 1) {
-        a0.add(v);
-      } else {
-        const float2 sc = w_pm[k];
-        const Ty h = (Ty)0.5 * v;
-        a0.add(h);
-        a1.add(h * (Ty)sc.x);
-        a2.add(h * (Ty)sc.y);
-      }
-    }
-    const double s0 = group_sum<G>(a0.value());
-    if (NS == 1) {
-      if (ok && lane == 0) q[(int64_t)r * n_obs + o] = s0;
-    } else {
-      const double s1 = group_sum<G>(a1.value());
-      const double s2 = group_sum<G>(a2.value());
-      if (ok && lane == 0) {
-        double* d = q + ((int64_t)r * n_obs + o) * 3;
-        d[0] = s0;
-        d[1] = s1;
-        d[2] = s2;
-      }
+__global__ void k_sell_fill(const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm,
+                            const float2* __restrict__ w_pm, int64_t n_obs,
+                            const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
+                            int32_t* __restrict__ sell_t, float2* __restrict__ sell_w, int ns) {
+  const int64_t n_sl = (n_obs + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; s < n_sl; s += wstride) {
+    const int64_t base = (int64_t)slice_end[s] - slice_len[s];
+    const int64_t width = slice_len[s] / 64;
+    const int64_t o = s * 64 + lane;
+    const int64_t k0 = o < n_obs ? pix_ptr[o] : 0, k1 = o < n_obs ? pix_ptr[o + 1] : 0;
+    for (int64_t j = 0; j < width; ++j) {
+      const int64_t e = base + j * 64 + lane;
+      const bool hit = k0 + j < k1;
+      sell_t[e] = hit ? perm[k0 + j] : -1;
+      if (ns == 3) sell_w[e] = hit ? w_pm[k0 + j] : make_float2(0.f, 0.f);
     }
   }
 }
 
-template <typename Ty, int NS>
-static hipError_t scatter_g(int group, dim3 g, hipStream_t s, const int64_t* pp, const int32_t* perm,
-                            const float2* w, const Ty* y, double* q, int64_t n_obs, int64_t n_t,
-                            int n_rhs) {
-  const dim3 b(256);
-  switch (group) {
-    case 4: hipLaunchKernelGGL((k_scatter<Ty, NS, 4>), g, b, 0, s, pp, perm, w, y, q, n_obs, n_t, n_rhs); break;
-    case 8: hipLaunchKernelGGL((k_scatter<Ty, NS, 8>), g, b, 0, s, pp, perm, w, y, q, n_obs, n_t, n_rhs); break;
-    case 16: hipLaunchKernelGGL((k_scatter<Ty, NS, 16>), g, b, 0, s, pp, perm, w, y, q, n_obs, n_t, n_rhs); break;
-    case 32: hipLaunchKernelGGL((k_scatter<Ty, NS, 32>), g, b, 0, s, pp, perm, w, y, q, n_obs, n_t, n_rhs); break;
-    case 64: hipLaunchKernelGGL((k_scatter<Ty, NS, 64>), g, b, 0, s, pp, perm, w, y, q, n_obs, n_t, n_rhs); break;
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_sell_widths(const int64_t* pix_ptr, int64_t n_obs, uint32_t* slice_len, hipStream_t s) {
+  const int64_t n_sl = (n_obs + 63) / 64;
+  if (n_sl == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sell_widths, dim3((unsigned)((n_sl + 255) / 256)), dim3(256), 0, s, pix_ptr, n_obs, slice_len);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(bool in_f64, int ns, int group, const int64_t* pix_ptr,
-                          const int32_t* perm, const float* w_pm, const void* y, double* q,
-                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s) {
+hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const float* w_pm, int64_t n_obs,
+                            const uint32_t* slice_end, const uint32_t* slice_len, int32_t* sell_t,
+                            float* sell_w, int ns, hipStream_t s) {
+  const int64_t n_sl = (n_obs + 63) / 64;
+  if (n_sl == 0) return hipSuccess;
+  int64_t nb = (n_sl + 3) / 4;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)nb), dim3(256), 0, s, pix_ptr, perm, (const float2*)w_pm, n_obs,
+                     slice_end, slice_len, sell_t, (float2*)sell_w, ns);
+  return hipGetLastError();
+}
+
+// q = P^T y over the sliced layout.  A block of four wavefronts owns one slice
+// at a time: wavefront w adds the entries j = w, w + 4, ... of its lane's pixel,
+// and the four partial sums are combined in that fixed order through LDS.
+// Grid-stride over slices with a bounded grid (kScatterBlocks), so the
+// optional p.q partial sums form a short, fixed list.
+template <typename Ty, int NS>
+__global__ __launch_bounds__(256) void k_scatter(
+    const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
+    const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
+    double* __restrict__ q, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
+    double* __restrict__ pq_part) {
+  __shared__ double part[4][NS][64];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int64_t n_sl = (n_obs + 63) / 64;
+  for (int r = 0; r < n_rhs; ++r) {
+    const Ty* __restrict__ yr = y + (int64_t)r * n_t;
+    double pq = 0.0;
+    for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
+      const int64_t base = (int64_t)slice_end[s] - slice_len[s] + lane;
+      const int width = (int)(slice_len[s] >> 6);
+      Acc<Ty> a0, a1, a2;
+#pragma unroll 2
+      for (int j = wv; j < width; j += 4) {
+        const int64_t e = base + (int64_t)j * 64;
+        const int32_t t = sell_t[e];
+        if (t >= 0) {
+          const Ty v = yr[t];
+          if (NS == 1) {
+            a0.add(v);
+          } else {
+            const float2 sc = sell_w[e];
+            const Ty h = (Ty)0.5 * v;
+            a0.add(h);
+            a1.add(h * (Ty)sc.x);
+            a2.add(h * (Ty)sc.y);
+          }
+        }
+      }
+      part[wv][0][lane] = a0.value();
+      if (NS == 3) {
+        part[wv][1][lane] = a1.value();
+        part[wv][2][lane] = a2.value();
+      }
+      __syncthreads();
+      const int64_t o = s * 64 + lane;
+      if (wv == 0 && o < n_obs) {
+        const int64_t i = ((int64_t)r * n_obs + o) * NS;
+        double v[NS];
+#pragma unroll
+        for (int c = 0; c < NS; ++c) v[c] = ((part[0][c][lane] + part[1][c][lane]) + part[2][c][lane]) + part[3][c][lane];
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+          q[i + c] = v[c];
+          if (p) pq += p[i + c] * v[c];
+        }
+      }
+      __syncthreads();
+    }
+    if (p) {   // block sum of the p.q contributions (wavefront 0 holds them), fixed order
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) pq += __shfl_xor(pq, off, 64);
+      if ((tid & 63) == 0) sh[tid >> 6] = pq;
+      __syncthreads();
+      if (tid == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < 4; ++w) sum += sh[w];
+        pq_part[(int64_t)r * gridDim.x + blockIdx.x] = sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+int scatter_blocks(int64_t n_obs) {
+  const int64_t n_sl = (n_obs + 63) / 64;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(n_sl, kScatterBlocks));
+}
+
+hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q,
+                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
+                          double* pq_part) {
   if (n_obs == 0) return hipSuccess;
-  const int64_t threads = n_obs * group;
-  const dim3 g((unsigned)((threads + 255) / 256));
-  const float2* w = (const float2*)w_pm;
-  if (in_f64)
-    return ns == 1 ? scatter_g<double, 1>(group, g, s, pix_ptr, perm, w, (const double*)y, q, n_obs, n_t, n_rhs)
-                   : scatter_g<double, 3>(group, g, s, pix_ptr, perm, w, (const double*)y, q, n_obs, n_t, n_rhs);
-  return ns == 1 ? scatter_g<float, 1>(group, g, s, pix_ptr, perm, w, (const float*)y, q, n_obs, n_t, n_rhs)
-                 : scatter_g<float, 3>(group, g, s, pix_ptr, perm, w, (const float*)y, q, n_obs, n_t, n_rhs);
+  const dim3 g((unsigned)scatter_blocks(n_obs)), b(256);
+  const float2* w = (const float2*)L.w;
+  if (in_f64) {
+    if (ns == 1) hipLaunchKernelGGL((k_scatter<double, 1>), g, b, 0, s, L.end, L.len, L.t, w, (const double*)y, q, n_obs, n_t, n_rhs, p, pq_part);
+    else hipLaunchKernelGGL((k_scatter<double, 3>), g, b, 0, s, L.end, L.len, L.t, w, (const double*)y, q, n_obs, n_t, n_rhs, p, pq_part);
+  } else {
+    if (ns == 1) hipLaunchKernelGGL((k_scatter<float, 1>), g, b, 0, s, L.end, L.len, L.t, w, (const float*)y, q, n_obs, n_t, n_rhs, p, pq_part);
+    else hipLaunchKernelGGL((k_scatter<float, 3>), g, b, 0, s, L.end, L.len, L.t, w, (const float*)y, q, n_obs, n_t, n_rhs, p, pq_part);
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- layout helpers

@@ -88,7 +88,8 @@ struct FilterSetup {
   bool fp64 = true;
   int logn = 0;
   int N = 0, nf = 0, m = 0;
-  void* tw2 = nullptr;
+  void* tw2 = nullptr;     // exp(-2 pi i k / n_f), k < N (real-to-complex packing)
+  void* ptw = nullptr;     // per-pass twiddle tables of the transform
   void* spec = nullptr;
   OlsChunk* chunks = nullptr;
   int n_chunks = 0;
@@ -121,10 +122,13 @@ struct mm_plan_s {
   float* w_pm = nullptr;
   int64_t* pix_ptr = nullptr;
   int32_t* obs2glob = nullptr;
-  int scatter_group = 8;
+  int scatter_group = 8;          // lanes per pixel in the plan-time preconditioner build
+  SellLayout sell;                // sliced pointing of the scatter
+  int64_t sell_entries = 0;
 
   // noise
   double* lags = nullptr;
+  double* d_params = nullptr;    // [n_filters][3] (sigma, f_knee, alpha) when given
   int64_t* d_iv_start = nullptr;
   int32_t* d_iv_filter = nullptr;
   FilterSetup fs_main, fs64;
@@ -141,6 +145,8 @@ struct mm_plan_s {
   double *vx = nullptr, *vp = nullptr, *vr = nullptr, *vz = nullptr, *vq = nullptr,
          *vxb = nullptr, *vb = nullptr;   // [R][n_obs][ns]
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
+  double* part_pq = nullptr;     // [R][scatter blocks] partial sums of p.q
+  double *vb64 = nullptr, *vr64 = nullptr, *vxacc = nullptr, *vxbest = nullptr;  // residual correction
   CgState* st = nullptr;
   CgState* st_host = nullptr;
   double* hist = nullptr;
@@ -233,11 +239,15 @@ void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool 
   const int esz = fp64 ? 8 : 4;
   fs.tw2 = P->alloc<char>((int64_t)fs.N * 2 * esz);
   hipchk(launch_tw2_table(fs.tw2, logn, fp64, s), "twiddle table");
+  const int ntw = pass_twiddle_count(logn, fp64);
+  if (ntw < 0) fail(MM_EUNSUPPORTED, "no transform for this FFT length");
+  fs.ptw = P->alloc<char>((int64_t)std::max(ntw, 1) * 2 * esz);
+  hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s), "pass twiddle tables");
   fs.spec = P->alloc<char>((int64_t)P->n_filt * (fs.N + 1) * esz);
-  double* ctab = P->alloc<double>((int64_t)fs.nf);
-  hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, ctab, s), "filter spectra");
+  char* sscr = P->alloc<char>((int64_t)spectra_scratch_bytes(logn));
+  hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, sscr, s), "filter spectra");
   hipchk(hipStreamSynchronize(s), "filter setup");
-  P->release(ctab);
+  P->release(sscr);
   fs.ready = true;
 }
 
@@ -245,8 +255,8 @@ void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool 
 // y_out has the element type of fs
 void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, void* y_out, int R,
             hipStream_t s) {
-  hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, fs.spec, fs.tw2,
-                    P->n_t, P->n_c, fs.m, R, s),
+  hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, fs.spec, fs.ptw,
+                    fs.tw2, P->n_t, P->n_c, fs.m, R, s),
          "overlap-save filter");
 }
 
@@ -255,17 +265,13 @@ void apply_H_obs(mm_plan_s* P, const FilterSetup& fs, const double* in, double* 
                  int R, hipStream_t s) {
   hipchk(launch_gather(fs.fp64, P->ns, P->pix_obs, P->w, in, ya, P->n_t, P->n_obs, R, s), "gather");
   weight(P, fs, ya, fs.fp64, yb, R, s);
-  hipchk(launch_scatter(fs.fp64, P->ns, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, yb, out,
-                        P->n_obs, P->n_t, R, s),
-         "scatter");
+  hipchk(launch_scatter(fs.fp64, P->ns, P->sell, yb, out, P->n_obs, P->n_t, R, s), "scatter");
 }
 
 void rhs_obs(mm_plan_s* P, const FilterSetup& fs, const void* tod, bool tod_f64, double* out, void* yb,
              int R, hipStream_t s) {
   weight(P, fs, tod, tod_f64, yb, R, s);
-  hipchk(launch_scatter(fs.fp64, P->ns, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, yb, out,
-                        P->n_obs, P->n_t, R, s),
-         "scatter");
+  hipchk(launch_scatter(fs.fp64, P->ns, P->sell, yb, out, P->n_obs, P->n_t, R, s), "scatter");
 }
 
 void ensure_fp64_path(mm_plan_s* P, hipStream_t s) {
@@ -410,6 +416,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
            "lag upload");
   } else {
     double* dparams = P->alloc<double>(3 * (int64_t)P->n_filt);
+    P->d_params = dparams;
     hipchk(hipMemcpyAsync(dparams, P->params.data(), sizeof(double) * 3 * P->n_filt,
                           hipMemcpyHostToDevice, s),
            "parameter upload");
@@ -420,7 +427,6 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
            "lag construction");
     hipchk(hipStreamSynchronize(s), "lag construction");
     P->release(scr);
-    P->release(dparams);
   }
   P->lags_host.resize((size_t)P->n_filt * P->n_c);
   hipchk(hipMemcpyAsync(P->lags_host.data(), P->lags, sizeof(double) * P->lags_host.size(),
@@ -439,7 +445,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   {
     int32_t* sing = P->alloc<int32_t>(P->n_obs);
     double* cnt = P->alloc<double>(1);
-    hipchk(launch_precond_build(P->ns, P->precond, P->pix_ptr, P->perm, P->w_pm, P->d_iv_start, P->n_iv,
+    hipchk(launch_precond_build(P->ns, P->precond, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, P->d_iv_start, P->n_iv,
                                 P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
            "preconditioner");
     hipchk(launch_count_nonzero(sing, P->n_obs, nullptr, cnt, s), "singular count");
@@ -449,6 +455,42 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
     P->n_singular = (int)hc;
     P->release(sing);
     P->release(cnt);
+  }
+
+  // ---- sliced pointing for the scatter; the plain pixel-major copy is then dropped
+  {
+    const int64_t n_sl = (P->n_obs + 63) / 64;
+    uint32_t* len = P->alloc<uint32_t>(n_sl);
+    uint32_t* end = P->alloc<uint32_t>(n_sl);
+    char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(std::max<int64_t>(n_sl, 1)));
+    uint32_t total = 0;
+    if (n_sl > 0) {
+      hipchk(launch_sell_widths(P->pix_ptr, P->n_obs, len, s), "slice widths");
+      hipchk(launch_scan_inclusive(len, end, n_sl, sscr, s), "slice offsets");
+      hipchk(hipMemcpyAsync(&total, end + (n_sl - 1), 4, hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipStreamSynchronize(s), "slices");
+      // the 32-bit slice sizes and their prefix sum are exact while the padded total
+      // stays below 2^32 - 1 (a saturated size also trips this test)
+      double check = 0;
+      std::vector<uint32_t> hl(n_sl);
+      hipchk(hipMemcpy(hl.data(), len, 4 * n_sl, hipMemcpyDeviceToHost), "copy");
+      for (uint32_t v : hl) check += v;
+      if (check >= 4294967295.0) fail(MM_EUNSUPPORTED, "sliced pointing exceeds 2^32 - 1 entries");
+    }
+    P->release(sscr);
+    P->sell_entries = total;
+    int32_t* st = P->alloc<int32_t>(std::max<int64_t>(total, 1));
+    float* sw = P->ns == 3 ? P->alloc<float>(2 * std::max<int64_t>(total, 1)) : nullptr;
+    hipchk(launch_sell_fill(P->pix_ptr, P->perm, P->w_pm, P->n_obs, end, len, st, sw, P->ns, s), "slice fill");
+    hipchk(hipStreamSynchronize(s), "slices");
+    P->sell.end = end;
+    P->sell.len = len;
+    P->sell.t = st;
+    P->sell.w = sw;
+    P->release(P->perm);
+    P->perm = nullptr;
+    P->release(P->w_pm);
+    P->w_pm = nullptr;
   }
 
   // ---- work buffers
@@ -466,55 +508,48 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->part1 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part2 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part3 = P->alloc<double>((int64_t)P->R * kDotBlocks);
+  P->part_pq = P->alloc<double>((int64_t)P->R * kScatterBlocks);
   P->st = P->alloc<CgState>(P->R);
 }
 
 // queue one PCG iteration for every RHS
 void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   const int R = P->R;
-  apply_H_obs(P, P->fs_main, P->vp, P->vq, P->y1, P->y2, R, s);
-  hipchk(launch_dot(P->vp, P->vq, P->nu(), R, P->part1, s), "dot");
-  hipchk(launch_cg_alpha(P->st, P->part1, R, s), "alpha");
+  // q = H p, with the partial sums of p.q formed by the scatter
+  hipchk(launch_gather(P->fs_main.fp64, P->ns, P->pix_obs, P->w, P->vp, P->y1, P->n_t, P->n_obs, R, s),
+         "gather");
+  weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s);
+  hipchk(launch_scatter(P->fs_main.fp64, P->ns, P->sell, P->y2, P->vq, P->n_obs, P->n_t, R, s, P->vp,
+                        P->part_pq),
+         "scatter");
+  const int n_pq = scatter_blocks(P->n_obs);
   hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, R,
-                          P->part2, P->part3, s),
+                          P->part_pq, n_pq, P->part2, P->part3, s),
          "update");
   hipchk(launch_cg_finalize(P->st, P->part2, P->part3, R, P->hist, P->hist_cap, s), "finalize");
-  hipchk(launch_cg_copy_best(P->vx, P->vxb, P->st, P->nu(), R, s), "copy best");
-  hipchk(launch_cg_update_p(P->vp, P->vz, P->st, P->nu(), R, s), "update p");
+  hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s), "next direction");
 }
 
-void solve_impl(mm_plan_s* P, const void* d_tod, int32_t tod_dtype, double* d_x,
-                const mm_solve_opts_t* o_in, mm_solve_info_t* info, hipStream_t caller,
-                mm_status_t* result) {
-  check_tod_dtype(tod_dtype);
-  mm_solve_opts_t o;
-  mm_solve_opts_default(&o);
-  if (o_in) o = *o_in;
-  if (!d_x) fail(MM_EINVAL, "d_x is NULL");
-  if (!d_tod && P->n_t > 0) fail(MM_EINVAL, "d_tod is NULL");
-  if (o.fixed_iters < 0 || o.max_iter < 0) fail(MM_EINVAL, "iteration counts must be >= 0");
-  if (!(o.tol >= 0)) fail(MM_EINVAL, "tol must be >= 0");
-  if (o.check_every < 1) o.check_every = 1;
-  const bool fixed = o.fixed_iters > 0;
-  const int n_max = fixed ? o.fixed_iters : o.max_iter;
+// per-RHS sums of x.y over [R][nu] vectors (float64, fixed order)
+std::vector<double> dots(mm_plan_s* P, const double* x, const double* y, int R, hipStream_t s) {
+  const int64_t nu = P->nu();
+  std::vector<double> h((size_t)R * kDotBlocks), out(R, 0.0);
+  hipchk(launch_dot(x, y, nu, R, P->part1, s), "dot");
+  hipchk(hipMemcpyAsync(h.data(), P->part1, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s), "copy");
+  hipchk(hipStreamSynchronize(s), "dot");
+  for (int r = 0; r < R; ++r)
+    for (int i = 0; i < kDotBlocks; ++i) out[r] += h[(size_t)r * kDotBlocks + i];
+  return out;
+}
+
+// PCG on H x = vb (observed layout) in the iteration precision of fs_main.
+// vb must hold the right-hand sides; x0 is read from vx when have_x0.  On
+// exit vxb holds the lowest-residual iterate and st_host the final states.
+void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int check_every,
+             bool use_graph, bool have_x0) {
   const int R = P->R;
   const int64_t nu = P->nu();
-  const bool tod64 = tod_dtype == MM_F64;
-  hipStream_t s = P->own;
-
-  // order the plan stream after the caller's work
-  hipchk(hipEventRecord(P->ev_in, caller), "event");
-  hipchk(hipStreamWaitEvent(s, P->ev_in, 0), "event wait");
-
-  if (P->hist_cap < n_max + 1) {
-    if (P->hist) P->release(P->hist);
-    P->hist_cap = n_max + 1;
-    P->hist = P->alloc<double>((int64_t)R * P->hist_cap);
-  }
-
-  rhs_obs(P, P->fs_main, d_tod, tod64, P->vb, P->y2, R, s);
-  if (o.d_x0) {
-    hipchk(launch_to_observed(o.d_x0, P->vx, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "x0");
+  if (have_x0) {
     apply_H_obs(P, P->fs_main, P->vx, P->vq, P->y1, P->y2, R, s);
     hipchk(launch_sub(P->vr, P->vb, P->vq, (int64_t)R * nu, s), "residual");
   } else {
@@ -527,7 +562,7 @@ void solve_impl(mm_plan_s* P, const void* d_tod, int32_t tod_dtype, double* d_x,
   hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
   hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
   hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
-  hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, o.tol, fixed ? 1 : 0, R, P->hist,
+  hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, tol, fixed ? 1 : 0, R, P->hist,
                         P->hist_cap, s),
          "init");
 
@@ -541,10 +576,10 @@ void solve_impl(mm_plan_s* P, const void* d_tod, int32_t tod_dtype, double* d_x,
 
   int done = 0;
   bool finished = all_done();
-  const int k = std::min(o.check_every, std::max(1, n_max));
+  const int k = std::min(check_every, std::max(1, n_max));
   while (!finished && done < n_max) {
     const int step = std::min(k, n_max - done);
-    if (o.use_graph && step == k && k > 0) {
+    if (use_graph && step == k && k > 0) {
       if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
         if (P->graph) {
           hipGraphExecDestroy(P->graph);
@@ -572,61 +607,203 @@ void solve_impl(mm_plan_s* P, const void* d_tod, int32_t tod_dtype, double* d_x,
     done += step;
     finished = all_done();
   }
+}
 
-  hipchk(launch_to_global(P->vxb, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "map output");
+void ensure_refine_vectors(mm_plan_s* P) {
+  if (P->vb64) return;
+  const int64_t vn = (int64_t)P->R * P->nu();
+  P->vb64 = P->alloc<double>(vn);
+  P->vr64 = P->alloc<double>(vn);
+  P->vxacc = P->alloc<double>(vn);
+  P->vxbest = P->alloc<double>(vn);
+}
 
-  std::vector<double> tres(R, std::nan(""));
-  if (o.true_residual && P->n_obs > 0) {
+// out[r] = b64_r - H64 xacc_r in float64 (one RHS at a time through the float64 filter)
+void residual64(mm_plan_s* P, const double* x, double* out, hipStream_t s) {
+  const int64_t nu = P->nu();
+  const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
+  void* ya = P->main_fp64() ? P->y1 : (void*)P->y64a;
+  void* yb = P->main_fp64() ? P->y2 : (void*)P->y64b;
+  for (int r = 0; r < P->R; ++r) {
+    apply_H_obs(P, f64, x + (int64_t)r * nu, P->vq, ya, yb, 1, s);
+    hipchk(launch_sub(out + (int64_t)r * nu, P->vb64 + (int64_t)r * nu, P->vq, nu, s), "residual");
+  }
+}
+
+// Right-hand side of a solve: b = P^T N^-1 d from a TOD, or a map given directly.
+struct RhsSource {
+  const void* tod = nullptr;
+  bool tod64 = false;
+  const double* map = nullptr;   // global layout [R][n_pix][ns]
+};
+
+// b (observed layout) of RHS rows [r0, r0 + nr) with the filter fs into dst
+void make_rhs(mm_plan_s* P, const RhsSource& src, const FilterSetup& fs, int r0, int nr, double* dst,
+              void* yb, hipStream_t s) {
+  if (src.map) {
+    hipchk(launch_to_observed(src.map + (int64_t)r0 * P->n_pix * P->ns, dst, P->obs2glob, P->n_obs, P->n_pix,
+                              P->ns, nr, s),
+           "rhs layout");
+  } else {
+    const int esz = src.tod64 ? 8 : 4;
+    rhs_obs(P, fs, (const char*)src.tod + (size_t)r0 * P->n_t * esz, src.tod64, dst, yb, nr, s);
+  }
+}
+
+void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_opts_t* o_in,
+                mm_solve_info_t* info, hipStream_t caller, mm_status_t* result) {
+  mm_solve_opts_t o;
+  mm_solve_opts_default(&o);
+  if (o_in) o = *o_in;
+  if (!d_x) fail(MM_EINVAL, "d_x is NULL");
+  if (!src.map && !src.tod && P->n_t > 0) fail(MM_EINVAL, "right-hand side is NULL");
+  if (o.fixed_iters < 0 || o.max_iter < 0) fail(MM_EINVAL, "iteration counts must be >= 0");
+  if (!(o.tol >= 0)) fail(MM_EINVAL, "tol must be >= 0");
+  if (o.check_every < 1) o.check_every = 1;
+  const bool fixed = o.fixed_iters > 0;
+  const int n_max = fixed ? o.fixed_iters : o.max_iter;
+  const int R = P->R;
+  const int64_t nu = P->nu();
+  const bool refine = !P->main_fp64() && o.refine && !fixed;
+  hipStream_t s = P->own;
+
+  // order the plan stream after the caller's work
+  hipchk(hipEventRecord(P->ev_in, caller), "event");
+  hipchk(hipStreamWaitEvent(s, P->ev_in, 0), "event wait");
+
+  if (P->hist_cap < n_max + 1) {
+    if (P->hist) P->release(P->hist);
+    P->hist_cap = n_max + 1;
+    P->hist = P->alloc<double>((int64_t)R * P->hist_cap);
+  }
+
+  std::vector<int> iters(R, 0), best_iter(R, 0);
+  std::vector<double> best_rel(R, 0.0), tres(R, std::nan(""));
+  std::vector<double> hist_out((size_t)R * (n_max + 1), std::nan(""));
+  bool notconv = false;
+
+  if (!refine) {
+    make_rhs(P, src, P->fs_main, 0, R, P->vb, P->y2, s);
+    if (o.d_x0) hipchk(launch_to_observed(o.d_x0, P->vx, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "x0");
+    run_pcg(P, s, o.tol, n_max, fixed, o.check_every, o.use_graph != 0, o.d_x0 != nullptr);
+    std::vector<double> hh((size_t)R * P->hist_cap);
+    hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipStreamSynchronize(s), "history");
+    for (int r = 0; r < R; ++r) {
+      const CgState& c = P->st_host[r];
+      iters[r] = c.iter;
+      best_iter[r] = c.best_iter;
+      best_rel[r] = c.best_rel;
+      for (int i = 0; i <= c.iter && i <= n_max; ++i) hist_out[(size_t)r * (n_max + 1) + i] = hh[(size_t)r * P->hist_cap + i];
+      if (!fixed && c.bnorm > 0 && !(c.rel <= o.tol) && !(c.best_rel <= o.tol)) notconv = true;
+    }
+    hipchk(launch_to_global(P->vxb, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "map output");
+  } else {
+    // Mixed precision with float64 residual correction: the float32-operator PCG
+    // solves H d = r64 for a correction, the float64 operator recomputes the true
+    // residual r64 = b64 - H64 x, and the iterate with the lowest true residual is kept.
+    ensure_fp64_path(P, s);
+    ensure_refine_vectors(P);
+    for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
+    if (o.d_x0) {
+      hipchk(launch_to_observed(o.d_x0, P->vxacc, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "x0");
+      residual64(P, P->vxacc, P->vr64, s);
+    } else {
+      hipchk(launch_fill_f64(P->vxacc, 0.0, (int64_t)R * nu, s), "fill");
+      hipchk(hipMemcpyAsync(P->vr64, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    hipchk(hipMemcpyAsync(P->vxbest, P->vxacc, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    const std::vector<double> bb = dots(P, P->vb64, P->vb64, R, s);
+    std::vector<double> rel(R), bn(R);
+    {
+      const std::vector<double> rr = dots(P, P->vr64, P->vr64, R, s);
+      for (int r = 0; r < R; ++r) {
+        bn[r] = std::sqrt(bb[r]);
+        rel[r] = bn[r] > 0 ? std::sqrt(rr[r]) / bn[r] : 0.0;
+        best_rel[r] = rel[r];
+        hist_out[(size_t)r * (n_max + 1)] = rel[r];
+      }
+    }
+    std::vector<double> hh((size_t)R * P->hist_cap);
+    for (int outer = 0; outer < 30; ++outer) {
+      // right-hand sides of the correction equation; RHS already converged get 0
+      double worst = 0.0;
+      bool any = false;
+      for (int r = 0; r < R; ++r) {
+        const bool act = bn[r] > 0 && rel[r] > o.tol && iters[r] < n_max;
+        double* dst = P->vb + (int64_t)r * nu;
+        if (act) {
+          hipchk(hipMemcpyAsync(dst, P->vr64 + (int64_t)r * nu, sizeof(double) * nu, hipMemcpyDeviceToDevice, s), "copy");
+          worst = std::max(worst, rel[r]);
+          any = true;
+        } else {
+          hipchk(launch_fill_f64(dst, 0.0, nu, s), "fill");
+        }
+      }
+      if (!any) break;
+      // inner tolerance: reach the target in this pass if the float32 operator allows,
+      // otherwise gain about five decades
+      const double tau = std::max(o.tol / worst, 1e-5);
+      int budget = 0;
+      for (int r = 0; r < R; ++r) budget = std::max(budget, n_max - iters[r]);
+      run_pcg(P, s, tau, budget, false, o.check_every, o.use_graph != 0, false);
+      hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipStreamSynchronize(s), "history");
+      // x += d (rows of converged RHS add 0)
+      hipchk(launch_axpby(P->vxacc, P->vxb, 1.0, 1.0, (int64_t)R * nu, s), "accumulate");
+      residual64(P, P->vxacc, P->vr64, s);
+      const std::vector<double> rr = dots(P, P->vr64, P->vr64, R, s);
+      for (int r = 0; r < R; ++r) {
+        const CgState& c = P->st_host[r];
+        const double scale = rel[r];
+        for (int i = 1; i <= c.iter && iters[r] + i <= n_max; ++i)
+          hist_out[(size_t)r * (n_max + 1) + iters[r] + i] = scale * hh[(size_t)r * P->hist_cap + i];
+        iters[r] += c.iter;
+        rel[r] = bn[r] > 0 ? std::sqrt(rr[r]) / bn[r] : 0.0;
+        if (iters[r] <= n_max) hist_out[(size_t)r * (n_max + 1) + iters[r]] = rel[r];
+        if (rel[r] < best_rel[r]) {
+          best_rel[r] = rel[r];
+          best_iter[r] = iters[r];
+          hipchk(hipMemcpyAsync(P->vxbest + (int64_t)r * nu, P->vxacc + (int64_t)r * nu, sizeof(double) * nu,
+                                hipMemcpyDeviceToDevice, s), "copy");
+        }
+      }
+    }
+    for (int r = 0; r < R; ++r) {
+      tres[r] = best_rel[r];
+      if (bn[r] > 0 && !(best_rel[r] <= o.tol)) notconv = true;
+    }
+    hipchk(launch_to_global(P->vxbest, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "map output");
+  }
+
+  if (o.true_residual && P->n_obs > 0 && !refine) {
     // ||b - H x|| / ||b|| in float64, one RHS at a time
     if (!P->main_fp64()) ensure_fp64_path(P, s);
     const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
     void* ya = P->main_fp64() ? P->y1 : (void*)P->y64a;
     void* yb = P->main_fp64() ? P->y2 : (void*)P->y64b;
-    const int esz = tod64 ? 8 : 4;
-    std::vector<double> hb(kDotBlocks), hr(kDotBlocks);
     for (int r = 0; r < R; ++r) {
-      const void* tod_r = (const char*)d_tod + (size_t)r * P->n_t * esz;
-      rhs_obs(P, f64, tod_r, tod64, P->vr, yb, 1, s);                       // b (float64)
+      make_rhs(P, src, f64, r, 1, P->vr, yb, s);                            // b (float64)
       apply_H_obs(P, f64, P->vxb + (int64_t)r * nu, P->vq, ya, yb, 1, s);   // H x
       hipchk(launch_sub(P->vz, P->vr, P->vq, nu, s), "residual");
-      hipchk(launch_dot(P->vr, P->vr, nu, 1, P->part1, s), "dot");
-      hipchk(launch_dot(P->vz, P->vz, nu, 1, P->part2, s), "dot");
-      hipchk(hipMemcpyAsync(hb.data(), P->part1, 8 * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
-      hipchk(hipMemcpyAsync(hr.data(), P->part2, 8 * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
-      hipchk(hipStreamSynchronize(s), "true residual");
-      double bb = 0, rr = 0;
-      for (int i = 0; i < kDotBlocks; ++i) {
-        bb += hb[i];
-        rr += hr[i];
-      }
-      tres[r] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      const double b2 = dots(P, P->vr, P->vr, 1, s)[0];
+      const double r2 = dots(P, P->vz, P->vz, 1, s)[0];
+      tres[r] = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
     }
   }
 
-  hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
-  std::vector<double> hh;
-  if (info && info->history) {
-    hh.resize((size_t)R * P->hist_cap);
-    hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
-  }
   hipchk(hipStreamSynchronize(s), "solve end");
   hipchk(hipEventRecord(P->ev_out, s), "event");
   hipchk(hipStreamWaitEvent(caller, P->ev_out, 0), "event wait");
 
-  bool notconv = false;
-  for (int r = 0; r < R; ++r) {
-    const CgState& c = P->st_host[r];
-    if (!fixed && c.bnorm > 0 && !(c.rel <= o.tol) && !(c.best_rel <= o.tol)) notconv = true;
-    if (info) {
-      if (info->iters) info->iters[r] = c.iter;
-      if (info->best_iter) info->best_iter[r] = c.best_iter;
-      if (info->best_rel_res) info->best_rel_res[r] = c.best_rel;
+  if (info) {
+    for (int r = 0; r < R; ++r) {
+      if (info->iters) info->iters[r] = iters[r];
+      if (info->best_iter) info->best_iter[r] = best_iter[r];
+      if (info->best_rel_res) info->best_rel_res[r] = best_rel[r];
       if (info->true_rel_res) info->true_rel_res[r] = tres[r];
-      if (info->history) {
-        for (int i = 0; i <= n_max; ++i)
-          info->history[(size_t)r * (n_max + 1) + i] = i <= c.iter ? hh[(size_t)r * P->hist_cap + i] : std::nan("");
-      }
     }
+    if (info->history) std::memcpy(info->history, hist_out.data(), sizeof(double) * hist_out.size());
   }
   if (P->n_singular > 0) {
     g_last_error = std::to_string(P->n_singular) + " singular preconditioner block(s)";
@@ -650,6 +827,7 @@ void mm_solve_opts_default(mm_solve_opts_t* o) {
   o->use_graph = 1;
   o->true_residual = 0;
   o->d_x0 = nullptr;
+  o->refine = 1;
 }
 
 mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* stream,
@@ -684,6 +862,7 @@ mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
     info->n_f = P->fs_main.nf;
     info->n_chunks = P->fs_main.n_chunks;
     info->n_singular = P->n_singular;
+    info->n_sliced = P->sell_entries;
     info->device_bytes = P->bytes;
   });
 }
@@ -719,9 +898,7 @@ mm_status_t mm_point(mm_plan_t P, const void* d_y, int32_t tod_dtype, double* d_
     if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
-    hipchk(launch_scatter(tod_dtype == MM_F64, P->ns, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, d_y,
-                          P->vq, P->n_obs, P->n_t, P->R, s),
-           "scatter");
+    hipchk(launch_scatter(tod_dtype == MM_F64, P->ns, P->sell, d_y, P->vq, P->n_obs, P->n_t, P->R, s), "scatter");
     hipchk(launch_to_global(P->vq, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
   });
 }
@@ -768,9 +945,80 @@ mm_status_t mm_solve(mm_plan_t P, const void* d_tod, int32_t tod_dtype, double* 
   mm_status_t result = MM_OK;
   const mm_status_t st = guarded([&] {
     if (!P) fail(MM_EINVAL, "plan is NULL");
-    solve_impl(P, d_tod, tod_dtype, d_x, opts, info, as_stream(stream), &result);
+    check_tod_dtype(tod_dtype);
+    RhsSource src;
+    src.tod = d_tod;
+    src.tod64 = tod_dtype == MM_F64;
+    solve_impl(P, src, d_x, opts, info, as_stream(stream), &result);
   });
   return st != MM_OK ? st : result;
+}
+
+mm_status_t mm_solve_rhs(mm_plan_t P, const double* d_b, double* d_x, const mm_solve_opts_t* opts,
+                         mm_solve_info_t* info, void* stream) {
+  mm_status_t result = MM_OK;
+  const mm_status_t st = guarded([&] {
+    if (!P || !d_b) fail(MM_EINVAL, "NULL argument");
+    RhsSource src;
+    src.map = d_b;
+    solve_impl(P, src, d_x, opts, info, as_stream(stream), &result);
+  });
+  return st != MM_OK ? st : result;
+}
+
+mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_u, const void* d_v, int32_t tod_dtype,
+                              double* grad_out, void* stream) {
+  return guarded([&] {
+    if (!P || !grad_out || ((!d_u || !d_v) && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
+    check_tod_dtype(tod_dtype);
+    if (!P->d_params) fail(MM_EUNSUPPORTED, "the plan was built from explicit lags: no noise parameters");
+    hipStream_t s = as_stream(stream);
+    ensure_fp64_path(P, s);
+    const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
+    double* ya = P->main_fp64() ? (double*)P->y1 : P->y64a;   // u_r in float64
+    double* yb = P->main_fp64() ? (double*)P->y2 : P->y64b;   // dN^-1/dtheta v_r
+    const bool in64 = tod_dtype == MM_F64;
+    const int esz = in64 ? 8 : 4;
+    double* dlags = P->alloc<double>((int64_t)P->n_filt * P->n_c);
+    double* dspec = P->alloc<double>((int64_t)P->n_filt * (f64.N + 1));
+    double* ivd = P->alloc<double>(std::max(P->n_iv, 1));
+    const int batch = std::max(1, std::min(P->n_filt, 16));
+    const size_t lsb = lags_scratch_bytes(P->n_c, P->lag_len, batch);
+    char* lscr = P->alloc<char>((int64_t)std::max(lsb, spectra_scratch_bytes(f64.logn)));
+    std::vector<double> hd(std::max(P->n_iv, 1));
+    std::vector<double> grad((size_t)P->R * P->n_filt * 3, 0.0);
+    try {
+      for (int mode = 1; mode <= 3; ++mode) {
+        hipchk(launch_lags(P->d_params, P->n_filt, P->f_samp, P->n_c, P->lag_len, dlags, lscr, lsb, s, mode),
+               "derivative lags");
+        hipchk(launch_spectra(dlags, P->n_filt, P->n_c, f64.logn, true, dspec, lscr, s), "derivative spectra");
+        for (int r = 0; r < P->R; ++r) {
+          const void* u_r = (const char*)d_u + (size_t)r * P->n_t * esz;
+          const void* v_r = (const char*)d_v + (size_t)r * P->n_t * esz;
+          hipchk(launch_ols(true, in64, f64.logn, v_r, yb, f64.chunks, f64.n_chunks, dspec, f64.ptw, f64.tw2,
+                            P->n_t, P->n_c, f64.m, 1, s),
+                 "derivative filter");
+          hipchk(launch_convert(in64, true, u_r, ya, P->n_t, s), "convert");
+          hipchk(launch_interval_dots(ya, yb, P->d_iv_start, P->n_iv, ivd, s), "interval dots");
+          hipchk(hipMemcpyAsync(hd.data(), ivd, sizeof(double) * P->n_iv, hipMemcpyDeviceToHost, s), "copy");
+          hipchk(hipStreamSynchronize(s), "noise gradient");
+          for (int b = 0; b < P->n_iv; ++b)
+            grad[((size_t)r * P->n_filt + P->iv_filter[b]) * 3 + (mode - 1)] += hd[b];
+        }
+      }
+    } catch (...) {
+      P->release(dlags);
+      P->release(dspec);
+      P->release(ivd);
+      P->release(lscr);
+      throw;
+    }
+    P->release(dlags);
+    P->release(dspec);
+    P->release(ivd);
+    P->release(lscr);
+    std::memcpy(grad_out, grad.data(), sizeof(double) * grad.size());
+  });
 }
 
 int32_t mm_fft_length_rule(int32_t n_c, int64_t longest) { return fft_length_rule(n_c, longest); }

@@ -30,34 +30,62 @@ struct CgState {
   int32_t active;    // 1 while the RHS still iterates
   int32_t copy_best; // set when the current iterate became the best
   int32_t fixed;     // 1 = ignore tol
-  int32_t pad;
+  int32_t breakdown; // set when p.q <= 0 (H not positive definite on p)
 };
 
 constexpr int kDotBlocks = 256;     // partial sums per dot product (fixed => deterministic)
 constexpr int kDotThreads = 256;
+constexpr int kScatterBlocks = 2048; // bound on the scatter grid (and its p.q partial sums)
+
+// sum over aligned groups of G lanes (G a power of two <= 64)
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
 
 // ---------------------------------------------------------------- filter (k_filter.hip)
 int ols_max_logn(bool fp64);
 hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s);
+// per-pass twiddle tables of the workgroup transform of 2^logn points
+int pass_twiddle_count(int logn, bool fp64);
+hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s);
+// lags (mode 0) or their derivative with respect to sigma (1), f_knee (2), alpha (3)
 hipError_t launch_lags(const double* params /*dev [nf][3]*/, int n_filters, double f_samp, int n_c,
                        int64_t lag_len, double* lags /*dev [nf][n_c]*/, void* scratch,
-                       size_t scratch_bytes, hipStream_t s);
+                       size_t scratch_bytes, hipStream_t s, int mode = 0);
 size_t lags_scratch_bytes(int n_c, int64_t lag_len, int filters_per_batch);
+// spec[f][k] = F_k / (4N), k = 0..N, the symbol of filter f's circulant of n_f = 2N points
+size_t spectra_scratch_bytes(int logn);
 hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, bool fp64,
-                          void* spec /*[nf][N+1]*/, double* ctab /*scratch, 2N doubles*/,
-                          hipStream_t s);
+                          void* spec /*[nf][N+1]*/, void* scratch, hipStream_t s);
 // y_out[r][t] = (N^-1 y_in)[r][t]; compute type T (fp64 flag); input type in_f64; output type T
 hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* y_out,
-                      const OlsChunk* chunks, int n_chunks, const void* spec, const void* tw2,
-                      int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s);
+                      const OlsChunk* chunks, int n_chunks, const void* spec, const void* ptw,
+                      const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s);
 
 // ---------------------------------------------------------------- pointing (k_pointing.hip)
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
                          hipStream_t s);
-hipError_t launch_scatter(bool in_f64, int ns, int group, const int64_t* pix_ptr,
-                          const int32_t* perm, const float* w_pm, const void* y, double* q,
-                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s);
+// Sliced pixel-major pointing (64 pixels per slice, one lane per pixel)
+struct SellLayout {
+  const uint32_t* end = nullptr;   // [n_slices] inclusive prefix sum of the slice sizes
+  const uint32_t* len = nullptr;   // [n_slices] entries of each slice (64 x its widest pixel)
+  const int32_t* t = nullptr;      // sample index per entry, -1 = padding
+  const float* w = nullptr;        // (sin, cos) per entry (polarisation only)
+};
+hipError_t launch_sell_widths(const int64_t* pix_ptr, int64_t n_obs, uint32_t* slice_len, hipStream_t s);
+hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const float* w_pm, int64_t n_obs,
+                            const uint32_t* slice_end, const uint32_t* slice_len, int32_t* sell_t,
+                            float* sell_w, int ns, hipStream_t s);
+// q = P^T y (observed layout).  When p is given, also pq_part[r][block] =
+// partial sums of p.q over the pixels of each scatter block (scatter_blocks() blocks).
+hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q,
+                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s,
+                          const double* p = nullptr, double* pq_part = nullptr);
+int scatter_blocks(int64_t n_obs);
 hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, int64_t n,
                           hipStream_t s);
 hipError_t launch_to_observed(const double* glob, double* obs, const int32_t* obs2glob,
@@ -94,8 +122,12 @@ hipError_t launch_build_layout(const uint32_t* keys, const int32_t* vals, const 
                                int32_t* obs2glob, int32_t* pix_obs, float* w_pm, int32_t* perm,
                                hipStream_t s);
 
+// out[b] = sum over interval b of u_t v_t (one workgroup per interval, fixed order)
+hipError_t launch_interval_dots(const double* u, const double* v, const int64_t* iv_start, int n_iv,
+                                double* out, hipStream_t s);
+
 // ---------------------------------------------------------------- CG (k_cg.hip)
-hipError_t launch_precond_build(int ns, int kind, const int64_t* pix_ptr, const int32_t* perm,
+hipError_t launch_precond_build(int ns, int kind, int group, const int64_t* pix_ptr, const int32_t* perm,
                                 const float* w_pm, const int64_t* iv_start, int n_iv,
                                 const int32_t* iv_filter, const double* lags, int n_c,
                                 int64_t n_obs, double* minv, int32_t* singular, hipStream_t s);
@@ -106,16 +138,17 @@ hipError_t launch_dot(const double* x, const double* y, int64_t nu, int n_rhs, d
 hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* partial_rr,
                           const double* partial_rz, double tol, int fixed, int n_rhs,
                           double* history, int hist_stride, hipStream_t s);
-hipError_t launch_cg_alpha(CgState* st, const double* partial_pq, int n_rhs, hipStream_t s);
+// x += alpha p, r -= alpha q, z = M r with alpha = rho / (p.q) folded from the
+// n_pq partial sums of p.q; writes the r.z and r.r partial sums
 hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
-                            double* z, const double* minv, const CgState* st, int64_t n_obs,
-                            int n_rhs, double* partial_rz, double* partial_rr, hipStream_t s);
+                            double* z, const double* minv, CgState* st, int64_t n_obs,
+                            int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
+                            double* partial_rr, hipStream_t s);
 hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
                               int n_rhs, double* history, int hist_stride, hipStream_t s);
-hipError_t launch_cg_copy_best(const double* x, double* xbest, const CgState* st, int64_t nu,
-                               int n_rhs, hipStream_t s);
-hipError_t launch_cg_update_p(double* p, const double* z, const CgState* st, int64_t nu,
-                              int n_rhs, hipStream_t s);
+// p = z + beta p (active RHS) and x_best = x (RHS whose iterate became the best)
+hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
+                          const CgState* st, int64_t nu, int n_rhs, hipStream_t s);
 hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
                                 int64_t n_obs, int n_rhs, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);

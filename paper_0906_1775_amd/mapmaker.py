@@ -105,7 +105,7 @@ class MapMaker:
         i = L.MMPlanInfo()
         L.check(self._lib.mm_plan_get_info(self._h, ctypes.byref(i)), self._lib)
         return dict(n_obs=i.n_obs, n_valid=i.n_valid, n_f=i.n_f, n_chunks=i.n_chunks,
-                    n_singular=i.n_singular, device_bytes=i.device_bytes)
+                    n_singular=i.n_singular, device_bytes=i.device_bytes, n_sliced=i.n_sliced)
 
     # ------------------------------------------------------------------ helpers
     def _map_like(self) -> torch.Tensor:
@@ -162,12 +162,8 @@ class MapMaker:
         L.check(self._lib.mm_rhs(self._h, _ptr(tod), dt, _ptr(b), _stream()), self._lib)
         return b
 
-    def solve(self, tod: torch.Tensor, tol: float = 1e-6, max_iter: int = 50, fixed_iters: int = 0,
-              check_every: int = 8, use_graph: bool = True, true_residual: bool = False,
-              x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-              raise_on_notconv: bool = False):
-        """PCG solve; returns (map [n_rhs, n_pix, n_stokes], info dict)."""
-        dt = self._check_tod(tod)
+    def _solve_call(self, fn, rhs_args, tol, max_iter, fixed_iters, check_every, use_graph, true_residual,
+                    x0, out, raise_on_notconv, refine):
         if x0 is not None:
             self._check_map(x0)
         x = out if out is not None else self._map_like()
@@ -177,6 +173,7 @@ class MapMaker:
         o.tol, o.max_iter, o.fixed_iters = float(tol), int(max_iter), int(fixed_iters)
         o.check_every, o.use_graph, o.true_residual = int(check_every), int(bool(use_graph)), int(bool(true_residual))
         o.d_x0 = None if x0 is None else x0.data_ptr()
+        o.refine = int(bool(refine))
         R = self.n_rhs
         n_hist = (fixed_iters if fixed_iters > 0 else max_iter) + 1
         iters = (ctypes.c_int32 * R)()
@@ -190,9 +187,38 @@ class MapMaker:
         inf.best_rel_res = ctypes.cast(best_rel, ctypes.POINTER(ctypes.c_double))
         inf.true_rel_res = ctypes.cast(true_rel, ctypes.POINTER(ctypes.c_double))
         inf.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        st = self._lib.mm_solve(self._h, _ptr(tod), dt, _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())
+        st = fn(self._h, *rhs_args, _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())
         allow = () if raise_on_notconv else (L.MM_ENOTCONV,)
         L.check(st, self._lib, allow=allow)
         info = dict(status=L.STATUS_NAMES[st], iters=list(iters), best_iter=list(best),
                     best_rel_res=list(best_rel), true_rel_res=list(true_rel), history=hist)
         return x, info
+
+    def solve(self, tod: torch.Tensor, tol: float = 1e-6, max_iter: int = 50, fixed_iters: int = 0,
+              check_every: int = 8, use_graph: bool = True, true_residual: bool = False,
+              x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+              raise_on_notconv: bool = False, refine: bool = True):
+        """PCG solve of H m = P^T N^-1 d; returns (map [n_rhs, n_pix, n_stokes], info dict)."""
+        dt = self._check_tod(tod)
+        return self._solve_call(self._lib.mm_solve, (_ptr(tod), dt), tol, max_iter, fixed_iters, check_every,
+                                use_graph, true_residual, x0, out, raise_on_notconv, refine)
+
+    def solve_rhs(self, b: torch.Tensor, tol: float = 1e-6, max_iter: int = 50, fixed_iters: int = 0,
+                  check_every: int = 8, use_graph: bool = True, true_residual: bool = False,
+                  x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                  raise_on_notconv: bool = False, refine: bool = True):
+        """PCG solve of H x = b for a map right-hand side b [n_rhs, n_pix, n_stokes]."""
+        self._check_map(b)
+        return self._solve_call(self._lib.mm_solve_rhs, (_ptr(b),), tol, max_iter, fixed_iters, check_every,
+                                use_graph, true_residual, x0, out, raise_on_notconv, refine)
+
+    def noise_gradient(self, u: torch.Tensor, v: torch.Tensor) -> np.ndarray:
+        """u^T (dN^-1/dtheta) v per RHS and filter: float64 array [n_rhs, n_filters, 3]."""
+        du = self._check_tod(u)
+        dv = self._check_tod(v)
+        if du != dv:
+            raise TypeError("u and v must have the same dtype")
+        out = np.zeros((self.n_rhs, self.n_filters, 3))
+        L.check(self._lib.mm_noise_gradient(self._h, _ptr(u), _ptr(v), du,
+                                            out.ctypes.data_as(ctypes.c_void_p), _stream()), self._lib)
+        return out

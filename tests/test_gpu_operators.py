@@ -111,9 +111,10 @@ def test_weight_fp64(which, n_f, T, TQU):
 
 
 @pytest.mark.parametrize("which", ["T", "TQU"])
-def test_weight_mixed(which, T, TQU):
+@pytest.mark.parametrize("n_f", [0, 2048, 1 << 16])
+def test_weight_mixed(which, n_f, T, TQU):
     p, o = T if which == "T" else TQU
-    mm = plan_for(p, precision="mixed", lag_dft_len=L_K)
+    mm = plan_for(p, precision="mixed", lag_dft_len=L_K, n_f=n_f)
     y = np.random.default_rng(9).standard_normal((1, p.n_samples)).astype(np.float32)
     out = mm.weight(torch.from_numpy(y).cuda()).cpu().numpy()
     ref = o.apply_ninv(y[0].astype(np.float64))
