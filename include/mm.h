@@ -82,8 +82,11 @@ typedef struct {
   double f_samp;                /* sampling frequency in Hz (used with filter_params) */
   int32_t n_c;                  /* correlation length: f(tau) = 0 for tau >= n_c; >= 1 */
   int32_t n_f;                  /* overlap-save FFT length: 0 = library default (the
-                                   paper's rule capped at the largest on-chip length),
-                                   > 0 = forced power of two with n_f > 2 n_c */
+                                   paper's rule capped at 2^14, or the smallest power of
+                                   two above 2 n_c when that is longer), -1 = autotune
+                                   (time every on-chip length on the plan's intervals
+                                   and keep the fastest), > 0 = forced power of two with
+                                   n_f > 2 n_c */
   int32_t lag_dft_len;          /* L_K, frequencies on which 1/p is sampled to build f
                                    from filter_params; 0 = 2^20; power of two >= 4 n_c */
   int32_t precision;            /* MM_FP64 or MM_MIXED */

@@ -141,3 +141,15 @@ def white_weights(iv_start: np.ndarray, iv_filter: np.ndarray, lag_tab: np.ndarr
     for b in range(iv_filter.shape[0]):
         out[int(iv_start[b]):int(iv_start[b + 1])] = lag_tab[int(iv_filter[b]), 0]
     return out
+
+
+def apply_ninv_at(y_window, t: int, a: int, e: int, f: np.ndarray) -> float:
+    """(N^-1 y)_t by the definition, for one sample t of the interval [a, e).
+
+    ``y_window(lo, hi)`` returns y[lo:hi] (float64); only samples with
+    |t' - t| < n_c inside the interval contribute, with weight f(|t' - t|).
+    """
+    n_c = f.shape[0]
+    lo, hi = max(a, t - n_c + 1), min(e, t + n_c)
+    ys = np.asarray(y_window(lo, hi), dtype=np.float64)
+    return float(np.dot(f[np.abs(np.arange(lo, hi) - t)], ys))

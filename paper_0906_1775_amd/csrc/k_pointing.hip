@@ -8,8 +8,8 @@
 // Gather streams the time-ordered pointing (observed pixel id, sin/cos pair)
 // coalesced and reads the map through the caches.  Scatter walks a sliced,
 // pixel-major copy of the pointing built by the plan: one lane (of each of
-// four wavefronts) owns one pixel, so every pixel sum is formed in a fixed
-// order and no atomics are needed.  The scatter can also return
+// the slice's wavefronts) owns one pixel, so every pixel sum is formed in a
+// fixed order and no atomics are needed.  The scatter can also return
 // the per-block partial sums of p.q for the CG step length.  Maps are float64
 // [R][n_obs][ns].
 #include <algorithm>
@@ -18,26 +18,46 @@
 
 namespace mm {
 
+// Each block covers kGatherUnroll x 256 consecutive samples; a thread takes
+// samples tid, tid + 256, ... of its block, issuing all pointing loads, then
+// all map loads, before any store, so several independent chains are in
+// flight while every load instruction stays coalesced across the wavefront.
+constexpr int kGatherUnroll = 4;
+
 template <typename Ty, int NS>
-__global__ void k_gather(const int32_t* __restrict__ pix_obs, const float2* __restrict__ w,
-                         const double* __restrict__ p, Ty* __restrict__ y, int64_t n_t,
-                         int64_t n_obs, int n_rhs) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += stride) {
-    const int32_t o = pix_obs[t];
-    if (NS == 1) {
-      for (int r = 0; r < n_rhs; ++r)
-        y[(int64_t)r * n_t + t] = o >= 0 ? (Ty)p[(int64_t)r * n_obs + o] : (Ty)0;
-    } else {
-      const float2 sc = w[t];
-      const double s = sc.x, c = sc.y;
-      for (int r = 0; r < n_rhs; ++r) {
-        double v = 0.0;
-        if (o >= 0) {
-          const double* m = p + ((int64_t)r * n_obs + o) * 3;
-          v = 0.5 * (m[0] + s * m[1] + c * m[2]);
+__global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
+                                                const float2* __restrict__ w,
+                                                const double* __restrict__ p, Ty* __restrict__ y,
+                                                int64_t n_t, int64_t n_obs, int n_rhs) {
+  constexpr int U = kGatherUnroll;
+  const int64_t step = (int64_t)gridDim.x * 256 * U;
+  for (int64_t t0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; t0 < n_t; t0 += step) {
+    int32_t o[U];
+    float2 sc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t t = t0 + u * 256;
+      o[u] = t < n_t ? pix_obs[t] : -1;
+      if (NS == 3) sc[u] = t < n_t ? w[t] : make_float2(0.f, 0.f);
+    }
+    for (int r = 0; r < n_rhs; ++r) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = 0.0;
+        if (o[u] >= 0) {
+          if (NS == 1) {
+            v[u] = p[(int64_t)r * n_obs + o[u]];
+          } else {
+            const double* m = p + ((int64_t)r * n_obs + o[u]) * 3;
+            v[u] = 0.5 * (m[0] + (double)sc[u].x * m[1] + (double)sc[u].y * m[2]);
+          }
         }
-        y[(int64_t)r * n_t + t] = (Ty)v;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = t0 + u * 256;
+        if (t < n_t) y[(int64_t)r * n_t + t] = (Ty)v[u];
       }
     }
   }
@@ -47,7 +67,7 @@ hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const flo
                          const double* p, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
                          hipStream_t s) {
   if (n_t == 0) return hipSuccess;
-  int64_t nb = (n_t + 255) / 256;
+  int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
   if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
@@ -85,9 +105,9 @@ template <> struct Acc<float> {
 
 // Sliced layout of the pixel-major pointing: slice s holds the 64 observed
 // pixels 64s .. 64s+63; entry (j, L) at sell_off[s] + 64 j + L is the j-th
-// sample (in time order) of pixel 64s + L, or -1 past that pixel's hits.  One
-// wavefront walks one slice with one lane per pixel, so each step reads 64
-// consecutive entries and, for a raster scan, neighbouring TOD samples.
+// sample (in time order) of pixel 64s + L, or -1 past that pixel's hits.  A
+// wavefront reads 64 consecutive entries per step, one per pixel, which for a
+// raster scan are neighbouring TOD samples.
 __global__ void k_sell_widths(const int64_t* __restrict__ pix_ptr, int64_t n_obs,
                               uint32_t* __restrict__ slice_len) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,19 +158,24 @@ hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const f
   return hipGetLastError();
 }
 
-// q = P^T y over the sliced layout.  A block of four wavefronts owns one slice
-// at a time: wavefront w adds the entries j = w, w + 4, ... of its lane's pixel,
-// and the four partial sums are combined in that fixed order through LDS.
-// Grid-stride over slices with a bounded grid (kScatterBlocks), so the
-// optional p.q partial sums form a short, fixed list.
+// q = P^T y over the sliced layout.  A block of kSliceWaves wavefronts owns one
+// slice at a time: wavefront w adds the entries j = w, w + W, w + 2W, ... of
+// its lane's pixel (W = kSliceWaves), fetching kBatch entries ahead so that
+// their loads overlap, and the W partial sums are combined in wavefront order
+// through LDS.  Grid-stride over slices with a bounded grid (kScatterBlocks),
+// so the optional p.q partial sums form a short, fixed list.
+constexpr int kSliceWaves = 8;
+constexpr int kBatch = 4;
+
 template <typename Ty, int NS>
-__global__ __launch_bounds__(256) void k_scatter(
+__global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
     double* __restrict__ q, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
     double* __restrict__ pq_part) {
-  __shared__ double part[4][NS][64];
-  __shared__ double sh[4];
+  constexpr int W = kSliceWaves;
+  __shared__ double part[W][NS][64];
+  __shared__ double sh[W];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int64_t n_sl = (n_obs + 63) / 64;
@@ -161,20 +186,29 @@ __global__ __launch_bounds__(256) void k_scatter(
       const int64_t base = (int64_t)slice_end[s] - slice_len[s] + lane;
       const int width = (int)(slice_len[s] >> 6);
       Acc<Ty> a0, a1, a2;
-#pragma unroll 2
-      for (int j = wv; j < width; j += 4) {
-        const int64_t e = base + (int64_t)j * 64;
-        const int32_t t = sell_t[e];
-        if (t >= 0) {
-          const Ty v = yr[t];
+      for (int j0 = wv; j0 < width; j0 += W * kBatch) {
+        int32_t tt[kBatch];
+        float2 ww[kBatch];
+        Ty vv[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int j = j0 + b * W;
+          const int64_t e = base + (int64_t)j * 64;
+          tt[b] = j < width ? sell_t[e] : -1;
+          if (NS == 3) ww[b] = j < width ? sell_w[e] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) vv[b] = tt[b] >= 0 ? yr[tt[b]] : (Ty)0;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          if (tt[b] < 0) continue;
           if (NS == 1) {
-            a0.add(v);
+            a0.add(vv[b]);
           } else {
-            const float2 sc = sell_w[e];
-            const Ty h = (Ty)0.5 * v;
+            const Ty h = (Ty)0.5 * vv[b];
             a0.add(h);
-            a1.add(h * (Ty)sc.x);
-            a2.add(h * (Ty)sc.y);
+            a1.add(h * (Ty)ww[b].x);
+            a2.add(h * (Ty)ww[b].y);
           }
         }
       }
@@ -187,13 +221,13 @@ __global__ __launch_bounds__(256) void k_scatter(
       const int64_t o = s * 64 + lane;
       if (wv == 0 && o < n_obs) {
         const int64_t i = ((int64_t)r * n_obs + o) * NS;
-        double v[NS];
-#pragma unroll
-        for (int c = 0; c < NS; ++c) v[c] = ((part[0][c][lane] + part[1][c][lane]) + part[2][c][lane]) + part[3][c][lane];
 #pragma unroll
         for (int c = 0; c < NS; ++c) {
-          q[i + c] = v[c];
-          if (p) pq += p[i + c] * v[c];
+          double v = part[0][c][lane];
+#pragma unroll
+          for (int w = 1; w < W; ++w) v += part[w][c][lane];
+          q[i + c] = v;
+          if (p) pq += p[i + c] * v;
         }
       }
       __syncthreads();
@@ -205,7 +239,7 @@ __global__ __launch_bounds__(256) void k_scatter(
       __syncthreads();
       if (tid == 0) {
         double sum = 0.0;
-        for (int w = 0; w < 4; ++w) sum += sh[w];
+        for (int w = 0; w < W; ++w) sum += sh[w];
         pq_part[(int64_t)r * gridDim.x + blockIdx.x] = sum;
       }
       __syncthreads();
@@ -222,7 +256,7 @@ hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* 
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
                           double* pq_part) {
   if (n_obs == 0) return hipSuccess;
-  const dim3 g((unsigned)scatter_blocks(n_obs)), b(256);
+  const dim3 g((unsigned)scatter_blocks(n_obs)), b(64 * kSliceWaves);
   const float2* w = (const float2*)L.w;
   if (in_f64) {
     if (ns == 1) hipLaunchKernelGGL((k_scatter<double, 1>), g, b, 0, s, L.end, L.len, L.t, w, (const double*)y, q, n_obs, n_t, n_rhs, p, pq_part);

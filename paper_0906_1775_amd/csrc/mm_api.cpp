@@ -125,6 +125,7 @@ struct mm_plan_s {
   int scatter_group = 8;          // lanes per pixel in the plan-time preconditioner build
   SellLayout sell;                // sliced pointing of the scatter
   int64_t sell_entries = 0;
+  std::vector<std::pair<int, float>> tuned;   // (n_f, ms per filter pass) tried by the autotuner
 
   // noise
   double* lags = nullptr;
@@ -140,7 +141,7 @@ struct mm_plan_s {
   // work
   void* y1 = nullptr;            // [R][n_t] of the iteration precision
   void* y2 = nullptr;
-  double* y64a = nullptr;        // [n_t] float64 (true residual in mixed mode)
+  double* y64a = nullptr;        // [n_t] float64 views of y1 / y2 (true residual in mixed mode)
   double* y64b = nullptr;
   double *vx = nullptr, *vp = nullptr, *vr = nullptr, *vz = nullptr, *vq = nullptr,
          *vxb = nullptr, *vb = nullptr;   // [R][n_obs][ns]
@@ -195,8 +196,72 @@ namespace {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s);
+
+void release_filter(mm_plan_s* P, FilterSetup& fs) {
+  P->release(fs.chunks);
+  P->release(fs.tw2);
+  P->release(fs.ptw);
+  P->release(fs.spec);
+  fs = FilterSetup();
+}
+
+// Autotuner: build every admissible on-chip transform length and keep the one
+// whose overlap-save pass over the plan's own intervals runs fastest.
+void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
+  const int maxlog = ols_max_logn(fp64);
+  int64_t longest = 1;
+  for (int b = 0; b < P->n_iv; ++b) longest = std::max<int64_t>(longest, P->iv_start[b + 1] - P->iv_start[b]);
+  int64_t nf = 1;
+  while (nf <= 2 * (int64_t)P->n_c) nf <<= 1;
+  nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
+  if (ilog2(nf) - 1 > maxlog) fail(MM_EUNSUPPORTED, "n_c too large for the on-chip transforms");
+  hipEvent_t e0, e1;
+  hipchk(hipEventCreate(&e0), "event");
+  hipchk(hipEventCreate(&e1), "event");
+  const int esz = fp64 ? 8 : 4;
+  void* ya = P->alloc<char>(std::max<int64_t>(P->n_t, 1) * esz);
+  void* yb = P->alloc<char>(std::max<int64_t>(P->n_t, 1) * esz);
+  hipchk(hipMemsetAsync(ya, 0, std::max<int64_t>(P->n_t, 1) * esz, s), "memset");
+  float best_ms = 0;
+  P->tuned.clear();
+  for (; ilog2(nf) - 1 <= maxlog; nf <<= 1) {
+    FilterSetup cand;
+    build_filter_nf(P, cand, fp64, nf, s);
+    hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw, cand.tw2,
+                      P->n_t, P->n_c, cand.m, 1, s),
+           "autotune warm-up");
+    hipchk(hipEventRecord(e0, s), "event");
+    for (int rep = 0; rep < 3; ++rep)
+      hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw,
+                        cand.tw2, P->n_t, P->n_c, cand.m, 1, s),
+             "autotune");
+    hipchk(hipEventRecord(e1, s), "event");
+    hipchk(hipEventSynchronize(e1), "autotune");
+    float ms = 0;
+    hipchk(hipEventElapsedTime(&ms, e0, e1), "event time");
+    P->tuned.push_back({(int)nf, ms / 3.0f});
+    if (!fs.ready || ms < best_ms) {
+      if (fs.ready) release_filter(P, fs);
+      fs = cand;
+      best_ms = ms;
+    } else {
+      release_filter(P, cand);
+    }
+    if ((nf >> 1) >= 2 * longest) break;   // longer transforms only add padding
+  }
+  P->release(ya);
+  P->release(yb);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+}
+
 void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
   const int maxlog = ols_max_logn(fp64);
+  if (P->nf_req < 0 && !secondary) {
+    autotune_filter(P, fs, fp64, s);
+    return;
+  }
   int64_t nf;
   if (P->nf_req > 0 && !(secondary && ilog2(P->nf_req) - 1 > maxlog)) {
     nf = P->nf_req;
@@ -212,6 +277,11 @@ void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool 
     }
     nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
   }
+  build_filter_nf(P, fs, fp64, nf, s);
+}
+
+void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s) {
+  const int maxlog = ols_max_logn(fp64);
   const int logn = ilog2(nf) - 1;
   if (logn > maxlog)
     fail(MM_EUNSUPPORTED, "FFT length " + std::to_string(nf) + " exceeds the on-chip transform limit " +
@@ -277,10 +347,10 @@ void rhs_obs(mm_plan_s* P, const FilterSetup& fs, const void* tod, bool tod_f64,
 void ensure_fp64_path(mm_plan_s* P, hipStream_t s) {
   if (P->main_fp64()) return;
   if (!P->fs64.ready) build_filter(P, P->fs64, true, s, true);
-  if (!P->y64a) {
-    P->y64a = P->alloc<double>(P->n_t);
-    P->y64b = P->alloc<double>(P->n_t);
-  }
+  // the float64 residual pass never overlaps the float32 iteration: it reuses
+  // the TOD work buffers, which mixed plans size for one float64 row
+  P->y64a = (double*)P->y1;
+  P->y64b = (double*)P->y2;
 }
 
 void check_tod_dtype(int32_t dt) {
@@ -302,8 +372,8 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   if (d->n_rhs < 1 || d->n_rhs > 64) fail(MM_EINVAL, "n_rhs must be in [1, 64]");
   if (d->n_samples > 0 && !d_pix) fail(MM_EINVAL, "d_pix is NULL");
   if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
-  if (d->n_f != 0 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
-    fail(MM_EINVAL, "n_f must be 0 or a power of two above 2 n_c");
+  if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
+    fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
 
   P->ns = d->n_stokes;
   P->n_pix = d->n_pix;
@@ -494,9 +564,9 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   }
 
   // ---- work buffers
-  const int tsz = P->main_fp64() ? 8 : 4;
-  P->y1 = P->alloc<char>((int64_t)P->R * n * tsz);
-  P->y2 = P->alloc<char>((int64_t)P->R * n * tsz);
+  const int64_t ybytes = P->main_fp64() ? (int64_t)P->R * n * 8 : std::max<int64_t>((int64_t)P->R * 4, 8) * n;
+  P->y1 = P->alloc<char>(ybytes);
+  P->y2 = P->alloc<char>(ybytes);
   const int64_t vn = (int64_t)P->R * P->nu();
   P->vx = P->alloc<double>(vn);
   P->vp = P->alloc<double>(vn);

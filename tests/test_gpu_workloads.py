@@ -1,0 +1,187 @@
+"""The two large workloads, generated on the device, against the oracle.
+
+* Batched uneven intervals: 64 detectors x 2^22 samples (2^28), intervals
+  log-uniform in [2^14, 2^21], 2^20 TQU pixels, per-detector noise.
+* Large batch: 256 detectors x 2^22 samples (2^30), intervals log-uniform in
+  [2^16, 2^22], 12 x 2048^2 TQU pixels, 8 noise realisations.
+
+Slices of each recipe (a few detectors) are small enough for the oracle's
+full operators and PCG: hits bit-exact, H x and b element by element, and a
+fixed-iteration solve.  At full size the oracle evaluates (H x)_p and b_p at a
+few pixels sample by sample from the definitions (outputs it can compute one
+by one), hits at those pixels are counted exactly, and the converged maps'
+residual H m - b at those pixels is checked against the oracle's H and b.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import max_rel, sampled_AtNinv
+from oracle import Oracle
+from oracle import noise as onoise
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-5}
+
+
+def _gen(name, **kw):
+    from synth.gpu import make_device_problem
+    print(f"generating {name} {kw}", flush=True)
+    p = make_device_problem(name, device="cuda:0", **kw)
+    torch.cuda.empty_cache()          # the plan allocates outside torch's cache
+    return p
+
+
+def _plan(p, precision, n_f=0):
+    from paper_0906_1775_amd import MapMaker
+    return MapMaker(p.pix, p.w, p.n_pix, 3, p.iv_start, p.iv_filter, filter_params=p.filter_params,
+                    f_samp=p.f_samp, n_c=p.n_c, n_f=n_f, precision=precision, n_rhs=p.n_rhs)
+
+
+def _host_oracle(p):
+    return Oracle(p.pix.cpu().numpy(), p.w.cpu().numpy(), p.n_pix, 3, p.iv_start, p.iv_filter,
+                  p.filter_params, p.f_samp, p.n_c)
+
+
+def _random_map(n_rhs, n_pix, seed):
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    return torch.randn((n_rhs, n_pix, 3), generator=g, device="cuda:0", dtype=torch.float64)
+
+
+# ---------------------------------------------------------------- slices
+
+SLICES = {
+    "c3": dict(n_det=2, det_len=1 << 20),
+    "c5": dict(n_det=8, det_len=1 << 20, n_rhs=2),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(SLICES))
+def slice_case(request):
+    p = _gen(request.param, **SLICES[request.param])
+    o = _host_oracle(p)
+    assert o.n_obs > 1000
+    tod = p.tod.double().cpu().numpy()
+    b = np.stack([o.rhs(tod[r]) for r in range(p.n_rhs)])
+    x = _random_map(p.n_rhs, p.n_pix, 11)
+    xo = np.stack([o.to_observed(x[r].cpu().numpy()) for r in range(p.n_rhs)])
+    hx = np.stack([o.to_global(o.apply_H(xo[r])) for r in range(p.n_rhs)])
+    fixed = [o.to_global(o.pcg(b[r], fixed_iters=5)[0]) for r in range(p.n_rhs)]
+    return request.param, p, o, dict(b=b, x=x, hx=hx, fixed=fixed)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_slice_operators_and_fixed_iterations(slice_case, precision):
+    name, p, o, ref = slice_case
+    print(f"{name} slice, {precision}", flush=True)
+    mm = _plan(p, precision)
+    assert np.array_equal(mm.hits().cpu().numpy(), o.hits.astype(np.int32))
+    tol = TOL[precision]
+    hx = mm.apply_A(ref["x"]).cpu().numpy()
+    assert max_rel(hx, ref["hx"]) <= tol
+    b = mm.rhs(p.tod).cpu().numpy()
+    for r in range(p.n_rhs):
+        assert max_rel(b[r], o.to_global(ref["b"][r])) <= tol
+    m, info = mm.solve(p.tod, fixed_iters=5, refine=False)
+    m = m.cpu().numpy()
+    for r in range(p.n_rhs):
+        assert max_rel(m[r], ref["fixed"][r]) <= (1e-10 if precision == "fp64" else 1e-4)
+
+
+# ---------------------------------------------------------------- full size
+
+def _pick_pixels(p, k, seed):
+    """k distinct observed pixels chosen at seeded sample positions."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < k:
+        t = int(rng.integers(0, p.n_samples))
+        q = int(p.pix[t].item())
+        if q >= 0 and q not in out:
+            out.append(q)
+    return np.asarray(sorted(out), dtype=np.int64)
+
+
+def _fetch(p):
+    def f(lo, hi):
+        return p.pix[lo:hi].cpu().numpy(), p.w[lo:hi].cpu().numpy()
+    return f
+
+
+def _hit_samples(p, pixels):
+    sel = torch.isin(p.pix, torch.from_numpy(pixels.astype(np.int32)).to(p.pix.device))
+    return torch.nonzero(sel).flatten().cpu().numpy()
+
+
+def _check_full(p, precision, n_f=0):
+    lag_tab = onoise.lag_table(p.filter_params, p.f_samp, p.n_c)
+    pixels = _pick_pixels(p, 4, 5)
+    ts = _hit_samples(p, pixels)
+    mm = _plan(p, precision, n_f=n_f)
+    print(f"{p.name} full: plan {mm.info()}", flush=True)
+    h = mm.hits()[torch.from_numpy(pixels).cuda()].cpu().numpy()
+    assert np.array_equal(h, np.array([np.count_nonzero(p.pix[ts].cpu().numpy() == q) for q in pixels]))
+    rs = sorted({0, p.n_rhs - 1})
+    x = _random_map(p.n_rhs, p.n_pix, 13)
+    hx = mm.apply_A(x)
+    tol = TOL[precision]
+    for r in rs:
+        xr = x[r]
+        ref = sampled_AtNinv(_fetch(p), ts, 3, p.iv_start, p.iv_filter, lag_tab, p.n_c,
+                             lambda lo, hi, pix, rows: np.sum(
+                                 rows * xr[torch.from_numpy(np.maximum(pix, 0)).cuda()].cpu().numpy(), axis=1))
+        got = hx[r, torch.from_numpy(pixels).cuda()].cpu().numpy()
+        want = np.stack([ref[int(q)] for q in pixels])
+        print(f"  H x rhs {r}: max rel {max_rel(got, want):.3e}", flush=True)
+        assert max_rel(got, want) <= tol
+    del x, hx
+    torch.cuda.empty_cache()
+    # converged maps: oracle residual (H m - b) at the chosen pixels
+    m, info = mm.solve(p.tod, tol=1e-8, max_iter=300)
+    print(f"  solve {info['status']} iters {info['iters']} best {info['best_rel_res']}", flush=True)
+    assert info["status"] == "MM_OK"
+    for r in rs:
+        mr = m[r]
+        hm = sampled_AtNinv(_fetch(p), ts, 3, p.iv_start, p.iv_filter, lag_tab, p.n_c,
+                            lambda lo, hi, pix, rows: np.sum(
+                                rows * mr[torch.from_numpy(np.maximum(pix, 0)).cuda()].cpu().numpy(), axis=1))
+        tod_r = p.tod[r]
+        bb = sampled_AtNinv(_fetch(p), ts, 3, p.iv_start, p.iv_filter, lag_tab, p.n_c,
+                            lambda lo, hi, pix, rows: tod_r[lo:hi].double().cpu().numpy())
+        res = np.stack([hm[int(q)] - bb[int(q)] for q in pixels])
+        bs = np.stack([bb[int(q)] for q in pixels])
+        print(f"  residual at sampled pixels rhs {r}: {np.abs(res).max() / np.abs(bs).max():.3e}", flush=True)
+        assert np.abs(res).max() <= 1e-6 * np.abs(bs).max()
+    mm.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_uneven_full_size_sampled(precision):
+    p = _gen("c3")
+    assert p.n_samples == 1 << 28
+    _check_full(p, precision)
+
+
+def test_large_batch_full_size_sampled():
+    p = _gen("c5")
+    assert p.n_samples == 1 << 30 and p.n_rhs == 8
+    _check_full(p, "mixed")
+
+
+# ---------------------------------------------------------------- autotuner
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotuned_transform_length(precision):
+    """n_f = -1 times every admissible length; operators match the oracle whatever it picks."""
+    p = _gen("c3", n_det=2, det_len=1 << 18)
+    o = _host_oracle(p)
+    mm = _plan(p, precision, n_f=-1)
+    nf = mm.info()["n_f"]
+    assert nf & (nf - 1) == 0 and nf > 2 * p.n_c
+    x = _random_map(1, p.n_pix, 17)
+    hx = mm.apply_A(x).cpu().numpy()[0]
+    want = o.to_global(o.apply_H(o.to_observed(x[0].cpu().numpy())))
+    assert max_rel(hx, want) <= TOL[precision]
