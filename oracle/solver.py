@@ -13,6 +13,10 @@ Implementation section:
     (defaults 50 and 1e-6), returning the iterate with the lowest relative
     residual seen so far.
 
+With templates ("Using MADmap" section, eq. PmatExt) the pointing matrix is
+[A B] and the unknowns are [z; y]: the observed map followed by the template
+amplitudes (``templates.py``).
+
 The iteration is the textbook preconditioned conjugate gradient method the
 paper cites (Barrett et al.; Shewchuk), in its usual order.  Relative
 residual = ||r_k||_2 / ||b||_2 with r_k the recurrence residual.
@@ -27,6 +31,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import noise, pointing
+from . import templates as tmpl
 
 
 @dataclasses.dataclass
@@ -42,7 +47,7 @@ class Oracle:
     """Plain FP64 statement of the map-making operators for one workload."""
 
     def __init__(self, pix, w, n_pix, n_stokes, iv_start, iv_filter, filter_params=None,
-                 f_samp=None, n_c=None, lag_tab=None, L_K: int = noise.L_K_DEFAULT):
+                 f_samp=None, n_c=None, lag_tab=None, L_K: int = noise.L_K_DEFAULT, templates=None):
         self.n_pix = int(n_pix)
         self.n_stokes = int(n_stokes)
         self.n_t = int(pix.shape[0])
@@ -62,7 +67,15 @@ class Oracle:
         self.hits = pointing.hits(self.pix, self.n_pix)
         self.obs2glob = np.flatnonzero(self.hits > 0)
         self.n_obs = int(self.obs2glob.shape[0])
-        self.A = pointing.pointing_matrix(self.pix, self.w, self.n_pix, self.n_stokes, self.obs2glob)
+        self.A_sky = pointing.pointing_matrix(self.pix, self.w, self.n_pix, self.n_stokes, self.obs2glob)
+        self.templates = list(templates) if templates else []
+        self.n_tmpl = tmpl.total_columns(self.templates)
+        if self.templates:
+            self.B = tmpl.template_matrix(self.templates, self.n_t)
+            self.A = sp.hstack([self.A_sky, self.B]).tocsr()
+        else:
+            self.B = None
+            self.A = self.A_sky
         self.At = self.A.T.tocsr()
 
     @classmethod
@@ -73,6 +86,10 @@ class Oracle:
     # ---- operators -------------------------------------------------------
     @property
     def n_unknowns(self) -> int:
+        return self.n_obs * self.n_stokes + self.n_tmpl
+
+    @property
+    def n_map(self) -> int:
         return self.n_obs * self.n_stokes
 
     def apply_A(self, x: np.ndarray) -> np.ndarray:
@@ -96,13 +113,22 @@ class Oracle:
 
     # ---- layouts ---------------------------------------------------------
     def to_global(self, x: np.ndarray) -> np.ndarray:
-        """Observed-layout unknowns -> [n_pix, n_stokes] map with zeros elsewhere."""
+        """Observed-layout unknowns -> [n_pix, n_stokes] map with zeros elsewhere
+        (the map part only; ``amplitudes`` returns the template part)."""
         out = np.zeros((self.n_pix, self.n_stokes))
-        out[self.obs2glob] = np.asarray(x).reshape(self.n_obs, self.n_stokes)
+        out[self.obs2glob] = np.asarray(x)[:self.n_map].reshape(self.n_obs, self.n_stokes)
         return out
 
-    def to_observed(self, m: np.ndarray) -> np.ndarray:
-        return np.asarray(m, dtype=np.float64).reshape(self.n_pix, self.n_stokes)[self.obs2glob].ravel()
+    def amplitudes(self, x: np.ndarray) -> np.ndarray:
+        """The template amplitudes of an unknown vector (all templates, in order)."""
+        return np.asarray(x)[self.n_map:]
+
+    def to_observed(self, m: np.ndarray, amps=None) -> np.ndarray:
+        xm = np.asarray(m, dtype=np.float64).reshape(self.n_pix, self.n_stokes)[self.obs2glob].ravel()
+        if self.n_tmpl == 0:
+            return xm
+        a = np.zeros(self.n_tmpl) if amps is None else np.asarray(amps, dtype=np.float64).ravel()
+        return np.concatenate([xm, a])
 
     # ---- preconditioners -------------------------------------------------
     def precond_blocks(self) -> np.ndarray:
@@ -132,13 +158,22 @@ class Oracle:
             return lambda r: r.copy()
         if kind == "jacobi":
             d = np.asarray((self.At @ self.A).diagonal())
-            return lambda r: r / d
+            dinv = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
+            return lambda r: r * dinv
         if kind != "block":
             raise ValueError(kind)
         Minv = np.linalg.inv(self.precond_blocks())
+        nm = self.n_map
+        if self.n_tmpl:
+            wdiag = noise.white_weights(self.iv_start, self.iv_filter, self.lag_tab, self.n_t)
+            dg = tmpl.amplitude_diagonal(self.B, wdiag)
+            dinv = np.where(dg > 0, 1.0 / np.where(dg > 0, dg, 1.0), 0.0)
+        else:
+            dinv = np.zeros(0)
 
         def apply(r):
-            return np.einsum("pij,pj->pi", Minv, r.reshape(-1, ns)).ravel()
+            zm = np.einsum("pij,pj->pi", Minv, r[:nm].reshape(-1, ns)).ravel()
+            return np.concatenate([zm, dinv * r[nm:]]) if self.n_tmpl else zm
         return apply
 
     # ---- solver ----------------------------------------------------------

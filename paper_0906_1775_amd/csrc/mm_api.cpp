@@ -683,7 +683,9 @@ void ensure_refine_vectors(mm_plan_s* P) {
   if (P->vb64) return;
   const int64_t vn = (int64_t)P->R * P->nu();
   P->vb64 = P->alloc<double>(vn);
-  P->vr64 = P->alloc<double>(vn);
+  // the true residual is the correction equation's right-hand side: it lives in
+  // the PCG's b vector, which it is recomputed into after every inner solve
+  P->vr64 = P->vb;
   P->vxacc = P->alloc<double>(vn);
   P->vxbest = P->alloc<double>(vn);
 }
@@ -801,9 +803,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       bool any = false;
       for (int r = 0; r < R; ++r) {
         const bool act = bn[r] > 0 && rel[r] > o.tol && iters[r] < n_max;
-        double* dst = P->vb + (int64_t)r * nu;
+        double* dst = P->vb + (int64_t)r * nu;       // = the residual r64 of RHS r
         if (act) {
-          hipchk(hipMemcpyAsync(dst, P->vr64 + (int64_t)r * nu, sizeof(double) * nu, hipMemcpyDeviceToDevice, s), "copy");
           worst = std::max(worst, rel[r]);
           any = true;
         } else {
