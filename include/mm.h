@@ -16,6 +16,14 @@
  * white-noise block inverse (P^T W^-1 P)^-1 with W^-1 = diag(N^-1), or the
  * point-Jacobi diag(P^T P)^-1 (Implementation section).
  *
+ * Templates ("Using MADmap" section, eqs. eDSN1 and PmatExt): a plan may
+ * append template columns B to the pointing matrix, P -> [P B], and the
+ * template amplitudes y to the unknowns, m -> [m; y].  Supported B: one-hot
+ * columns (a signal synchronous with a binned parameter, or destriping
+ * offsets: B[t, idx_t] = 1) and the 32-column half-wave-plate block of
+ * eq. HWPmat per segment of samples.  Every operator and solve below then
+ * acts on the extended system.
+ *
  * Conventions for every entry point:
  *   - Pointers named d_* are device (HBM) pointers on the current HIP device;
  *     all others are host pointers.  The caller owns every buffer it passes;
@@ -25,7 +33,10 @@
  *     on the host (plan creation, mm_solve) synchronise that stream.
  *   - Maps cross the boundary in global pixel layout, float64,
  *     [n_rhs][n_pix][n_stokes] (Stokes fastest).  Pixels never observed are
- *     written as 0.
+ *     written as 0.  With templates every map-shaped buffer is the extended
+ *     vector: per RHS, the n_pix * n_stokes map values followed by the
+ *     n_tmpl template amplitudes (mm_plan_info_t.n_tmpl), templates in
+ *     descriptor order; amplitudes no sample touches are written as 0.
  *   - Time-ordered data (TOD) cross the boundary as [n_rhs][n_samples] of
  *     float32 (MM_F32) or float64 (MM_F64).
  *   - Every entry point returns an mm_status_t and never throws; on failure
@@ -66,6 +77,38 @@ enum { MM_PRECOND_BLOCK = 0,   /* (P^T W^-1 P)^-1, 1x1 or 3x3 per pixel */
 /* element type of a TOD buffer */
 enum { MM_F32 = 0, MM_F64 = 1 };
 
+/* template kinds */
+enum { MM_TMPL_ONEHOT = 1,   /* B[t, idx_t] = 1: synchronous bins, destriping offsets */
+       MM_TMPL_HWP = 2 };    /* half-wave-plate parametric block, 32 columns per segment */
+
+/*
+ * One block of template columns (section "Using MADmap").
+ *   MM_TMPL_ONEHOT: n_amp amplitudes; d_idx (device int32 [n_samples]) holds
+ *     the amplitude of each sample in [0, n_amp), or -1 for none.
+ *   MM_TMPL_HWP: for each segment g of seg_start (host int64 [n_seg + 1],
+ *     seg_start[0] = 0, non-decreasing, seg_start[n_seg] = n_samples) the 32
+ *     columns of eq. HWPmat, in this order for k = 1..8: cos(k w_t), then
+ *     tau_t cos(k w_t), then sin(k w_t), then tau_t sin(k w_t), where w_t is
+ *     d_omega[t] (device float32 [n_samples], radians) and
+ *     tau_t = (2 (t - s_g) - (L_g - 1)) / L_g is the sample index centred on
+ *     the segment [s_g, s_g + L_g) and scaled to (-1, 1) (an affine change of
+ *     the paper's time factor: same column span, so the same fitted signal
+ *     and map).  Amplitudes: 32 per segment, segment-major.
+ * Template rows do not depend on the pointing index: a sample with pixel -1
+ * still carries its template columns.  d_idx and d_omega are read by every
+ * operator and must stay allocated and unchanged until mm_plan_destroy.
+ * Amplitude preconditioner: diag(B^T W^-1 B)^-1 (MM_PRECOND_BLOCK),
+ * diag(B^T B)^-1 (MM_PRECOND_JACOBI) or 1, with 0 for an all-zero column.
+ */
+typedef struct {
+  int32_t kind;                 /* MM_TMPL_ONEHOT or MM_TMPL_HWP */
+  int32_t n_seg;                /* HWP: number of segments, >= 1 */
+  int64_t n_amp;                /* ONEHOT: number of amplitudes, 1 .. 2^31 - 2 */
+  const int32_t* d_idx;         /* ONEHOT: device [n_samples] */
+  const float* d_omega;         /* HWP: device [n_samples] */
+  const int64_t* seg_start;     /* HWP: host [n_seg + 1] */
+} mm_template_t;
+
 typedef struct {
   int32_t n_stokes;             /* 1 (T) or 3 (I, Q, U) */
   int64_t n_pix;                /* global pixel count; pointing indices lie in [-1, n_pix) */
@@ -92,6 +135,8 @@ typedef struct {
   int32_t precision;            /* MM_FP64 or MM_MIXED */
   int32_t precond;              /* MM_PRECOND_* */
   int32_t n_rhs;                /* right-hand sides solved together, 1 .. 64 */
+  int32_t n_templates;          /* template blocks appended to P, 0 .. 16 */
+  const mm_template_t* templates;  /* host [n_templates], or NULL when n_templates = 0 */
 } mm_desc_t;
 
 typedef struct {
@@ -103,6 +148,7 @@ typedef struct {
   int64_t device_bytes;         /* device memory held by the plan */
   int64_t n_sliced;             /* entries of the sliced pixel-major pointing (>= n_valid;
                                    the excess is padding to the widest pixel of each slice) */
+  int64_t n_tmpl;               /* template amplitudes per RHS in map-shaped buffers (0 = none) */
 } mm_plan_info_t;
 
 /*
@@ -115,8 +161,11 @@ typedef struct {
  *   d_w:   device float32 [n_samples][2] = (sin 2a_t, cos 2a_t); required
  *          when n_stokes == 3, ignored (may be NULL) when n_stokes == 1.
  *          d_w must stay allocated and unchanged until mm_plan_destroy.
- * Errors: MM_EINVAL (descriptor, pixel out of range), MM_ENOMEM, MM_EDEVICE,
- * MM_EUNSUPPORTED (forced n_f longer than the on-chip transforms).  A
+ * With n_c = 1 (white noise) N^-1 is applied as the diagonal f_b(0) without
+ * transforms (the destriping case of the "Using MADmap" section).
+ * Errors: MM_EINVAL (descriptor, pixel or template index out of range),
+ * MM_ENOMEM, MM_EDEVICE, MM_EUNSUPPORTED (forced n_f longer than the on-chip
+ * transforms).  A
  * singular preconditioner block does not fail the plan; it is counted in
  * mm_plan_info_t.n_singular and makes mm_solve return MM_ESINGULAR.
  */

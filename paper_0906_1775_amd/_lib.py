@@ -15,11 +15,17 @@ STATUS_NAMES = {0: "MM_OK", 1: "MM_EINVAL", 2: "MM_ENOMEM", 3: "MM_EDEVICE", 4: 
 MM_FP64, MM_MIXED = 0, 1
 MM_PRECOND_BLOCK, MM_PRECOND_JACOBI, MM_PRECOND_NONE = 0, 1, 2
 MM_F32, MM_F64 = 0, 1
+MM_TMPL_ONEHOT, MM_TMPL_HWP = 1, 2
 
 EXPORTED = ["mm_plan_create", "mm_plan_destroy", "mm_plan_get_info", "mm_hits", "mm_filter_lags",
             "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A", "mm_rhs", "mm_solve_opts_default",
             "mm_solve", "mm_solve_rhs", "mm_noise_gradient", "mm_fft_length_rule", "mm_last_error",
             "mm_version"]
+
+
+class MMTemplate(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("n_seg", c_int32), ("n_amp", c_int64), ("d_idx", c_void_p),
+                ("d_omega", c_void_p), ("seg_start", POINTER(c_int64))]
 
 
 class MMDesc(ctypes.Structure):
@@ -28,13 +34,15 @@ class MMDesc(ctypes.Structure):
         ("iv_start", POINTER(c_int64)), ("iv_filter", POINTER(c_int32)), ("n_filters", c_int32),
         ("filter_params", POINTER(c_double)), ("filter_lags", POINTER(c_double)), ("f_samp", c_double),
         ("n_c", c_int32), ("n_f", c_int32), ("lag_dft_len", c_int32), ("precision", c_int32),
-        ("precond", c_int32), ("n_rhs", c_int32),
+        ("precond", c_int32), ("n_rhs", c_int32), ("n_templates", c_int32),
+        ("templates", POINTER(MMTemplate)),
     ]
 
 
 class MMPlanInfo(ctypes.Structure):
     _fields_ = [("n_obs", c_int64), ("n_valid", c_int64), ("n_f", c_int32), ("n_chunks", c_int32),
-                ("n_singular", c_int32), ("device_bytes", c_int64), ("n_sliced", c_int64)]
+                ("n_singular", c_int32), ("device_bytes", c_int64), ("n_sliced", c_int64),
+                ("n_tmpl", c_int64)]
 
 
 class MMSolveOpts(ctypes.Structure):

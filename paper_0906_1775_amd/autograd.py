@@ -47,7 +47,11 @@ def solve_map(tod: torch.Tensor, plan: MapMaker, params: torch.Tensor | None = N
     tod: CUDA tensor [n_rhs, n_samples] (float32 or float64).
     params: optional CPU float64 tensor [n_filters, 3] = (sigma, f_knee, alpha); it must hold the
       parameters ``plan`` was built with and receives dL/d(sigma, f_knee, alpha) when it requires grad.
-    Returns the map [n_rhs, n_pix, n_stokes] (float64, CUDA).
+    Returns the map [n_rhs, n_pix, n_stokes] (float64, CUDA); for a plan with templates, the
+    extended vector [n_rhs, n_pix * n_stokes + n_tmpl] (map values, then template amplitudes),
+    the amplitudes being marginalised in the gradients.  The adjoint solve needs dL/dm in the
+    range of H: with templates that make H singular (offsets against the temperature
+    monopole), a loss must not depend on the degenerate direction.
     """
     if params is None:
         params = torch.zeros(plan.n_filters, 3, dtype=torch.float64)

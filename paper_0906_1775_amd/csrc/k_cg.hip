@@ -1,7 +1,8 @@
 // Preconditioned conjugate-gradient vector kernels and the block
 // preconditioner (Implementation section of the MADmap paper).
 //
-// All pixel-domain vectors are float64 [R][n_obs][ns].  Dot products are
+// All pixel-domain vectors are float64 rows [R][vs]: n_obs blocks of ns
+// pixel values, then the template amplitudes (diagonal preconditioner).  Dot products are
 // formed as kDotBlocks partial sums per RHS (fixed grid => fixed summation
 // order => bitwise repeatable) and folded by the scalar kernels, which keep
 // every CG scalar on the device (CgState), so an iteration needs no host
@@ -120,8 +121,8 @@ template <int NS>
 __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     double* __restrict__ x, const double* __restrict__ p, double* __restrict__ rv,
     const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ minv,
-    CgState* __restrict__ st, int64_t n_obs, const double* __restrict__ pq_part, int n_pq,
-    double* __restrict__ prz, double* __restrict__ prr) {
+    CgState* __restrict__ st, int64_t n_obs, int64_t vs, const double* __restrict__ minv_t, int64_t n_tail,
+    const double* __restrict__ pq_part, int n_pq, double* __restrict__ prz, double* __restrict__ prr) {
   __shared__ double sh[kDotThreads / 64];
   __shared__ double s_alpha;
   constexpr int NM = NS == 1 ? 1 : 6;
@@ -147,9 +148,21 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
   __syncthreads();
   const double alpha = s_alpha;
   const bool active = was_active && alpha != 0.0;
-  const int64_t off = (int64_t)r * n_obs * NS;
+  const int64_t off = (int64_t)r * vs;
   double arz = 0.0, arr = 0.0;
   if (active) {
+    // template amplitudes (diagonal preconditioner)
+    for (int64_t j = (int64_t)blockIdx.x * kDotThreads + tid; j < n_tail;
+         j += (int64_t)kDotBlocks * kDotThreads) {
+      const int64_t b = off + n_obs * NS + j;
+      x[b] += alpha * p[b];
+      const double rr = rv[b] - alpha * q[b];
+      rv[b] = rr;
+      const double zz = minv_t[j] * rr;
+      z[b] = zz;
+      arz += rr * zz;
+      arr += rr * rr;
+    }
     for (int64_t o = (int64_t)blockIdx.x * kDotThreads + tid; o < n_obs;
          o += (int64_t)kDotBlocks * kDotThreads) {
       const int64_t b = off + o * NS;
@@ -179,15 +192,16 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
 
 hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
                             double* z, const double* minv, CgState* st, int64_t n_obs,
+                            int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s) {
   const dim3 g(kDotBlocks, n_rhs), b(kDotThreads);
   if (ns == 1)
-    hipLaunchKernelGGL(k_cg_update<1>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, pq_part, n_pq,
-                       partial_rz, partial_rr);
+    hipLaunchKernelGGL(k_cg_update<1>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, vs, minv_t, n_tail,
+                       pq_part, n_pq, partial_rz, partial_rr);
   else
-    hipLaunchKernelGGL(k_cg_update<3>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, pq_part, n_pq,
-                       partial_rz, partial_rr);
+    hipLaunchKernelGGL(k_cg_update<3>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, vs, minv_t, n_tail,
+                       pq_part, n_pq, partial_rz, partial_rr);
   return hipGetLastError();
 }
 
@@ -254,26 +268,35 @@ hipError_t launch_cg_next(double* p, const double* z, const double* x, double* x
 
 template <int NS>
 __global__ void k_apply_precond(const double* __restrict__ minv, const double* __restrict__ r,
-                                double* __restrict__ z, int64_t n_obs, int n_rhs) {
+                                double* __restrict__ z, int64_t n_obs, int64_t vs,
+                                const double* __restrict__ minv_t, int64_t n_tail, int n_rhs) {
   constexpr int NM = NS == 1 ? 1 : 6;
-  const int64_t n = n_obs * n_rhs;
+  const int64_t per = n_obs + n_tail;
+  const int64_t n = per * n_rhs;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int64_t o = i % n_obs;
+    const int64_t rr_ = i / per, o = i % per;
+    const int64_t base = rr_ * vs;
+    if (o >= n_obs) {   // template amplitude
+      const int64_t b = base + n_obs * NS + (o - n_obs);
+      z[b] = minv_t[o - n_obs] * r[b];
+      continue;
+    }
     double rr[NS], zz[NS];
 #pragma unroll
-    for (int c = 0; c < NS; ++c) rr[c] = r[i * NS + c];
+    for (int c = 0; c < NS; ++c) rr[c] = r[base + o * NS + c];
     precond_apply<NS>(minv + o * NM, rr, zz);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) z[i * NS + c] = zz[c];
+    for (int c = 0; c < NS; ++c) z[base + o * NS + c] = zz[c];
   }
 }
 
 hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
-                                int64_t n_obs, int n_rhs, hipStream_t s) {
-  const dim3 g = grid_for(n_obs * n_rhs);
-  if (ns == 1) hipLaunchKernelGGL(k_apply_precond<1>, g, dim3(256), 0, s, minv, r, z, n_obs, n_rhs);
-  else hipLaunchKernelGGL(k_apply_precond<3>, g, dim3(256), 0, s, minv, r, z, n_obs, n_rhs);
+                                int64_t n_obs, int64_t vs, const double* minv_t, int64_t n_tail,
+                                int n_rhs, hipStream_t s) {
+  const dim3 g = grid_for((n_obs + n_tail) * n_rhs);
+  if (ns == 1) hipLaunchKernelGGL(k_apply_precond<1>, g, dim3(256), 0, s, minv, r, z, n_obs, vs, minv_t, n_tail, n_rhs);
+  else hipLaunchKernelGGL(k_apply_precond<3>, g, dim3(256), 0, s, minv, r, z, n_obs, vs, minv_t, n_tail, n_rhs);
   return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@
 // the slice's wavefronts) owns one pixel, so every pixel sum is formed in a
 // fixed order and no atomics are needed.  The scatter can also return
 // the per-block partial sums of p.q for the CG step length.  Maps are float64
-// [R][n_obs][ns].
+// rows [R][vs] whose first n_obs * ns values are the observed pixels (the rest
+// of a row holds template amplitudes).
 #include <algorithm>
 
 #include "mm_internal.h"
@@ -27,8 +28,8 @@ constexpr int kGatherUnroll = 4;
 template <typename Ty, int NS>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
                                                 const float2* __restrict__ w,
-                                                const double* __restrict__ p, Ty* __restrict__ y,
-                                                int64_t n_t, int64_t n_obs, int n_rhs) {
+                                                const double* __restrict__ p, int64_t vs,
+                                                Ty* __restrict__ y, int64_t n_t, int n_rhs) {
   constexpr int U = kGatherUnroll;
   const int64_t step = (int64_t)gridDim.x * 256 * U;
   for (int64_t t0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; t0 < n_t; t0 += step) {
@@ -47,9 +48,9 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
         v[u] = 0.0;
         if (o[u] >= 0) {
           if (NS == 1) {
-            v[u] = p[(int64_t)r * n_obs + o[u]];
+            v[u] = p[(int64_t)r * vs + o[u]];
           } else {
-            const double* m = p + ((int64_t)r * n_obs + o[u]) * 3;
+            const double* m = p + (int64_t)r * vs + (int64_t)o[u] * 3;
             v[u] = 0.5 * (m[0] + (double)sc[u].x * m[1] + (double)sc[u].y * m[2]);
           }
         }
@@ -64,19 +65,20 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
 }
 
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
-                         const double* p, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
+                         const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
                          hipStream_t s) {
+  (void)n_obs;
   if (n_t == 0) return hipSuccess;
   int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
   if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
   if (out_f64) {
-    if (ns == 1) hipLaunchKernelGGL((k_gather<double, 1>), g, b, 0, s, pix_obs, w2, p, (double*)y, n_t, n_obs, n_rhs);
-    else hipLaunchKernelGGL((k_gather<double, 3>), g, b, 0, s, pix_obs, w2, p, (double*)y, n_t, n_obs, n_rhs);
+    if (ns == 1) hipLaunchKernelGGL((k_gather<double, 1>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs);
+    else hipLaunchKernelGGL((k_gather<double, 3>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs);
   } else {
-    if (ns == 1) hipLaunchKernelGGL((k_gather<float, 1>), g, b, 0, s, pix_obs, w2, p, (float*)y, n_t, n_obs, n_rhs);
-    else hipLaunchKernelGGL((k_gather<float, 3>), g, b, 0, s, pix_obs, w2, p, (float*)y, n_t, n_obs, n_rhs);
+    if (ns == 1) hipLaunchKernelGGL((k_gather<float, 1>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs);
+    else hipLaunchKernelGGL((k_gather<float, 3>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs);
   }
   return hipGetLastError();
 }
@@ -171,8 +173,8 @@ template <typename Ty, int NS>
 __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
-    double* __restrict__ q, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
-    double* __restrict__ pq_part) {
+    double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
+    double* __restrict__ pq_part, int pq_stride, int pq_slot) {
   constexpr int W = kSliceWaves;
   __shared__ double part[W][NS][64];
   __shared__ double sh[W];
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
       __syncthreads();
       const int64_t o = s * 64 + lane;
       if (wv == 0 && o < n_obs) {
-        const int64_t i = ((int64_t)r * n_obs + o) * NS;
+        const int64_t i = (int64_t)r * vs + o * NS;
 #pragma unroll
         for (int c = 0; c < NS; ++c) {
           double v = part[0][c][lane];
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
       if (tid == 0) {
         double sum = 0.0;
         for (int w = 0; w < W; ++w) sum += sh[w];
-        pq_part[(int64_t)r * gridDim.x + blockIdx.x] = sum;
+        pq_part[(int64_t)r * pq_stride + pq_slot + blockIdx.x] = sum;
       }
       __syncthreads();
     }
@@ -252,19 +254,22 @@ int scatter_blocks(int64_t n_obs) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(n_sl, kScatterBlocks));
 }
 
-hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q,
+hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
-                          double* pq_part) {
+                          double* pq_part, int pq_stride, int pq_slot) {
   if (n_obs == 0) return hipSuccess;
   const dim3 g((unsigned)scatter_blocks(n_obs)), b(64 * kSliceWaves);
   const float2* w = (const float2*)L.w;
+#define MM_SC(T, NS) hipLaunchKernelGGL((k_scatter<T, NS>), g, b, 0, s, L.end, L.len, L.t, w, (const T*)y, q, vs, \
+                                        n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot)
   if (in_f64) {
-    if (ns == 1) hipLaunchKernelGGL((k_scatter<double, 1>), g, b, 0, s, L.end, L.len, L.t, w, (const double*)y, q, n_obs, n_t, n_rhs, p, pq_part);
-    else hipLaunchKernelGGL((k_scatter<double, 3>), g, b, 0, s, L.end, L.len, L.t, w, (const double*)y, q, n_obs, n_t, n_rhs, p, pq_part);
+    if (ns == 1) MM_SC(double, 1);
+    else MM_SC(double, 3);
   } else {
-    if (ns == 1) hipLaunchKernelGGL((k_scatter<float, 1>), g, b, 0, s, L.end, L.len, L.t, w, (const float*)y, q, n_obs, n_t, n_rhs, p, pq_part);
-    else hipLaunchKernelGGL((k_scatter<float, 3>), g, b, 0, s, L.end, L.len, L.t, w, (const float*)y, q, n_obs, n_t, n_rhs, p, pq_part);
+    if (ns == 1) MM_SC(float, 1);
+    else MM_SC(float, 3);
   }
+#undef MM_SC
   return hipGetLastError();
 }
 
@@ -293,20 +298,19 @@ hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, 
   return hipGetLastError();
 }
 
-__global__ void k_to_observed(const double* __restrict__ glob, double* __restrict__ obs,
-                              const int32_t* __restrict__ obs2glob, int64_t n_obs, int64_t n_pix,
-                              int ns, int n_rhs) {
-  const int64_t n = n_obs * ns * n_rhs;
+__global__ void k_to_observed(const double* __restrict__ glob, int64_t gs, double* __restrict__ obs, int64_t os,
+                              const int32_t* __restrict__ obs2glob, int64_t n_obs, int ns, int n_rhs) {
+  const int64_t per = n_obs * ns;
+  const int64_t n = per * n_rhs;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int64_t per = n_obs * ns;
     const int64_t r = i / per, rem = i % per, o = rem / ns, c = rem % ns;
-    obs[i] = glob[(r * n_pix + obs2glob[o]) * ns + c];
+    obs[r * os + rem] = glob[r * gs + (int64_t)obs2glob[o] * ns + c];
   }
 }
 
 // global map = observed values at observed pixels, 0 elsewhere (one pass over the global map)
-__global__ void k_to_global(const double* __restrict__ obs, double* __restrict__ glob,
+__global__ void k_to_global(const double* __restrict__ obs, int64_t os, double* __restrict__ glob, int64_t gs,
                             const int32_t* __restrict__ obs2glob, int64_t n_obs, int64_t n_pix,
                             int ns, int n_rhs) {
   const int64_t n = n_pix * n_rhs;
@@ -321,23 +325,28 @@ __global__ void k_to_global(const double* __restrict__ obs, double* __restrict__
     }
     const bool seen = lo < n_obs && obs2glob[lo] == gp;
     for (int c = 0; c < ns; ++c)
-      glob[i * ns + c] = seen ? obs[(r * n_obs + lo) * ns + c] : 0.0;
+      glob[r * gs + gp * ns + c] = seen ? obs[r * os + lo * ns + c] : 0.0;
   }
 }
 
-hipError_t launch_to_observed(const double* glob, double* obs, const int32_t* obs2glob,
-                              int64_t n_obs, int64_t n_pix, int ns, int n_rhs, hipStream_t s) {
+hipError_t launch_to_observed(const double* glob, int64_t glob_stride, double* obs, int64_t obs_stride,
+                              const int32_t* obs2glob, int64_t n_obs, int64_t n_pix, int ns, int n_rhs,
+                              hipStream_t s) {
+  (void)n_pix;
   const int64_t n = n_obs * ns * n_rhs;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_to_observed, grid_for(n), dim3(256), 0, s, glob, obs, obs2glob, n_obs, n_pix, ns, n_rhs);
+  hipLaunchKernelGGL(k_to_observed, grid_for(n), dim3(256), 0, s, glob, glob_stride, obs, obs_stride, obs2glob,
+                     n_obs, ns, n_rhs);
   return hipGetLastError();
 }
 
-hipError_t launch_to_global(const double* obs, double* glob, const int32_t* obs2glob,
-                            int64_t n_obs, int64_t n_pix, int ns, int n_rhs, hipStream_t s) {
+hipError_t launch_to_global(const double* obs, int64_t obs_stride, double* glob, int64_t glob_stride,
+                            const int32_t* obs2glob, int64_t n_obs, int64_t n_pix, int ns, int n_rhs,
+                            hipStream_t s) {
   const int64_t n = n_pix * n_rhs;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_to_global, grid_for(n), dim3(256), 0, s, obs, glob, obs2glob, n_obs, n_pix, ns, n_rhs);
+  hipLaunchKernelGGL(k_to_global, grid_for(n), dim3(256), 0, s, obs, obs_stride, glob, glob_stride, obs2glob,
+                     n_obs, n_pix, ns, n_rhs);
   return hipGetLastError();
 }
 

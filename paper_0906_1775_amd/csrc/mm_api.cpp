@@ -95,6 +95,39 @@ struct FilterSetup {
   int n_chunks = 0;
 };
 
+// Pixel-major layout of one pointing matrix with one non-zero per row: the sky
+// pointing, or a one-hot template read as a temperature-only pointing.
+struct Layout {
+  int64_t n_obs = 0, n_valid = 0;
+  int32_t* obs_idx = nullptr;    // [n_t] observed id of each sample, -1 = none (time-major)
+  int64_t* ptr = nullptr;        // [n_obs + 1] CSR offsets of the pixel-major order
+  int32_t* obs2glob = nullptr;   // [n_obs] global id of each observed id (sorted)
+  int32_t* perm = nullptr;       // [n_valid] sample ids, pixel-major (released once sliced)
+  float* w_pm = nullptr;         // [n_valid][2] (sin, cos), pixel-major (released once sliced)
+  int group = 8;                 // lanes per pixel in the plan-time preconditioner build
+  SellLayout sell;               // sliced pointing of the scatter
+  int64_t sell_entries = 0;
+};
+
+// One block of template columns appended to the pointing.
+struct Template {
+  int kind = 0;
+  int64_t n_glob = 0;            // amplitudes in map-shaped API buffers
+  int64_t n_unk = 0;             // unknowns in the iteration vectors
+  int64_t goff = 0;              // offset of its amplitudes after the map values (API layout)
+  int64_t ooff = 0;              // offset after the map values (iteration layout)
+  int pq_slot = 0, pq_n = 0;     // its p.q partial sums
+  Layout lay;                    // one-hot: the index as a pointing
+  const float* omega = nullptr;  // HWP: polarizer angle per sample
+  int n_seg = 0;
+  std::vector<int64_t> seg_host;
+  int64_t* d_seg = nullptr;      // [n_seg + 1]
+  int32_t* d_seg_tile = nullptr; // [n_seg + 1] first tile of each segment
+  SampleTile* tiles = nullptr;
+  int n_tiles = 0;
+  double* partial = nullptr;     // [n_tiles][R][32] tile partial sums of the scatter
+};
+
 }  // namespace
 
 struct mm_plan_s {
@@ -117,15 +150,16 @@ struct mm_plan_s {
   // pointing
   int64_t n_obs = 0, n_valid = 0;
   const float* w = nullptr;     // caller's (sin, cos) pairs, time-major
-  int32_t* pix_obs = nullptr;
-  int32_t* perm = nullptr;
-  float* w_pm = nullptr;
-  int64_t* pix_ptr = nullptr;
-  int32_t* obs2glob = nullptr;
-  int scatter_group = 8;          // lanes per pixel in the plan-time preconditioner build
-  SellLayout sell;                // sliced pointing of the scatter
-  int64_t sell_entries = 0;
+  Layout px;                    // sky pointing
   std::vector<std::pair<int, float>> tuned;   // (n_f, ms per filter pass) tried by the autotuner
+
+  // templates
+  std::vector<Template> tmpl;
+  int64_t n_tglob = 0, n_tunk = 0;   // template amplitudes (API layout / iteration layout)
+  double* minv_t = nullptr;          // [n_tunk] diagonal preconditioner of the amplitudes
+  int n_pq = 0;                      // p.q partial sums per RHS over all scatters
+  SampleTile* white_tiles = nullptr; // n_c = 1: tiles of the stationary intervals
+  int n_white_tiles = 0;
 
   // noise
   double* lags = nullptr;
@@ -144,9 +178,9 @@ struct mm_plan_s {
   double* y64a = nullptr;        // [n_t] float64 views of y1 / y2 (true residual in mixed mode)
   double* y64b = nullptr;
   double *vx = nullptr, *vp = nullptr, *vr = nullptr, *vz = nullptr, *vq = nullptr,
-         *vxb = nullptr, *vb = nullptr;   // [R][n_obs][ns]
+         *vxb = nullptr, *vb = nullptr;   // [R][nu]
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
-  double* part_pq = nullptr;     // [R][scatter blocks] partial sums of p.q
+  double* part_pq = nullptr;     // [R][n_pq] partial sums of p.q
   double *vb64 = nullptr, *vr64 = nullptr, *vxacc = nullptr, *vxbest = nullptr;  // residual correction
   CgState* st = nullptr;
   CgState* st_host = nullptr;
@@ -188,7 +222,9 @@ struct mm_plan_s {
     if (own) hipStreamDestroy(own);
   }
 
-  int64_t nu() const { return n_obs * ns; }
+  int64_t nmap() const { return n_obs * ns; }            // map unknowns per RHS
+  int64_t nu() const { return n_obs * ns + n_tunk; }     // iteration vector row
+  int64_t ng() const { return n_pix * ns + n_tglob; }    // API map-shaped row
   bool main_fp64() const { return precision == MM_FP64; }
 };
 
@@ -321,27 +357,94 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   fs.ready = true;
 }
 
-// y_out = N^-1 y_in with the transforms of fs; in_f64 = element type of y_in;
-// y_out has the element type of fs
+// y_out = N^-1 y_in with the transforms of fs (or the diagonal f_b(0) when
+// n_c = 1); in_f64 = element type of y_in; y_out has the element type of fs
 void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, void* y_out, int R,
             hipStream_t s) {
+  if (P->n_c == 1) {
+    hipchk(launch_white(fs.fp64, in_f64, P->white_tiles, P->n_white_tiles, P->d_iv_filter, P->lags, P->n_c, y_in,
+                        y_out, P->n_t, R, s),
+           "white-noise weight");
+    return;
+  }
   hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, fs.spec, fs.ptw,
                     fs.tw2, P->n_t, P->n_c, fs.m, R, s),
          "overlap-save filter");
 }
 
-// out = P^T N^-1 P in (observed layout), R right-hand sides, precision of fs
+// y_r = [P B] x_r: x in iteration layout (rows of stride nu), y a TOD of type y_f64
+void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipStream_t s) {
+  const int64_t vs = P->nu();
+  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s), "gather");
+  for (const Template& T : P->tmpl) {
+    const int64_t off = P->nmap() + T.ooff;
+    if (T.kind == MM_TMPL_ONEHOT)
+      hipchk(launch_onehot_gather(y_f64, T.lay.obs_idx, x, vs, off, y, P->n_t, R, s), "template gather");
+    else
+      hipchk(launch_hwp_gather(y_f64, T.tiles, T.n_tiles, T.d_seg, T.omega, x, vs, off, y, P->n_t, R, s),
+             "template gather");
+  }
+}
+
+// q_r = [P B]^T y_r (iteration layout); with p also the p.q partial sums of
+// every scatter block in part_pq [R][n_pq]
+void scatter_all(mm_plan_s* P, bool y_f64, const void* y, double* q, int R, hipStream_t s,
+                 const double* p = nullptr) {
+  const int64_t vs = P->nu();
+  hipchk(launch_scatter(y_f64, P->ns, P->px.sell, y, q, vs, P->n_obs, P->n_t, R, s, p, P->part_pq, P->n_pq, 0),
+         "scatter");
+  for (const Template& T : P->tmpl) {
+    const int64_t off = P->nmap() + T.ooff;
+    if (T.kind == MM_TMPL_ONEHOT) {
+      if (T.lay.n_obs == 0) continue;
+      hipchk(launch_scatter(y_f64, 1, T.lay.sell, y, q + off, vs, T.lay.n_obs, P->n_t, R, s, p ? p + off : nullptr,
+                            P->part_pq, P->n_pq, T.pq_slot),
+             "template scatter");
+    } else {
+      hipchk(launch_hwp_scatter(y_f64, T.tiles, T.n_tiles, T.d_seg_tile, T.n_seg, T.d_seg, T.omega, y, P->n_t, R,
+                                T.partial, q, vs, off, p, P->part_pq, P->n_pq, T.pq_slot, s),
+             "template scatter");
+    }
+  }
+}
+
+// API map-shaped rows (stride ng, global ids) <-> iteration rows (stride nu, observed ids)
+void to_obs(mm_plan_s* P, const double* glob, double* obs, int R, hipStream_t s) {
+  hipchk(launch_to_observed(glob, P->ng(), obs, P->nu(), P->px.obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "layout");
+  for (const Template& T : P->tmpl) {
+    const double* g = glob + P->n_pix * P->ns + T.goff;
+    double* o = obs + P->nmap() + T.ooff;
+    if (T.kind == MM_TMPL_ONEHOT)
+      hipchk(launch_to_observed(g, P->ng(), o, P->nu(), T.lay.obs2glob, T.lay.n_obs, T.n_glob, 1, R, s), "layout");
+    else
+      hipchk(launch_copy_rows(g, P->ng(), o, P->nu(), T.n_unk, R, s), "layout");
+  }
+}
+
+void to_glob(mm_plan_s* P, const double* obs, double* glob, int R, hipStream_t s) {
+  hipchk(launch_to_global(obs, P->nu(), glob, P->ng(), P->px.obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "layout");
+  for (const Template& T : P->tmpl) {
+    double* g = glob + P->n_pix * P->ns + T.goff;
+    const double* o = obs + P->nmap() + T.ooff;
+    if (T.kind == MM_TMPL_ONEHOT)
+      hipchk(launch_to_global(o, P->nu(), g, P->ng(), T.lay.obs2glob, T.lay.n_obs, T.n_glob, 1, R, s), "layout");
+    else
+      hipchk(launch_copy_rows(o, P->nu(), g, P->ng(), T.n_unk, R, s), "layout");
+  }
+}
+
+// out = [P B]^T N^-1 [P B] in (iteration layout), R right-hand sides, precision of fs
 void apply_H_obs(mm_plan_s* P, const FilterSetup& fs, const double* in, double* out, void* ya, void* yb,
                  int R, hipStream_t s) {
-  hipchk(launch_gather(fs.fp64, P->ns, P->pix_obs, P->w, in, ya, P->n_t, P->n_obs, R, s), "gather");
+  gather_all(P, fs.fp64, in, ya, R, s);
   weight(P, fs, ya, fs.fp64, yb, R, s);
-  hipchk(launch_scatter(fs.fp64, P->ns, P->sell, yb, out, P->n_obs, P->n_t, R, s), "scatter");
+  scatter_all(P, fs.fp64, yb, out, R, s);
 }
 
 void rhs_obs(mm_plan_s* P, const FilterSetup& fs, const void* tod, bool tod_f64, double* out, void* yb,
              int R, hipStream_t s) {
   weight(P, fs, tod, tod_f64, yb, R, s);
-  hipchk(launch_scatter(fs.fp64, P->ns, P->sell, yb, out, P->n_obs, P->n_t, R, s), "scatter");
+  scatter_all(P, fs.fp64, yb, out, R, s);
 }
 
 void ensure_fp64_path(mm_plan_s* P, hipStream_t s) {
@@ -355,6 +458,205 @@ void ensure_fp64_path(mm_plan_s* P, hipStream_t s) {
 
 void check_tod_dtype(int32_t dt) {
   if (dt != MM_F32 && dt != MM_F64) fail(MM_EINVAL, "tod_dtype must be MM_F32 or MM_F64");
+}
+
+// Pixel-major layout of a pointing with one non-zero per row: range check,
+// stable sort of the samples by key, observed compaction (Implementation
+// section, observed index scheme).  Keys lie in [-1, n_keys); -1 = no column.
+void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, const float* d_w, Layout& L,
+                  hipStream_t s, const char* range_msg) {
+  const int64_t n = P->n_t;
+  {
+    int32_t* flag = P->alloc<int32_t>(1);
+    hipchk(launch_fill_i32(flag, 0, 1, s), "fill");
+    hipchk(launch_check_pix(d_key, n, n_keys, flag, s), "index check");
+    int32_t hflag = 0;
+    hipchk(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
+    hipchk(hipStreamSynchronize(s), "index check");
+    P->release(flag);
+    if (hflag) fail(MM_EINVAL, range_msg);
+  }
+  L.obs_idx = P->alloc<int32_t>(n);
+  if (n > 0) {
+    char* scratch = P->alloc<char>((int64_t)sort_scratch_bytes(n));
+    uint32_t* keys = P->alloc<uint32_t>(n);
+    int32_t* vals = P->alloc<int32_t>(n);
+    hipchk(launch_sort_by_pixel(d_key, n, n_keys, keys, vals, scratch, s), "sort by pixel");
+    P->release(scratch);
+    uint32_t* flags = P->alloc<uint32_t>(n);
+    uint32_t* seg = P->alloc<uint32_t>(n);
+    char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(n));
+    int64_t* nvalid_d = P->alloc<int64_t>(1);
+    hipchk(launch_segment_flags(keys, n, (uint32_t)n_keys, flags, s), "segment flags");
+    hipchk(launch_scan_inclusive(flags, seg, n, sscr, s), "segment scan");
+    hipchk(hipMemsetAsync(nvalid_d, 0, sizeof(int64_t), s), "memset");
+    hipchk(launch_find_nvalid(keys, n, (uint32_t)n_keys, nvalid_d, s), "valid count");
+    uint32_t nobs_h = 0;
+    int64_t nvalid_h = 0;
+    hipchk(hipMemcpyAsync(&nobs_h, seg + (n - 1), 4, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(&nvalid_h, nvalid_d, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipStreamSynchronize(s), "observed count");
+    L.n_obs = nobs_h;
+    L.n_valid = nvalid_h;
+    L.ptr = P->alloc<int64_t>(L.n_obs + 1);
+    L.obs2glob = P->alloc<int32_t>(L.n_obs);
+    L.perm = P->alloc<int32_t>(L.n_valid);
+    if (ns == 3) L.w_pm = P->alloc<float>(2 * L.n_valid);
+    hipchk(launch_build_layout(keys, vals, seg, n, (uint32_t)n_keys, d_w, ns, L.ptr, L.obs2glob, L.obs_idx,
+                               L.w_pm, L.perm, s),
+           "pointing layout");
+    hipchk(hipMemcpyAsync(L.ptr + L.n_obs, &L.n_valid, 8, hipMemcpyHostToDevice, s), "copy");
+    hipchk(hipStreamSynchronize(s), "pointing layout");
+    P->release(keys);
+    P->release(vals);
+    P->release(flags);
+    P->release(seg);
+    P->release(sscr);
+    P->release(nvalid_d);
+  } else {
+    L.ptr = P->alloc<int64_t>(1);
+    hipchk(hipMemsetAsync(L.ptr, 0, 8, s), "memset");
+    L.obs2glob = P->alloc<int32_t>(1);
+    L.perm = P->alloc<int32_t>(1);
+  }
+  const double avg = L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0;
+  int g = 4;
+  while (g < 64 && g * 4 < avg) g *= 2;
+  L.group = g;
+}
+
+// Sliced copy of a layout for the scatter; the plain pixel-major copy is dropped.
+void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
+  const int64_t n_sl = (L.n_obs + 63) / 64;
+  uint32_t* len = P->alloc<uint32_t>(n_sl);
+  uint32_t* end = P->alloc<uint32_t>(n_sl);
+  char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(std::max<int64_t>(n_sl, 1)));
+  uint32_t total = 0;
+  if (n_sl > 0) {
+    hipchk(launch_sell_widths(L.ptr, L.n_obs, len, s), "slice widths");
+    hipchk(launch_scan_inclusive(len, end, n_sl, sscr, s), "slice offsets");
+    hipchk(hipMemcpyAsync(&total, end + (n_sl - 1), 4, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipStreamSynchronize(s), "slices");
+    // the 32-bit slice sizes and their prefix sum are exact while the padded total
+    // stays below 2^32 - 1 (a saturated size also trips this test)
+    double check = 0;
+    std::vector<uint32_t> hl(n_sl);
+    hipchk(hipMemcpy(hl.data(), len, 4 * n_sl, hipMemcpyDeviceToHost), "copy");
+    for (uint32_t v : hl) check += v;
+    if (check >= 4294967295.0) fail(MM_EUNSUPPORTED, "sliced pointing exceeds 2^32 - 1 entries");
+  }
+  P->release(sscr);
+  L.sell_entries = total;
+  int32_t* st = P->alloc<int32_t>(std::max<int64_t>(total, 1));
+  float* sw = ns == 3 ? P->alloc<float>(2 * std::max<int64_t>(total, 1)) : nullptr;
+  hipchk(launch_sell_fill(L.ptr, L.perm, L.w_pm, L.n_obs, end, len, st, sw, ns, s), "slice fill");
+  hipchk(hipStreamSynchronize(s), "slices");
+  L.sell.end = end;
+  L.sell.len = len;
+  L.sell.t = st;
+  L.sell.w = sw;
+  P->release(L.perm);
+  L.perm = nullptr;
+  P->release(L.w_pm);
+  L.w_pm = nullptr;
+}
+
+// Validate the descriptor's templates and build their layouts ("Using MADmap" section).
+// host-side checks of the template descriptors (before any device work)
+void validate_templates(const mm_desc_t* d) {
+  if (d->n_templates < 0 || d->n_templates > 16) fail(MM_EINVAL, "n_templates must be in [0, 16]");
+  if (d->n_templates > 0 && !d->templates) fail(MM_EINVAL, "templates is NULL");
+  for (int k = 0; k < d->n_templates; ++k) {
+    const mm_template_t& D = d->templates[k];
+    if (D.kind == MM_TMPL_ONEHOT) {
+      if (D.n_amp < 1 || D.n_amp >= (int64_t(1) << 31) - 1) fail(MM_EINVAL, "template n_amp must be in [1, 2^31 - 1)");
+      if (d->n_samples > 0 && !D.d_idx) fail(MM_EINVAL, "template d_idx is NULL");
+    } else if (D.kind == MM_TMPL_HWP) {
+      if (D.n_seg < 1 || !D.seg_start) fail(MM_EINVAL, "HWP template needs n_seg >= 1 and seg_start");
+      if (d->n_samples > 0 && !D.d_omega) fail(MM_EINVAL, "template d_omega is NULL");
+      if (D.seg_start[0] != 0 || D.seg_start[D.n_seg] != d->n_samples)
+        fail(MM_EINVAL, "HWP segments must start at 0 and end at n_samples");
+      for (int g = 0; g < D.n_seg; ++g)
+        if (D.seg_start[g + 1] < D.seg_start[g]) fail(MM_EINVAL, "seg_start must be non-decreasing");
+    } else {
+      fail(MM_EINVAL, "unknown template kind");
+    }
+  }
+}
+
+void setup_templates(mm_plan_s* P, const mm_desc_t* d, hipStream_t s) {
+  P->tmpl.resize(d->n_templates);
+  int64_t goff = 0, ooff = 0;
+  for (int k = 0; k < d->n_templates; ++k) {
+    const mm_template_t& D = d->templates[k];
+    Template& T = P->tmpl[k];
+    T.kind = D.kind;
+    if (D.kind == MM_TMPL_ONEHOT) {
+      build_layout(P, D.d_idx, D.n_amp, 1, nullptr, T.lay, s, "template index outside [-1, n_amp)");
+      T.n_glob = D.n_amp;
+      T.n_unk = T.lay.n_obs;
+    } else {
+      T.omega = D.d_omega;
+      T.n_seg = D.n_seg;
+      T.seg_host.assign(D.seg_start, D.seg_start + D.n_seg + 1);
+      std::vector<SampleTile> tiles;
+      std::vector<int32_t> first(D.n_seg + 1);
+      for (int g = 0; g < D.n_seg; ++g) {
+        first[g] = (int32_t)std::min<size_t>(tiles.size(), 0x7fffffff);
+        for (int64_t t0 = T.seg_host[g]; t0 < T.seg_host[g + 1]; t0 += kTileSamples)
+          tiles.push_back(SampleTile{t0, std::min<int64_t>(t0 + kTileSamples, T.seg_host[g + 1]), g, 0});
+      }
+      if (tiles.size() > (size_t)0x7fffffff) fail(MM_EUNSUPPORTED, "too many template tiles");
+      first[D.n_seg] = (int32_t)tiles.size();
+      T.n_tiles = (int)tiles.size();
+      T.tiles = P->alloc<SampleTile>(std::max<int64_t>(T.n_tiles, 1));
+      T.d_seg = P->alloc<int64_t>(D.n_seg + 1);
+      T.d_seg_tile = P->alloc<int32_t>(D.n_seg + 1);
+      T.partial = P->alloc<double>((int64_t)std::max(T.n_tiles, 1) * P->R * kHwpColumns);
+      if (T.n_tiles > 0)
+        hipchk(hipMemcpyAsync(T.tiles, tiles.data(), tiles.size() * sizeof(SampleTile), hipMemcpyHostToDevice, s),
+               "tile upload");
+      hipchk(hipMemcpyAsync(T.d_seg, T.seg_host.data(), 8 * (D.n_seg + 1), hipMemcpyHostToDevice, s), "copy");
+      hipchk(hipMemcpyAsync(T.d_seg_tile, first.data(), 4 * (D.n_seg + 1), hipMemcpyHostToDevice, s), "copy");
+      hipchk(hipStreamSynchronize(s), "template tiles");
+      T.n_glob = T.n_unk = (int64_t)kHwpColumns * D.n_seg;
+    }
+    T.goff = goff;
+    T.ooff = ooff;
+    goff += T.n_glob;
+    ooff += T.n_unk;
+  }
+  P->n_tglob = goff;
+  P->n_tunk = ooff;
+}
+
+// Diagonal preconditioner of the template amplitudes: diag(B^T W^-1 B)^-1
+// (block), diag(B^T B)^-1 (Jacobi) or 1; 0 for an all-zero column.
+void build_template_precond(mm_plan_s* P, hipStream_t s) {
+  P->minv_t = P->alloc<double>(std::max<int64_t>(P->n_tunk, 1));
+  for (Template& T : P->tmpl) {
+    double* dst = P->minv_t + T.ooff;
+    if (T.kind == MM_TMPL_ONEHOT) {
+      if (T.lay.n_obs == 0) continue;
+      int32_t* sing = P->alloc<int32_t>(T.lay.n_obs);
+      hipchk(launch_precond_build(1, P->precond, T.lay.group, T.lay.ptr, T.lay.perm, nullptr, P->d_iv_start,
+                                  P->n_iv, P->d_iv_filter, P->lags, P->n_c, T.lay.n_obs, dst, sing, s),
+             "template preconditioner");
+      hipchk(hipStreamSynchronize(s), "template preconditioner");
+      P->release(sing);
+    } else if (P->precond == MM_PRECOND_NONE) {
+      hipchk(launch_fill_f64(dst, 1.0, T.n_unk, s), "fill");
+    } else {
+      double* diag = P->alloc<double>(T.n_unk);
+      hipchk(launch_hwp_diag(P->precond == MM_PRECOND_BLOCK ? 0 : 1, T.tiles, T.n_tiles, T.d_seg_tile, T.n_seg,
+                             T.d_seg, T.omega, P->d_iv_start, P->n_iv, P->d_iv_filter, P->lags, P->n_c, T.partial,
+                             diag, s),
+             "template preconditioner");
+      hipchk(launch_invert_diag(diag, dst, T.n_unk, s), "template preconditioner");
+      hipchk(hipStreamSynchronize(s), "template preconditioner");
+      P->release(diag);
+    }
+  }
 }
 
 void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const float* d_w, hipStream_t s) {
@@ -374,6 +676,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
   if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
     fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
+  validate_templates(d);
 
   P->ns = d->n_stokes;
   P->n_pix = d->n_pix;
@@ -418,65 +721,10 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
 
   const int64_t n = P->n_t;
   // ---- pointing: range check, sort by pixel, observed layout
-  {
-    int32_t* flag = P->alloc<int32_t>(1);
-    hipchk(launch_fill_i32(flag, 0, 1, s), "fill");
-    hipchk(launch_check_pix(d_pix, n, P->n_pix, flag, s), "pixel check");
-    int32_t hflag = 0;
-    hipchk(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "pixel check copy");
-    hipchk(hipStreamSynchronize(s), "pixel check");
-    P->release(flag);
-    if (hflag) fail(MM_EINVAL, "pointing index outside [-1, n_pix)");
-  }
-  P->pix_obs = P->alloc<int32_t>(n);
-  if (n > 0) {
-    char* scratch = P->alloc<char>((int64_t)sort_scratch_bytes(n));
-    uint32_t* keys = P->alloc<uint32_t>(n);
-    int32_t* vals = P->alloc<int32_t>(n);
-    hipchk(launch_sort_by_pixel(d_pix, n, P->n_pix, keys, vals, scratch, s), "pixel sort");
-    P->release(scratch);
-    uint32_t* flags = P->alloc<uint32_t>(n);
-    uint32_t* seg = P->alloc<uint32_t>(n);
-    char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(n));
-    int64_t* nvalid_d = P->alloc<int64_t>(1);
-    hipchk(launch_segment_flags(keys, n, (uint32_t)P->n_pix, flags, s), "segment flags");
-    hipchk(launch_scan_inclusive(flags, seg, n, sscr, s), "segment scan");
-    hipchk(hipMemsetAsync(nvalid_d, 0, sizeof(int64_t), s), "memset");
-    hipchk(launch_find_nvalid(keys, n, (uint32_t)P->n_pix, nvalid_d, s), "valid count");
-    uint32_t nobs_h = 0;
-    int64_t nvalid_h = 0;
-    hipchk(hipMemcpyAsync(&nobs_h, seg + (n - 1), 4, hipMemcpyDeviceToHost, s), "copy");
-    hipchk(hipMemcpyAsync(&nvalid_h, nvalid_d, 8, hipMemcpyDeviceToHost, s), "copy");
-    hipchk(hipStreamSynchronize(s), "observed count");
-    P->n_obs = nobs_h;
-    P->n_valid = nvalid_h;
-    P->pix_ptr = P->alloc<int64_t>(P->n_obs + 1);
-    P->obs2glob = P->alloc<int32_t>(P->n_obs);
-    P->perm = P->alloc<int32_t>(P->n_valid);
-    if (P->ns == 3) P->w_pm = P->alloc<float>(2 * P->n_valid);
-    hipchk(launch_build_layout(keys, vals, seg, n, (uint32_t)P->n_pix, d_w, P->ns, P->pix_ptr,
-                               P->obs2glob, P->pix_obs, P->w_pm, P->perm, s),
-           "pointing layout");
-    hipchk(hipMemcpyAsync(P->pix_ptr + P->n_obs, &P->n_valid, 8, hipMemcpyHostToDevice, s), "copy");
-    hipchk(hipStreamSynchronize(s), "pointing layout");
-    P->release(keys);
-    P->release(vals);
-    P->release(flags);
-    P->release(seg);
-    P->release(sscr);
-    P->release(nvalid_d);
-  } else {
-    P->pix_ptr = P->alloc<int64_t>(1);
-    hipchk(hipMemsetAsync(P->pix_ptr, 0, 8, s), "memset");
-    P->obs2glob = P->alloc<int32_t>(1);
-    P->perm = P->alloc<int32_t>(1);
-  }
-  {
-    const double avg = P->n_obs > 0 ? (double)P->n_valid / (double)P->n_obs : 1.0;
-    int g = 4;
-    while (g < 64 && g * 4 < avg) g *= 2;
-    P->scatter_group = g;
-  }
+  build_layout(P, d_pix, P->n_pix, P->ns, d_w, P->px, s, "pointing index outside [-1, n_pix)");
+  P->n_obs = P->px.n_obs;
+  P->n_valid = P->px.n_valid;
+  setup_templates(P, d, s);
 
   // ---- noise filters
   P->lags = P->alloc<double>((int64_t)P->n_filt * P->n_c);
@@ -515,8 +763,8 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   {
     int32_t* sing = P->alloc<int32_t>(P->n_obs);
     double* cnt = P->alloc<double>(1);
-    hipchk(launch_precond_build(P->ns, P->precond, P->scatter_group, P->pix_ptr, P->perm, P->w_pm, P->d_iv_start, P->n_iv,
-                                P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
+    hipchk(launch_precond_build(P->ns, P->precond, P->px.group, P->px.ptr, P->px.perm, P->px.w_pm, P->d_iv_start,
+                                P->n_iv, P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
            "preconditioner");
     hipchk(launch_count_nonzero(sing, P->n_obs, nullptr, cnt, s), "singular count");
     double hc = 0;
@@ -526,41 +774,35 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
     P->release(sing);
     P->release(cnt);
   }
+  build_template_precond(P, s);
 
-  // ---- sliced pointing for the scatter; the plain pixel-major copy is then dropped
-  {
-    const int64_t n_sl = (P->n_obs + 63) / 64;
-    uint32_t* len = P->alloc<uint32_t>(n_sl);
-    uint32_t* end = P->alloc<uint32_t>(n_sl);
-    char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(std::max<int64_t>(n_sl, 1)));
-    uint32_t total = 0;
-    if (n_sl > 0) {
-      hipchk(launch_sell_widths(P->pix_ptr, P->n_obs, len, s), "slice widths");
-      hipchk(launch_scan_inclusive(len, end, n_sl, sscr, s), "slice offsets");
-      hipchk(hipMemcpyAsync(&total, end + (n_sl - 1), 4, hipMemcpyDeviceToHost, s), "copy");
-      hipchk(hipStreamSynchronize(s), "slices");
-      // the 32-bit slice sizes and their prefix sum are exact while the padded total
-      // stays below 2^32 - 1 (a saturated size also trips this test)
-      double check = 0;
-      std::vector<uint32_t> hl(n_sl);
-      hipchk(hipMemcpy(hl.data(), len, 4 * n_sl, hipMemcpyDeviceToHost), "copy");
-      for (uint32_t v : hl) check += v;
-      if (check >= 4294967295.0) fail(MM_EUNSUPPORTED, "sliced pointing exceeds 2^32 - 1 entries");
-    }
-    P->release(sscr);
-    P->sell_entries = total;
-    int32_t* st = P->alloc<int32_t>(std::max<int64_t>(total, 1));
-    float* sw = P->ns == 3 ? P->alloc<float>(2 * std::max<int64_t>(total, 1)) : nullptr;
-    hipchk(launch_sell_fill(P->pix_ptr, P->perm, P->w_pm, P->n_obs, end, len, st, sw, P->ns, s), "slice fill");
-    hipchk(hipStreamSynchronize(s), "slices");
-    P->sell.end = end;
-    P->sell.len = len;
-    P->sell.t = st;
-    P->sell.w = sw;
-    P->release(P->perm);
-    P->perm = nullptr;
-    P->release(P->w_pm);
-    P->w_pm = nullptr;
+  // ---- sliced pointing for the scatters; the plain pixel-major copies are then dropped
+  build_sell(P, P->px, P->ns, s);
+  for (Template& T : P->tmpl)
+    if (T.kind == MM_TMPL_ONEHOT) build_sell(P, T.lay, 1, s);
+
+  // ---- p.q partial sums: the sky scatter's blocks, then each template's
+  // (a scatter with no observed column writes none)
+  P->n_pq = P->n_obs > 0 ? scatter_blocks(P->n_obs) : 0;
+  for (Template& T : P->tmpl) {
+    T.pq_slot = P->n_pq;
+    T.pq_n = T.kind == MM_TMPL_ONEHOT ? (T.lay.n_obs > 0 ? scatter_blocks(T.lay.n_obs) : 0) : 1;
+    P->n_pq += T.pq_n;
+  }
+
+  // ---- white noise: N^-1 = f_b(0) on tiles of the intervals, no transforms
+  if (P->n_c == 1) {
+    std::vector<SampleTile> wt;
+    for (int b = 0; b < P->n_iv; ++b)
+      for (int64_t t0 = P->iv_start[b]; t0 < P->iv_start[b + 1]; t0 += kTileSamples)
+        wt.push_back(SampleTile{t0, std::min<int64_t>(t0 + kTileSamples, P->iv_start[b + 1]), b, 0});
+    if (wt.size() > (size_t)0x7fffffff) fail(MM_EUNSUPPORTED, "too many interval tiles");
+    P->n_white_tiles = (int)wt.size();
+    P->white_tiles = P->alloc<SampleTile>((int64_t)wt.size());
+    if (!wt.empty())
+      hipchk(hipMemcpyAsync(P->white_tiles, wt.data(), wt.size() * sizeof(SampleTile), hipMemcpyHostToDevice, s),
+             "tile upload");
+    hipchk(hipStreamSynchronize(s), "tiles");
   }
 
   // ---- work buffers
@@ -578,23 +820,19 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->part1 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part2 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part3 = P->alloc<double>((int64_t)P->R * kDotBlocks);
-  P->part_pq = P->alloc<double>((int64_t)P->R * kScatterBlocks);
+  P->part_pq = P->alloc<double>((int64_t)P->R * std::max(P->n_pq, 1));
   P->st = P->alloc<CgState>(P->R);
 }
 
 // queue one PCG iteration for every RHS
 void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   const int R = P->R;
-  // q = H p, with the partial sums of p.q formed by the scatter
-  hipchk(launch_gather(P->fs_main.fp64, P->ns, P->pix_obs, P->w, P->vp, P->y1, P->n_t, P->n_obs, R, s),
-         "gather");
+  // q = H p, with the partial sums of p.q formed by the scatters
+  gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s);
   weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s);
-  hipchk(launch_scatter(P->fs_main.fp64, P->ns, P->sell, P->y2, P->vq, P->n_obs, P->n_t, R, s, P->vp,
-                        P->part_pq),
-         "scatter");
-  const int n_pq = scatter_blocks(P->n_obs);
-  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, R,
-                          P->part_pq, n_pq, P->part2, P->part3, s),
+  scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp);
+  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, P->nu(), P->minv_t,
+                          P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
   hipchk(launch_cg_finalize(P->st, P->part2, P->part3, R, P->hist, P->hist_cap, s), "finalize");
   hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s), "next direction");
@@ -627,7 +865,8 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
     hipchk(hipMemcpyAsync(P->vr, P->vb, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
   }
   hipchk(hipMemcpyAsync(P->vxb, P->vx, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
-  hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, R, s), "precondition");
+  hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
+         "precondition");
   hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
   hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
   hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
@@ -713,9 +952,7 @@ struct RhsSource {
 void make_rhs(mm_plan_s* P, const RhsSource& src, const FilterSetup& fs, int r0, int nr, double* dst,
               void* yb, hipStream_t s) {
   if (src.map) {
-    hipchk(launch_to_observed(src.map + (int64_t)r0 * P->n_pix * P->ns, dst, P->obs2glob, P->n_obs, P->n_pix,
-                              P->ns, nr, s),
-           "rhs layout");
+    to_obs(P, src.map + (int64_t)r0 * P->ng(), dst, nr, s);
   } else {
     const int esz = src.tod64 ? 8 : 4;
     rhs_obs(P, fs, (const char*)src.tod + (size_t)r0 * P->n_t * esz, src.tod64, dst, yb, nr, s);
@@ -756,7 +993,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
 
   if (!refine) {
     make_rhs(P, src, P->fs_main, 0, R, P->vb, P->y2, s);
-    if (o.d_x0) hipchk(launch_to_observed(o.d_x0, P->vx, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "x0");
+    if (o.d_x0) to_obs(P, o.d_x0, P->vx, R, s);
     run_pcg(P, s, o.tol, n_max, fixed, o.check_every, o.use_graph != 0, o.d_x0 != nullptr);
     std::vector<double> hh((size_t)R * P->hist_cap);
     hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
@@ -769,7 +1006,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       for (int i = 0; i <= c.iter && i <= n_max; ++i) hist_out[(size_t)r * (n_max + 1) + i] = hh[(size_t)r * P->hist_cap + i];
       if (!fixed && c.bnorm > 0 && !(c.rel <= o.tol) && !(c.best_rel <= o.tol)) notconv = true;
     }
-    hipchk(launch_to_global(P->vxb, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "map output");
+    to_glob(P, P->vxb, d_x, R, s);
   } else {
     // Mixed precision with float64 residual correction: the float32-operator PCG
     // solves H d = r64 for a correction, the float64 operator recomputes the true
@@ -778,7 +1015,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     ensure_refine_vectors(P);
     for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
     if (o.d_x0) {
-      hipchk(launch_to_observed(o.d_x0, P->vxacc, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "x0");
+      to_obs(P, o.d_x0, P->vxacc, R, s);
       residual64(P, P->vxacc, P->vr64, s);
     } else {
       hipchk(launch_fill_f64(P->vxacc, 0.0, (int64_t)R * nu, s), "fill");
@@ -844,7 +1081,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       tres[r] = best_rel[r];
       if (bn[r] > 0 && !(best_rel[r] <= o.tol)) notconv = true;
     }
-    hipchk(launch_to_global(P->vxbest, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, R, s), "map output");
+    to_glob(P, P->vxbest, d_x, R, s);
   }
 
   if (o.true_residual && P->n_obs > 0 && !refine) {
@@ -933,7 +1170,8 @@ mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
     info->n_f = P->fs_main.nf;
     info->n_chunks = P->fs_main.n_chunks;
     info->n_singular = P->n_singular;
-    info->n_sliced = P->sell_entries;
+    info->n_sliced = P->px.sell_entries;
+    info->n_tmpl = P->n_tglob;
     info->device_bytes = P->bytes;
   });
 }
@@ -941,7 +1179,7 @@ mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
 mm_status_t mm_hits(mm_plan_t P, int32_t* d_hits, void* stream) {
   return guarded([&] {
     if (!P || !d_hits) fail(MM_EINVAL, "NULL argument");
-    hipchk(launch_hits(P->pix_ptr, P->obs2glob, d_hits, P->n_obs, P->n_pix, as_stream(stream)), "hits");
+    hipchk(launch_hits(P->px.ptr, P->px.obs2glob, d_hits, P->n_obs, P->n_pix, as_stream(stream)), "hits");
   });
 }
 
@@ -958,9 +1196,8 @@ mm_status_t mm_unpoint(mm_plan_t P, const double* d_x, void* d_y, int32_t tod_dt
     if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
-    hipchk(launch_to_observed(d_x, P->vq, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
-    hipchk(launch_gather(tod_dtype == MM_F64, P->ns, P->pix_obs, P->w, P->vq, d_y, P->n_t, P->n_obs, P->R, s),
-           "gather");
+    to_obs(P, d_x, P->vq, P->R, s);
+    gather_all(P, tod_dtype == MM_F64, P->vq, d_y, P->R, s);
   });
 }
 
@@ -969,8 +1206,8 @@ mm_status_t mm_point(mm_plan_t P, const void* d_y, int32_t tod_dtype, double* d_
     if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
-    hipchk(launch_scatter(tod_dtype == MM_F64, P->ns, P->sell, d_y, P->vq, P->n_obs, P->n_t, P->R, s), "scatter");
-    hipchk(launch_to_global(P->vq, d_x, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+    scatter_all(P, tod_dtype == MM_F64, d_y, P->vq, P->R, s);
+    to_glob(P, P->vq, d_x, P->R, s);
   });
 }
 
@@ -995,9 +1232,9 @@ mm_status_t mm_apply_A(mm_plan_t P, const double* d_x, double* d_y, void* stream
   return guarded([&] {
     if (!P || !d_x || !d_y) fail(MM_EINVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
-    hipchk(launch_to_observed(d_x, P->vz, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+    to_obs(P, d_x, P->vz, P->R, s);
     apply_H_obs(P, P->fs_main, P->vz, P->vq, P->y1, P->y2, P->R, s);
-    hipchk(launch_to_global(P->vq, d_y, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+    to_glob(P, P->vq, d_y, P->R, s);
   });
 }
 
@@ -1007,7 +1244,7 @@ mm_status_t mm_rhs(mm_plan_t P, const void* d_tod, int32_t tod_dtype, double* d_
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
     rhs_obs(P, P->fs_main, d_tod, tod_dtype == MM_F64, P->vq, P->y2, P->R, s);
-    hipchk(launch_to_global(P->vq, d_b, P->obs2glob, P->n_obs, P->n_pix, P->ns, P->R, s), "layout");
+    to_glob(P, P->vq, d_b, P->R, s);
   });
 }
 

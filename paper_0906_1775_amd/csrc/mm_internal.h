@@ -33,6 +33,20 @@ struct CgState {
   int32_t breakdown; // set when p.q <= 0 (H not positive definite on p)
 };
 
+// A run of samples [t0, t1) inside one HWP-template segment or one stationary
+// interval (id = segment or interval index).
+struct SampleTile {
+  int64_t t0;
+  int64_t t1;
+  int32_t id;
+  int32_t pad;
+};
+
+constexpr int kTileSamples = 4096;  // samples per SampleTile
+constexpr int kHwpHarmonics = 8;    // harmonics k = 1..8 of the HWP template
+constexpr int kHwpColumns = 32;     // its columns per segment
+constexpr int kMaxRhs = 64;
+
 constexpr int kDotBlocks = 256;     // partial sums per dot product (fixed => deterministic)
 constexpr int kDotThreads = 256;
 constexpr int kScatterBlocks = 2048; // bound on the scatter grid (and its p.q partial sums)
@@ -66,8 +80,9 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
                       const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s);
 
 // ---------------------------------------------------------------- pointing (k_pointing.hip)
+// y[r][t] = (P p_r)_t; p rows of stride vs (map values first, observed layout)
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
-                         const double* p, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
+                         const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
                          hipStream_t s);
 // Sliced pixel-major pointing (64 pixels per slice, one lane per pixel)
 struct SellLayout {
@@ -80,18 +95,23 @@ hipError_t launch_sell_widths(const int64_t* pix_ptr, int64_t n_obs, uint32_t* s
 hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const float* w_pm, int64_t n_obs,
                             const uint32_t* slice_end, const uint32_t* slice_len, int32_t* sell_t,
                             float* sell_w, int ns, hipStream_t s);
-// q = P^T y (observed layout).  When p is given, also pq_part[r][block] =
-// partial sums of p.q over the pixels of each scatter block (scatter_blocks() blocks).
-hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q,
+// q = P^T y (observed layout, rows of stride vs).  When p is given, also
+// pq_part[r * pq_stride + pq_slot + block] = partial sums of p.q over the pixels
+// of each scatter block (scatter_blocks() blocks).
+hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s,
-                          const double* p = nullptr, double* pq_part = nullptr);
+                          const double* p = nullptr, double* pq_part = nullptr, int pq_stride = 0,
+                          int pq_slot = 0);
 int scatter_blocks(int64_t n_obs);
 hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, int64_t n,
                           hipStream_t s);
-hipError_t launch_to_observed(const double* glob, double* obs, const int32_t* obs2glob,
-                              int64_t n_obs, int64_t n_pix, int ns, int n_rhs, hipStream_t s);
-hipError_t launch_to_global(const double* obs, double* glob, const int32_t* obs2glob,
-                            int64_t n_obs, int64_t n_pix, int ns, int n_rhs, hipStream_t s);
+// observed <-> global layout of n_rhs rows (strides obs_stride, glob_stride in doubles)
+hipError_t launch_to_observed(const double* glob, int64_t glob_stride, double* obs, int64_t obs_stride,
+                              const int32_t* obs2glob, int64_t n_obs, int64_t n_pix, int ns, int n_rhs,
+                              hipStream_t s);
+hipError_t launch_to_global(const double* obs, int64_t obs_stride, double* glob, int64_t glob_stride,
+                            const int32_t* obs2glob, int64_t n_obs, int64_t n_pix, int ns, int n_rhs,
+                            hipStream_t s);
 hipError_t launch_hits(const int64_t* pix_ptr, const int32_t* obs2glob, int32_t* hits,
                        int64_t n_obs, int64_t n_pix, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
@@ -140,8 +160,11 @@ hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* p
                           double* history, int hist_stride, hipStream_t s);
 // x += alpha p, r -= alpha q, z = M r with alpha = rho / (p.q) folded from the
 // n_pq partial sums of p.q; writes the r.z and r.r partial sums
+// Vectors are rows of stride vs: n_obs pixel blocks, then n_tail template
+// amplitudes preconditioned by the diagonal minv_t.
 hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
                             double* z, const double* minv, CgState* st, int64_t n_obs,
+                            int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s);
 hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
@@ -150,8 +173,36 @@ hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const doubl
 hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
                           const CgState* st, int64_t nu, int n_rhs, hipStream_t s);
 hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
-                                int64_t n_obs, int n_rhs, hipStream_t s);
+                                int64_t n_obs, int64_t vs, const double* minv_t, int64_t n_tail,
+                                int n_rhs, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- templates (k_template.hip)
+// y[r][t] += p[r * vs + off + obs_idx[t]] where obs_idx[t] >= 0
+hipError_t launch_onehot_gather(bool y_f64, const int32_t* obs_idx, const double* p, int64_t vs, int64_t off,
+                                void* y, int64_t n_t, int n_rhs, hipStream_t s);
+// y[r][t] += sum of the 32 HWP columns of t's segment times p[r * vs + off + 32 seg + i]
+hipError_t launch_hwp_gather(bool y_f64, const SampleTile* tiles, int n_tiles, const int64_t* seg_start,
+                             const float* omega, const double* p, int64_t vs, int64_t off, void* y, int64_t n_t,
+                             int n_rhs, hipStream_t s);
+// q[r * vs + off + 32 g + i] = sum over segment g of C[t][i] y[r][t] (tile partials in `partial`,
+// [n_tiles][n_rhs][32]); with p also the block's p.q in pq_part[r * pq_stride + pq_slot]
+hipError_t launch_hwp_scatter(bool y_f64, const SampleTile* tiles, int n_tiles, const int32_t* seg_tile, int n_seg,
+                              const int64_t* seg_start, const float* omega, const void* y, int64_t n_t, int n_rhs,
+                              double* partial, double* q, int64_t vs, int64_t off, const double* p,
+                              double* pq_part, int pq_stride, int pq_slot, hipStream_t s);
+// diag[32 g + i] = sum over segment g of C[t][i]^2 w_t, w_t = f_b(0) (kind 0) or 1 (kind 1)
+hipError_t launch_hwp_diag(int kind, const SampleTile* tiles, int n_tiles, const int32_t* seg_tile, int n_seg,
+                           const int64_t* seg_start, const float* omega, const int64_t* iv_start, int n_iv,
+                           const int32_t* iv_filter, const double* lags, int n_c, double* partial,
+                           double* diag, hipStream_t s);
+hipError_t launch_invert_diag(const double* d, double* out, int64_t n, hipStream_t s);
+hipError_t launch_copy_rows(const double* src, int64_t src_stride, double* dst, int64_t dst_stride, int64_t n,
+                            int n_rhs, hipStream_t s);
+// y_out = f_b(0) y_in over tiles of the stationary intervals (white noise, n_c = 1)
+hipError_t launch_white(bool out_f64, bool in_f64, const SampleTile* tiles, int n_tiles, const int32_t* iv_filter,
+                        const double* lags, int n_c, const void* y_in, void* y_out, int64_t n_t, int n_rhs,
+                        hipStream_t s);
 
 }  // namespace mm

@@ -3,7 +3,9 @@
 Every computation runs in the HIP library; this module only checks tensor
 shapes and dtypes, passes pointers and the current stream, and converts
 results.  Maps are float64 tensors [n_rhs, n_pix, n_stokes]; TOD tensors are
-float32 or float64 [n_rhs, n_samples].
+float32 or float64 [n_rhs, n_samples].  A plan with templates (the extended
+pointing [P B]) uses flat map-shaped tensors [n_rhs, n_pix * n_stokes + n_tmpl]
+instead: the map values, then the template amplitudes (``split`` separates them).
 """
 
 from __future__ import annotations
@@ -46,7 +48,11 @@ class MapMaker:
     def __init__(self, pix: torch.Tensor, w: Optional[torch.Tensor], n_pix: int, n_stokes: int,
                  iv_start, iv_filter, filter_params=None, filter_lags=None, f_samp: float = 0.0,
                  n_c: int = 1, n_f: int = 0, lag_dft_len: int = 0, precision: str = "fp64",
-                 precond: str = "block", n_rhs: int = 1):
+                 precond: str = "block", n_rhs: int = 1, templates=None):
+        """``templates``: optional list of dicts, each
+        ``{"kind": "onehot", "idx": int32 CUDA tensor [n_samples], "n_amp": int}`` or
+        ``{"kind": "hwp", "omega": float32 CUDA tensor [n_samples], "seg_start": int sequence}``;
+        the plan reads the tensors until it is destroyed."""
         self._lib = L.load()
         if not pix.is_cuda or pix.dtype != torch.int32 or not pix.is_contiguous():
             raise ValueError("pix must be a contiguous int32 CUDA tensor")
@@ -83,11 +89,40 @@ class MapMaker:
         d.precision = _PREC[precision]
         d.precond = _PRECOND[precond]
         d.n_rhs = self.n_rhs
+        self._tmpl_keep = []
+        self.templates = list(templates or [])
+        if self.templates:
+            arr = (L.MMTemplate * len(self.templates))()
+            for k, t in enumerate(self.templates):
+                if t["kind"] == "onehot":
+                    idx = t["idx"]
+                    if not idx.is_cuda or idx.dtype != torch.int32 or not idx.is_contiguous() \
+                            or tuple(idx.shape) != (self.n_samples,):
+                        raise ValueError("one-hot idx must be a contiguous int32 CUDA tensor [n_samples]")
+                    arr[k].kind, arr[k].n_amp, arr[k].d_idx = L.MM_TMPL_ONEHOT, int(t["n_amp"]), idx.data_ptr()
+                    self._tmpl_keep.append(idx)
+                elif t["kind"] == "hwp":
+                    om = t["omega"]
+                    if not om.is_cuda or om.dtype != torch.float32 or not om.is_contiguous() \
+                            or tuple(om.shape) != (self.n_samples,):
+                        raise ValueError("HWP omega must be a contiguous float32 CUDA tensor [n_samples]")
+                    seg = np.ascontiguousarray(t["seg_start"], dtype=np.int64)
+                    arr[k].kind, arr[k].n_seg, arr[k].d_omega = L.MM_TMPL_HWP, int(seg.shape[0] - 1), om.data_ptr()
+                    arr[k].seg_start = seg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+                    self._tmpl_keep += [om, seg]
+                else:
+                    raise ValueError(f"unknown template kind {t['kind']!r}")
+            d.n_templates = len(self.templates)
+            d.templates = ctypes.cast(arr, ctypes.POINTER(L.MMTemplate))
+            self._tmpl_keep.append(arr)
         self.precision = precision
         h = ctypes.c_void_p()
         L.check(self._lib.mm_plan_create(ctypes.byref(d), _ptr(pix), _ptr(w), _stream(), ctypes.byref(h)),
                 self._lib)
         self._h = h
+        self.n_tmpl = int(self.info()["n_tmpl"])
+        self._map_shape = (self.n_rhs, self.n_pix, self.n_stokes) if self.n_tmpl == 0 else \
+            (self.n_rhs, self.n_pix * self.n_stokes + self.n_tmpl)
 
     # ------------------------------------------------------------------ lifecycle
     def close(self):
@@ -105,16 +140,29 @@ class MapMaker:
         i = L.MMPlanInfo()
         L.check(self._lib.mm_plan_get_info(self._h, ctypes.byref(i)), self._lib)
         return dict(n_obs=i.n_obs, n_valid=i.n_valid, n_f=i.n_f, n_chunks=i.n_chunks,
-                    n_singular=i.n_singular, device_bytes=i.device_bytes, n_sliced=i.n_sliced)
+                    n_singular=i.n_singular, device_bytes=i.device_bytes, n_sliced=i.n_sliced,
+                    n_tmpl=i.n_tmpl)
+
+    def split(self, x: torch.Tensor):
+        """(map view [n_rhs, n_pix, n_stokes], [amplitude views, one per template]) of a
+        map-shaped tensor of this plan."""
+        if self.n_tmpl == 0:
+            return x, []
+        n_map = self.n_pix * self.n_stokes
+        out, pos = [], n_map
+        for t in self.templates:
+            n = int(t["n_amp"]) if t["kind"] == "onehot" else 32 * (len(t["seg_start"]) - 1)
+            out.append(x[:, pos:pos + n])
+            pos += n
+        return x[:, :n_map].view(self.n_rhs, self.n_pix, self.n_stokes), out
 
     # ------------------------------------------------------------------ helpers
     def _map_like(self) -> torch.Tensor:
-        return torch.empty((self.n_rhs, self.n_pix, self.n_stokes), dtype=torch.float64, device=self.pix.device)
+        return torch.empty(self._map_shape, dtype=torch.float64, device=self.pix.device)
 
     def _check_map(self, x: torch.Tensor):
-        if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous() or \
-                tuple(x.shape) != (self.n_rhs, self.n_pix, self.n_stokes):
-            raise ValueError(f"map must be contiguous float64 CUDA [{self.n_rhs}, {self.n_pix}, {self.n_stokes}]")
+        if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous() or tuple(x.shape) != self._map_shape:
+            raise ValueError(f"map must be a contiguous float64 CUDA tensor of shape {list(self._map_shape)}")
 
     def _check_tod(self, y: torch.Tensor):
         if not y.is_cuda or not y.is_contiguous() or tuple(y.shape) != (self.n_rhs, self.n_samples):

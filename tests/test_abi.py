@@ -96,3 +96,76 @@ def test_null_descriptor(lib):
     h = ctypes.c_void_p()
     assert lib.mm_plan_create(None, None, None, None, ctypes.byref(h)) == _lib.MM_EINVAL
     assert lib.mm_plan_create(None, None, None, None, None) == _lib.MM_EINVAL
+
+
+def _template_desc(tmpl):
+    from paper_0906_1775_amd import _lib
+    d, keep = _desc()
+    arr = (_lib.MMTemplate * 1)(tmpl)
+    d.n_templates = 1
+    d.templates = ctypes.cast(arr, ctypes.POINTER(_lib.MMTemplate))
+    return d, (keep, arr)
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("kind", "unknown template kind"), ("n_amp", "n_amp"), ("idx", "d_idx"),
+    ("n_seg", "n_seg"), ("seg_end", "end at n_samples"), ("seg_order", "non-decreasing"),
+    ("omega", "d_omega"),
+])
+def test_template_validation_fails_before_touching_the_device(lib, case, msg):
+    from paper_0906_1775_amd import _lib
+    fake = 0x1000                     # never dereferenced: validation fails first
+    seg_ok = np.array([0, 40, 100], np.int64)
+    seg_end = np.array([0, 40, 99], np.int64)
+    seg_order = np.array([0, 60, 40, 100], np.int64)
+    t = _lib.MMTemplate()
+    if case in ("kind", "n_amp", "idx"):
+        t.kind, t.n_amp, t.d_idx = _lib.MM_TMPL_ONEHOT, 5, fake
+        if case == "kind":
+            t.kind = 9
+        if case == "n_amp":
+            t.n_amp = 0
+        if case == "idx":
+            t.d_idx = None
+    else:
+        seg = {"seg_end": seg_end, "seg_order": seg_order}.get(case, seg_ok)
+        t.kind, t.n_seg, t.d_omega = _lib.MM_TMPL_HWP, seg.shape[0] - 1, fake
+        t.seg_start = seg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        if case == "n_seg":
+            t.n_seg = 0
+        if case == "omega":
+            t.d_omega = None
+    d, keep = _template_desc(t)
+    h = ctypes.c_void_p()
+    st = lib.mm_plan_create(ctypes.byref(d), ctypes.c_void_p(fake), None, None, ctypes.byref(h))
+    assert st == _lib.MM_EINVAL
+    assert msg in lib.mm_last_error().decode()
+    assert not h.value
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """sizeof / offsetof of every ABI struct, from a C program built with gcc, equal the binding's."""
+    import shutil
+    import subprocess
+    from paper_0906_1775_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"mm_desc_t": _lib.MMDesc, "mm_template_t": _lib.MMTemplate, "mm_plan_info_t": _lib.MMPlanInfo,
+               "mm_solve_opts_t": _lib.MMSolveOpts, "mm_solve_info_t": _lib.MMSolveInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mm.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

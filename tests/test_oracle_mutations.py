@@ -122,3 +122,86 @@ def test_best_iterate_rule_is_caught(monkeypatch):
         return cb_x.get("x", x), info
     monkeypatch.setattr(solver.Oracle, "pcg", last_iterate)
     _fails(sv.test_returns_the_lowest_residual_iterate)
+
+
+# ---------------------------------------------------------------- templates
+import scipy.sparse as sp
+
+import test_oracle_templates as tt
+from oracle import templates as otm
+
+
+def test_hwp_harmonic_off_by_one_is_caught(monkeypatch):
+    orig = otm.hwp_block
+
+    def shifted(t, n_t):
+        om = np.asarray(t.omega, dtype=np.float64)
+        return orig(otm.HWP((om * 9.0 / 8.0).astype(np.float32), t.seg_start), n_t)
+    monkeypatch.setattr(otm, "hwp_block", shifted)
+    _fails(tt.test_hwp_columns_span_the_parametric_signal)
+
+
+def test_hwp_missing_time_factor_is_caught(monkeypatch):
+    monkeypatch.setattr(otm, "scaled_time", lambda seg, n_t: np.zeros(n_t))
+    _fails(tt.test_hwp_columns_span_the_parametric_signal)
+
+
+def test_hwp_sin_cos_swap_is_caught(monkeypatch):
+    # a swap keeps the column span, so the span pin passes; the layout closed form catches it
+    orig = otm.hwp_block
+
+    def swapped(t, n_t):
+        B = orig(t, n_t).tocsc()
+        cols = np.array(list(range(16, 32)) + list(range(0, 16)))
+        return sp.hstack([B[:, 32 * g + cols] for g in range(t.n_seg)]).tocsr()
+    monkeypatch.setattr(otm, "hwp_block", swapped)
+    _fails(_hwp_layout_check)
+
+
+def _hwp_layout_check():
+    """Columns 0..7 of a segment are cos(k w) (closed form at w = 0: all ones)."""
+    om = np.zeros(4, dtype=np.float32)
+    B = otm.hwp_block(otm.HWP(om, np.array([0, 4])), 4).toarray()
+    assert np.allclose(B[:, :8], 1.0) and np.allclose(B[:, 16:24], 0.0)
+
+
+def test_hwp_layout_check_passes_unmutated():
+    _hwp_layout_check()
+
+
+def test_one_hot_index_shift_is_caught(monkeypatch):
+    orig = otm.onehot_block
+
+    def shifted(t, n_t):
+        idx = np.asarray(t.idx).copy()
+        ok = idx >= 0
+        idx[ok] = (idx[ok] + 1) % t.n_amp
+        return orig(otm.OneHot(idx, t.n_amp), n_t)
+    monkeypatch.setattr(otm, "onehot_block", shifted)
+    _fails(tt.test_noiseless_one_hot_recovery_up_to_the_monopole, 1, "offsets")
+
+
+def test_template_preconditioner_on_wrong_weights_is_caught(monkeypatch):
+    # B^T B instead of B^T W^-1 B: caught by the closed form at sigma = 2
+    monkeypatch.setattr(otm, "amplitude_diagonal", lambda B, w: np.asarray(B.multiply(B).sum(axis=0)).ravel())
+    _fails(_template_precond_check)
+
+
+def _template_precond_check():
+    import synth
+    from synth import templates as st
+    p = synth.make_custom(1, grid=(6, 6), det_lens=(800,), n_c=1, filters=((2.0, 0.0, 1.0),),
+                          f_samp=20.0, seed=4)
+    p, ti = st.add_templates(p, offsets=100, seed=1)
+    o, _ = tt._oracle(p, ti, L_K=1 << 12)
+    # the diagonal of B^T W^-1 B is (number of samples) / sigma^2 for every offset
+    M = o.preconditioner("block")
+    r = np.zeros(o.n_unknowns)
+    r[o.n_map:] = 1.0
+    z = M(r)[o.n_map:]
+    counts = np.bincount(ti.offsets[0], minlength=ti.offsets[1])
+    assert np.allclose(z, 4.0 / counts)
+
+
+def test_template_precond_check_passes_unmutated():
+    _template_precond_check()
