@@ -137,6 +137,13 @@ typedef struct {
   int32_t n_rhs;                /* right-hand sides solved together, 1 .. 64 */
   int32_t n_templates;          /* template blocks appended to P, 0 .. 16 */
   const mm_template_t* templates;  /* host [n_templates], or NULL when n_templates = 0 */
+  int32_t fft_shape;            /* workgroup shape of the overlap-save transform: 0 = library
+                                   default; 1 = 2^LOGN/16 threads x 16 points, radix-16 passes;
+                                   2 = half the threads x 32 points, radix-32 passes; 3 = half
+                                   the threads x 32 points, radix-16 passes.  Shapes 2 and 3
+                                   exist for float32 transforms of 2^13 (shape 2) and 2^14
+                                   complex points; elsewhere shape 1 is used.  Ignored with
+                                   n_f = -1 (the autotuner tries every shape). */
 } mm_desc_t;
 
 typedef struct {
@@ -149,6 +156,7 @@ typedef struct {
   int64_t n_sliced;             /* entries of the sliced pixel-major pointing (>= n_valid;
                                    the excess is padding to the widest pixel of each slice) */
   int64_t n_tmpl;               /* template amplitudes per RHS in map-shaped buffers (0 = none) */
+  int32_t fft_shape;            /* transform shape the iterations use (1, 2 or 3, see mm_desc_t) */
 } mm_plan_info_t;
 
 /*
@@ -171,6 +179,8 @@ typedef struct {
  */
 mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w,
                            void* stream, mm_plan_t* out_plan);
+/* Destroy a plan (waits for the device to be idle).  Its device memory is kept by the
+ * library for later plans of the process, up to 16 GiB per device; the rest is freed. */
 mm_status_t mm_plan_destroy(mm_plan_t plan);
 mm_status_t mm_plan_get_info(mm_plan_t plan, mm_plan_info_t* info);
 

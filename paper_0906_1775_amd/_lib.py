@@ -35,14 +35,14 @@ class MMDesc(ctypes.Structure):
         ("filter_params", POINTER(c_double)), ("filter_lags", POINTER(c_double)), ("f_samp", c_double),
         ("n_c", c_int32), ("n_f", c_int32), ("lag_dft_len", c_int32), ("precision", c_int32),
         ("precond", c_int32), ("n_rhs", c_int32), ("n_templates", c_int32),
-        ("templates", POINTER(MMTemplate)),
+        ("templates", POINTER(MMTemplate)), ("fft_shape", c_int32),
     ]
 
 
 class MMPlanInfo(ctypes.Structure):
     _fields_ = [("n_obs", c_int64), ("n_valid", c_int64), ("n_f", c_int32), ("n_chunks", c_int32),
                 ("n_singular", c_int32), ("device_bytes", c_int64), ("n_sliced", c_int64),
-                ("n_tmpl", c_int64)]
+                ("n_tmpl", c_int64), ("fft_shape", c_int32)]
 
 
 class MMSolveOpts(ctypes.Structure):

@@ -61,13 +61,30 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int LOGN>
-using ShapeFFT = BlockFFT<T, LOGN, Shape<LOGN>::NT, Shape<LOGN>::LOGE, Shape<LOGN>::LOGR>;
+// Workgroup shapes of the overlap-save transform; the autotuner may pick any
+// shape that exists for a length and precision.  Variant 0 is Shape<LOGN>.
+// Variant 1 uses half the threads with twice the points each and radix-32
+// passes: a 2^14-point transform then takes three register passes and two LDS
+// exchanges instead of four and three, at 2 wavefronts per SIMD instead of 4.
+// Variant 2 is that thread count with radix-16 passes.
+template <int LOGN, int V> struct OlsShape : Shape<LOGN> {};
+template <> struct OlsShape<13, 1> { static constexpr int NT = 256, LOGE = 5, LOGR = 5; };
+template <> struct OlsShape<14, 1> { static constexpr int NT = 512, LOGE = 5, LOGR = 5; };
+template <> struct OlsShape<14, 2> { static constexpr int NT = 512, LOGE = 5, LOGR = 4; };
+
+bool ols_variant_exists(int logn, bool fp64, int v) {
+  if (v == 0) return logn >= kMinLogN && logn <= ols_max_logn(fp64);
+  if (fp64) return false;
+  return (v == 1 && (logn == 13 || logn == 14)) || (v == 2 && logn == 14);
+}
+
+template <typename T, int LOGN, int V = 0>
+using ShapeFFT = BlockFFT<T, LOGN, OlsShape<LOGN, V>::NT, OlsShape<LOGN, V>::LOGE, OlsShape<LOGN, V>::LOGR>;
 
 // per-pass twiddle rows: entry (j, r) of pass p = exp(-2 pi i j r / (Ns R))
-template <typename T, int LOGN>
+template <typename T, int LOGN, int V>
 __global__ void k_pass_tw(cx<T>* tab) {
-  using F = ShapeFFT<T, LOGN>;
+  using F = ShapeFFT<T, LOGN, V>;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= F::tw_total()) return;
   for (int sq = 0; sq < 2; ++sq) {
@@ -87,10 +104,13 @@ __global__ void k_pass_tw(cx<T>* tab) {
   }
 }
 
-template <typename T, int LOGN>
-static int pass_tw_total_t() { return ShapeFFT<T, LOGN>::tw_total(); }
+template <typename T, int LOGN, int V = 0>
+static int pass_tw_total_t() { return ShapeFFT<T, LOGN, V>::tw_total(); }
 
-int pass_twiddle_count(int logn, bool fp64) {
+int pass_twiddle_count(int logn, bool fp64, int variant) {
+  if (!ols_variant_exists(logn, fp64, variant)) return -1;
+  if (variant == 1) return logn == 13 ? pass_tw_total_t<float, 13, 1>() : pass_tw_total_t<float, 14, 1>();
+  if (variant == 2) return pass_tw_total_t<float, 14, 2>();
 #define MM_PTC(L) case L: return fp64 ? pass_tw_total_t<double, L>() : pass_tw_total_t<float, L>();
   switch (logn) {
     MM_PTC(6) MM_PTC(7) MM_PTC(8) MM_PTC(9) MM_PTC(10) MM_PTC(11) MM_PTC(12) MM_PTC(13) MM_PTC(14)
@@ -100,15 +120,18 @@ int pass_twiddle_count(int logn, bool fp64) {
 #undef MM_PTC
 }
 
-template <typename T, int LOGN>
+template <typename T, int LOGN, int V = 0>
 static hipError_t pass_tw_launch(void* tab, hipStream_t s) {
-  const int n = ShapeFFT<T, LOGN>::tw_total();
+  const int n = ShapeFFT<T, LOGN, V>::tw_total();
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_pass_tw<T, LOGN>), dim3((n + 255) / 256), dim3(256), 0, s, (cx<T>*)tab);
+  hipLaunchKernelGGL((k_pass_tw<T, LOGN, V>), dim3((n + 255) / 256), dim3(256), 0, s, (cx<T>*)tab);
   return hipGetLastError();
 }
 
-hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s) {
+hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, int variant) {
+  if (!ols_variant_exists(logn, fp64, variant)) return hipErrorInvalidValue;
+  if (variant == 1) return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s) : pass_tw_launch<float, 14, 1>(tab, s);
+  if (variant == 2) return pass_tw_launch<float, 14, 2>(tab, s);
 #define MM_PTL(L) case L: return fp64 ? pass_tw_launch<double, L>(tab, s) : pass_tw_launch<float, L>(tab, s);
   switch (logn) {
     MM_PTL(6) MM_PTL(7) MM_PTL(8) MM_PTL(9) MM_PTL(10) MM_PTL(11) MM_PTL(12) MM_PTL(13) MM_PTL(14)
@@ -446,12 +469,13 @@ template <typename V> struct Pair;
 template <> struct Pair<float> { using type = float2; };
 template <> struct Pair<double> { using type = double2; };
 
-template <typename T, typename Tin, int LOGN>
-__global__ __launch_bounds__(Shape<LOGN>::NT) void k_ols(
+template <typename T, typename Tin, int LOGN, int V>
+__global__ __launch_bounds__((OlsShape<LOGN, V>::NT)) void k_ols(
     const Tin* __restrict__ yin, T* __restrict__ yout, const OlsChunk* __restrict__ chunks,
     const T* __restrict__ spec, const cx<T>* __restrict__ ptw, const cx<T>* __restrict__ tw2,
-    int64_t n_t, int n_c, int m) {
-  using F = ShapeFFT<T, LOGN>;
+    int64_t n_t, int n_c, int m, const CgState* __restrict__ st) {
+  using F = ShapeFFT<T, LOGN, V>;
+  if (st && !st[blockIdx.y].active) return;   // this RHS has stopped iterating
   using PI = typename Pair<Tin>::type;
   using PO = typename Pair<T>::type;
   __shared__ __align__(16) char lds[F::LDS_BYTES];
@@ -540,56 +564,53 @@ __global__ __launch_bounds__(Shape<LOGN>::NT) void k_ols(
   }
 }
 
-template <typename T, typename Tin, int LOGN>
+template <typename T, typename Tin, int LOGN, int V = 0>
 static hipError_t ols_launch(const void* y_in, void* y_out, const OlsChunk* chunks, int n_chunks,
                              const void* spec, const void* ptw, const void* tw2, int64_t n_t, int n_c,
-                             int m, int n_rhs, hipStream_t s) {
-  hipLaunchKernelGGL((k_ols<T, Tin, LOGN>), dim3((unsigned)n_chunks, (unsigned)n_rhs),
-                     dim3(Shape<LOGN>::NT), 0, s, (const Tin*)y_in, (T*)y_out, chunks,
-                     (const T*)spec, (const cx<T>*)ptw, (const cx<T>*)tw2, n_t, n_c, m);
+                             int m, int n_rhs, hipStream_t s, const CgState* st) {
+  hipLaunchKernelGGL((k_ols<T, Tin, LOGN, V>), dim3((unsigned)n_chunks, (unsigned)n_rhs),
+                     dim3(OlsShape<LOGN, V>::NT), 0, s, (const Tin*)y_in, (T*)y_out, chunks,
+                     (const T*)spec, (const cx<T>*)ptw, (const cx<T>*)tw2, n_t, n_c, m, st);
   return hipGetLastError();
 }
 
 template <typename T, typename Tin>
-static hipError_t ols_dispatch(int logn, const void* y_in, void* y_out, const OlsChunk* chunks,
+static hipError_t ols_dispatch(int logn, int variant, const void* y_in, void* y_out, const OlsChunk* chunks,
                                int n_chunks, const void* spec, const void* ptw, const void* tw2,
-                               int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s) {
-#define MM_OLS_CASE(L) \
-  case L: return ols_launch<T, Tin, L>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s);
+                               int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s, const CgState* st) {
+  if (!ols_variant_exists(logn, sizeof(T) == 8, variant)) return hipErrorInvalidValue;
+#define MM_OLS_ARGS y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st
+  if constexpr (sizeof(T) == 4) {
+    if (variant == 1) return logn == 13 ? ols_launch<T, Tin, 13, 1>(MM_OLS_ARGS) : ols_launch<T, Tin, 14, 1>(MM_OLS_ARGS);
+    if (variant == 2) return ols_launch<T, Tin, 14, 2>(MM_OLS_ARGS);
+    if (logn == 15) return ols_launch<T, Tin, 15>(MM_OLS_ARGS);
+  }
+#define MM_OLS_CASE(L) case L: return ols_launch<T, Tin, L>(MM_OLS_ARGS);
   switch (logn) {
-    MM_OLS_CASE(6)
-    MM_OLS_CASE(7)
-    MM_OLS_CASE(8)
-    MM_OLS_CASE(9)
-    MM_OLS_CASE(10)
-    MM_OLS_CASE(11)
-    MM_OLS_CASE(12)
-    MM_OLS_CASE(13)
-    MM_OLS_CASE(14)
+    MM_OLS_CASE(6) MM_OLS_CASE(7) MM_OLS_CASE(8) MM_OLS_CASE(9) MM_OLS_CASE(10)
+    MM_OLS_CASE(11) MM_OLS_CASE(12) MM_OLS_CASE(13) MM_OLS_CASE(14)
     default: break;
   }
 #undef MM_OLS_CASE
-  if constexpr (sizeof(T) == 4) {
-    if (logn == 15)
-      return ols_launch<T, Tin, 15>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s);
-  }
+#undef MM_OLS_ARGS
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* y_out,
                       const OlsChunk* chunks, int n_chunks, const void* spec, const void* ptw,
-                      const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s) {
+                      const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s, int variant,
+                      const CgState* st) {
   if (n_chunks == 0 || n_rhs == 0) return hipSuccess;
   if (fp64) {
-    return in_f64 ? ols_dispatch<double, double>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
-                                                 n_t, n_c, m, n_rhs, s)
-                  : ols_dispatch<double, float>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
-                                                n_t, n_c, m, n_rhs, s);
+    return in_f64 ? ols_dispatch<double, double>(logn, variant, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
+                                                 n_t, n_c, m, n_rhs, s, st)
+                  : ols_dispatch<double, float>(logn, variant, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
+                                                n_t, n_c, m, n_rhs, s, st);
   }
-  return in_f64 ? ols_dispatch<float, double>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t,
-                                              n_c, m, n_rhs, s)
-                : ols_dispatch<float, float>(logn, y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t,
-                                             n_c, m, n_rhs, s);
+  return in_f64 ? ols_dispatch<float, double>(logn, variant, y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t,
+                                              n_c, m, n_rhs, s, st)
+                : ols_dispatch<float, float>(logn, variant, y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t,
+                                             n_c, m, n_rhs, s, st);
 }
 
 }  // namespace mm

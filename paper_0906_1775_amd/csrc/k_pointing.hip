@@ -29,7 +29,8 @@ template <typename Ty, int NS>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
                                                 const float2* __restrict__ w,
                                                 const double* __restrict__ p, int64_t vs,
-                                                Ty* __restrict__ y, int64_t n_t, int n_rhs) {
+                                                Ty* __restrict__ y, int64_t n_t, int n_rhs,
+                                                const CgState* __restrict__ st) {
   constexpr int U = kGatherUnroll;
   const int64_t step = (int64_t)gridDim.x * 256 * U;
   for (int64_t t0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; t0 < n_t; t0 += step) {
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
       if (NS == 3) sc[u] = t < n_t ? w[t] : make_float2(0.f, 0.f);
     }
     for (int r = 0; r < n_rhs; ++r) {
+      if (st && !st[r].active) continue;   // this RHS has stopped iterating
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
 
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
-                         hipStream_t s) {
+                         hipStream_t s, const CgState* st) {
   (void)n_obs;
   if (n_t == 0) return hipSuccess;
   int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
@@ -74,11 +76,11 @@ hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const flo
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
   if (out_f64) {
-    if (ns == 1) hipLaunchKernelGGL((k_gather<double, 1>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs);
-    else hipLaunchKernelGGL((k_gather<double, 3>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs);
+    if (ns == 1) hipLaunchKernelGGL((k_gather<double, 1>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs, st);
+    else hipLaunchKernelGGL((k_gather<double, 3>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs, st);
   } else {
-    if (ns == 1) hipLaunchKernelGGL((k_gather<float, 1>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs);
-    else hipLaunchKernelGGL((k_gather<float, 3>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs);
+    if (ns == 1) hipLaunchKernelGGL((k_gather<float, 1>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs, st);
+    else hipLaunchKernelGGL((k_gather<float, 3>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs, st);
   }
   return hipGetLastError();
 }
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
     double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
-    double* __restrict__ pq_part, int pq_stride, int pq_slot) {
+    double* __restrict__ pq_part, int pq_stride, int pq_slot, const CgState* __restrict__ st) {
   constexpr int W = kSliceWaves;
   __shared__ double part[W][NS][64];
   __shared__ double sh[W];
@@ -182,6 +184,7 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
   const int lane = tid & 63, wv = tid >> 6;
   const int64_t n_sl = (n_obs + 63) / 64;
   for (int r = 0; r < n_rhs; ++r) {
+    if (st && !st[r].active) continue;     // uniform over the block
     const Ty* __restrict__ yr = y + (int64_t)r * n_t;
     double pq = 0.0;
     for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
@@ -256,12 +259,12 @@ int scatter_blocks(int64_t n_obs) {
 
 hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
-                          double* pq_part, int pq_stride, int pq_slot) {
+                          double* pq_part, int pq_stride, int pq_slot, const CgState* st) {
   if (n_obs == 0) return hipSuccess;
   const dim3 g((unsigned)scatter_blocks(n_obs)), b(64 * kSliceWaves);
   const float2* w = (const float2*)L.w;
 #define MM_SC(T, NS) hipLaunchKernelGGL((k_scatter<T, NS>), g, b, 0, s, L.end, L.len, L.t, w, (const T*)y, q, vs, \
-                                        n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot)
+                                        n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot, st)
   if (in_f64) {
     if (ns == 1) MM_SC(double, 1);
     else MM_SC(double, 3);

@@ -29,12 +29,14 @@ static dim3 grid_for(int64_t n) {
 // ---------------------------------------------------------------- one-hot gather
 template <typename Ty>
 __global__ void k_onehot_gather(const int32_t* __restrict__ obs_idx, const double* __restrict__ p,
-                                int64_t vs, int64_t off, Ty* __restrict__ y, int64_t n_t, int n_rhs) {
+                                int64_t vs, int64_t off, Ty* __restrict__ y, int64_t n_t, int n_rhs,
+                                const CgState* __restrict__ st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += stride) {
     const int32_t o = obs_idx[t];
     if (o < 0) continue;
     for (int r = 0; r < n_rhs; ++r) {
+      if (st && !st[r].active) continue;
       const int64_t i = (int64_t)r * n_t + t;
       y[i] = (Ty)((double)y[i] + p[(int64_t)r * vs + off + o]);
     }
@@ -42,10 +44,10 @@ __global__ void k_onehot_gather(const int32_t* __restrict__ obs_idx, const doubl
 }
 
 hipError_t launch_onehot_gather(bool y_f64, const int32_t* obs_idx, const double* p, int64_t vs, int64_t off,
-                                void* y, int64_t n_t, int n_rhs, hipStream_t s) {
+                                void* y, int64_t n_t, int n_rhs, hipStream_t s, const CgState* st) {
   if (n_t == 0) return hipSuccess;
-  if (y_f64) hipLaunchKernelGGL(k_onehot_gather<double>, grid_for(n_t), dim3(256), 0, s, obs_idx, p, vs, off, (double*)y, n_t, n_rhs);
-  else hipLaunchKernelGGL(k_onehot_gather<float>, grid_for(n_t), dim3(256), 0, s, obs_idx, p, vs, off, (float*)y, n_t, n_rhs);
+  if (y_f64) hipLaunchKernelGGL(k_onehot_gather<double>, grid_for(n_t), dim3(256), 0, s, obs_idx, p, vs, off, (double*)y, n_t, n_rhs, st);
+  else hipLaunchKernelGGL(k_onehot_gather<float>, grid_for(n_t), dim3(256), 0, s, obs_idx, p, vs, off, (float*)y, n_t, n_rhs, st);
   return hipGetLastError();
 }
 
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void k_hwp_gather(const SampleTile* __restrict
                                                     const int64_t* __restrict__ seg_start,
                                                     const float* __restrict__ omega, const double* __restrict__ p,
                                                     int64_t vs, int64_t off, Ty* __restrict__ y, int64_t n_t,
-                                                    int n_rhs) {
+                                                    int n_rhs, const CgState* __restrict__ st) {
   __shared__ double a[kMaxRhs][kHwpColumns];
   const SampleTile T = tiles[blockIdx.x];
   for (int i = threadIdx.x; i < n_rhs * kHwpColumns; i += blockDim.x)
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(256) void k_hwp_gather(const SampleTile* __restrict
     hwp_harmonics(omega[t], c, sn);
     const double tau = hwp_tau(t, s0, L);
     for (int r = 0; r < n_rhs; ++r) {
+      if (st && !st[r].active) continue;
       const double* ar = a[r];
       double v = 0.0;
 #pragma unroll
@@ -99,11 +102,11 @@ __global__ __launch_bounds__(256) void k_hwp_gather(const SampleTile* __restrict
 
 hipError_t launch_hwp_gather(bool y_f64, const SampleTile* tiles, int n_tiles, const int64_t* seg_start,
                              const float* omega, const double* p, int64_t vs, int64_t off, void* y, int64_t n_t,
-                             int n_rhs, hipStream_t s) {
+                             int n_rhs, hipStream_t s, const CgState* st) {
   if (n_tiles == 0) return hipSuccess;
   if (n_rhs > kMaxRhs) return hipErrorInvalidValue;
-  if (y_f64) hipLaunchKernelGGL(k_hwp_gather<double>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega, p, vs, off, (double*)y, n_t, n_rhs);
-  else hipLaunchKernelGGL(k_hwp_gather<float>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega, p, vs, off, (float*)y, n_t, n_rhs);
+  if (y_f64) hipLaunchKernelGGL(k_hwp_gather<double>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega, p, vs, off, (double*)y, n_t, n_rhs, st);
+  else hipLaunchKernelGGL(k_hwp_gather<float>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega, p, vs, off, (float*)y, n_t, n_rhs, st);
   return hipGetLastError();
 }
 
@@ -129,7 +132,8 @@ __global__ __launch_bounds__(256) void k_hwp_scatter(const SampleTile* __restric
                                                      int64_t n_t, int n_rhs, double* __restrict__ partial, int mode,
                                                      const int64_t* __restrict__ iv_start, int n_iv,
                                                      const int32_t* __restrict__ iv_filter,
-                                                     const double* __restrict__ lags, int n_c) {
+                                                     const double* __restrict__ lags, int n_c,
+                                                     const CgState* __restrict__ st) {
   __shared__ double red[256 / 64][kHwpColumns];
   const SampleTile T = tiles[blockIdx.x];
   const int64_t s0 = seg_start[T.id];
@@ -137,6 +141,7 @@ __global__ __launch_bounds__(256) void k_hwp_scatter(const SampleTile* __restric
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int R = mode == 0 ? n_rhs : 1;
   for (int r = 0; r < R; ++r) {
+    if (st && !st[r].active) continue;     // uniform over the block
     double acc[kHwpColumns];
 #pragma unroll
     for (int i = 0; i < kHwpColumns; ++i) acc[i] = 0.0;
@@ -189,9 +194,10 @@ __global__ __launch_bounds__(256) void k_hwp_reduce(const double* __restrict__ p
                                                     const int32_t* __restrict__ seg_tile, int n_seg, int n_rhs,
                                                     double* __restrict__ q, int64_t vs, int64_t off,
                                                     const double* __restrict__ p, double* __restrict__ pq_part,
-                                                    int pq_stride, int pq_slot) {
+                                                    int pq_stride, int pq_slot, const CgState* __restrict__ st) {
   __shared__ double sh[256 / 64];
   const int r = blockIdx.x;
+  if (st && !st[r].active) return;
   double pq = 0.0;
   for (int64_t j = threadIdx.x; j < (int64_t)n_seg * kHwpColumns; j += blockDim.x) {
     const int g = (int)(j / kHwpColumns), i = (int)(j % kHwpColumns);
@@ -218,20 +224,20 @@ __global__ __launch_bounds__(256) void k_hwp_reduce(const double* __restrict__ p
 hipError_t launch_hwp_scatter(bool y_f64, const SampleTile* tiles, int n_tiles, const int32_t* seg_tile, int n_seg,
                               const int64_t* seg_start, const float* omega, const void* y, int64_t n_t, int n_rhs,
                               double* partial, double* q, int64_t vs, int64_t off, const double* p,
-                              double* pq_part, int pq_stride, int pq_slot, hipStream_t s) {
+                              double* pq_part, int pq_stride, int pq_slot, hipStream_t s, const CgState* st) {
   if (n_seg == 0) return hipSuccess;
   if (n_tiles > 0) {
     if (y_f64)
       hipLaunchKernelGGL(k_hwp_scatter<double>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega,
-                         (const double*)y, n_t, n_rhs, partial, 0, nullptr, 0, nullptr, nullptr, 1);
+                         (const double*)y, n_t, n_rhs, partial, 0, nullptr, 0, nullptr, nullptr, 1, st);
     else
       hipLaunchKernelGGL(k_hwp_scatter<float>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega,
-                         (const float*)y, n_t, n_rhs, partial, 0, nullptr, 0, nullptr, nullptr, 1);
+                         (const float*)y, n_t, n_rhs, partial, 0, nullptr, 0, nullptr, nullptr, 1, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_hwp_reduce, dim3(n_rhs), dim3(256), 0, s, partial, seg_tile, n_seg, n_rhs, q, vs, off, p,
-                     pq_part, pq_stride, pq_slot);
+                     pq_part, pq_stride, pq_slot, st);
   return hipGetLastError();
 }
 
@@ -244,12 +250,12 @@ hipError_t launch_hwp_diag(int kind, const SampleTile* tiles, int n_tiles, const
   if (n_tiles > 0) {
     hipLaunchKernelGGL(k_hwp_scatter<float>, dim3(n_tiles), dim3(256), 0, s, tiles, seg_start, omega,
                        (const float*)nullptr, (int64_t)0, 1, partial, kind == 0 ? 1 : 2, iv_start, n_iv, iv_filter,
-                       lags, n_c);
+                       lags, n_c, (const CgState*)nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_hwp_reduce, dim3(1), dim3(256), 0, s, partial, seg_tile, n_seg, 1, diag, (int64_t)0,
-                     (int64_t)0, (const double*)nullptr, (double*)nullptr, 0, 0);
+                     (int64_t)0, (const double*)nullptr, (double*)nullptr, 0, 0, (const CgState*)nullptr);
   return hipGetLastError();
 }
 
@@ -290,9 +296,10 @@ hipError_t launch_copy_rows(const double* src, int64_t src_stride, double* dst, 
 template <typename Ti, typename To>
 __global__ __launch_bounds__(256) void k_white(const SampleTile* __restrict__ tiles, const int32_t* __restrict__ iv_filter,
                                                const double* __restrict__ lags, int n_c, const Ti* __restrict__ y_in,
-                                               To* __restrict__ y_out, int64_t n_t) {
+                                               To* __restrict__ y_out, int64_t n_t, const CgState* __restrict__ st) {
   const SampleTile T = tiles[blockIdx.x];
   const int r = blockIdx.y;
+  if (st && !st[r].active) return;
   const double f0 = lags[(int64_t)iv_filter[T.id] * n_c];
   const Ti* yi = y_in + (int64_t)r * n_t;
   To* yo = y_out + (int64_t)r * n_t;
@@ -301,13 +308,13 @@ __global__ __launch_bounds__(256) void k_white(const SampleTile* __restrict__ ti
 
 hipError_t launch_white(bool out_f64, bool in_f64, const SampleTile* tiles, int n_tiles, const int32_t* iv_filter,
                         const double* lags, int n_c, const void* y_in, void* y_out, int64_t n_t, int n_rhs,
-                        hipStream_t s) {
+                        hipStream_t s, const CgState* st) {
   if (n_tiles == 0) return hipSuccess;
   const dim3 g(n_tiles, n_rhs), b(256);
-  if (in_f64 && out_f64) hipLaunchKernelGGL((k_white<double, double>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const double*)y_in, (double*)y_out, n_t);
-  else if (in_f64) hipLaunchKernelGGL((k_white<double, float>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const double*)y_in, (float*)y_out, n_t);
-  else if (out_f64) hipLaunchKernelGGL((k_white<float, double>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const float*)y_in, (double*)y_out, n_t);
-  else hipLaunchKernelGGL((k_white<float, float>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const float*)y_in, (float*)y_out, n_t);
+  if (in_f64 && out_f64) hipLaunchKernelGGL((k_white<double, double>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const double*)y_in, (double*)y_out, n_t, st);
+  else if (in_f64) hipLaunchKernelGGL((k_white<double, float>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const double*)y_in, (float*)y_out, n_t, st);
+  else if (out_f64) hipLaunchKernelGGL((k_white<float, double>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const float*)y_in, (double*)y_out, n_t, st);
+  else hipLaunchKernelGGL((k_white<float, float>), g, b, 0, s, tiles, iv_filter, lags, n_c, (const float*)y_in, (float*)y_out, n_t, st);
   return hipGetLastError();
 }
 

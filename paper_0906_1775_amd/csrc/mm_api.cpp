@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -87,6 +88,7 @@ struct FilterSetup {
   bool ready = false;
   bool fp64 = true;
   int logn = 0;
+  int variant = 0;         // workgroup shape of the transform (ols_variant_exists)
   int N = 0, nf = 0, m = 0;
   void* tw2 = nullptr;     // exp(-2 pi i k / n_f), k < N (real-to-complex packing)
   void* ptw = nullptr;     // per-pass twiddle tables of the transform
@@ -94,6 +96,95 @@ struct FilterSetup {
   OlsChunk* chunks = nullptr;
   int n_chunks = 0;
 };
+
+// Device memory and streams of destroyed plans, kept per device for later
+// plans of the process: hipFree synchronises the whole device and hipMalloc of
+// large blocks maps pages, which together cost more than the plan's kernels.
+// At most kCacheCap bytes stay cached per device; a failed hipMalloc empties
+// the cache and retries once.
+constexpr size_t kCacheCap = size_t(16) << 30;
+
+struct DeviceCache {
+  std::mutex mu;
+  std::vector<std::pair<size_t, void*>> blocks[64];
+  size_t held[64] = {};
+  std::vector<hipStream_t> streams[64];
+};
+
+DeviceCache& cache() {
+  static DeviceCache* c = new DeviceCache();   // never destroyed: blocks outlive static teardown
+  return *c;
+}
+
+// smallest cached block of at least b bytes and at most b + b/8 + 1 MiB
+void* cache_take(int dev, size_t b, size_t* got) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  DeviceCache& c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto& v = c.blocks[dev];
+  const size_t hi = b + b / 8 + (size_t(1) << 20);
+  size_t best = v.size();
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].first >= b && v[i].first <= hi && (best == v.size() || v[i].first < v[best].first)) best = i;
+  if (best == v.size()) return nullptr;
+  void* p = v[best].second;
+  *got = v[best].first;
+  c.held[dev] -= v[best].first;
+  v.erase(v.begin() + best);
+  return p;
+}
+
+void cache_put(int dev, size_t b, void* p) {
+  DeviceCache& c = cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (dev >= 0 && dev < 64 && c.held[dev] + b <= kCacheCap) {
+      c.blocks[dev].push_back({b, p});
+      c.held[dev] += b;
+      return;
+    }
+  }
+  hipFree(p);
+}
+
+void cache_flush(int dev) {
+  if (dev < 0 || dev >= 64) return;
+  std::vector<std::pair<size_t, void*>> v;
+  {
+    DeviceCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    v.swap(c.blocks[dev]);
+    c.held[dev] = 0;
+  }
+  for (auto& e : v) hipFree(e.second);
+}
+
+hipStream_t stream_take(int dev) {
+  if (dev >= 0 && dev < 64) {
+    DeviceCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (!c.streams[dev].empty()) {
+      hipStream_t st = c.streams[dev].back();
+      c.streams[dev].pop_back();
+      return st;
+    }
+  }
+  hipStream_t st = nullptr;
+  hipchk(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream");
+  return st;
+}
+
+void stream_put(int dev, hipStream_t st) {
+  if (dev >= 0 && dev < 64) {
+    DeviceCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.streams[dev].size() < 16) {
+      c.streams[dev].push_back(st);
+      return;
+    }
+  }
+  hipStreamDestroy(st);
+}
 
 // Pixel-major layout of one pointing matrix with one non-zero per row: the sky
 // pointing, or a one-hot template read as a temperature-only pointing.
@@ -137,6 +228,7 @@ struct mm_plan_s {
   int n_iv = 0, n_filt = 0, n_c = 0;
   int precision = MM_FP64, precond = MM_PRECOND_BLOCK, R = 1;
   int nf_req = 0;
+  int shape_req = 0;            // requested transform shape (0 = default)
   int64_t lag_len = 0;
   double f_samp = 0;
   std::vector<int64_t> iv_start;
@@ -151,7 +243,7 @@ struct mm_plan_s {
   int64_t n_obs = 0, n_valid = 0;
   const float* w = nullptr;     // caller's (sin, cos) pairs, time-major
   Layout px;                    // sky pointing
-  std::vector<std::pair<int, float>> tuned;   // (n_f, ms per filter pass) tried by the autotuner
+  std::vector<std::pair<int, float>> tuned;   // (n_f * kOlsVariants + shape, ms per filter pass) tried by the autotuner
 
   // templates
   std::vector<Template> tmpl;
@@ -192,34 +284,63 @@ struct mm_plan_s {
   int graph_k = 0;
   const double* graph_hist = nullptr;
 
-  std::vector<void*> allocs;
+  // live device blocks, and blocks the plan released: the plan's own work is
+  // stream-ordered, so a released block is reused by its later allocations at once
+  std::vector<std::pair<size_t, void*>> allocs, spare;
   int64_t bytes = 0;
 
   template <typename T>
   T* alloc(int64_t count) {
     if (count <= 0) count = 1;
-    void* p = nullptr;
     const size_t b = (size_t)count * sizeof(T);
-    hipchk(hipMalloc(&p, b), "hipMalloc");
-    allocs.push_back(p);
-    bytes += (int64_t)b;
+    void* p = nullptr;
+    const size_t hi = b + b / 8 + (size_t(1) << 20);
+    size_t best = spare.size();
+    for (size_t i = 0; i < spare.size(); ++i)
+      if (spare[i].first >= b && spare[i].first <= hi && (best == spare.size() || spare[i].first < spare[best].first))
+        best = i;
+    size_t got = b;
+    if (best < spare.size()) {
+      got = spare[best].first;
+      p = spare[best].second;
+      spare.erase(spare.begin() + best);
+    } else if ((p = cache_take(device, b, &got)) != nullptr) {
+    } else {
+      hipError_t e = hipMalloc(&p, b);
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        for (auto& s : spare) hipFree(s.second);
+        spare.clear();
+        cache_flush(device);
+        e = hipMalloc(&p, b);
+      }
+      hipchk(e, "hipMalloc");
+    }
+    allocs.push_back({got, p});
+    bytes += (int64_t)got;
     return (T*)p;
   }
   void release(void* p) {
     if (!p) return;
-    auto it = std::find(allocs.begin(), allocs.end(), p);
-    if (it != allocs.end()) {
-      allocs.erase(it);
-      hipFree(p);
-    }
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i].second == p) {
+        spare.push_back(allocs[i]);
+        bytes -= (int64_t)allocs[i].first;
+        allocs.erase(allocs.begin() + i);
+        return;
+      }
   }
   ~mm_plan_s() {
     if (graph) hipGraphExecDestroy(graph);
-    for (void* p : allocs) hipFree(p);
+    // work the caller queued on its own streams may still read the blocks: drain
+    // the device once before they become available to other plans
+    hipDeviceSynchronize();
+    for (auto& a : allocs) cache_put(device, a.first, a.second);
+    for (auto& a : spare) cache_put(device, a.first, a.second);
     if (st_host) hipHostFree(st_host);
     if (ev_in) hipEventDestroy(ev_in);
     if (ev_out) hipEventDestroy(ev_out);
-    if (own) hipStreamDestroy(own);
+    if (own) stream_put(device, own);
   }
 
   int64_t nmap() const { return n_obs * ns; }            // map unknowns per RHS
@@ -232,7 +353,7 @@ namespace {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
-void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s);
+void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant = 0);
 
 void release_filter(mm_plan_s* P, FilterSetup& fs) {
   P->release(fs.chunks);
@@ -242,8 +363,8 @@ void release_filter(mm_plan_s* P, FilterSetup& fs) {
   fs = FilterSetup();
 }
 
-// Autotuner: build every admissible on-chip transform length and keep the one
-// whose overlap-save pass over the plan's own intervals runs fastest.
+// Autotuner: build every admissible on-chip transform (length x workgroup shape)
+// and keep the one whose overlap-save pass over the plan's own intervals runs fastest.
 void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
   const int maxlog = ols_max_logn(fp64);
   int64_t longest = 1;
@@ -262,27 +383,30 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
   float best_ms = 0;
   P->tuned.clear();
   for (; ilog2(nf) - 1 <= maxlog; nf <<= 1) {
-    FilterSetup cand;
-    build_filter_nf(P, cand, fp64, nf, s);
-    hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw, cand.tw2,
-                      P->n_t, P->n_c, cand.m, 1, s),
-           "autotune warm-up");
-    hipchk(hipEventRecord(e0, s), "event");
-    for (int rep = 0; rep < 3; ++rep)
-      hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw,
-                        cand.tw2, P->n_t, P->n_c, cand.m, 1, s),
-             "autotune");
-    hipchk(hipEventRecord(e1, s), "event");
-    hipchk(hipEventSynchronize(e1), "autotune");
-    float ms = 0;
-    hipchk(hipEventElapsedTime(&ms, e0, e1), "event time");
-    P->tuned.push_back({(int)nf, ms / 3.0f});
-    if (!fs.ready || ms < best_ms) {
-      if (fs.ready) release_filter(P, fs);
-      fs = cand;
-      best_ms = ms;
-    } else {
-      release_filter(P, cand);
+    for (int v = 0; v < kOlsVariants; ++v) {
+      if (!ols_variant_exists(ilog2(nf) - 1, fp64, v)) continue;
+      FilterSetup cand;
+      build_filter_nf(P, cand, fp64, nf, s, v);
+      hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw, cand.tw2,
+                        P->n_t, P->n_c, cand.m, 1, s, v),
+             "autotune warm-up");
+      hipchk(hipEventRecord(e0, s), "event");
+      for (int rep = 0; rep < 3; ++rep)
+        hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw,
+                          cand.tw2, P->n_t, P->n_c, cand.m, 1, s, v),
+               "autotune");
+      hipchk(hipEventRecord(e1, s), "event");
+      hipchk(hipEventSynchronize(e1), "autotune");
+      float ms = 0;
+      hipchk(hipEventElapsedTime(&ms, e0, e1), "event time");
+      P->tuned.push_back({(int)nf * kOlsVariants + v, ms / 3.0f});
+      if (!fs.ready || ms < best_ms) {
+        if (fs.ready) release_filter(P, fs);
+        fs = cand;
+        best_ms = ms;
+      } else {
+        release_filter(P, cand);
+      }
     }
     if ((nf >> 1) >= 2 * longest) break;   // longer transforms only add padding
   }
@@ -291,6 +415,10 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
 }
+
+// transform shape used when the descriptor leaves it open: the fastest measured
+// for each length (float32 2^14 points: 512 threads x 32 points, radix-16 passes)
+int default_ols_variant(int logn, bool fp64) { return (!fp64 && logn == 14) ? 2 : 0; }
 
 void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
   const int maxlog = ols_max_logn(fp64);
@@ -313,10 +441,11 @@ void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool 
     }
     nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
   }
-  build_filter_nf(P, fs, fp64, nf, s);
+  const int variant = P->shape_req > 0 ? P->shape_req - 1 : default_ols_variant(ilog2(nf) - 1, fp64);
+  build_filter_nf(P, fs, fp64, nf, s, variant);
 }
 
-void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s) {
+void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant) {
   const int maxlog = ols_max_logn(fp64);
   const int logn = ilog2(nf) - 1;
   if (logn > maxlog)
@@ -324,8 +453,10 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
                               std::to_string(int64_t(1) << (maxlog + 1)) +
                               (fp64 ? " for float64" : " for float32"));
   if (logn < kMinLogN) fail(MM_EUNSUPPORTED, "FFT length below 128");
+  if (!ols_variant_exists(logn, fp64, variant)) variant = 0;
   fs.fp64 = fp64;
   fs.logn = logn;
+  fs.variant = variant;
   fs.N = 1 << logn;
   fs.nf = (int)nf;
   fs.m = fs.nf - 2 * P->n_c;
@@ -345,10 +476,10 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   const int esz = fp64 ? 8 : 4;
   fs.tw2 = P->alloc<char>((int64_t)fs.N * 2 * esz);
   hipchk(launch_tw2_table(fs.tw2, logn, fp64, s), "twiddle table");
-  const int ntw = pass_twiddle_count(logn, fp64);
+  const int ntw = pass_twiddle_count(logn, fp64, variant);
   if (ntw < 0) fail(MM_EUNSUPPORTED, "no transform for this FFT length");
   fs.ptw = P->alloc<char>((int64_t)std::max(ntw, 1) * 2 * esz);
-  hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s), "pass twiddle tables");
+  hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s, variant), "pass twiddle tables");
   fs.spec = P->alloc<char>((int64_t)P->n_filt * (fs.N + 1) * esz);
   char* sscr = P->alloc<char>((int64_t)spectra_scratch_bytes(logn));
   hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, sscr, s), "filter spectra");
@@ -359,29 +490,31 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
 
 // y_out = N^-1 y_in with the transforms of fs (or the diagonal f_b(0) when
 // n_c = 1); in_f64 = element type of y_in; y_out has the element type of fs
+// st (optional): CG states, rows of RHS that stopped iterating are skipped
 void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, void* y_out, int R,
-            hipStream_t s) {
+            hipStream_t s, const CgState* st = nullptr) {
   if (P->n_c == 1) {
     hipchk(launch_white(fs.fp64, in_f64, P->white_tiles, P->n_white_tiles, P->d_iv_filter, P->lags, P->n_c, y_in,
-                        y_out, P->n_t, R, s),
+                        y_out, P->n_t, R, s, st),
            "white-noise weight");
     return;
   }
   hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, fs.spec, fs.ptw,
-                    fs.tw2, P->n_t, P->n_c, fs.m, R, s),
+                    fs.tw2, P->n_t, P->n_c, fs.m, R, s, fs.variant, st),
          "overlap-save filter");
 }
 
 // y_r = [P B] x_r: x in iteration layout (rows of stride nu), y a TOD of type y_f64
-void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipStream_t s) {
+void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipStream_t s,
+                const CgState* st = nullptr) {
   const int64_t vs = P->nu();
-  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s), "gather");
+  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s, st), "gather");
   for (const Template& T : P->tmpl) {
     const int64_t off = P->nmap() + T.ooff;
     if (T.kind == MM_TMPL_ONEHOT)
-      hipchk(launch_onehot_gather(y_f64, T.lay.obs_idx, x, vs, off, y, P->n_t, R, s), "template gather");
+      hipchk(launch_onehot_gather(y_f64, T.lay.obs_idx, x, vs, off, y, P->n_t, R, s, st), "template gather");
     else
-      hipchk(launch_hwp_gather(y_f64, T.tiles, T.n_tiles, T.d_seg, T.omega, x, vs, off, y, P->n_t, R, s),
+      hipchk(launch_hwp_gather(y_f64, T.tiles, T.n_tiles, T.d_seg, T.omega, x, vs, off, y, P->n_t, R, s, st),
              "template gather");
   }
 }
@@ -389,20 +522,20 @@ void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipSt
 // q_r = [P B]^T y_r (iteration layout); with p also the p.q partial sums of
 // every scatter block in part_pq [R][n_pq]
 void scatter_all(mm_plan_s* P, bool y_f64, const void* y, double* q, int R, hipStream_t s,
-                 const double* p = nullptr) {
+                 const double* p = nullptr, const CgState* st = nullptr) {
   const int64_t vs = P->nu();
-  hipchk(launch_scatter(y_f64, P->ns, P->px.sell, y, q, vs, P->n_obs, P->n_t, R, s, p, P->part_pq, P->n_pq, 0),
+  hipchk(launch_scatter(y_f64, P->ns, P->px.sell, y, q, vs, P->n_obs, P->n_t, R, s, p, P->part_pq, P->n_pq, 0, st),
          "scatter");
   for (const Template& T : P->tmpl) {
     const int64_t off = P->nmap() + T.ooff;
     if (T.kind == MM_TMPL_ONEHOT) {
       if (T.lay.n_obs == 0) continue;
       hipchk(launch_scatter(y_f64, 1, T.lay.sell, y, q + off, vs, T.lay.n_obs, P->n_t, R, s, p ? p + off : nullptr,
-                            P->part_pq, P->n_pq, T.pq_slot),
+                            P->part_pq, P->n_pq, T.pq_slot, st),
              "template scatter");
     } else {
       hipchk(launch_hwp_scatter(y_f64, T.tiles, T.n_tiles, T.d_seg_tile, T.n_seg, T.d_seg, T.omega, y, P->n_t, R,
-                                T.partial, q, vs, off, p, P->part_pq, P->n_pq, T.pq_slot, s),
+                                T.partial, q, vs, off, p, P->part_pq, P->n_pq, T.pq_slot, s, st),
              "template scatter");
     }
   }
@@ -676,6 +809,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
   if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
     fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
+  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 3]");
   validate_templates(d);
 
   P->ns = d->n_stokes;
@@ -688,6 +822,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->precond = d->precond;
   P->R = d->n_rhs;
   P->nf_req = d->n_f;
+  P->shape_req = d->fft_shape;
   P->f_samp = d->f_samp;
   P->w = d_w;
   P->iv_start.assign(d->iv_start, d->iv_start + d->n_intervals + 1);
@@ -714,7 +849,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   }
 
   hipchk(hipGetDevice(&P->device), "hipGetDevice");
-  hipchk(hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking), "stream");
+  P->own = stream_take(P->device);
   hipchk(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming), "event");
   hipchk(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming), "event");
   hipchk(hipHostMalloc((void**)&P->st_host, sizeof(CgState) * P->R, hipHostMallocDefault), "pinned state");
@@ -828,9 +963,11 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
 void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   const int R = P->R;
   // q = H p, with the partial sums of p.q formed by the scatters
-  gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s);
-  weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s);
-  scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp);
+  // (RHS that stopped iterating skip the TOD work: convergence is checked by
+  // the host only every check_every iterations)
+  gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s, P->st);
+  weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s, P->st);
+  scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp, P->st);
   hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, P->nu(), P->minv_t,
                           P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
@@ -1172,6 +1309,7 @@ mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
     info->n_singular = P->n_singular;
     info->n_sliced = P->px.sell_entries;
     info->n_tmpl = P->n_tglob;
+    info->fft_shape = P->fs_main.variant + 1;
     info->device_bytes = P->bytes;
   });
 }
@@ -1304,7 +1442,7 @@ mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_u, const void* d_v, int
           const void* u_r = (const char*)d_u + (size_t)r * P->n_t * esz;
           const void* v_r = (const char*)d_v + (size_t)r * P->n_t * esz;
           hipchk(launch_ols(true, in64, f64.logn, v_r, yb, f64.chunks, f64.n_chunks, dspec, f64.ptw, f64.tw2,
-                            P->n_t, P->n_c, f64.m, 1, s),
+                            P->n_t, P->n_c, f64.m, 1, s, f64.variant),
                  "derivative filter");
           hipchk(launch_convert(in64, true, u_r, ya, P->n_t, s), "convert");
           hipchk(launch_interval_dots(ya, yb, P->d_iv_start, P->n_iv, ivd, s), "interval dots");

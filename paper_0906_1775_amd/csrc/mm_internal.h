@@ -63,8 +63,12 @@ __device__ __forceinline__ double group_sum(double v) {
 int ols_max_logn(bool fp64);
 hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s);
 // per-pass twiddle tables of the workgroup transform of 2^logn points
-int pass_twiddle_count(int logn, bool fp64);
-hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s);
+// (variant: workgroup shape of the overlap-save transform; 0 for every other use)
+int pass_twiddle_count(int logn, bool fp64, int variant = 0);
+hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, int variant = 0);
+// whether the overlap-save transform of 2^logn points has workgroup shape `variant`
+constexpr int kOlsVariants = 3;
+bool ols_variant_exists(int logn, bool fp64, int variant);
 // lags (mode 0) or their derivative with respect to sigma (1), f_knee (2), alpha (3)
 hipError_t launch_lags(const double* params /*dev [nf][3]*/, int n_filters, double f_samp, int n_c,
                        int64_t lag_len, double* lags /*dev [nf][n_c]*/, void* scratch,
@@ -75,15 +79,17 @@ size_t spectra_scratch_bytes(int logn);
 hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, bool fp64,
                           void* spec /*[nf][N+1]*/, void* scratch, hipStream_t s);
 // y_out[r][t] = (N^-1 y_in)[r][t]; compute type T (fp64 flag); input type in_f64; output type T
+// st (optional): per-RHS CG states; rows of RHS no longer active are skipped
 hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* y_out,
                       const OlsChunk* chunks, int n_chunks, const void* spec, const void* ptw,
-                      const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s);
+                      const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s,
+                      int variant = 0, const CgState* st = nullptr);
 
 // ---------------------------------------------------------------- pointing (k_pointing.hip)
 // y[r][t] = (P p_r)_t; p rows of stride vs (map values first, observed layout)
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
-                         hipStream_t s);
+                         hipStream_t s, const CgState* st = nullptr);
 // Sliced pixel-major pointing (64 pixels per slice, one lane per pixel)
 struct SellLayout {
   const uint32_t* end = nullptr;   // [n_slices] inclusive prefix sum of the slice sizes
@@ -101,7 +107,7 @@ hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const f
 hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s,
                           const double* p = nullptr, double* pq_part = nullptr, int pq_stride = 0,
-                          int pq_slot = 0);
+                          int pq_slot = 0, const CgState* st = nullptr);
 int scatter_blocks(int64_t n_obs);
 hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, int64_t n,
                           hipStream_t s);
@@ -181,17 +187,18 @@ hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, 
 // ---------------------------------------------------------------- templates (k_template.hip)
 // y[r][t] += p[r * vs + off + obs_idx[t]] where obs_idx[t] >= 0
 hipError_t launch_onehot_gather(bool y_f64, const int32_t* obs_idx, const double* p, int64_t vs, int64_t off,
-                                void* y, int64_t n_t, int n_rhs, hipStream_t s);
+                                void* y, int64_t n_t, int n_rhs, hipStream_t s, const CgState* st = nullptr);
 // y[r][t] += sum of the 32 HWP columns of t's segment times p[r * vs + off + 32 seg + i]
 hipError_t launch_hwp_gather(bool y_f64, const SampleTile* tiles, int n_tiles, const int64_t* seg_start,
                              const float* omega, const double* p, int64_t vs, int64_t off, void* y, int64_t n_t,
-                             int n_rhs, hipStream_t s);
+                             int n_rhs, hipStream_t s, const CgState* st = nullptr);
 // q[r * vs + off + 32 g + i] = sum over segment g of C[t][i] y[r][t] (tile partials in `partial`,
 // [n_tiles][n_rhs][32]); with p also the block's p.q in pq_part[r * pq_stride + pq_slot]
 hipError_t launch_hwp_scatter(bool y_f64, const SampleTile* tiles, int n_tiles, const int32_t* seg_tile, int n_seg,
                               const int64_t* seg_start, const float* omega, const void* y, int64_t n_t, int n_rhs,
                               double* partial, double* q, int64_t vs, int64_t off, const double* p,
-                              double* pq_part, int pq_stride, int pq_slot, hipStream_t s);
+                              double* pq_part, int pq_stride, int pq_slot, hipStream_t s,
+                              const CgState* st = nullptr);
 // diag[32 g + i] = sum over segment g of C[t][i]^2 w_t, w_t = f_b(0) (kind 0) or 1 (kind 1)
 hipError_t launch_hwp_diag(int kind, const SampleTile* tiles, int n_tiles, const int32_t* seg_tile, int n_seg,
                            const int64_t* seg_start, const float* omega, const int64_t* iv_start, int n_iv,
@@ -203,6 +210,6 @@ hipError_t launch_copy_rows(const double* src, int64_t src_stride, double* dst, 
 // y_out = f_b(0) y_in over tiles of the stationary intervals (white noise, n_c = 1)
 hipError_t launch_white(bool out_f64, bool in_f64, const SampleTile* tiles, int n_tiles, const int32_t* iv_filter,
                         const double* lags, int n_c, const void* y_in, void* y_out, int64_t n_t, int n_rhs,
-                        hipStream_t s);
+                        hipStream_t s, const CgState* st = nullptr);
 
 }  // namespace mm

@@ -48,7 +48,7 @@ class MapMaker:
     def __init__(self, pix: torch.Tensor, w: Optional[torch.Tensor], n_pix: int, n_stokes: int,
                  iv_start, iv_filter, filter_params=None, filter_lags=None, f_samp: float = 0.0,
                  n_c: int = 1, n_f: int = 0, lag_dft_len: int = 0, precision: str = "fp64",
-                 precond: str = "block", n_rhs: int = 1, templates=None):
+                 precond: str = "block", n_rhs: int = 1, templates=None, fft_shape: int = 0):
         """``templates``: optional list of dicts, each
         ``{"kind": "onehot", "idx": int32 CUDA tensor [n_samples], "n_amp": int}`` or
         ``{"kind": "hwp", "omega": float32 CUDA tensor [n_samples], "seg_start": int sequence}``;
@@ -89,6 +89,7 @@ class MapMaker:
         d.precision = _PREC[precision]
         d.precond = _PRECOND[precond]
         d.n_rhs = self.n_rhs
+        d.fft_shape = int(fft_shape)
         self._tmpl_keep = []
         self.templates = list(templates or [])
         if self.templates:
@@ -141,7 +142,7 @@ class MapMaker:
         L.check(self._lib.mm_plan_get_info(self._h, ctypes.byref(i)), self._lib)
         return dict(n_obs=i.n_obs, n_valid=i.n_valid, n_f=i.n_f, n_chunks=i.n_chunks,
                     n_singular=i.n_singular, device_bytes=i.device_bytes, n_sliced=i.n_sliced,
-                    n_tmpl=i.n_tmpl)
+                    n_tmpl=i.n_tmpl, fft_shape=i.fft_shape)
 
     def split(self, x: torch.Tensor):
         """(map view [n_rhs, n_pix, n_stokes], [amplitude views, one per template]) of a

@@ -34,10 +34,11 @@ def _gen(name, **kw):
     return p
 
 
-def _plan(p, precision, n_f=0):
+def _plan(p, precision, n_f=0, fft_shape=0):
     from paper_0906_1775_amd import MapMaker
     return MapMaker(p.pix, p.w, p.n_pix, 3, p.iv_start, p.iv_filter, filter_params=p.filter_params,
-                    f_samp=p.f_samp, n_c=p.n_c, n_f=n_f, precision=precision, n_rhs=p.n_rhs)
+                    f_samp=p.f_samp, n_c=p.n_c, n_f=n_f, precision=precision, n_rhs=p.n_rhs,
+                    fft_shape=fft_shape)
 
 
 def _host_oracle(p):
@@ -181,7 +182,26 @@ def test_autotuned_transform_length(precision):
     mm = _plan(p, precision, n_f=-1)
     nf = mm.info()["n_f"]
     assert nf & (nf - 1) == 0 and nf > 2 * p.n_c
+    assert mm.info()["fft_shape"] in ((1, 2, 3) if precision == "mixed" else (1,))
     x = _random_map(1, p.n_pix, 17)
     hx = mm.apply_A(x).cpu().numpy()[0]
     want = o.to_global(o.apply_H(o.to_observed(x[0].cpu().numpy())))
     assert max_rel(hx, want) <= TOL[precision]
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3])
+def test_forced_transform_shapes_match_the_oracle(shape):
+    """Each workgroup shape of the 2^14-point float32 transform gives the oracle's H x;
+    float64 plans, which have one shape, fall back to it."""
+    p = _gen("c3", n_det=2, det_len=1 << 18)
+    o = _host_oracle(p)
+    mm = _plan(p, "mixed", n_f=32768, fft_shape=shape)
+    assert mm.info()["fft_shape"] == shape and mm.info()["n_f"] == 32768
+    x = _random_map(1, p.n_pix, 19)
+    hx = mm.apply_A(x).cpu().numpy()[0]
+    want = o.to_global(o.apply_H(o.to_observed(x[0].cpu().numpy())))
+    assert max_rel(hx, want) <= TOL["mixed"]
+    y = p.tod[:1].contiguous()
+    wy = mm.weight(y).double().cpu().numpy()[0]
+    assert max_rel(wy, o.apply_ninv(y.double().cpu().numpy()[0])) <= 1e-5
+    assert _plan(p, "fp64", n_f=32768, fft_shape=shape).info()["fft_shape"] == 1
