@@ -220,23 +220,28 @@ typedef struct {
   int32_t use_graph;            /* capture each block of check_every iterations in a hipGraph */
   int32_t true_residual;        /* recompute ||b - H x_best|| / ||b|| in float64 at exit */
   const double* d_x0;           /* optional initial map [n_rhs][n_pix][n_stokes]; NULL = 0 */
-  int32_t refine;               /* MM_MIXED only: 1 = float64 residual correction (the float32-
-                                   operator PCG solves for corrections of the float64 residual
-                                   b - H x, recomputed with the float64 filter after each inner
-                                   solve; the map then reaches float64 accuracy); 0 = plain
+  int32_t refine;               /* MM_MIXED only: 1 = reliable updates: the iterate and the CG
+                                   vectors are float64 and H is applied in float32; at the host's
+                                   check points each RHS whose recurrence residual fell tenfold
+                                   since its last replacement (or reached tol) gets its residual
+                                   replaced by the float64 true residual b - H x (float64 filter)
+                                   and CG continues along the same direction; tol is tested on
+                                   those true residuals and the iterate with the lowest one is
+                                   returned, so the map reaches float64 accuracy.  0 = plain
                                    mixed iterations.  Ignored with fixed_iters. */
 } mm_solve_opts_t;
 
 typedef struct {
   int32_t* iters;               /* [n_rhs] H applications performed per RHS */
   int32_t* best_iter;           /* [n_rhs] iteration of the returned iterate (0 = x0) */
-  double* best_rel_res;         /* [n_rhs] its recurrence relative residual */
+  double* best_rel_res;         /* [n_rhs] its relative residual (recurrence; true with refine) */
   double* true_rel_res;         /* [n_rhs] float64 ||b - H x||/||b|| of the returned map, or NaN
                                    (always set with refine; with true_residual otherwise) */
   double* history;              /* [n_rhs][n + 1], n = fixed_iters if > 0 else max_iter:
                                    relative residual per iteration (entry 0 = start, NaN after
-                                   the last iteration); with refine, inner residuals scaled to
-                                   ||b|| and the float64 residual at each correction; may be NULL */
+                                   the last iteration); with refine, the recurrence residual
+                                   between replacements and the float64 true residual at each
+                                   replacement; may be NULL */
 } mm_solve_info_t;
 
 /* Fill opts with the paper's defaults (tol 1e-6, max_iter 50) and check_every 8, graph on,

@@ -273,7 +273,8 @@ struct mm_plan_s {
          *vxb = nullptr, *vb = nullptr;   // [R][nu]
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
   double* part_pq = nullptr;     // [R][n_pq] partial sums of p.q
-  double *vb64 = nullptr, *vr64 = nullptr, *vxacc = nullptr, *vxbest = nullptr;  // residual correction
+  double *vb64 = nullptr, *vxbest = nullptr;   // mixed refinement: b and the best iterate in float64
+  double* vxacc = nullptr;                      // accumulated map of the restarted correction
   CgState* st = nullptr;
   CgState* st_host = nullptr;
   double* hist = nullptr;
@@ -987,6 +988,36 @@ std::vector<double> dots(mm_plan_s* P, const double* x, const double* y, int R, 
   return out;
 }
 
+// queue `step` PCG iterations; a full block of k iterations runs as one hipGraph,
+// captured once per plan (and k)
+void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph) {
+  if (use_graph && step == k && k > 0) {
+    if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
+      if (P->graph) {
+        hipGraphExecDestroy(P->graph);
+        P->graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+      try {
+        for (int i = 0; i < k; ++i) enqueue_iteration(P, s);
+      } catch (...) {
+        hipStreamEndCapture(s, &g);
+        if (g) hipGraphDestroy(g);
+        throw;
+      }
+      hipchk(hipStreamEndCapture(s, &g), "end capture");
+      hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
+      hipGraphDestroy(g);
+      P->graph_k = k;
+      P->graph_hist = P->hist;
+    }
+    hipchk(hipGraphLaunch(P->graph, s), "graph launch");
+  } else {
+    for (int i = 0; i < step; ++i) enqueue_iteration(P, s);
+  }
+}
+
 // PCG on H x = vb (observed layout) in the iteration precision of fs_main.
 // vb must hold the right-hand sides; x0 is read from vx when have_x0.  On
 // exit vxb holds the lowest-residual iterate and st_host the final states.
@@ -1025,31 +1056,7 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
   const int k = std::min(check_every, std::max(1, n_max));
   while (!finished && done < n_max) {
     const int step = std::min(k, n_max - done);
-    if (use_graph && step == k && k > 0) {
-      if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
-        if (P->graph) {
-          hipGraphExecDestroy(P->graph);
-          P->graph = nullptr;
-        }
-        hipGraph_t g = nullptr;
-        hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-        try {
-          for (int i = 0; i < k; ++i) enqueue_iteration(P, s);
-        } catch (...) {
-          hipStreamEndCapture(s, &g);
-          if (g) hipGraphDestroy(g);
-          throw;
-        }
-        hipchk(hipStreamEndCapture(s, &g), "end capture");
-        hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
-        hipGraphDestroy(g);
-        P->graph_k = k;
-        P->graph_hist = P->hist;
-      }
-      hipchk(hipGraphLaunch(P->graph, s), "graph launch");
-    } else {
-      for (int i = 0; i < step; ++i) enqueue_iteration(P, s);
-    }
+    iterate_block(P, s, step, k, use_graph);
     done += step;
     finished = all_done();
   }
@@ -1059,23 +1066,17 @@ void ensure_refine_vectors(mm_plan_s* P) {
   if (P->vb64) return;
   const int64_t vn = (int64_t)P->R * P->nu();
   P->vb64 = P->alloc<double>(vn);
-  // the true residual is the correction equation's right-hand side: it lives in
-  // the PCG's b vector, which it is recomputed into after every inner solve
-  P->vr64 = P->vb;
-  P->vxacc = P->alloc<double>(vn);
   P->vxbest = P->alloc<double>(vn);
 }
 
-// out[r] = b64_r - H64 xacc_r in float64 (one RHS at a time through the float64 filter)
-void residual64(mm_plan_s* P, const double* x, double* out, hipStream_t s) {
+// out_r = b64_r - H64 x_r for RHS r, in float64 (through the float64 filter)
+void residual64_row(mm_plan_s* P, const double* x, double* out, int r, hipStream_t s) {
   const int64_t nu = P->nu();
   const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
   void* ya = P->main_fp64() ? P->y1 : (void*)P->y64a;
   void* yb = P->main_fp64() ? P->y2 : (void*)P->y64b;
-  for (int r = 0; r < P->R; ++r) {
-    apply_H_obs(P, f64, x + (int64_t)r * nu, P->vq, ya, yb, 1, s);
-    hipchk(launch_sub(out + (int64_t)r * nu, P->vb64 + (int64_t)r * nu, P->vq, nu, s), "residual");
-  }
+  apply_H_obs(P, f64, x + (int64_t)r * nu, P->vq, ya, yb, 1, s);
+  hipchk(launch_sub(out + (int64_t)r * nu, P->vb64 + (int64_t)r * nu, P->vq, nu, s), "residual");
 }
 
 // Right-hand side of a solve: b = P^T N^-1 d from a TOD, or a map given directly.
@@ -1144,25 +1145,147 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       if (!fixed && c.bnorm > 0 && !(c.rel <= o.tol) && !(c.best_rel <= o.tol)) notconv = true;
     }
     to_glob(P, P->vxb, d_x, R, s);
-  } else {
-    // Mixed precision with float64 residual correction: the float32-operator PCG
-    // solves H d = r64 for a correction, the float64 operator recomputes the true
-    // residual r64 = b64 - H64 x, and the iterate with the lowest true residual is kept.
+  } else if (P->tmpl.empty()) {
+    // Mixed precision with reliable updates (float64 residual replacement): the
+    // iterate and every CG vector are float64 and H is applied in float32; at the
+    // host's check points, for each RHS whose recurrence residual fell tenfold
+    // since its last replacement (or reached tol, or stopped), the residual is
+    // replaced by the float64 true residual b - H64 x, z = M r and rho = r.z are
+    // recomputed, and CG continues along the same direction p (no restart).  The
+    // iterate with the lowest true residual is returned.
     ensure_fp64_path(P, s);
     ensure_refine_vectors(P);
     for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
+    hipchk(hipMemcpyAsync(P->vb, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    if (o.d_x0) {
+      to_obs(P, o.d_x0, P->vx, R, s);
+      for (int r = 0; r < R; ++r) residual64_row(P, P->vx, P->vr, r, s);
+    } else {
+      hipchk(launch_fill_f64(P->vx, 0.0, (int64_t)R * nu, s), "fill");
+      hipchk(hipMemcpyAsync(P->vr, P->vb, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    hipchk(hipMemcpyAsync(P->vxbest, P->vx, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
+           "precondition");
+    hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
+    hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
+    hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
+    hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, o.tol, 0, R, P->hist, P->hist_cap, s), "init");
+    hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
+    hipchk(hipStreamSynchronize(s), "init");
+    std::vector<double> last_true(R), best_true(R);
+    std::vector<int> rep_iter(R, 0);
+    for (int r = 0; r < R; ++r) {
+      CgState& c = P->st_host[r];
+      last_true[r] = best_true[r] = c.rel;
+      best_rel[r] = c.rel;
+      hist_out[(size_t)r * (n_max + 1)] = c.rel;
+      c.best_rel = -1.0;            // the device keeps no best copy: the host tracks true residuals
+    }
+    hipchk(hipMemcpyAsync(P->st, P->st_host, sizeof(CgState) * R, hipMemcpyHostToDevice, s), "state copy");
+
+    // replace the residual of the RHS in `rows` (and restart the direction p = z of
+    // those that broke down); returns after updating the device states
+    std::vector<int> restarted(R, -1);
+    auto replace = [&](const std::vector<int>& rows) {
+      for (int r : rows) residual64_row(P, P->vx, P->vr, r, s);
+      hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
+             "precondition");
+      for (int r : rows)
+        if (P->st_host[r].breakdown) {
+          hipchk(hipMemcpyAsync(P->vp + (int64_t)r * nu, P->vz + (int64_t)r * nu, sizeof(double) * nu,
+                                hipMemcpyDeviceToDevice, s), "restart");
+        }
+      const std::vector<double> rr = dots(P, P->vr, P->vr, R, s);
+      const std::vector<double> rz = dots(P, P->vr, P->vz, R, s);
+      for (int r : rows) {
+        CgState& c = P->st_host[r];
+        const double tr = c.bnorm > 0 ? std::sqrt(rr[r]) / c.bnorm : 0.0;
+        last_true[r] = tr;
+        rep_iter[r] = c.iter;
+        if (c.iter <= n_max) hist_out[(size_t)r * (n_max + 1) + c.iter] = tr;
+        if (tr < best_true[r]) {
+          best_true[r] = tr;
+          best_iter[r] = c.iter;
+          hipchk(hipMemcpyAsync(P->vxbest + (int64_t)r * nu, P->vx + (int64_t)r * nu, sizeof(double) * nu,
+                                hipMemcpyDeviceToDevice, s), "copy");
+        }
+        // p.q <= 0 can occur where the float32 operator is indefinite (directions
+        // the float64 H nearly annihilates): restart once per iteration count
+        bool give_up = false;
+        if (c.breakdown) {
+          give_up = restarted[r] == c.iter;
+          restarted[r] = c.iter;
+        }
+        c.rho = rz[r];
+        c.rel = tr;
+        c.breakdown = 0;
+        c.copy_best = 0;
+        c.active = (c.bnorm > 0 && tr > o.tol && c.iter < n_max && !give_up) ? 1 : 0;
+      }
+      hipchk(hipMemcpyAsync(P->st, P->st_host, sizeof(CgState) * R, hipMemcpyHostToDevice, s), "state copy");
+    };
+
+    std::vector<double> hh((size_t)R * P->hist_cap);
+    const int k = std::min(std::max(o.check_every, 1), std::max(1, n_max));
+    int done = 0;
+    auto any_active = [&]() {
+      for (int r = 0; r < R; ++r)
+        if (P->st_host[r].active) return true;
+      return false;
+    };
+    while (any_active() && done < n_max) {
+      const int step = std::min(k, n_max - done);
+      iterate_block(P, s, step, k, o.use_graph != 0);
+      done += step;
+      hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
+      hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipStreamSynchronize(s), "solve");
+      std::vector<int> rows;
+      for (int r = 0; r < R; ++r) {
+        const CgState& c = P->st_host[r];
+        for (int i = rep_iter[r] + 1; i <= c.iter && i <= n_max; ++i)
+          hist_out[(size_t)r * (n_max + 1) + i] = hh[(size_t)r * P->hist_cap + i];
+        if (c.bnorm > 0 && (c.iter > rep_iter[r] || (c.breakdown && restarted[r] != c.iter)) &&
+            (!c.active || c.rel <= o.tol || c.rel <= 0.1 * last_true[r] || done >= n_max))
+          rows.push_back(r);
+      }
+      if (!rows.empty()) replace(rows);
+    }
+    for (int r = 0; r < R; ++r) {
+      const CgState& c = P->st_host[r];
+      iters[r] = c.iter;
+      best_rel[r] = best_true[r];
+      tres[r] = best_true[r];
+      if (c.bnorm > 0 && !(best_true[r] <= o.tol)) notconv = true;
+    }
+    to_glob(P, P->vxbest, d_x, R, s);
+  } else {
+    // Plans with templates, whose extended system can be singular or nearly so:
+    // float64 residual correction by restarted solves.  The float32-operator PCG
+    // solves H d = r64 for a correction from d = 0 to a bounded depth, the float64
+    // operator recomputes the true residual r64 = b64 - H64 x, and the iterate with
+    // the lowest true residual is kept.  (One long float32-operator CG, as in the
+    // reliable updates, drifts along directions the float64 H nearly annihilates:
+    // invisible in the residual, not in the fitted TOD.)
+    ensure_fp64_path(P, s);
+    ensure_refine_vectors(P);
+    if (!P->vxacc) P->vxacc = P->alloc<double>((int64_t)R * nu);
+    double* const vr64 = P->vb;   // the true residual is the correction equation's right-hand side
+    for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
     if (o.d_x0) {
       to_obs(P, o.d_x0, P->vxacc, R, s);
-      residual64(P, P->vxacc, P->vr64, s);
+      for (int r = 0; r < R; ++r) residual64_row(P, P->vxacc, vr64, r, s);
     } else {
       hipchk(launch_fill_f64(P->vxacc, 0.0, (int64_t)R * nu, s), "fill");
-      hipchk(hipMemcpyAsync(P->vr64, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+      hipchk(hipMemcpyAsync(vr64, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     }
     hipchk(hipMemcpyAsync(P->vxbest, P->vxacc, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     const std::vector<double> bb = dots(P, P->vb64, P->vb64, R, s);
     std::vector<double> rel(R), bn(R);
     {
-      const std::vector<double> rr = dots(P, P->vr64, P->vr64, R, s);
+      const std::vector<double> rr = dots(P, vr64, vr64, R, s);
       for (int r = 0; r < R; ++r) {
         bn[r] = std::sqrt(bb[r]);
         rel[r] = bn[r] > 0 ? std::sqrt(rr[r]) / bn[r] : 0.0;
@@ -1196,8 +1319,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       hipchk(hipStreamSynchronize(s), "history");
       // x += d (rows of converged RHS add 0)
       hipchk(launch_axpby(P->vxacc, P->vxb, 1.0, 1.0, (int64_t)R * nu, s), "accumulate");
-      residual64(P, P->vxacc, P->vr64, s);
-      const std::vector<double> rr = dots(P, P->vr64, P->vr64, R, s);
+      for (int r = 0; r < R; ++r) residual64_row(P, P->vxacc, vr64, r, s);
+      const std::vector<double> rr = dots(P, vr64, vr64, R, s);
       for (int r = 0; r < R; ++r) {
         const CgState& c = P->st_host[r];
         const double scale = rel[r];
