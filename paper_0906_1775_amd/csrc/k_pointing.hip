@@ -25,10 +25,20 @@ namespace mm {
 // flight while every load instruction stays coalesced across the wavefront.
 constexpr int kGatherUnroll = 4;
 
-template <typename Ty, int NS>
+// one 8-byte nontemporal load of a (sin, cos) pair
+__device__ __forceinline__ float2 load_nt(const float2* p) {
+  const unsigned long long u = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+  float2 r;
+  __builtin_memcpy(&r, &u, sizeof(r));
+  return r;
+}
+
+// Tp: element type of the map (float64, or the float32 copy of the search
+// direction that mixed-precision iterations gather from)
+template <typename Ty, int NS, typename Tp>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
                                                 const float2* __restrict__ w,
-                                                const double* __restrict__ p, int64_t vs,
+                                                const Tp* __restrict__ p, int64_t vs,
                                                 Ty* __restrict__ y, int64_t n_t, int n_rhs,
                                                 const CgState* __restrict__ st) {
   constexpr int U = kGatherUnroll;
@@ -39,8 +49,10 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t t = t0 + u * 256;
-      o[u] = t < n_t ? pix_obs[t] : -1;
-      if (NS == 3) sc[u] = t < n_t ? w[t] : make_float2(0.f, 0.f);
+      // the pointing streams are read once per pass: nontemporal, so they do not
+      // evict the map (and the TOD rows other kernels re-read) from the caches
+      o[u] = t < n_t ? __builtin_nontemporal_load(pix_obs + t) : -1;
+      if (NS == 3) sc[u] = t < n_t ? load_nt(w + t) : make_float2(0.f, 0.f);
     }
     for (int r = 0; r < n_rhs; ++r) {
       if (st && !st[r].active) continue;   // this RHS has stopped iterating
@@ -50,10 +62,10 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
         v[u] = 0.0;
         if (o[u] >= 0) {
           if (NS == 1) {
-            v[u] = p[(int64_t)r * vs + o[u]];
+            v[u] = (double)p[(int64_t)r * vs + o[u]];
           } else {
-            const double* m = p + (int64_t)r * vs + (int64_t)o[u] * 3;
-            v[u] = 0.5 * (m[0] + (double)sc[u].x * m[1] + (double)sc[u].y * m[2]);
+            const Tp* m = p + (int64_t)r * vs + (int64_t)o[u] * 3;
+            v[u] = 0.5 * ((double)m[0] + (double)sc[u].x * (double)m[1] + (double)sc[u].y * (double)m[2]);
           }
         }
       }
@@ -68,21 +80,34 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
 
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
-                         hipStream_t s, const CgState* st) {
+                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32) {
   (void)n_obs;
   if (n_t == 0) return hipSuccess;
   int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
   if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
-  if (out_f64) {
-    if (ns == 1) hipLaunchKernelGGL((k_gather<double, 1>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs, st);
-    else hipLaunchKernelGGL((k_gather<double, 3>), g, b, 0, s, pix_obs, w2, p, vs, (double*)y, n_t, n_rhs, st);
+#define MM_GA(TY, NS, TP, PP, VS) hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, n_rhs, st)
+  if (p32) {
+    if (out_f64) { if (ns == 1) MM_GA(double, 1, float, p32, vs32); else MM_GA(double, 3, float, p32, vs32); }
+    else { if (ns == 1) MM_GA(float, 1, float, p32, vs32); else MM_GA(float, 3, float, p32, vs32); }
   } else {
-    if (ns == 1) hipLaunchKernelGGL((k_gather<float, 1>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs, st);
-    else hipLaunchKernelGGL((k_gather<float, 3>), g, b, 0, s, pix_obs, w2, p, vs, (float*)y, n_t, n_rhs, st);
+    if (out_f64) { if (ns == 1) MM_GA(double, 1, double, p, vs); else MM_GA(double, 3, double, p, vs); }
+    else { if (ns == 1) MM_GA(float, 1, double, p, vs); else MM_GA(float, 3, double, p, vs); }
   }
+#undef MM_GA
   return hipGetLastError();
+}
+
+// dst[r * dst_stride + i] = (float)src[r * src_stride + i], i < n
+__global__ void k_rows_to_f32(const double* __restrict__ src, int64_t ss, float* __restrict__ dst, int64_t ds,
+                              int64_t n, int n_rhs) {
+  const int64_t total = n * n_rhs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+    const int64_t r = k / n, i = k % n;
+    dst[r * ds + i] = (float)src[r * ss + i];
+  }
 }
 
 // ---------------------------------------------------------------- scatter
@@ -171,81 +196,105 @@ hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const f
 constexpr int kSliceWaves = 8;
 constexpr int kBatch = 4;
 
-template <typename Ty, int NS>
+// RG right-hand sides share one pass over the sliced pointing: the entries are
+// loaded once per group and each RHS keeps its own accumulators, so the
+// pointing is streamed ceil(R / RG) times instead of R times.  Every (pixel,
+// RHS) sum keeps the order of a single-RHS pass.
+template <typename Ty, int NS, int RG>
 __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
     double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
     double* __restrict__ pq_part, int pq_stride, int pq_slot, const CgState* __restrict__ st) {
   constexpr int W = kSliceWaves;
-  __shared__ double part[W][NS][64];
-  __shared__ double sh[W];
+  __shared__ double part[W][RG * NS][64];
+  __shared__ double sh[W][RG];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int64_t n_sl = (n_obs + 63) / 64;
-  for (int r = 0; r < n_rhs; ++r) {
-    if (st && !st[r].active) continue;     // uniform over the block
-    const Ty* __restrict__ yr = y + (int64_t)r * n_t;
-    double pq = 0.0;
+  for (int r0 = 0; r0 < n_rhs; r0 += RG) {
+    bool act[RG];
+    bool any = false;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      act[g] = r0 + g < n_rhs && !(st && !st[r0 + g].active);   // RHS that stopped iterating are skipped
+      any = any || act[g];
+    }
+    if (!any) continue;                    // uniform over the block
+    double pq[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) pq[g] = 0.0;
     for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
       const int64_t base = (int64_t)slice_end[s] - slice_len[s] + lane;
       const int width = (int)(slice_len[s] >> 6);
-      Acc<Ty> a0, a1, a2;
+      Acc<Ty> a[RG][NS];
       for (int j0 = wv; j0 < width; j0 += W * kBatch) {
         int32_t tt[kBatch];
         float2 ww[kBatch];
-        Ty vv[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
           const int j = j0 + b * W;
           const int64_t e = base + (int64_t)j * 64;
-          tt[b] = j < width ? sell_t[e] : -1;
-          if (NS == 3) ww[b] = j < width ? sell_w[e] : make_float2(0.f, 0.f);
+          tt[b] = j < width ? __builtin_nontemporal_load(sell_t + e) : -1;
+          if (NS == 3) ww[b] = j < width ? load_nt(sell_w + e) : make_float2(0.f, 0.f);
         }
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) vv[b] = tt[b] >= 0 ? yr[tt[b]] : (Ty)0;
+        for (int g = 0; g < RG; ++g) {
+          if (!act[g]) continue;
+          const Ty* __restrict__ yr = y + (int64_t)(r0 + g) * n_t;
+          Ty vv[kBatch];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          if (tt[b] < 0) continue;
-          if (NS == 1) {
-            a0.add(vv[b]);
-          } else {
-            const Ty h = (Ty)0.5 * vv[b];
-            a0.add(h);
-            a1.add(h * (Ty)ww[b].x);
-            a2.add(h * (Ty)ww[b].y);
+          for (int b = 0; b < kBatch; ++b) vv[b] = tt[b] >= 0 ? yr[tt[b]] : (Ty)0;
+#pragma unroll
+          for (int b = 0; b < kBatch; ++b) {
+            if (tt[b] < 0) continue;
+            if (NS == 1) {
+              a[g][0].add(vv[b]);
+            } else {
+              const Ty h = (Ty)0.5 * vv[b];
+              a[g][0].add(h);
+              a[g][1].add(h * (Ty)ww[b].x);
+              a[g][2].add(h * (Ty)ww[b].y);
+            }
           }
         }
       }
-      part[wv][0][lane] = a0.value();
-      if (NS == 3) {
-        part[wv][1][lane] = a1.value();
-        part[wv][2][lane] = a2.value();
-      }
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) part[wv][g * NS + c][lane] = a[g][c].value();
       __syncthreads();
       const int64_t o = s * 64 + lane;
       if (wv == 0 && o < n_obs) {
-        const int64_t i = (int64_t)r * vs + o * NS;
 #pragma unroll
-        for (int c = 0; c < NS; ++c) {
-          double v = part[0][c][lane];
+        for (int g = 0; g < RG; ++g) {
+          if (!act[g]) continue;
+          const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
 #pragma unroll
-          for (int w = 1; w < W; ++w) v += part[w][c][lane];
-          q[i + c] = v;
-          if (p) pq += p[i + c] * v;
+          for (int c = 0; c < NS; ++c) {
+            double v = part[0][g * NS + c][lane];
+#pragma unroll
+            for (int w = 1; w < W; ++w) v += part[w][g * NS + c][lane];
+            q[i + c] = v;
+            if (p) pq[g] += p[i + c] * v;
+          }
         }
       }
       __syncthreads();
     }
-    if (p) {   // block sum of the p.q contributions (wavefront 0 holds them), fixed order
+    if (p) {   // block sums of the p.q contributions (wavefront 0 holds them), fixed order
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) pq += __shfl_xor(pq, off, 64);
-      if ((tid & 63) == 0) sh[tid >> 6] = pq;
+      for (int g = 0; g < RG; ++g) {
+        double v = pq[g];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) sh[tid >> 6][g] = v;
+      }
       __syncthreads();
-      if (tid == 0) {
+      if (tid < RG && act[tid]) {
         double sum = 0.0;
-        for (int w = 0; w < W; ++w) sum += sh[w];
-        pq_part[(int64_t)r * pq_stride + pq_slot + blockIdx.x] = sum;
+        for (int w = 0; w < W; ++w) sum += sh[w][tid];
+        pq_part[(int64_t)(r0 + tid) * pq_stride + pq_slot + blockIdx.x] = sum;
       }
       __syncthreads();
     }
@@ -263,14 +312,15 @@ hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* 
   if (n_obs == 0) return hipSuccess;
   const dim3 g((unsigned)scatter_blocks(n_obs)), b(64 * kSliceWaves);
   const float2* w = (const float2*)L.w;
-#define MM_SC(T, NS) hipLaunchKernelGGL((k_scatter<T, NS>), g, b, 0, s, L.end, L.len, L.t, w, (const T*)y, q, vs, \
-                                        n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot, st)
+#define MM_SC(T, NS, RG) hipLaunchKernelGGL((k_scatter<T, NS, RG>), g, b, 0, s, L.end, L.len, L.t, w, (const T*)y, q, vs, \
+                                            n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot, st)
+  // one accumulator set for a single RHS; groups of 4 otherwise
   if (in_f64) {
-    if (ns == 1) MM_SC(double, 1);
-    else MM_SC(double, 3);
+    if (ns == 1) { if (n_rhs == 1) MM_SC(double, 1, 1); else MM_SC(double, 1, 4); }
+    else { if (n_rhs == 1) MM_SC(double, 3, 1); else MM_SC(double, 3, 4); }
   } else {
-    if (ns == 1) MM_SC(float, 1);
-    else MM_SC(float, 3);
+    if (ns == 1) { if (n_rhs == 1) MM_SC(float, 1, 1); else MM_SC(float, 1, 4); }
+    else { if (n_rhs == 1) MM_SC(float, 3, 1); else MM_SC(float, 3, 4); }
   }
 #undef MM_SC
   return hipGetLastError();
@@ -288,6 +338,13 @@ static dim3 grid_for(int64_t n) {
   if (nb > 65536) nb = 65536;
   if (nb < 1) nb = 1;
   return dim3((unsigned)nb);
+}
+
+hipError_t launch_rows_to_f32(const double* src, int64_t src_stride, float* dst, int64_t dst_stride, int64_t n,
+                              int n_rhs, hipStream_t s) {
+  if (n == 0 || n_rhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_to_f32, grid_for(n * n_rhs), dim3(256), 0, s, src, src_stride, dst, dst_stride, n, n_rhs);
+  return hipGetLastError();
 }
 
 hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, int64_t n,

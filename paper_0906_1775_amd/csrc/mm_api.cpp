@@ -273,6 +273,7 @@ struct mm_plan_s {
          *vxb = nullptr, *vb = nullptr;   // [R][nu]
   double *part1 = nullptr, *part2 = nullptr, *part3 = nullptr;
   double* part_pq = nullptr;     // [R][n_pq] partial sums of p.q
+  float* vp32 = nullptr;         // [R][n_obs * ns] float32 copy of p's map part (mixed plans)
   double *vb64 = nullptr, *vxbest = nullptr;   // mixed refinement: b and the best iterate in float64
   double* vxacc = nullptr;                      // accumulated map of the restarted correction
   CgState* st = nullptr;
@@ -506,10 +507,12 @@ void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, 
 }
 
 // y_r = [P B] x_r: x in iteration layout (rows of stride nu), y a TOD of type y_f64
+// x32 (optional): a float32 copy of the map part of x, which the sky gather reads instead
 void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipStream_t s,
-                const CgState* st = nullptr) {
+                const CgState* st = nullptr, const float* x32 = nullptr) {
   const int64_t vs = P->nu();
-  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s, st), "gather");
+  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s, st, x32, P->nmap()),
+         "gather");
   for (const Template& T : P->tmpl) {
     const int64_t off = P->nmap() + T.ooff;
     if (T.kind == MM_TMPL_ONEHOT)
@@ -518,6 +521,11 @@ void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipSt
       hipchk(launch_hwp_gather(y_f64, T.tiles, T.n_tiles, T.d_seg, T.omega, x, vs, off, y, P->n_t, R, s, st),
              "template gather");
   }
+}
+
+// refresh the float32 copy of p after p was set outside the iteration kernels
+void sync_p32(mm_plan_s* P, hipStream_t s) {
+  if (P->vp32) hipchk(launch_rows_to_f32(P->vp, P->nu(), P->vp32, P->nmap(), P->nmap(), P->R, s), "p copy");
 }
 
 // q_r = [P B]^T y_r (iteration layout); with p also the p.q partial sums of
@@ -958,6 +966,9 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->part3 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part_pq = P->alloc<double>((int64_t)P->R * std::max(P->n_pq, 1));
   P->st = P->alloc<CgState>(P->R);
+  // mixed iterations gather the search direction from a float32 copy of its map part
+  // (half the map bytes; the gathered TOD is float32 anyway)
+  if (!P->main_fp64()) P->vp32 = P->alloc<float>((int64_t)P->R * std::max<int64_t>(P->nmap(), 1));
 }
 
 // queue one PCG iteration for every RHS
@@ -966,14 +977,14 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   // q = H p, with the partial sums of p.q formed by the scatters
   // (RHS that stopped iterating skip the TOD work: convergence is checked by
   // the host only every check_every iterations)
-  gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s, P->st);
+  gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s, P->st, P->vp32);
   weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s, P->st);
   scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp, P->st);
   hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, P->nu(), P->minv_t,
                           P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
   hipchk(launch_cg_finalize(P->st, P->part2, P->part3, R, P->hist, P->hist_cap, s), "finalize");
-  hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s), "next direction");
+  hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s, P->vp32, P->nmap()), "next direction");
 }
 
 // per-RHS sums of x.y over [R][nu] vectors (float64, fixed order)
@@ -1036,6 +1047,7 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
   hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
          "precondition");
   hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+  sync_p32(P, s);
   hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
   hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
   hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
@@ -1168,6 +1180,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
            "precondition");
     hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    sync_p32(P, s);
     hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
     hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
     hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
@@ -1192,11 +1205,14 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       for (int r : rows) residual64_row(P, P->vx, P->vr, r, s);
       hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
              "precondition");
+      bool any_restart = false;
       for (int r : rows)
         if (P->st_host[r].breakdown) {
           hipchk(hipMemcpyAsync(P->vp + (int64_t)r * nu, P->vz + (int64_t)r * nu, sizeof(double) * nu,
                                 hipMemcpyDeviceToDevice, s), "restart");
+          any_restart = true;
         }
+      if (any_restart) sync_p32(P, s);
       const std::vector<double> rr = dots(P, P->vr, P->vr, R, s);
       const std::vector<double> rz = dots(P, P->vr, P->vz, R, s);
       for (int r : rows) {

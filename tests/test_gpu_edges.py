@@ -1,0 +1,128 @@
+"""Edge cases and failure paths of the GPU path, against the oracle where it applies.
+
+* max_iter reached: MM_ENOTCONV with the lowest-residual iterate written, equal to the
+  oracle's best iterate after the same number of iterations (Implementation section);
+* a singular 3x3 preconditioner block (a pixel seen at a single polarisation angle):
+  the plan counts it and the solve reports MM_ESINGULAR (raised by the binding);
+* degenerate inputs: no samples, every sample excised, empty stationary intervals;
+* the largest batch, 64 right-hand sides, against one-at-a-time solves;
+* repeatability: fixed-order reductions give bitwise identical maps on repeated solves.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_helpers import oracle_for, plan_for, rel_err, tod_tensor
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+L_K = 1 << 14
+
+
+def _small(n_stokes=3, **kw):
+    args = dict(grid=(8, 8), det_lens=(3000, 2400), n_c=32, f_samp=20.0, seed=12)
+    args.update(kw)
+    return synth.make_custom(n_stokes, **args)
+
+
+def test_max_iter_returns_the_best_iterate_and_enotconv():
+    p = _small()
+    o = oracle_for(p, L_K)
+    mm = plan_for(p, lag_dft_len=L_K)
+    m, info = mm.solve(tod_tensor(p), tol=1e-14, max_iter=4)
+    assert info["status"] == "MM_ENOTCONV"
+    x, rinfo = o.pcg(o.rhs(p.tod[0]), tol=1e-14, max_iter=4)
+    assert info["best_iter"][0] == rinfo.best_iter
+    assert rel_err(m.cpu().numpy()[0], o.to_global(x)) <= 1e-10
+    from paper_0906_1775_amd import MMError
+    with pytest.raises(MMError, match="ENOTCONV"):
+        mm.solve(tod_tensor(p), tol=1e-14, max_iter=4, raise_on_notconv=True)
+
+
+def test_singular_block_is_reported():
+    # polarised pointing seen at one fixed angle: every pixel's 3x3 block has rank one
+    p = synth.make_custom(1, grid=(6, 6), det_lens=(2000,), n_c=16, f_samp=20.0, seed=2)
+    w = np.tile(np.array([[0.6, 0.8]], dtype=np.float32), (p.n_samples, 1))
+    dev = torch.device("cuda:0")
+    from paper_0906_1775_amd import MapMaker
+    o = oracle_for(p, L_K)
+    mm = MapMaker(torch.from_numpy(p.pix).to(dev), torch.from_numpy(w).to(dev), p.n_pix, 3, p.iv_start,
+                  p.iv_filter, filter_lags=o.lag_tab, n_c=p.n_c)
+    assert mm.info()["n_singular"] == mm.info()["n_obs"] > 0
+    from paper_0906_1775_amd import MMError
+    with pytest.raises(MMError, match="ESINGULAR"):
+        mm.solve(tod_tensor(p), tol=1e-6, max_iter=5)
+
+
+def test_no_samples():
+    from paper_0906_1775_amd import MapMaker
+    dev = torch.device("cuda:0")
+    pix = torch.empty(0, dtype=torch.int32, device=dev)
+    w = torch.empty((0, 2), dtype=torch.float32, device=dev)
+    lags = np.array([[1.0, 0.1, 0.01]])
+    mm = MapMaker(pix, w, 16, 3, np.array([0, 0]), np.array([0]), filter_lags=lags, n_c=3)
+    assert mm.info()["n_obs"] == 0
+    m, info = mm.solve(torch.empty((1, 0), dtype=torch.float32, device=dev), tol=1e-8)
+    assert info["status"] == "MM_OK" and info["iters"][0] == 0
+    assert torch.all(m == 0)
+    assert torch.all(mm.hits() == 0)
+
+
+def test_every_sample_excised():
+    p = _small(n_stokes=1)
+    pix = np.full_like(p.pix, -1)
+    from paper_0906_1775_amd import MapMaker
+    dev = torch.device("cuda:0")
+    o = oracle_for(p, L_K)
+    mm = MapMaker(torch.from_numpy(pix).to(dev), None, p.n_pix, 1, p.iv_start, p.iv_filter,
+                  filter_lags=o.lag_tab, n_c=p.n_c)
+    m, info = mm.solve(tod_tensor(p), tol=1e-8)
+    assert info["status"] == "MM_OK"
+    assert torch.all(m == 0)
+
+
+def test_empty_intervals_change_nothing():
+    p = _small(interval_lens=[[1000, 2000], [2400]])
+    # the same samples with zero-length intervals inserted at the start, in the middle and at the end
+    iv = np.array([0, 0, 1000, 1000, 3000, 5400, 5400], dtype=np.int64)
+    flt = np.zeros(6, dtype=np.int32)
+    o = oracle_for(p, L_K)
+    dev = torch.device("cuda:0")
+    from paper_0906_1775_amd import MapMaker
+    a = MapMaker(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.w).to(dev), p.n_pix, 3, p.iv_start,
+                 p.iv_filter, filter_lags=o.lag_tab, n_c=p.n_c)
+    b = MapMaker(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.w).to(dev), p.n_pix, 3, iv, flt,
+                 filter_lags=o.lag_tab, n_c=p.n_c)
+    ma, _ = a.solve(tod_tensor(p), fixed_iters=6)
+    mb, _ = b.solve(tod_tensor(p), fixed_iters=6)
+    assert torch.equal(ma, mb)
+    x, _ = o.pcg(o.rhs(p.tod[0]), fixed_iters=6)
+    assert rel_err(ma.cpu().numpy()[0], o.to_global(x)) <= 1e-10
+
+
+def test_sixty_four_right_hand_sides():
+    p = _small(n_stokes=1, n_rhs=64, det_lens=(1500,), seed=5)
+    o = oracle_for(p, L_K)
+    mm = plan_for(p, n_rhs=64, lag_dft_len=L_K)
+    m, info = mm.solve(tod_tensor(p), fixed_iters=5)
+    m = m.cpu().numpy()
+    for r in (0, 17, 63):
+        x, _ = o.pcg(o.rhs(p.tod[r]), fixed_iters=5)
+        assert rel_err(m[r], o.to_global(x)) <= 1e-10
+    from paper_0906_1775_amd import MMError
+    with pytest.raises(MMError, match="EINVAL"):
+        plan_for(p, n_rhs=65, lag_dft_len=L_K)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solves_are_bitwise_repeatable(precision):
+    p = _small(n_rhs=2)
+    mm = plan_for(p, precision=precision, lag_dft_len=L_K)
+    tod = tod_tensor(p)
+    m1, i1 = mm.solve(tod, tol=1e-10, max_iter=300)
+    m2, i2 = mm.solve(tod, tol=1e-10, max_iter=300)
+    assert torch.equal(m1, m2)
+    assert i1["iters"] == i2["iters"]
