@@ -193,24 +193,28 @@ hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const f
 // their loads overlap, and the W partial sums are combined in wavefront order
 // through LDS.  Grid-stride over slices with a bounded grid (kScatterBlocks),
 // so the optional p.q partial sums form a short, fixed list.
-constexpr int kSliceWaves = 8;
+constexpr int kBlockWaves = 8;   // wavefronts per scatter block
 constexpr int kBatch = 4;
 
 // RG right-hand sides share one pass over the sliced pointing: the entries are
 // loaded once per group and each RHS keeps its own accumulators, so the
-// pointing is streamed ceil(R / RG) times instead of R times.  Every (pixel,
-// RHS) sum keeps the order of a single-RHS pass.
-template <typename Ty, int NS, int RG>
-__global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
+// pointing is streamed ceil(R / RG) times instead of R times.  WPS wavefronts
+// split a slice's entries (the plan picks 8 for pixels with hundreds of hits, 1
+// for a few tens, where the cross-wave combine would dominate); a block of 8
+// wavefronts works on 8 / WPS slices at a time.  Every (pixel, RHS) sum has a
+// fixed order for a given WPS.
+template <typename Ty, int NS, int RG, int WPS>
+__global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
     double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
     double* __restrict__ pq_part, int pq_stride, int pq_slot, const CgState* __restrict__ st) {
-  constexpr int W = kSliceWaves;
-  __shared__ double part[W][RG * NS][64];
-  __shared__ double sh[W][RG];
+  constexpr int NW = kBlockWaves, SPB = NW / WPS;
+  __shared__ double part[WPS > 1 ? NW : 1][RG * NS][64];
+  __shared__ double sh[NW][RG];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  const int sg = wv / WPS, wi = wv % WPS;
   const int64_t n_sl = (n_obs + 63) / 64;
   for (int r0 = 0; r0 < n_rhs; r0 += RG) {
     bool act[RG];
@@ -224,16 +228,18 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
     double pq[RG];
 #pragma unroll
     for (int g = 0; g < RG; ++g) pq[g] = 0.0;
-    for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
-      const int64_t base = (int64_t)slice_end[s] - slice_len[s] + lane;
-      const int width = (int)(slice_len[s] >> 6);
+    for (int64_t s0 = (int64_t)blockIdx.x * SPB; s0 < n_sl; s0 += (int64_t)gridDim.x * SPB) {
+      const int64_t s = s0 + sg;
+      const bool sv = s < n_sl;
+      const int64_t base = sv ? (int64_t)slice_end[s] - slice_len[s] + lane : 0;
+      const int width = sv ? (int)(slice_len[s] >> 6) : 0;
       Acc<Ty> a[RG][NS];
-      for (int j0 = wv; j0 < width; j0 += W * kBatch) {
+      for (int j0 = wi; j0 < width; j0 += WPS * kBatch) {
         int32_t tt[kBatch];
         float2 ww[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
-          const int j = j0 + b * W;
+          const int j = j0 + b * WPS;
           const int64_t e = base + (int64_t)j * 64;
           tt[b] = j < width ? __builtin_nontemporal_load(sell_t + e) : -1;
           if (NS == 3) ww[b] = j < width ? load_nt(sell_w + e) : make_float2(0.f, 0.f);
@@ -259,30 +265,37 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
           }
         }
       }
-#pragma unroll
-      for (int g = 0; g < RG; ++g)
-#pragma unroll
-        for (int c = 0; c < NS; ++c) part[wv][g * NS + c][lane] = a[g][c].value();
-      __syncthreads();
       const int64_t o = s * 64 + lane;
-      if (wv == 0 && o < n_obs) {
+      if constexpr (WPS > 1) {
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+          for (int c = 0; c < NS; ++c) part[wv][g * NS + c][lane] = a[g][c].value();
+        __syncthreads();
+      }
+      if (wi == 0 && sv && o < n_obs) {
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
           if (!act[g]) continue;
           const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
 #pragma unroll
           for (int c = 0; c < NS; ++c) {
-            double v = part[0][g * NS + c][lane];
+            double v;
+            if constexpr (WPS > 1) {
+              v = part[sg * WPS][g * NS + c][lane];
 #pragma unroll
-            for (int w = 1; w < W; ++w) v += part[w][g * NS + c][lane];
+              for (int w = 1; w < WPS; ++w) v += part[sg * WPS + w][g * NS + c][lane];
+            } else {
+              v = a[g][c].value();
+            }
             q[i + c] = v;
             if (p) pq[g] += p[i + c] * v;
           }
         }
       }
-      __syncthreads();
+      if constexpr (WPS > 1) __syncthreads();
     }
-    if (p) {   // block sums of the p.q contributions (wavefront 0 holds them), fixed order
+    if (p) {   // block sums of the p.q contributions, fixed order
 #pragma unroll
       for (int g = 0; g < RG; ++g) {
         double v = pq[g];
@@ -293,7 +306,7 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
       __syncthreads();
       if (tid < RG && act[tid]) {
         double sum = 0.0;
-        for (int w = 0; w < W; ++w) sum += sh[w][tid];
+        for (int w = 0; w < NW; ++w) sum += sh[w][tid];
         pq_part[(int64_t)(r0 + tid) * pq_stride + pq_slot + blockIdx.x] = sum;
       }
       __syncthreads();
@@ -301,27 +314,40 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_scatter(
   }
 }
 
-int scatter_blocks(int64_t n_obs) {
+int scatter_blocks(int64_t n_obs, int wps) {
   const int64_t n_sl = (n_obs + 63) / 64;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(n_sl, kScatterBlocks));
+  const int64_t spb = kBlockWaves / std::max(1, wps);
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n_sl + spb - 1) / spb, kScatterBlocks));
 }
+
+// wavefronts per slice for a layout whose pixels have `avg` entries on average
+int scatter_waves_per_slice(double avg) { return avg >= 128 ? 8 : avg >= 64 ? 4 : avg >= 32 ? 2 : 1; }
 
 hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
                           double* pq_part, int pq_stride, int pq_slot, const CgState* st) {
   if (n_obs == 0) return hipSuccess;
-  const dim3 g((unsigned)scatter_blocks(n_obs)), b(64 * kSliceWaves);
+  const dim3 g((unsigned)scatter_blocks(n_obs, L.wps)), b(64 * kBlockWaves);
   const float2* w = (const float2*)L.w;
-#define MM_SC(T, NS, RG) hipLaunchKernelGGL((k_scatter<T, NS, RG>), g, b, 0, s, L.end, L.len, L.t, w, (const T*)y, q, vs, \
-                                            n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot, st)
+#define MM_SC(T, NS, RG, WPS) hipLaunchKernelGGL((k_scatter<T, NS, RG, WPS>), g, b, 0, s, L.end, L.len, L.t, w, \
+                                                 (const T*)y, q, vs, n_obs, n_t, n_rhs, p, pq_part, pq_stride, \
+                                                 pq_slot, st)
+#define MM_SC_W(T, NS, RG)                     \
+  switch (L.wps) {                             \
+    case 1: MM_SC(T, NS, RG, 1); break;        \
+    case 2: MM_SC(T, NS, RG, 2); break;        \
+    case 4: MM_SC(T, NS, RG, 4); break;        \
+    default: MM_SC(T, NS, RG, 8); break;       \
+  }
   // one accumulator set for a single RHS; groups of 4 otherwise
   if (in_f64) {
-    if (ns == 1) { if (n_rhs == 1) MM_SC(double, 1, 1); else MM_SC(double, 1, 4); }
-    else { if (n_rhs == 1) MM_SC(double, 3, 1); else MM_SC(double, 3, 4); }
+    if (ns == 1) { if (n_rhs == 1) { MM_SC_W(double, 1, 1) } else { MM_SC_W(double, 1, 4) } }
+    else { if (n_rhs == 1) { MM_SC_W(double, 3, 1) } else { MM_SC_W(double, 3, 4) } }
   } else {
-    if (ns == 1) { if (n_rhs == 1) MM_SC(float, 1, 1); else MM_SC(float, 1, 4); }
-    else { if (n_rhs == 1) MM_SC(float, 3, 1); else MM_SC(float, 3, 4); }
+    if (ns == 1) { if (n_rhs == 1) { MM_SC_W(float, 1, 1) } else { MM_SC_W(float, 1, 4) } }
+    else { if (n_rhs == 1) { MM_SC_W(float, 3, 1) } else { MM_SC_W(float, 3, 4) } }
   }
+#undef MM_SC_W
 #undef MM_SC
   return hipGetLastError();
 }

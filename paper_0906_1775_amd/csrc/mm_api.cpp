@@ -697,6 +697,7 @@ void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
   L.sell.len = len;
   L.sell.t = st;
   L.sell.w = sw;
+  L.sell.wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
   P->release(L.perm);
   L.perm = nullptr;
   P->release(L.w_pm);
@@ -927,10 +928,10 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
 
   // ---- p.q partial sums: the sky scatter's blocks, then each template's
   // (a scatter with no observed column writes none)
-  P->n_pq = P->n_obs > 0 ? scatter_blocks(P->n_obs) : 0;
+  P->n_pq = P->n_obs > 0 ? scatter_blocks(P->n_obs, P->px.sell.wps) : 0;
   for (Template& T : P->tmpl) {
     T.pq_slot = P->n_pq;
-    T.pq_n = T.kind == MM_TMPL_ONEHOT ? (T.lay.n_obs > 0 ? scatter_blocks(T.lay.n_obs) : 0) : 1;
+    T.pq_n = T.kind == MM_TMPL_ONEHOT ? (T.lay.n_obs > 0 ? scatter_blocks(T.lay.n_obs, T.lay.sell.wps) : 0) : 1;
     P->n_pq += T.pq_n;
   }
 

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import synth
-from gpu_helpers import oracle_for, plan_for, rel_err, tod_tensor
+from gpu_helpers import max_rel, oracle_for, plan_for, rel_err, tod_tensor
 from oracle import Oracle
 
 pytestmark = pytest.mark.gpu
@@ -126,3 +126,26 @@ def test_solves_are_bitwise_repeatable(precision):
     m2, i2 = mm.solve(tod, tol=1e-10, max_iter=300)
     assert torch.equal(m1, m2)
     assert i1["iters"] == i2["iters"]
+
+
+@pytest.mark.parametrize("grid,wps", [((4, 4), 8), ((7, 7), 4), ((10, 10), 2), ((18, 18), 1)])
+@pytest.mark.parametrize("n_rhs", [1, 3])
+def test_scatter_widths_match_the_oracle(grid, wps, n_rhs):
+    # the scatter splits a slice of 64 pixels over 8, 4, 2 or 1 wavefronts depending on the
+    # mean hits per observed pixel (>= 128, >= 64, >= 32, fewer); each width against A^T y
+    p = _small(grid=grid, n_rhs=n_rhs)
+    o = oracle_for(p, L_K)
+    mm = plan_for(p, lag_dft_len=L_K)
+    n_obs = mm.info()["n_obs"]
+    hits = int(np.count_nonzero(p.pix >= 0)) / n_obs
+    assert wps == (8 if hits >= 128 else 4 if hits >= 64 else 2 if hits >= 32 else 1), hits
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal((n_rhs, p.n_samples))
+    for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-6)):
+        pt = mm.point(torch.from_numpy(y).cuda().to(dt)).cpu().numpy()
+        for r in range(n_rhs):
+            want = o.to_global(o.apply_At(torch.from_numpy(y[r]).to(dt).double().numpy())).ravel()
+            assert max_rel(pt[r].ravel(), want) <= tol
+    m, _ = mm.solve(tod_tensor(p), fixed_iters=5)
+    x, _ = o.pcg(o.rhs(p.tod[n_rhs - 1]), fixed_iters=5)
+    assert rel_err(m.cpu().numpy()[n_rhs - 1], o.to_global(x)) <= 1e-10
