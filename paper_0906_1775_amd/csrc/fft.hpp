@@ -18,6 +18,13 @@
 // Thread t owns butterflies b = t + i NT.  After the last pass the output of
 // (b, r) is point b + r N/R_last, i.e. the natural order, strided.
 //
+// Paired layout (PAIRED, for shapes with two butterflies per thread in the
+// last forward pass): there thread t owns butterflies t and 2 NT - t (0 and
+// NT for t = 0) instead of t and t + NT.  Butterfly b and N/R - b hold the
+// points k and N - k, so after the forward transform every thread has both
+// members of its conjugate pairs (Z_k, Z_{N-k}) in registers.  The first
+// pass of the radix-reversed sequence shares that layout.
+//
 // Twiddles come from per-pass tables built once in float64 and rounded to T:
 // pass p with radix R and span Ns owns Ns rows of R entries,
 // row j = exp(-2 pi i j r / (Ns R)), r < R, so a thread reads its R-1 factors
@@ -115,7 +122,11 @@ __device__ __forceinline__ void dft_reg(cx<T>* v) {
 
 // LOGR: log2 of the largest radix (default: one butterfly of E points per thread
 // per pass); with LOGR < LOGE each thread runs E / R butterflies per pass.
-template <typename T, int LOGN, int NT_, int LOGE, int LOGR_ = LOGE>
+// FORCE_SPLIT: exchange real and imaginary parts separately even when N complex
+// points fit in LDS (half the LDS, so two workgroups can share a CU).
+// PAIRED: the paired layout of the last forward pass (see above).
+template <typename T, int LOGN, int NT_, int LOGE, int LOGR_ = LOGE, bool FORCE_SPLIT = false,
+          bool PAIRED_ = false>
 struct BlockFFT {
   static constexpr int N = 1 << LOGN;
   static constexpr int NT = NT_;
@@ -136,23 +147,50 @@ struct BlockFFT {
   static constexpr int sc_pad_log = (sizeof(T) == 4) ? 5 : 4;  // 128 B / sizeof T
   static constexpr int cx_bytes = (N + (N >> cx_pad_log)) * 2 * (int)sizeof(T);
   static constexpr int sc_bytes = (N + (N >> sc_pad_log)) * (int)sizeof(T);
-  static constexpr bool SPLIT = cx_bytes > kLdsLimit;
+  static constexpr bool SPLIT = FORCE_SPLIT || cx_bytes > kLdsLimit;
+  static constexpr bool PAIRED = PAIRED_;
+  static_assert(!PAIRED || (NP >= 2 && E == 2 * (1 << LOGR_)), "paired layout needs two butterflies per thread");
+  // is pass p of a sequence in the paired layout (last forward pass, first reversed pass)
+  static constexpr bool pass_paired(bool fwd, int p) { return PAIRED && (fwd ? p == NP - 1 : p == 0); }
   static constexpr int LDS_BYTES = SPLIT ? sc_bytes : cx_bytes;
   static_assert(LDS_BYTES <= kLdsLimit, "transform does not fit in LDS");
 
   __device__ static __forceinline__ int cpad(int i) { return i + (i >> cx_pad_log); }
   __device__ static __forceinline__ int spad(int i) { return i + (i >> sc_pad_log); }
 
+  // butterfly handled as the i-th of thread t in a pass (PAIR: paired layout)
+  template <bool PAIR>
+  __device__ static __forceinline__ int bfly(int t, int i) {
+    if constexpr (PAIR) return i == 0 ? t : (t == 0 ? NT : 2 * NT - t);
+    else return t + i * NT;
+  }
   // output position of element (i, r) of thread t after a pass (LOGR, LOGNS)
-  template <int LOGR, int LOGNS>
+  template <int LOGR, int LOGNS, bool PAIR = false>
   __device__ static __forceinline__ int out_index(int t, int i, int r) {
-    const int b = t + i * NT;
+    const int b = bfly<PAIR>(t, i);
     return ((b >> LOGNS) << (LOGNS + LOGR)) + (b & ((1 << LOGNS) - 1)) + (r << LOGNS);
   }
   // input position of element (i, r) of thread t for a pass of radix 2^LOGR
-  template <int LOGR>
+  template <int LOGR, bool PAIR = false>
   __device__ static __forceinline__ int in_index(int t, int i, int r) {
-    return t + i * NT + (r << (LOGN - LOGR));
+    return bfly<PAIR>(t, i) + (r << (LOGN - LOGR));
+  }
+  // out_index(t, i, r) = out_base(t, i) + (r << LOGNS)
+  template <int LOGR, int LOGNS, bool PAIR>
+  __device__ static __forceinline__ int out_base(int t, int i) {
+    const int b = bfly<PAIR>(t, i);
+    return ((b >> LOGNS) << (LOGNS + LOGR)) + (b & ((1 << LOGNS) - 1));
+  }
+  // Padded LDS slot of v + (r << LOGC), with the padding of the constant part
+  // folded at compile time: v + c and v stay in rows (of 2^PL elements) that
+  // differ by exactly floor(c / 2^PL) for every index an exchange forms.  Reads
+  // have v = b, c = r N/R': c is a multiple of 2^PL, or v < N/R' divides 2^PL.
+  // Writes have v = M + (b mod Ns), c = r Ns < Ns R with M a multiple of Ns R,
+  // so (v + c) mod 2^PL never wraps past the row of v.
+  template <int PL, int LOGC>
+  __device__ static __forceinline__ int padded(int v, int r) {
+    const int c = r << LOGC;
+    return v + (v >> PL) + c + (c >> PL);
   }
 
   // ---- per-pass twiddle tables
@@ -178,14 +216,14 @@ struct BlockFFT {
   static constexpr int tw_total() { return tw_total_seq(true) + tw_total_seq(false); }
 
   // butterflies of one pass, in registers; ptab = this pass's table (rows of R factors)
-  template <int LOGR, int LOGNS>
+  template <int LOGR, int LOGNS, bool PAIR>
   __device__ static __forceinline__ void butterflies(cx<T>* v, const cx<T>* __restrict__ ptab, int t) {
     constexpr int R = 1 << LOGR;
     constexpr int NB = E / R;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       if (LOGNS > 0) {
-        const int j = (t + i * NT) & ((1 << LOGNS) - 1);
+        const int j = bfly<PAIR>(t, i) & ((1 << LOGNS) - 1);
         const cx<T>* __restrict__ w = ptab + (j << LOGR);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], w[r]);
@@ -195,7 +233,7 @@ struct BlockFFT {
   }
 
   // redistribute: element (i, r) of a pass (LOGR, LOGNS) goes to the slot of the next pass (LOGR2)
-  template <int LOGR, int LOGNS, int LOGR2>
+  template <int LOGR, int LOGNS, int LOGR2, bool PAIR_OUT, bool PAIR_IN>
   __device__ static __forceinline__ void exchange(cx<T>* v, void* lds_raw, int t) {
     constexpr int R = 1 << LOGR, NB = E / R;
     constexpr int R2 = 1 << LOGR2, NB2 = E / R2;
@@ -203,14 +241,18 @@ struct BlockFFT {
       cx<T>* lds = reinterpret_cast<cx<T>*>(lds_raw);
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
+      for (int i = 0; i < NB; ++i) {
+        const int vb = out_base<LOGR, LOGNS, PAIR_OUT>(t, i);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[cpad(out_index<LOGR, LOGNS>(t, i, r))] = v[i * R + r];
+        for (int r = 0; r < R; ++r) lds[padded<cx_pad_log, LOGNS>(vb, r)] = v[i * R + r];
+      }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < NB2; ++i)
+      for (int i = 0; i < NB2; ++i) {
+        const int vb = bfly<PAIR_IN>(t, i);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds[cpad(in_index<LOGR2>(t, i, r))];
+        for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds[padded<cx_pad_log, LOGN - LOGR2>(vb, r)];
+      }
     } else {
       T* lds = reinterpret_cast<T*>(lds_raw);
       // real parts, then imaginary parts; a component can be overwritten as soon as
@@ -219,18 +261,22 @@ struct BlockFFT {
       for (int part = 0; part < 2; ++part) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
+        for (int i = 0; i < NB; ++i) {
+          const int vb = out_base<LOGR, LOGNS, PAIR_OUT>(t, i);
 #pragma unroll
           for (int r = 0; r < R; ++r)
-            lds[spad(out_index<LOGR, LOGNS>(t, i, r))] = part ? v[i * R + r].im : v[i * R + r].re;
+            lds[padded<sc_pad_log, LOGNS>(vb, r)] = part ? v[i * R + r].im : v[i * R + r].re;
+        }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NB2; ++i)
+        for (int i = 0; i < NB2; ++i) {
+          const int vb = bfly<PAIR_IN>(t, i);
 #pragma unroll
           for (int r = 0; r < R2; ++r) {
-            const T x = lds[spad(in_index<LOGR2>(t, i, r))];
+            const T x = lds[padded<sc_pad_log, LOGN - LOGR2>(vb, r)];
             if (part) v[i * R2 + r].im = x; else v[i * R2 + r].re = x;
           }
+        }
       }
     }
   }
@@ -240,25 +286,33 @@ struct BlockFFT {
   __device__ static __forceinline__ void run_from(cx<T>* v, void* lds, const cx<T>* __restrict__ ptw,
                                                   int t) {
     constexpr int LR = FWD ? flog(p) : ilog(p);
-    butterflies<LR, LOGNS>(v, ptw + tw_offset(FWD, p), t);
+    constexpr bool PO = pass_paired(FWD, p);
+    butterflies<LR, LOGNS, PO>(v, ptw + tw_offset(FWD, p), t);
     if constexpr (p + 1 < NP) {
       constexpr int LR2 = FWD ? flog(p + 1) : ilog(p + 1);
-      exchange<LR, LOGNS, LR2>(v, lds, t);
+      exchange<LR, LOGNS, LR2, PO, pass_paired(FWD, p + 1)>(v, lds, t);
       run_from<FWD, p + 1, LOGNS + LR>(v, lds, ptw, t);
     }
   }
 
   // Input: point (i, r) of thread t holds x[in_index<first radix>(t, i, r)].
-  // Output: point (i, r) holds X[t + i NT + r N / R_last] (forward DFT, no scaling).
+  // Output: point (i, r) holds X[fwd_out_index(t, i, r)] (forward DFT, no scaling).
   // ptw: the per-pass twiddle tables of this shape (tw_total() entries).
   __device__ static __forceinline__ void forward(cx<T>* v, void* lds, const cx<T>* __restrict__ ptw,
                                                  int t) {
     run_from<true, 0, 0>(v, lds, ptw, t);
   }
-  // Same transform with the radix order reversed (first pass = forward's last radix).
+  // Same transform with the radix order reversed (first pass = forward's last radix);
+  // its input layout is the forward output layout, its output point (i, r) holds
+  // X[t + i NT + r N / R_last] with R_last its last radix.
   __device__ static __forceinline__ void forward_rev(cx<T>* v, void* lds, const cx<T>* __restrict__ ptw,
                                                      int t) {
     run_from<false, 0, 0>(v, lds, ptw, t);
+  }
+
+  // position of point (i, r) of thread t after forward()
+  __device__ static __forceinline__ int fwd_out_index(int t, int i, int r) {
+    return bfly<PAIRED>(t, i) + (r << (LOGN - flog(NP - 1)));
   }
 
   static constexpr int first_log_fwd() { return flog(0); }

@@ -66,20 +66,44 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s) {
 // Variant 1 uses half the threads with twice the points each and radix-32
 // passes: a 2^14-point transform then takes three register passes and two LDS
 // exchanges instead of four and three, at 2 wavefronts per SIMD instead of 4.
-// Variant 2 is that thread count with radix-16 passes.
-template <int LOGN, int V> struct OlsShape : Shape<LOGN> {};
-template <> struct OlsShape<13, 1> { static constexpr int NT = 256, LOGE = 5, LOGR = 5; };
-template <> struct OlsShape<14, 1> { static constexpr int NT = 512, LOGE = 5, LOGR = 5; };
-template <> struct OlsShape<14, 2> { static constexpr int NT = 512, LOGE = 5, LOGR = 4; };
+// Variant 2 is that thread count with radix-16 passes, two butterflies per
+// thread and the paired layout, so the conjugate pairs of the real-to-complex
+// step meet in registers.  Variant 3 is variant 2 with the LDS exchanges split
+// into real and imaginary halves (68 KB) and at most 128 VGPRs, so that two
+// workgroups share a CU and one's global loads and stores overlap the other's
+// arithmetic.  Variant 4 is 256 threads x 64 points with radix-32 passes, split
+// and two per CU.  Variant 5 is 1024 threads x 16 points with radix-8 passes
+// and the paired layout (the fastest 2^14-point shape measured, in float32 and
+// float64); variant 6 is variant 5 split, two per CU.  BPC: workgroups per CU
+// the register budget is sized for.
+template <int NT_, int LOGE_, int LOGR_, bool SPLIT_ = false, bool PAIRED_ = false, int BPC_ = 1>
+struct OlsCfg {
+  static constexpr int NT = NT_, LOGE = LOGE_, LOGR = LOGR_, BPC = BPC_;
+  static constexpr bool SPLIT = SPLIT_, PAIRED = PAIRED_;
+  // minimum wavefronts per SIMD asked of the register allocator
+  static constexpr int WPE = (BPC_ * NT_ / 256) > 1 ? (BPC_ * NT_ / 256) : 1;
+};
+template <int LOGN, int V> struct OlsShape : OlsCfg<Shape<LOGN>::NT, Shape<LOGN>::LOGE, Shape<LOGN>::LOGR> {};
+template <> struct OlsShape<15, 0> : OlsCfg<1024, 5, 4, false, true> {};
+template <> struct OlsShape<13, 1> : OlsCfg<256, 5, 5> {};
+template <> struct OlsShape<14, 1> : OlsCfg<512, 5, 5> {};
+template <> struct OlsShape<14, 2> : OlsCfg<512, 5, 4, false, true> {};
+template <> struct OlsShape<14, 3> : OlsCfg<512, 5, 4, true, true, 2> {};
+template <> struct OlsShape<14, 4> : OlsCfg<256, 6, 5, true, true, 2> {};
+template <> struct OlsShape<14, 5> : OlsCfg<1024, 4, 3, false, true> {};
+template <> struct OlsShape<14, 6> : OlsCfg<1024, 4, 3, true, true, 2> {};
+template <> struct OlsShape<15, 1> : OlsCfg<512, 6, 5, false, true> {};
 
 bool ols_variant_exists(int logn, bool fp64, int v) {
   if (v == 0) return logn >= kMinLogN && logn <= ols_max_logn(fp64);
+  if (v == 5) return logn == 14;
   if (fp64) return false;
-  return (v == 1 && (logn == 13 || logn == 14)) || (v == 2 && logn == 14);
+  return (v == 1 && (logn == 13 || logn == 14 || logn == 15)) || ((v >= 2 && v <= 6) && logn == 14);
 }
 
 template <typename T, int LOGN, int V = 0>
-using ShapeFFT = BlockFFT<T, LOGN, OlsShape<LOGN, V>::NT, OlsShape<LOGN, V>::LOGE, OlsShape<LOGN, V>::LOGR>;
+using ShapeFFT = BlockFFT<T, LOGN, OlsShape<LOGN, V>::NT, OlsShape<LOGN, V>::LOGE, OlsShape<LOGN, V>::LOGR,
+                          OlsShape<LOGN, V>::SPLIT, OlsShape<LOGN, V>::PAIRED>;
 
 // per-pass twiddle rows: entry (j, r) of pass p = exp(-2 pi i j r / (Ns R))
 template <typename T, int LOGN, int V>
@@ -109,8 +133,14 @@ static int pass_tw_total_t() { return ShapeFFT<T, LOGN, V>::tw_total(); }
 
 int pass_twiddle_count(int logn, bool fp64, int variant) {
   if (!ols_variant_exists(logn, fp64, variant)) return -1;
-  if (variant == 1) return logn == 13 ? pass_tw_total_t<float, 13, 1>() : pass_tw_total_t<float, 14, 1>();
+  if (variant == 1)
+    return logn == 13 ? pass_tw_total_t<float, 13, 1>()
+                      : (logn == 14 ? pass_tw_total_t<float, 14, 1>() : pass_tw_total_t<float, 15, 1>());
   if (variant == 2) return pass_tw_total_t<float, 14, 2>();
+  if (variant == 3) return pass_tw_total_t<float, 14, 3>();
+  if (variant == 4) return pass_tw_total_t<float, 14, 4>();
+  if (variant == 5) return fp64 ? pass_tw_total_t<double, 14, 5>() : pass_tw_total_t<float, 14, 5>();
+  if (variant == 6) return pass_tw_total_t<float, 14, 6>();
 #define MM_PTC(L) case L: return fp64 ? pass_tw_total_t<double, L>() : pass_tw_total_t<float, L>();
   switch (logn) {
     MM_PTC(6) MM_PTC(7) MM_PTC(8) MM_PTC(9) MM_PTC(10) MM_PTC(11) MM_PTC(12) MM_PTC(13) MM_PTC(14)
@@ -130,8 +160,14 @@ static hipError_t pass_tw_launch(void* tab, hipStream_t s) {
 
 hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, int variant) {
   if (!ols_variant_exists(logn, fp64, variant)) return hipErrorInvalidValue;
-  if (variant == 1) return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s) : pass_tw_launch<float, 14, 1>(tab, s);
+  if (variant == 1)
+    return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s)
+                      : (logn == 14 ? pass_tw_launch<float, 14, 1>(tab, s) : pass_tw_launch<float, 15, 1>(tab, s));
   if (variant == 2) return pass_tw_launch<float, 14, 2>(tab, s);
+  if (variant == 3) return pass_tw_launch<float, 14, 3>(tab, s);
+  if (variant == 4) return pass_tw_launch<float, 14, 4>(tab, s);
+  if (variant == 5) return fp64 ? pass_tw_launch<double, 14, 5>(tab, s) : pass_tw_launch<float, 14, 5>(tab, s);
+  if (variant == 6) return pass_tw_launch<float, 14, 6>(tab, s);
 #define MM_PTL(L) case L: return fp64 ? pass_tw_launch<double, L>(tab, s) : pass_tw_launch<float, L>(tab, s);
   switch (logn) {
     MM_PTL(6) MM_PTL(7) MM_PTL(8) MM_PTL(9) MM_PTL(10) MM_PTL(11) MM_PTL(12) MM_PTL(13) MM_PTL(14)
@@ -337,6 +373,35 @@ __device__ __forceinline__ void with_partner(cx<T>* v, void* lds, int t, Fn fn) 
   }
 }
 
+// Paired shapes: after the forward transform the thread already holds Z_{N-k}
+// beside each of its Z_k (fft.hpp, paired layout).  fn(k, Z_k, Z_{N-k}, out_k,
+// out_{N-k}) replaces both members of a pair.  Thread 0 owns butterflies 0 and
+// NT, which pair with themselves; k = 0 and k = N/2 are their own partners
+// (then only out_k is kept).
+template <typename F, typename T, typename Fn>
+__device__ __forceinline__ void with_partner_paired(cx<T>* v, int t, Fn fn) {
+  constexpr int N = F::N, R = 1 << F::last_log_fwd();
+  static_assert(F::PAIRED && F::E == 2 * R, "paired layout expected");
+  if (t != 0) {
+    // (0, r) holds k = t + r N/R; (1, R - 1 - r) holds N - k
+#pragma unroll
+    for (int r = 0; r < R; ++r) fn(F::fwd_out_index(t, 0, r), v[r], v[2 * R - 1 - r]);
+  } else {
+    // butterfly 0: (0, r) <-> (0, R - r); butterfly NT: (1, r) <-> (1, R - 1 - r)
+#pragma unroll
+    for (int r = 0; r <= R / 2; ++r) {
+      if (r == 0 || r == R / 2) {
+        cx<T> self = v[r];
+        fn(F::fwd_out_index(0, 0, r), v[r], self);
+      } else {
+        fn(F::fwd_out_index(0, 0, r), v[r], v[R - r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r) fn(F::fwd_out_index(0, 1, r), v[R + r], v[2 * R - 1 - r]);
+  }
+}
+
 // ---------------------------------------------------------------- spectra
 // Symbol of the circulant that embeds one filter's band:
 //   F_k = f(0) + 2 sum_{tau=1}^{n_c-1} f(tau) cos(2 pi k tau / n_f),  k = 0 .. N,
@@ -470,7 +535,8 @@ template <> struct Pair<float> { using type = float2; };
 template <> struct Pair<double> { using type = double2; };
 
 template <typename T, typename Tin, int LOGN, int V>
-__global__ __launch_bounds__((OlsShape<LOGN, V>::NT)) void k_ols(
+__global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
+                          amdgpu_waves_per_eu(OlsShape<LOGN, V>::WPE))) void k_ols(
     const Tin* __restrict__ yin, T* __restrict__ yout, const OlsChunk* __restrict__ chunks,
     const T* __restrict__ spec, const cx<T>* __restrict__ ptw, const cx<T>* __restrict__ tw2,
     int64_t n_t, int n_c, int m, const CgState* __restrict__ st) {
@@ -497,7 +563,8 @@ __global__ __launch_bounds__((OlsShape<LOGN, V>::NT)) void k_ols(
     for (int i = 0; i < E / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        const PI x = src2[F::template in_index<L0>(t, i, r)];
+        // 32-bit offsets from the uniform window base: one VGPR per address
+        const PI x = src2[(uint32_t)F::template in_index<L0>(t, i, r)];
         v[i * R0 + r] = {(T)x.x, (T)x.y};
       }
   } else {
@@ -515,23 +582,38 @@ __global__ __launch_bounds__((OlsShape<LOGN, V>::NT)) void k_ols(
 
   F::forward(v, lds, ptw, t);
 
-  // pair Z_k with Z_{N-k} through LDS and apply the filter symbol
+  // pair Z_k with Z_{N-k} (in registers, or through LDS) and apply the filter symbol.
+  // For the pair (k, N-k): A = Z_k, B = conj Z_{N-k}, E = A + B, O = -i (A - B),
+  // Y = (E + W O) F_k, Y' = (E - W O) F_{N-k}; the new Z_k is conj(s + i W^-1 d) and
+  // the new Z_{N-k} is s - i W^-1 d, with s = Y + Y', d = Y - Y', W = e^{-2 pi i k/(2N)}.
   const T* __restrict__ S = spec + (int64_t)ch.filter * (N + 1);
-  with_partner<F>(v, lds, t, [&](int k, cx<T> A, cx<T> partner) -> cx<T> {
+  auto pair_terms = [&](int k, cx<T> A, cx<T> partner, cx<T>& sum, cx<T>& Wd) {
     const cx<T> B = cconj(partner);
     const cx<T> Ev = cadd(A, B);
     const cx<T> D = csub(A, B);
     const cx<T> O = {D.im, -D.re};            // -i (A - B)
-    const cx<T> W = tw2[k];                    // e^{-2 pi i k / (2N)}
+    const cx<T> W = tw2[k];
     const cx<T> WO = cmul(W, O);
     const T sa = S[k], sb = S[N - k];
     const cx<T> Y = cscale(cadd(Ev, WO), sa);
     const cx<T> Yp = cscale(csub(Ev, WO), sb);
-    const cx<T> sum = cadd(Y, Yp);
-    const cx<T> dif = csub(Y, Yp);
-    const cx<T> Wd = cmul(cconj(W), dif);      // W^{-k} (Y - Y')
-    return {sum.re - Wd.im, -(sum.im + Wd.re)};  // conj(sum + i Wd)
-  });
+    sum = cadd(Y, Yp);
+    Wd = cmul(cconj(W), csub(Y, Yp));          // W^{-k} (Y - Y')
+  };
+  if constexpr (F::PAIRED) {
+    with_partner_paired<F>(v, t, [&](int k, cx<T>& zk, cx<T>& znk) {
+      cx<T> sum, Wd;
+      pair_terms(k, zk, znk, sum, Wd);
+      zk = {sum.re - Wd.im, -(sum.im + Wd.re)};   // conj(sum + i Wd)
+      znk = {sum.re + Wd.im, sum.im - Wd.re};     // sum - i Wd
+    });
+  } else {
+    with_partner<F>(v, lds, t, [&](int k, cx<T> A, cx<T> partner) -> cx<T> {
+      cx<T> sum, Wd;
+      pair_terms(k, A, partner, sum, Wd);
+      return {sum.re - Wd.im, -(sum.im + Wd.re)};
+    });
+  }
 
   F::forward_rev(v, lds, ptw, t);
 
@@ -548,7 +630,7 @@ __global__ __launch_bounds__((OlsShape<LOGN, V>::NT)) void k_ols(
       for (int r = 0; r < RZ; ++r) {
         const int j = t + i * NT + r * (N >> LZ);
         const cx<T> z = v[i * RZ + r];
-        if (j >= j0 && j < j1) dst2[j] = PO{z.re, -z.im};
+        if (j >= j0 && j < j1) dst2[(uint32_t)j] = PO{z.re, -z.im};
       }
   } else {
 #pragma unroll
@@ -579,10 +661,16 @@ static hipError_t ols_dispatch(int logn, int variant, const void* y_in, void* y_
                                int n_chunks, const void* spec, const void* ptw, const void* tw2,
                                int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s, const CgState* st) {
   if (!ols_variant_exists(logn, sizeof(T) == 8, variant)) return hipErrorInvalidValue;
+  if (variant == 5) return ols_launch<T, Tin, 14, 5>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st);
 #define MM_OLS_ARGS y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st
   if constexpr (sizeof(T) == 4) {
-    if (variant == 1) return logn == 13 ? ols_launch<T, Tin, 13, 1>(MM_OLS_ARGS) : ols_launch<T, Tin, 14, 1>(MM_OLS_ARGS);
+    if (variant == 1)
+      return logn == 13 ? ols_launch<T, Tin, 13, 1>(MM_OLS_ARGS)
+                        : (logn == 14 ? ols_launch<T, Tin, 14, 1>(MM_OLS_ARGS) : ols_launch<T, Tin, 15, 1>(MM_OLS_ARGS));
     if (variant == 2) return ols_launch<T, Tin, 14, 2>(MM_OLS_ARGS);
+    if (variant == 3) return ols_launch<T, Tin, 14, 3>(MM_OLS_ARGS);
+    if (variant == 4) return ols_launch<T, Tin, 14, 4>(MM_OLS_ARGS);
+    if (variant == 6) return ols_launch<T, Tin, 14, 6>(MM_OLS_ARGS);
     if (logn == 15) return ols_launch<T, Tin, 15>(MM_OLS_ARGS);
   }
 #define MM_OLS_CASE(L) case L: return ols_launch<T, Tin, L>(MM_OLS_ARGS);

@@ -187,12 +187,12 @@ hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const f
   return hipGetLastError();
 }
 
-// q = P^T y over the sliced layout.  A block of kSliceWaves wavefronts owns one
-// slice at a time: wavefront w adds the entries j = w, w + W, w + 2W, ... of
-// its lane's pixel (W = kSliceWaves), fetching kBatch entries ahead so that
-// their loads overlap, and the W partial sums are combined in wavefront order
-// through LDS.  Grid-stride over slices with a bounded grid (kScatterBlocks),
-// so the optional p.q partial sums form a short, fixed list.
+// q = P^T y over the sliced layout.  WPS wavefronts share a slice: wavefront w
+// adds the entries j = w, w + WPS, w + 2 WPS, ... of its lane's pixel,
+// fetching kBatch entries ahead so that their loads overlap, and the WPS
+// partial sums are combined in wavefront order through LDS.  Grid-stride over
+// slices with a bounded grid (kScatterBlocks), so the optional p.q partial
+// sums form a short, fixed list.
 constexpr int kBlockWaves = 8;   // wavefronts per scatter block
 constexpr int kBatch = 4;
 
