@@ -39,7 +39,7 @@ template <typename Ty, int NS, typename Tp>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
                                                 const float2* __restrict__ w,
                                                 const Tp* __restrict__ p, int64_t vs,
-                                                Ty* __restrict__ y, int64_t n_t, int n_rhs,
+                                                Ty* __restrict__ y, int64_t n_t, int64_t ys, int n_rhs,
                                                 const CgState* __restrict__ st) {
   constexpr int U = kGatherUnroll;
   const int64_t step = (int64_t)gridDim.x * 256 * U;
@@ -64,7 +64,8 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
           if (NS == 1) {
             v[u] = (double)p[(int64_t)r * vs + o[u]];
           } else {
-            const Tp* m = p + (int64_t)r * vs + (int64_t)o[u] * 3;
+            // float32 copies are pixel-padded (4 values per pixel)
+            const Tp* m = p + (int64_t)r * vs + (int64_t)o[u] * (sizeof(Tp) == 4 ? 4 : 3);
             v[u] = 0.5 * ((double)m[0] + (double)sc[u].x * (double)m[1] + (double)sc[u].y * (double)m[2]);
           }
         }
@@ -72,22 +73,23 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t t = t0 + u * 256;
-        if (t < n_t) y[(int64_t)r * n_t + t] = (Ty)v[u];
+        if (t < n_t) y[(int64_t)r * ys + t] = (Ty)v[u];
       }
     }
   }
 }
 
-hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
-                         const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
-                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32) {
-  (void)n_obs;
+// per-sample gather of n samples into rows of stride ys
+static hipError_t launch_gather_samples(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
+                                        const double* p, int64_t vs, void* y, int64_t n_t, int64_t ys,
+                                        int n_rhs, hipStream_t s, const CgState* st, const float* p32,
+                                        int64_t vs32) {
   if (n_t == 0) return hipSuccess;
   int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
   if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
-#define MM_GA(TY, NS, TP, PP, VS) hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, n_rhs, st)
+#define MM_GA(TY, NS, TP, PP, VS) hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, ys, n_rhs, st)
   if (p32) {
     if (out_f64) { if (ns == 1) MM_GA(double, 1, float, p32, vs32); else MM_GA(double, 3, float, p32, vs32); }
     else { if (ns == 1) MM_GA(float, 1, float, p32, vs32); else MM_GA(float, 3, float, p32, vs32); }
@@ -99,14 +101,139 @@ hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const flo
   return hipGetLastError();
 }
 
+// Four consecutive samples per thread: the pointing is read with 16-byte loads
+// (4 pixel ids, then 2 x 2 (sin, cos) pairs) and, when every TOD row starts on a
+// 4-sample boundary, the TOD is written with 16-byte (float32) or 2 x 16-byte
+// (float64) stores.  Same values as k_gather; used when the pointing streams
+// are 16-byte aligned.  The n_t mod 4 trailing samples go through k_gather's
+// per-sample path (one block).
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+constexpr int kGather4Unroll = 2;
+
+// Tp = float: p is the pixel-padded float32 copy (pixel o at o * f32_pixel_stride(NS)).
+// o must be a valid pixel: excised samples are clamped to pixel 0 by the caller and
+// their value discarded, so that no load sits behind a branch.
+template <int NS, typename Tp>
+__device__ __forceinline__ double sky_value(const Tp* __restrict__ row, int32_t o, float s, float c) {
+  if constexpr (NS == 1) {
+    return (double)row[o];
+  } else if constexpr (sizeof(Tp) == 4) {
+    const v4f m = *reinterpret_cast<const v4f*>(row + (int64_t)o * 4);
+    return 0.5 * ((double)m.x + (double)s * (double)m.y + (double)c * (double)m.z);
+  } else {
+    const Tp* m = row + (int64_t)o * 3;
+    return 0.5 * ((double)m[0] + (double)s * (double)m[1] + (double)c * (double)m[2]);
+  }
+}
+
+// requires n_obs >= 1 (pixel 0 exists) and n_t >= 4
+template <typename Ty, int NS, typename Tp>
+__global__ __launch_bounds__(256) void k_gather4(const int32_t* __restrict__ pix_obs, const float* __restrict__ w,
+                                                 const Tp* __restrict__ p, int64_t vs, Ty* __restrict__ y,
+                                                 int64_t n_t, int n_rhs, const CgState* __restrict__ st,
+                                                 bool vec_out) {
+  constexpr int U = kGather4Unroll;
+  const int64_t n_q = n_t >> 2;
+  const int64_t step = (int64_t)gridDim.x * 256 * U;
+  for (int64_t q0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; q0 < n_q; q0 += step) {
+    v4i o[U];
+    v4f sc0[U], sc1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // an idle slot (past the last group) loads the last group and is discarded
+      const int64_t q = q0 + u * 256 < n_q ? q0 + u * 256 : n_q - 1;
+      o[u] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(pix_obs) + q);
+      if (NS == 3) {
+        const v4f* wq = reinterpret_cast<const v4f*>(w) + 2 * q;
+        sc0[u] = __builtin_nontemporal_load(wq);
+        sc1[u] = __builtin_nontemporal_load(wq + 1);
+      } else {
+        sc0[u] = sc1[u] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    for (int r = 0; r < n_rhs; ++r) {
+      if (st && !st[r].active) continue;   // this RHS has stopped iterating
+      const Tp* __restrict__ row = p + (int64_t)r * vs;
+      double v[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t oo[4] = {o[u].x, o[u].y, o[u].z, o[u].w};
+        const float ss[4] = {sc0[u].x, sc0[u].z, sc1[u].x, sc1[u].z};
+        const float cc[4] = {sc0[u].y, sc0[u].w, sc1[u].y, sc1[u].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double val = sky_value<NS, Tp>(row, oo[k] >= 0 ? oo[k] : 0, ss[k], cc[k]);
+          v[u][k] = oo[k] >= 0 ? val : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t q = q0 + u * 256;
+        if (q >= n_q) continue;
+        Ty* __restrict__ yr = y + (int64_t)r * n_t + 4 * q;
+        if (vec_out) {
+          if constexpr (sizeof(Ty) == 4) {
+            *reinterpret_cast<v4f*>(yr) = v4f{(float)v[u][0], (float)v[u][1], (float)v[u][2], (float)v[u][3]};
+          } else {
+            reinterpret_cast<v2d*>(yr)[0] = v2d{v[u][0], v[u][1]};
+            reinterpret_cast<v2d*>(yr)[1] = v2d{v[u][2], v[u][3]};
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) yr[k] = (Ty)v[u][k];
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
+                         const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
+                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32) {
+  if (n_t == 0) return hipSuccess;
+  const bool aligned = n_obs > 0 && n_t >= 4 && (reinterpret_cast<uintptr_t>(pix_obs) & 15) == 0 &&
+                       (ns == 1 || (reinterpret_cast<uintptr_t>(w) & 15) == 0);
+  if (aligned) {
+    const int64_t n_q = n_t >> 2;
+    const bool vec_out = (n_t & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 31) == 0;
+    if (n_q > 0) {
+      int64_t nb = (n_q + 256 * kGather4Unroll - 1) / (256 * kGather4Unroll);
+      if (nb > 65536) nb = 65536;
+      const dim3 g((unsigned)nb), b(256);
+#define MM_G4(TY, NS, TP, PP, VS) \
+  hipLaunchKernelGGL((k_gather4<TY, NS, TP>), g, b, 0, s, pix_obs, w, PP, VS, (TY*)y, n_t, n_rhs, st, vec_out)
+      if (p32) {
+        if (out_f64) { if (ns == 1) MM_G4(double, 1, float, p32, vs32); else MM_G4(double, 3, float, p32, vs32); }
+        else { if (ns == 1) MM_G4(float, 1, float, p32, vs32); else MM_G4(float, 3, float, p32, vs32); }
+      } else {
+        if (out_f64) { if (ns == 1) MM_G4(double, 1, double, p, vs); else MM_G4(double, 3, double, p, vs); }
+        else { if (ns == 1) MM_G4(float, 1, double, p, vs); else MM_G4(float, 3, double, p, vs); }
+      }
+#undef MM_G4
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const int64_t t0 = n_q * 4;
+    if (t0 == n_t) return hipSuccess;
+    // trailing samples: the per-sample kernel on the last n_t - t0 samples (one block)
+    const size_t yb = out_f64 ? sizeof(double) : sizeof(float);
+    return launch_gather_samples(out_f64, ns, pix_obs + t0, w ? w + 2 * t0 : nullptr, p, vs,
+                                 (char*)y + t0 * yb, n_t - t0, n_t, n_rhs, s, st, p32, vs32);
+  }
+  return launch_gather_samples(out_f64, ns, pix_obs, w, p, vs, y, n_t, n_t, n_rhs, s, st, p32, vs32);
+}
+
 // dst[r * dst_stride + i] = (float)src[r * src_stride + i], i < n
 __global__ void k_rows_to_f32(const double* __restrict__ src, int64_t ss, float* __restrict__ dst, int64_t ds,
-                              int64_t n, int n_rhs) {
+                              int64_t n, int n_rhs, int ns) {
   const int64_t total = n * n_rhs;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
     const int64_t r = k / n, i = k % n;
-    dst[r * ds + i] = (float)src[r * ss + i];
+    const int64_t j = ns == 3 ? (i / 3) * 4 + i % 3 : i;   // pixel-padded position
+    dst[r * ds + j] = (float)src[r * ss + i];
   }
 }
 
@@ -235,14 +362,18 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
       const int width = sv ? (int)(slice_len[s] >> 6) : 0;
       Acc<Ty> a[RG][NS];
       for (int j0 = wi; j0 < width; j0 += WPS * kBatch) {
+        // every load is issued unconditionally (a batch slot past the row re-reads the
+        // row's last entry, a padding entry reads sample 0) and masked afterwards, so
+        // that no load waits behind a branch
         int32_t tt[kBatch];
         float2 ww[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
           const int j = j0 + b * WPS;
-          const int64_t e = base + (int64_t)j * 64;
-          tt[b] = j < width ? __builtin_nontemporal_load(sell_t + e) : -1;
-          if (NS == 3) ww[b] = j < width ? load_nt(sell_w + e) : make_float2(0.f, 0.f);
+          const int64_t e = base + (int64_t)(j < width ? j : width - 1) * 64;
+          const int32_t tv = __builtin_nontemporal_load(sell_t + e);
+          tt[b] = j < width ? tv : -1;
+          if (NS == 3) ww[b] = load_nt(sell_w + e);
         }
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
@@ -250,7 +381,10 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
           const Ty* __restrict__ yr = y + (int64_t)(r0 + g) * n_t;
           Ty vv[kBatch];
 #pragma unroll
-          for (int b = 0; b < kBatch; ++b) vv[b] = tt[b] >= 0 ? yr[tt[b]] : (Ty)0;
+          for (int b = 0; b < kBatch; ++b) {
+            const Ty yv = yr[tt[b] >= 0 ? tt[b] : 0];
+            vv[b] = tt[b] >= 0 ? yv : (Ty)0;
+          }
 #pragma unroll
           for (int b = 0; b < kBatch; ++b) {
             if (tt[b] < 0) continue;
@@ -367,9 +501,10 @@ static dim3 grid_for(int64_t n) {
 }
 
 hipError_t launch_rows_to_f32(const double* src, int64_t src_stride, float* dst, int64_t dst_stride, int64_t n,
-                              int n_rhs, hipStream_t s) {
+                              int n_rhs, hipStream_t s, int ns) {
   if (n == 0 || n_rhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_to_f32, grid_for(n * n_rhs), dim3(256), 0, s, src, src_stride, dst, dst_stride, n, n_rhs);
+  hipLaunchKernelGGL(k_rows_to_f32, grid_for(n * n_rhs), dim3(256), 0, s, src, src_stride, dst, dst_stride, n, n_rhs,
+                     ns);
   return hipGetLastError();
 }
 
