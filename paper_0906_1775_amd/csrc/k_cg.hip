@@ -245,7 +245,7 @@ hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const doubl
 __global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z,
                           const double* __restrict__ x, double* __restrict__ xbest,
                           const CgState* __restrict__ st, int64_t nu, float* __restrict__ p32, int64_t n32,
-                          int ns, int64_t vs32) {
+                          int64_t vs32) {
   const int r = blockIdx.y;
   const bool upd = st[r].active != 0;
   const bool best = st[r].copy_best != 0;
@@ -258,20 +258,17 @@ __global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z,
     if (upd) {
       const double pn = z[j] + beta * p[j];
       p[j] = pn;
-      if (p32 && i < n32) {
-        const int64_t k = ns == 3 ? (i / 3) * 4 + i % 3 : i;   // pixel-padded position
-        p32[(int64_t)r * vs32 + k] = (float)pn;
-      }
+      if (p32 && i < n32) p32[(int64_t)r * vs32 + i] = (float)pn;
     }
   }
 }
 
 hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
                           const CgState* st, int64_t nu, int n_rhs, hipStream_t s, float* p32, int64_t n32,
-                          int ns, int64_t vs32) {
+                          int64_t vs32) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
-  hipLaunchKernelGGL(k_cg_next, g, dim3(256), 0, s, p, z, x, xbest, st, nu, p32, n32, ns, vs32);
+  hipLaunchKernelGGL(k_cg_next, g, dim3(256), 0, s, p, z, x, xbest, st, nu, p32, n32, vs32);
   return hipGetLastError();
 }
 

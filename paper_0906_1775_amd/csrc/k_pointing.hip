@@ -64,8 +64,7 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
           if (NS == 1) {
             v[u] = (double)p[(int64_t)r * vs + o[u]];
           } else {
-            // float32 copies are pixel-padded (4 values per pixel)
-            const Tp* m = p + (int64_t)r * vs + (int64_t)o[u] * (sizeof(Tp) == 4 ? 4 : 3);
+            const Tp* m = p + (int64_t)r * vs + (int64_t)o[u] * 3;
             v[u] = 0.5 * ((double)m[0] + (double)sc[u].x * (double)m[1] + (double)sc[u].y * (double)m[2]);
           }
         }
@@ -112,16 +111,12 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 constexpr int kGather4Unroll = 2;
 
-// Tp = float: p is the pixel-padded float32 copy (pixel o at o * f32_pixel_stride(NS)).
 // o must be a valid pixel: excised samples are clamped to pixel 0 by the caller and
 // their value discarded, so that no load sits behind a branch.
 template <int NS, typename Tp>
 __device__ __forceinline__ double sky_value(const Tp* __restrict__ row, int32_t o, float s, float c) {
   if constexpr (NS == 1) {
     return (double)row[o];
-  } else if constexpr (sizeof(Tp) == 4) {
-    const v4f m = *reinterpret_cast<const v4f*>(row + (int64_t)o * 4);
-    return 0.5 * ((double)m.x + (double)s * (double)m.y + (double)c * (double)m.z);
   } else {
     const Tp* m = row + (int64_t)o * 3;
     return 0.5 * ((double)m[0] + (double)s * (double)m[1] + (double)c * (double)m[2]);
@@ -227,13 +222,12 @@ hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const flo
 
 // dst[r * dst_stride + i] = (float)src[r * src_stride + i], i < n
 __global__ void k_rows_to_f32(const double* __restrict__ src, int64_t ss, float* __restrict__ dst, int64_t ds,
-                              int64_t n, int n_rhs, int ns) {
+                              int64_t n, int n_rhs) {
   const int64_t total = n * n_rhs;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
     const int64_t r = k / n, i = k % n;
-    const int64_t j = ns == 3 ? (i / 3) * 4 + i % 3 : i;   // pixel-padded position
-    dst[r * ds + j] = (float)src[r * ss + i];
+    dst[r * ds + i] = (float)src[r * ss + i];
   }
 }
 
@@ -501,10 +495,9 @@ static dim3 grid_for(int64_t n) {
 }
 
 hipError_t launch_rows_to_f32(const double* src, int64_t src_stride, float* dst, int64_t dst_stride, int64_t n,
-                              int n_rhs, hipStream_t s, int ns) {
+                              int n_rhs, hipStream_t s) {
   if (n == 0 || n_rhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_to_f32, grid_for(n * n_rhs), dim3(256), 0, s, src, src_stride, dst, dst_stride, n, n_rhs,
-                     ns);
+  hipLaunchKernelGGL(k_rows_to_f32, grid_for(n * n_rhs), dim3(256), 0, s, src, src_stride, dst, dst_stride, n, n_rhs);
   return hipGetLastError();
 }
 

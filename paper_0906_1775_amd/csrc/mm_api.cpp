@@ -346,7 +346,7 @@ struct mm_plan_s {
   }
 
   int64_t nmap() const { return n_obs * ns; }            // map unknowns per RHS
-  int64_t vs32() const { return n_obs * f32_pixel_stride(ns); }   // row of the pixel-padded float32 copy
+  int64_t vs32() const { return n_obs * ns; }             // row of the float32 copy of p
   int64_t nu() const { return n_obs * ns + n_tunk; }     // iteration vector row
   int64_t ng() const { return n_pix * ns + n_tglob; }    // API map-shaped row
   bool main_fp64() const { return precision == MM_FP64; }
@@ -508,7 +508,7 @@ void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, 
 }
 
 // y_r = [P B] x_r: x in iteration layout (rows of stride nu), y a TOD of type y_f64
-// x32 (optional): a pixel-padded float32 copy of the map part of x, which the sky gather reads instead
+// x32 (optional): a float32 copy of the map part of x, which the sky gather reads instead
 void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipStream_t s,
                 const CgState* st = nullptr, const float* x32 = nullptr) {
   const int64_t vs = P->nu();
@@ -526,7 +526,7 @@ void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipSt
 
 // refresh the float32 copy of p after p was set outside the iteration kernels
 void sync_p32(mm_plan_s* P, hipStream_t s) {
-  if (P->vp32) hipchk(launch_rows_to_f32(P->vp, P->nu(), P->vp32, P->vs32(), P->nmap(), P->R, s, P->ns), "p copy");
+  if (P->vp32) hipchk(launch_rows_to_f32(P->vp, P->nu(), P->vp32, P->vs32(), P->nmap(), P->R, s), "p copy");
 }
 
 // q_r = [P B]^T y_r (iteration layout); with p also the p.q partial sums of
@@ -969,13 +969,8 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->part_pq = P->alloc<double>((int64_t)P->R * std::max(P->n_pq, 1));
   P->st = P->alloc<CgState>(P->R);
   // mixed iterations gather the search direction from a float32 copy of its map part
-  // (half the map bytes; the gathered TOD is float32 anyway), pixel-padded so that a
-  // polarised pixel is one 16-byte load; the padding slots are cleared once
-  if (!P->main_fp64()) {
-    const int64_t n = (int64_t)P->R * std::max<int64_t>(P->vs32(), 1);
-    P->vp32 = P->alloc<float>(n);
-    hipchk(hipMemsetAsync(P->vp32, 0, n * sizeof(float), s), "clear");
-  }
+  // (half the map bytes; the gathered TOD is float32 anyway)
+  if (!P->main_fp64()) P->vp32 = P->alloc<float>((int64_t)P->R * std::max<int64_t>(P->vs32(), 1));
 }
 
 // queue one PCG iteration for every RHS
@@ -991,7 +986,7 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
                           P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
   hipchk(launch_cg_finalize(P->st, P->part2, P->part3, R, P->hist, P->hist_cap, s), "finalize");
-  hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s, P->vp32, P->nmap(), P->ns, P->vs32()),
+  hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
          "next direction");
 }
 

@@ -87,18 +87,15 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
 
 // ---------------------------------------------------------------- pointing (k_pointing.hip)
 // y[r][t] = (P p_r)_t; p rows of stride vs (map values first, observed layout)
-// p32 (optional): a float32 copy of the map part of p in the pixel-padded layout
-// (rows of stride vs32), read instead of p
+// p32 (optional): a float32 copy of the map part of p (rows of stride vs32), read
+// instead of p
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
                          hipStream_t s, const CgState* st = nullptr, const float* p32 = nullptr,
                          int64_t vs32 = 0);
-// Pixel-padded float32 maps: pixel o's ns values start at o * f32_pixel_stride(ns), so
-// that a polarised pixel (I, Q, U, unused) is one aligned 16-byte load.
-constexpr int f32_pixel_stride(int ns) { return ns == 3 ? 4 : 1; }
-// dst[r][padded(i)] = (float)src[r * src_stride + i], i < n (n a multiple of ns)
+// dst[r * dst_stride + i] = (float)src[r * src_stride + i], i < n
 hipError_t launch_rows_to_f32(const double* src, int64_t src_stride, float* dst, int64_t dst_stride, int64_t n,
-                              int n_rhs, hipStream_t s, int ns = 1);
+                              int n_rhs, hipStream_t s);
 // Sliced pixel-major pointing (64 pixels per slice, one lane per pixel)
 struct SellLayout {
   const uint32_t* end = nullptr;   // [n_slices] inclusive prefix sum of the slice sizes
@@ -188,11 +185,11 @@ hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const
 hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
                               int n_rhs, double* history, int hist_stride, hipStream_t s);
 // p = z + beta p (active RHS) and x_best = x (RHS whose iterate became the best);
-// p32 (optional): also a float32 copy of the first n32 entries of each row of p, in
-// the pixel-padded layout for ns values per pixel (rows of stride vs32)
+// p32 (optional): also a float32 copy of the first n32 entries of each row of p
+// (rows of stride vs32)
 hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
                           const CgState* st, int64_t nu, int n_rhs, hipStream_t s,
-                          float* p32 = nullptr, int64_t n32 = 0, int ns = 1, int64_t vs32 = 0);
+                          float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
 hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
                                 int64_t n_obs, int64_t vs, const double* minv_t, int64_t n_tail,
                                 int n_rhs, hipStream_t s);
