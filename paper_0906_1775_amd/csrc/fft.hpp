@@ -18,12 +18,13 @@
 // Thread t owns butterflies b = t + i NT.  After the last pass the output of
 // (b, r) is point b + r N/R_last, i.e. the natural order, strided.
 //
-// Paired layout (PAIRED, for shapes with two butterflies per thread in the
-// last forward pass): there thread t owns butterflies t and 2 NT - t (0 and
-// NT for t = 0) instead of t and t + NT.  Butterfly b and N/R - b hold the
-// points k and N - k, so after the forward transform every thread has both
-// members of its conjugate pairs (Z_k, Z_{N-k}) in registers.  The first
-// pass of the radix-reversed sequence shares that layout.
+// Paired layout (PAIRED, for shapes with an even number NB of butterflies per
+// thread in the last forward pass): there thread t > 0 owns butterflies
+// t + i NT (i even) and (NB - i + 1) NT - t (i odd), and thread 0 owns i NT,
+// instead of t + i NT.  Butterflies b and N/R - b hold the points k and N - k,
+// so after the forward transform every thread has both members of its
+// conjugate pairs (Z_k, Z_{N-k}) in registers.  The first pass of the
+// radix-reversed sequence shares that layout.
 //
 // Twiddles come from per-pass tables built once in float64 and rounded to T:
 // pass p with radix R and span Ns owns Ns rows of R entries,
@@ -149,7 +150,7 @@ struct BlockFFT {
   static constexpr int sc_bytes = (N + (N >> sc_pad_log)) * (int)sizeof(T);
   static constexpr bool SPLIT = FORCE_SPLIT || cx_bytes > kLdsLimit;
   static constexpr bool PAIRED = PAIRED_;
-  static_assert(!PAIRED || (NP >= 2 && E == 2 * (1 << LOGR_)), "paired layout needs two butterflies per thread");
+  static_assert(!PAIRED || (NP >= 2 && (E >> LOGR_) % 2 == 0), "paired layout needs an even butterfly count");
   // is pass p of a sequence in the paired layout (last forward pass, first reversed pass)
   static constexpr bool pass_paired(bool fwd, int p) { return PAIRED && (fwd ? p == NP - 1 : p == 0); }
   static constexpr int LDS_BYTES = SPLIT ? sc_bytes : cx_bytes;
@@ -161,8 +162,13 @@ struct BlockFFT {
   // butterfly handled as the i-th of thread t in a pass (PAIR: paired layout)
   template <bool PAIR>
   __device__ static __forceinline__ int bfly(int t, int i) {
-    if constexpr (PAIR) return i == 0 ? t : (t == 0 ? NT : 2 * NT - t);
-    else return t + i * NT;
+    if constexpr (PAIR) {
+      constexpr int NB = E >> LOGR_;   // butterflies per thread in the paired passes
+      if (i % 2 == 0) return t + i * NT;
+      return t == 0 ? i * NT : (NB - i + 1) * NT - t;
+    } else {
+      return t + i * NT;
+    }
   }
   // output position of element (i, r) of thread t after a pass (LOGR, LOGNS)
   template <int LOGR, int LOGNS, bool PAIR = false>

@@ -93,12 +93,14 @@ template <> struct OlsShape<14, 4> : OlsCfg<256, 6, 5, true, true, 2> {};
 template <> struct OlsShape<14, 5> : OlsCfg<1024, 4, 3, false, true> {};
 template <> struct OlsShape<14, 6> : OlsCfg<1024, 4, 3, true, true, 2> {};
 template <> struct OlsShape<15, 1> : OlsCfg<512, 6, 5, false, true> {};
+template <> struct OlsShape<15, 2> : OlsCfg<1024, 5, 3, false, true> {};
 
 bool ols_variant_exists(int logn, bool fp64, int v) {
   if (v == 0) return logn >= kMinLogN && logn <= ols_max_logn(fp64);
   if (v == 5) return logn == 14;
   if (fp64) return false;
-  return (v == 1 && (logn == 13 || logn == 14 || logn == 15)) || ((v >= 2 && v <= 6) && logn == 14);
+  return (v == 1 && (logn == 13 || logn == 14 || logn == 15)) || ((v >= 2 && v <= 6) && logn == 14) ||
+         (v == 2 && logn == 15);
 }
 
 template <typename T, int LOGN, int V = 0>
@@ -136,7 +138,7 @@ int pass_twiddle_count(int logn, bool fp64, int variant) {
   if (variant == 1)
     return logn == 13 ? pass_tw_total_t<float, 13, 1>()
                       : (logn == 14 ? pass_tw_total_t<float, 14, 1>() : pass_tw_total_t<float, 15, 1>());
-  if (variant == 2) return pass_tw_total_t<float, 14, 2>();
+  if (variant == 2) return logn == 14 ? pass_tw_total_t<float, 14, 2>() : pass_tw_total_t<float, 15, 2>();
   if (variant == 3) return pass_tw_total_t<float, 14, 3>();
   if (variant == 4) return pass_tw_total_t<float, 14, 4>();
   if (variant == 5) return fp64 ? pass_tw_total_t<double, 14, 5>() : pass_tw_total_t<float, 14, 5>();
@@ -163,7 +165,7 @@ hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, i
   if (variant == 1)
     return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s)
                       : (logn == 14 ? pass_tw_launch<float, 14, 1>(tab, s) : pass_tw_launch<float, 15, 1>(tab, s));
-  if (variant == 2) return pass_tw_launch<float, 14, 2>(tab, s);
+  if (variant == 2) return logn == 14 ? pass_tw_launch<float, 14, 2>(tab, s) : pass_tw_launch<float, 15, 2>(tab, s);
   if (variant == 3) return pass_tw_launch<float, 14, 3>(tab, s);
   if (variant == 4) return pass_tw_launch<float, 14, 4>(tab, s);
   if (variant == 5) return fp64 ? pass_tw_launch<double, 14, 5>(tab, s) : pass_tw_launch<float, 14, 5>(tab, s);
@@ -375,19 +377,21 @@ __device__ __forceinline__ void with_partner(cx<T>* v, void* lds, int t, Fn fn) 
 
 // Paired shapes: after the forward transform the thread already holds Z_{N-k}
 // beside each of its Z_k (fft.hpp, paired layout).  fn(k, Z_k, Z_{N-k}, out_k,
-// out_{N-k}) replaces both members of a pair.  Thread 0 owns butterflies 0 and
-// NT, which pair with themselves; k = 0 and k = N/2 are their own partners
-// (then only out_k is kept).
+// out_{N-k}) replaces both members of a pair.  With NB butterflies per thread,
+// element (i, r) of thread t > 0 pairs with (i ^ 1, R - 1 - r); thread 0 owns the
+// butterflies i NT: (0, r) pairs with (0, R - r) (k = 0 and k = N/2 are their
+// own partners, and then only out_k is kept) and (i, r) with (NB - i, R - 1 - r).
 template <typename F, typename T, typename Fn>
 __device__ __forceinline__ void with_partner_paired(cx<T>* v, int t, Fn fn) {
-  constexpr int N = F::N, R = 1 << F::last_log_fwd();
-  static_assert(F::PAIRED && F::E == 2 * R, "paired layout expected");
+  constexpr int N = F::N, R = 1 << F::last_log_fwd(), NB = F::E / R;
+  static_assert(F::PAIRED && NB % 2 == 0, "paired layout expected");
   if (t != 0) {
-    // (0, r) holds k = t + r N/R; (1, R - 1 - r) holds N - k
 #pragma unroll
-    for (int r = 0; r < R; ++r) fn(F::fwd_out_index(t, 0, r), v[r], v[2 * R - 1 - r]);
+    for (int q = 0; q < NB / 2; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        fn(F::fwd_out_index(t, 2 * q, r), v[2 * q * R + r], v[(2 * q + 1) * R + R - 1 - r]);
   } else {
-    // butterfly 0: (0, r) <-> (0, R - r); butterfly NT: (1, r) <-> (1, R - 1 - r)
 #pragma unroll
     for (int r = 0; r <= R / 2; ++r) {
       if (r == 0 || r == R / 2) {
@@ -398,7 +402,12 @@ __device__ __forceinline__ void with_partner_paired(cx<T>* v, int t, Fn fn) {
       }
     }
 #pragma unroll
-    for (int r = 0; r < R / 2; ++r) fn(F::fwd_out_index(0, 1, r), v[R + r], v[2 * R - 1 - r]);
+    for (int i = 1; i < NB / 2; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) fn(F::fwd_out_index(0, i, r), v[i * R + r], v[(NB - i) * R + R - 1 - r]);
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r)
+      fn(F::fwd_out_index(0, NB / 2, r), v[(NB / 2) * R + r], v[(NB / 2) * R + R - 1 - r]);
   }
 }
 
@@ -667,7 +676,7 @@ static hipError_t ols_dispatch(int logn, int variant, const void* y_in, void* y_
     if (variant == 1)
       return logn == 13 ? ols_launch<T, Tin, 13, 1>(MM_OLS_ARGS)
                         : (logn == 14 ? ols_launch<T, Tin, 14, 1>(MM_OLS_ARGS) : ols_launch<T, Tin, 15, 1>(MM_OLS_ARGS));
-    if (variant == 2) return ols_launch<T, Tin, 14, 2>(MM_OLS_ARGS);
+    if (variant == 2) return logn == 14 ? ols_launch<T, Tin, 14, 2>(MM_OLS_ARGS) : ols_launch<T, Tin, 15, 2>(MM_OLS_ARGS);
     if (variant == 3) return ols_launch<T, Tin, 14, 3>(MM_OLS_ARGS);
     if (variant == 4) return ols_launch<T, Tin, 14, 4>(MM_OLS_ARGS);
     if (variant == 6) return ols_launch<T, Tin, 14, 6>(MM_OLS_ARGS);

@@ -189,7 +189,7 @@ def test_autotuned_transform_length(precision):
     assert max_rel(hx, want) <= TOL[precision]
 
 
-@pytest.mark.parametrize("n_f,shape", [(32768, s) for s in range(1, 8)] + [(65536, 1), (65536, 2)])
+@pytest.mark.parametrize("n_f,shape", [(32768, s) for s in range(1, 8)] + [(65536, 1), (65536, 2), (65536, 3)])
 def test_forced_transform_shapes_match_the_oracle(n_f, shape):
     """Each workgroup shape of the float32 transforms of 2^14 and 2^15 complex points
     gives the oracle's H x; float64 plans use the shapes that exist in float64 (1 and 6)
