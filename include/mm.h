@@ -148,10 +148,12 @@ typedef struct {
                                    threads x 64 points, radix-32, split exchanges, two
                                    workgroups per CU; 6 = 1024 threads x 16 points, radix-8
                                    passes, pairs in registers; 7 = shape 6 with split exchanges,
-                                   two workgroups per CU.  Shape 2 exists for float32 transforms
-                                   of 2^13 .. 2^15 points, shapes 3 .. 7 for 2^14 points (6 also
-                                   in float64); elsewhere shape 1 is used.  Ignored with n_f = -1
-                                   (the autotuner tries every shape). */
+                                   two workgroups per CU.  For 2^15 points shape 3 is 1024
+                                   threads x 32 points, radix-8 passes, pairs in registers.
+                                   Shape 2 exists for float32 transforms of 2^13 .. 2^15 points,
+                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 7 for 2^14
+                                   points (6 also in float64); elsewhere shape 1 is used.  Ignored
+                                   with n_f = -1 (the autotuner tries every shape). */
 } mm_desc_t;
 
 typedef struct {
