@@ -144,7 +144,7 @@ void cache_put(int dev, size_t b, void* p) {
       return;
     }
   }
-  hipFree(p);
+  (void)hipFree(p);   // teardown: nothing to report to
 }
 
 void cache_flush(int dev) {
@@ -156,7 +156,7 @@ void cache_flush(int dev) {
     v.swap(c.blocks[dev]);
     c.held[dev] = 0;
   }
-  for (auto& e : v) hipFree(e.second);
+  for (auto& e : v) (void)hipFree(e.second);
 }
 
 hipStream_t stream_take(int dev) {
@@ -183,7 +183,7 @@ void stream_put(int dev, hipStream_t st) {
       return;
     }
   }
-  hipStreamDestroy(st);
+  (void)hipStreamDestroy(st);
 }
 
 // Pixel-major layout of one pointing matrix with one non-zero per row: the sky
@@ -311,7 +311,7 @@ struct mm_plan_s {
       hipError_t e = hipMalloc(&p, b);
       if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
         (void)hipGetLastError();
-        for (auto& s : spare) hipFree(s.second);
+        for (auto& s : spare) (void)hipFree(s.second);
         spare.clear();
         cache_flush(device);
         e = hipMalloc(&p, b);
@@ -333,15 +333,15 @@ struct mm_plan_s {
       }
   }
   ~mm_plan_s() {
-    if (graph) hipGraphExecDestroy(graph);
+    if (graph) (void)hipGraphExecDestroy(graph);   // destructor: statuses are discarded
     // work the caller queued on its own streams may still read the blocks: drain
     // the device once before they become available to other plans
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     for (auto& a : allocs) cache_put(device, a.first, a.second);
     for (auto& a : spare) cache_put(device, a.first, a.second);
-    if (st_host) hipHostFree(st_host);
-    if (ev_in) hipEventDestroy(ev_in);
-    if (ev_out) hipEventDestroy(ev_out);
+    if (st_host) (void)hipHostFree(st_host);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
     if (own) stream_put(device, own);
   }
 
@@ -415,8 +415,8 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
   }
   P->release(ya);
   P->release(yb);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  hipchk(hipEventDestroy(e0), "event");
+  hipchk(hipEventDestroy(e1), "event");
 }
 
 // transform shape used when the descriptor leaves it open: the fastest measured
@@ -1008,7 +1008,7 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
   if (use_graph && step == k && k > 0) {
     if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
       if (P->graph) {
-        hipGraphExecDestroy(P->graph);
+        hipchk(hipGraphExecDestroy(P->graph), "graph destroy");
         P->graph = nullptr;
       }
       hipGraph_t g = nullptr;
@@ -1016,13 +1016,13 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
       try {
         for (int i = 0; i < k; ++i) enqueue_iteration(P, s);
       } catch (...) {
-        hipStreamEndCapture(s, &g);
-        if (g) hipGraphDestroy(g);
+        (void)hipStreamEndCapture(s, &g);   // unwinding: the first error is the one reported
+        if (g) (void)hipGraphDestroy(g);
         throw;
       }
       hipchk(hipStreamEndCapture(s, &g), "end capture");
       hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
-      hipGraphDestroy(g);
+      hipchk(hipGraphDestroy(g), "graph destroy");
       P->graph_k = k;
       P->graph_hist = P->hist;
     }
