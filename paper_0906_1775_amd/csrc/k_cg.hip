@@ -117,76 +117,105 @@ __device__ __forceinline__ void precond_apply(const double* __restrict__ m, cons
 
 // Each block folds the p.q partial sums of the scatter in the same fixed
 // order, so every block derives the same alpha; block 0 records it.
-template <int NS>
+// One block walks a fixed set of pixels for a group of RG right-hand sides, so a
+// pixel's preconditioner block is read once per group instead of once per RHS;
+// every RHS's partial sums keep the order of a one-RHS pass (tail entries, then
+// pixels, in grid-stride order).
+template <int NS, int RG>
 __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     double* __restrict__ x, const double* __restrict__ p, double* __restrict__ rv,
     const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ minv,
     CgState* __restrict__ st, int64_t n_obs, int64_t vs, const double* __restrict__ minv_t, int64_t n_tail,
-    const double* __restrict__ pq_part, int n_pq, double* __restrict__ prz, double* __restrict__ prr) {
+    int n_rhs, const double* __restrict__ pq_part, int n_pq, double* __restrict__ prz,
+    double* __restrict__ prr) {
   __shared__ double sh[kDotThreads / 64];
-  __shared__ double s_alpha;
+  __shared__ double s_alpha[RG];
   constexpr int NM = NS == 1 ? 1 : 6;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RG;
   const int tid = threadIdx.x;
-  double acc = 0.0;
-  for (int i = tid; i < n_pq; i += kDotThreads) acc += pq_part[(int64_t)r * n_pq + i];
-  const double pq = block_sum(acc, sh);
-  const bool was_active = st[r].active != 0;
-  if (tid == 0) {
-    double alpha = 0.0;
-    bool brk = false;
-    if (was_active) {
-      if (pq > 0.0 && isfinite(pq)) alpha = st[r].rho / pq;
-      else brk = true;
+  bool act[RG];
+  double alpha[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int r = r0 + g;
+    if (r >= n_rhs) {               // uniform over the block
+      act[g] = false;
+      alpha[g] = 0.0;
+      continue;
     }
-    s_alpha = alpha;
-    if (blockIdx.x == 0) {
-      st[r].alpha = alpha;            // read by no other block of this kernel
-      st[r].breakdown = brk ? 1 : 0;
+    double acc = 0.0;
+    for (int i = tid; i < n_pq; i += kDotThreads) acc += pq_part[(int64_t)r * n_pq + i];
+    const double pq = block_sum(acc, sh);
+    const bool was_active = st[r].active != 0;
+    if (tid == 0) {
+      double al = 0.0;
+      bool brk = false;
+      if (was_active) {
+        if (pq > 0.0 && isfinite(pq)) al = st[r].rho / pq;
+        else brk = true;
+      }
+      s_alpha[g] = al;
+      if (blockIdx.x == 0) {
+        st[r].alpha = al;            // read by no other block of this kernel
+        st[r].breakdown = brk ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    alpha[g] = s_alpha[g];
+    act[g] = was_active && alpha[g] != 0.0;
+  }
+  double arz[RG], arr[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) arz[g] = arr[g] = 0.0;
+  // template amplitudes (diagonal preconditioner)
+  for (int64_t j = (int64_t)blockIdx.x * kDotThreads + tid; j < n_tail; j += (int64_t)kDotBlocks * kDotThreads) {
+    const double mt = minv_t[j];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      if (!act[g]) continue;
+      const int64_t b = (int64_t)(r0 + g) * vs + n_obs * NS + j;
+      x[b] += alpha[g] * p[b];
+      const double rr = rv[b] - alpha[g] * q[b];
+      rv[b] = rr;
+      const double zz = mt * rr;
+      z[b] = zz;
+      arz[g] += rr * zz;
+      arr[g] += rr * rr;
     }
   }
-  __syncthreads();
-  const double alpha = s_alpha;
-  const bool active = was_active && alpha != 0.0;
-  const int64_t off = (int64_t)r * vs;
-  double arz = 0.0, arr = 0.0;
-  if (active) {
-    // template amplitudes (diagonal preconditioner)
-    for (int64_t j = (int64_t)blockIdx.x * kDotThreads + tid; j < n_tail;
-         j += (int64_t)kDotBlocks * kDotThreads) {
-      const int64_t b = off + n_obs * NS + j;
-      x[b] += alpha * p[b];
-      const double rr = rv[b] - alpha * q[b];
-      rv[b] = rr;
-      const double zz = minv_t[j] * rr;
-      z[b] = zz;
-      arz += rr * zz;
-      arr += rr * rr;
-    }
-    for (int64_t o = (int64_t)blockIdx.x * kDotThreads + tid; o < n_obs;
-         o += (int64_t)kDotBlocks * kDotThreads) {
-      const int64_t b = off + o * NS;
+  for (int64_t o = (int64_t)blockIdx.x * kDotThreads + tid; o < n_obs; o += (int64_t)kDotBlocks * kDotThreads) {
+    double m[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) m[k] = minv[o * NM + k];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      if (!act[g]) continue;
+      const int64_t b = (int64_t)(r0 + g) * vs + o * NS;
       double rr[NS], zz[NS];
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
-        x[b + c] += alpha * p[b + c];
-        rr[c] = rv[b + c] - alpha * q[b + c];
+        x[b + c] += alpha[g] * p[b + c];
+        rr[c] = rv[b + c] - alpha[g] * q[b + c];
         rv[b + c] = rr[c];
       }
-      precond_apply<NS>(minv + o * NM, rr, zz);
+      precond_apply<NS>(m, rr, zz);
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
         z[b + c] = zz[c];
-        arz += rr[c] * zz[c];
-        arr += rr[c] * rr[c];
+        arz[g] += rr[c] * zz[c];
+        arr[g] += rr[c] * rr[c];
       }
     }
   }
-  const double s1 = block_sum(arz, sh);
-  const double s2 = block_sum(arr, sh);
-  if (tid == 0) {
-    prz[(int64_t)r * kDotBlocks + blockIdx.x] = s1;
-    prr[(int64_t)r * kDotBlocks + blockIdx.x] = s2;
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    if (r0 + g >= n_rhs) break;     // uniform over the block
+    const double s1 = block_sum(arz[g], sh);
+    const double s2 = block_sum(arr[g], sh);
+    if (tid == 0) {
+      prz[(int64_t)(r0 + g) * kDotBlocks + blockIdx.x] = s1;
+      prr[(int64_t)(r0 + g) * kDotBlocks + blockIdx.x] = s2;
+    }
   }
 }
 
@@ -195,13 +224,16 @@ hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s) {
-  const dim3 g(kDotBlocks, n_rhs), b(kDotThreads);
-  if (ns == 1)
-    hipLaunchKernelGGL(k_cg_update<1>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, vs, minv_t, n_tail,
-                       pq_part, n_pq, partial_rz, partial_rr);
-  else
-    hipLaunchKernelGGL(k_cg_update<3>, g, b, 0, s, x, p, r, q, z, minv, st, n_obs, vs, minv_t, n_tail,
-                       pq_part, n_pq, partial_rz, partial_rr);
+  const dim3 b(kDotThreads);
+#define MM_UPD(NS, RG)                                                                                     \
+  hipLaunchKernelGGL((k_cg_update<NS, RG>), dim3(kDotBlocks, (n_rhs + RG - 1) / RG), b, 0, s, x, p, r, q, z, \
+                     minv, st, n_obs, vs, minv_t, n_tail, n_rhs, pq_part, n_pq, partial_rz, partial_rr)
+  if (n_rhs == 1) {
+    if (ns == 1) MM_UPD(1, 1); else MM_UPD(3, 1);
+  } else {
+    if (ns == 1) MM_UPD(1, 8); else MM_UPD(3, 8);
+  }
+#undef MM_UPD
   return hipGetLastError();
 }
 
