@@ -190,8 +190,21 @@ typedef struct {
 mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w,
                            void* stream, mm_plan_t* out_plan);
 /* Destroy a plan (waits for the device to be idle).  Its device memory is kept by the
- * library for later plans of the process, up to 16 GiB per device; the rest is freed. */
+ * library for later plans of the process, up to the device's cache limit (16 GiB unless
+ * changed with mm_set_cache_limit); the rest is freed. */
 mm_status_t mm_plan_destroy(mm_plan_t plan);
+
+/* Device memory kept for later plans (plan-memory cache).  Freed device memory is
+ * cleared by the driver before it is handed out again, at a few tens of GB/s, so a
+ * process that re-plans problems of hundreds of GB spends seconds per plan unless
+ * the blocks are reused; the cache keeps them.  Sets the limit of HIP device
+ * `device` (0 .. device count - 1) to `bytes` (>= 0) and frees cached blocks above
+ * it at once (bytes = 0 empties the cache); the previous limit goes to *previous
+ * (may be NULL).  Blocks held by live plans are not affected.  Cached blocks are
+ * not available to other allocators of the process (a failed plan allocation
+ * empties the cache and retries).  Errors: MM_EINVAL (device out of range,
+ * bytes < 0), MM_EDEVICE. */
+mm_status_t mm_set_cache_limit(int32_t device, int64_t bytes, int64_t* previous);
 mm_status_t mm_plan_get_info(mm_plan_t plan, mm_plan_info_t* info);
 
 /* Hit count of every global pixel: device int32 [n_pix] (exact integers). */

@@ -20,7 +20,7 @@ MM_TMPL_ONEHOT, MM_TMPL_HWP = 1, 2
 EXPORTED = ["mm_plan_create", "mm_plan_destroy", "mm_plan_get_info", "mm_hits", "mm_filter_lags",
             "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A", "mm_rhs", "mm_solve_opts_default",
             "mm_solve", "mm_solve_rhs", "mm_noise_gradient", "mm_fft_length_rule", "mm_last_error",
-            "mm_version"]
+            "mm_version", "mm_set_cache_limit"]
 
 
 class MMTemplate(ctypes.Structure):
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     P = c_void_p
     lib.mm_plan_create.argtypes = [POINTER(MMDesc), P, P, P, POINTER(c_void_p)]
     lib.mm_plan_destroy.argtypes = [P]
+    lib.mm_set_cache_limit.argtypes = [c_int32, c_int64, POINTER(c_int64)]
     lib.mm_plan_get_info.argtypes = [P, POINTER(MMPlanInfo)]
     lib.mm_hits.argtypes = [P, P, P]
     lib.mm_filter_lags.argtypes = [P, P, P]

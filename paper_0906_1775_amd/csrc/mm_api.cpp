@@ -100,15 +100,22 @@ struct FilterSetup {
 // Device memory and streams of destroyed plans, kept per device for later
 // plans of the process: hipFree synchronises the whole device and hipMalloc of
 // large blocks maps pages, which together cost more than the plan's kernels.
-// At most kCacheCap bytes stay cached per device; a failed hipMalloc empties
-// the cache and retries once.
+// Freed VRAM is also cleared by the driver before it is handed out again, at a
+// few tens of GB/s, so re-planning a problem of hundreds of GB pays seconds unless
+// the blocks are reused.  At most cap[dev] bytes (default kCacheCap, changed with
+// mm_set_cache_limit) stay cached per device; a failed hipMalloc empties the
+// cache and retries once.
 constexpr size_t kCacheCap = size_t(16) << 30;
 
 struct DeviceCache {
   std::mutex mu;
   std::vector<std::pair<size_t, void*>> blocks[64];
   size_t held[64] = {};
+  size_t cap[64];
   std::vector<hipStream_t> streams[64];
+  DeviceCache() {
+    for (size_t& c : cap) c = kCacheCap;
+  }
 };
 
 DeviceCache& cache() {
@@ -138,7 +145,7 @@ void cache_put(int dev, size_t b, void* p) {
   DeviceCache& c = cache();
   {
     std::lock_guard<std::mutex> lk(c.mu);
-    if (dev >= 0 && dev < 64 && c.held[dev] + b <= kCacheCap) {
+    if (dev >= 0 && dev < 64 && c.held[dev] + b <= c.cap[dev]) {
       c.blocks[dev].push_back({b, p});
       c.held[dev] += b;
       return;
@@ -157,6 +164,27 @@ void cache_flush(int dev) {
     c.held[dev] = 0;
   }
   for (auto& e : v) (void)hipFree(e.second);
+}
+
+// set the cap of device dev; blocks above the new cap are freed (largest first)
+size_t cache_set_cap(int dev, size_t cap) {
+  std::vector<void*> drop;
+  size_t prev;
+  {
+    DeviceCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    prev = c.cap[dev];
+    c.cap[dev] = cap;
+    auto& v = c.blocks[dev];
+    std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    while (c.held[dev] > cap && !v.empty()) {
+      c.held[dev] -= v.back().first;
+      drop.push_back(v.back().second);
+      v.pop_back();
+    }
+  }
+  for (void* p : drop) hipchk(hipFree(p), "hipFree");
+  return prev;
 }
 
 hipStream_t stream_take(int dev) {
@@ -1439,6 +1467,17 @@ mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const fl
 
 mm_status_t mm_plan_destroy(mm_plan_t plan) {
   return guarded([&] { delete plan; });
+}
+
+mm_status_t mm_set_cache_limit(int32_t device, int64_t bytes, int64_t* previous) {
+  return guarded([&] {
+    int n = 0;
+    hipchk(hipGetDeviceCount(&n), "device count");
+    if (device < 0 || device >= n || device >= 64) fail(MM_EINVAL, "device out of range");
+    if (bytes < 0) fail(MM_EINVAL, "bytes must be >= 0");
+    const size_t prev = cache_set_cap(device, (size_t)bytes);
+    if (previous) *previous = (int64_t)prev;
+  });
 }
 
 mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {

@@ -42,6 +42,15 @@ def fft_length_rule(n_c: int, longest: int) -> int:
     return int(L.load().mm_fft_length_rule(int(n_c), int(longest)))
 
 
+def set_cache_limit(nbytes: int, device: int = 0) -> int:
+    """Limit of the device memory destroyed plans leave to later plans of the process
+    (mm_set_cache_limit); 0 empties the cache.  Returns the previous limit."""
+    lib = L.load()
+    prev = ctypes.c_int64(0)
+    L.check(lib.mm_set_cache_limit(int(device), int(nbytes), ctypes.byref(prev)), lib)
+    return int(prev.value)
+
+
 class MapMaker:
     """A plan of the map-making operators for one pointing and noise model."""
 
