@@ -13,6 +13,7 @@
 // wavefront holding the same digit find each other with eight ballots; the
 // per-wave counts in LDS order the four waves; rounds run in key order, so
 // the sort is stable and every output position is computed, not raced for.
+// Each tile is ordered by digit in LDS before it is written out.
 #include "mm_internal.h"
 
 namespace mm {
@@ -158,26 +159,41 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   counts[(int64_t)tid * n_tiles + blockIdx.x] = h[tid];
 }
 
+// Stable scatter of one tile by digit.  Ranks are formed round by round as keys
+// come (lanes of a wavefront with the same digit find each other with eight
+// ballots; per-wave counts order the four waves; a running count per digit
+// carries over rounds), then the tile is placed in LDS in (digit, rank) order
+// and written out in that order, so each digit's keys leave as one contiguous
+// run at offsets[digit][tile] instead of one scattered word per key.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n, int shift,
     int64_t n_tiles, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
     int32_t* __restrict__ vals_out) {
-  __shared__ uint32_t base[256];
+  __shared__ uint32_t s_key[kSortTile];
+  __shared__ int32_t s_val[kSortTile];
+  __shared__ uint32_t gbase[256];                   // output offset of this tile's digit d
+  __shared__ uint32_t lcnt[256];                    // keys of digit d seen so far in the tile
+  __shared__ uint32_t lstart[256];                  // first LDS slot of digit d
   __shared__ uint32_t wcnt[kSortThreads / 64][256];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  base[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+  gbase[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+  lcnt[tid] = 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int n_here = (int)((n - tile0) < kSortTile ? (n - tile0) : kSortTile);
+  uint32_t key[kSortRounds], rk[kSortRounds];
+  int32_t val[kSortRounds];
+#pragma unroll
   for (int i = 0; i < kSortRounds; ++i) {
 #pragma unroll
     for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    const int64_t idx = tile0 + (int64_t)i * kSortThreads + tid;
-    const bool valid = idx < n;
-    const uint32_t key = valid ? keys_in[idx] : 0u;
-    const int32_t val = valid ? vals_in[idx] : 0;
-    const uint32_t d = (key >> shift) & 255u;
+    const int j = i * kSortThreads + tid;
+    const bool valid = j < n_here;
+    key[i] = valid ? keys_in[tile0 + j] : 0u;
+    val[i] = valid ? vals_in[tile0 + j] : 0;
+    const uint32_t d = (key[i] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -188,18 +204,52 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
     if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      keys_out[pos] = key;
-      vals_out[pos] = val;
-    }
+    uint32_t r = lcnt[d] + rank;
+    for (int w = 0; w < wave; ++w) r += wcnt[w][d];
+    rk[i] = r;
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][tid];
-    base[tid] += add;
+    lcnt[tid] += add;
+  }
+  __syncthreads();
+  // exclusive scan of the tile's digit counts (256 entries, one per thread)
+  {
+    uint32_t v = lcnt[tid];
+    lstart[tid] = v;
     __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t x = tid >= off ? lstart[tid - off] : 0u;
+      __syncthreads();
+      lstart[tid] += x;
+      __syncthreads();
+    }
+    const uint32_t incl = lstart[tid];
+    __syncthreads();
+    lstart[tid] = incl - v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortRounds; ++i) {
+    const int j = i * kSortThreads + tid;
+    if (j < n_here) {
+      const uint32_t pos = lstart[(key[i] >> shift) & 255u] + rk[i];
+      s_key[pos] = key[i];
+      s_val[pos] = val[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortRounds; ++i) {
+    const int j = i * kSortThreads + tid;
+    if (j < n_here) {
+      const uint32_t k = s_key[j];
+      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
+      keys_out[pos] = k;
+      vals_out[pos] = s_val[j];
+    }
   }
 }
 
@@ -288,8 +338,8 @@ hipError_t launch_segment_flags(const uint32_t* keys, int64_t n, uint32_t n_pix,
 __global__ void k_build_layout(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals,
                                const uint32_t* __restrict__ seg_id, int64_t n, uint32_t n_pix,
                                const float2* __restrict__ w, int ns, int64_t* __restrict__ pix_ptr,
-                               int32_t* __restrict__ obs2glob, int32_t* __restrict__ pix_obs,
-                               float2* __restrict__ w_pm, int32_t* __restrict__ perm) {
+                               int32_t* __restrict__ obs2glob, float2* __restrict__ w_pm,
+                               int32_t* __restrict__ perm) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint32_t k = keys[i];
@@ -300,22 +350,48 @@ __global__ void k_build_layout(const uint32_t* __restrict__ keys, const int32_t*
         pix_ptr[o] = i;
         obs2glob[o] = (int32_t)k;
       }
-      pix_obs[v] = o;
       perm[i] = v;
       if (ns == 3) w_pm[i] = w[v];
-    } else {
-      pix_obs[v] = -1;
     }
   }
 }
 
+// glob2obs[obs2glob[o]] = o (the entries of unobserved pixels are set to -1 beforehand)
+__global__ void k_invert_obs(const int32_t* __restrict__ obs2glob, int64_t n_obs, int32_t* __restrict__ glob2obs) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n_obs; o += stride)
+    glob2obs[obs2glob[o]] = (int32_t)o;
+}
+
+// time-major observed index: pix_obs[t] = glob2obs[key[t]], -1 for excised samples
+__global__ void k_obs_index(const int32_t* __restrict__ key, int64_t n, const int32_t* __restrict__ glob2obs,
+                            int32_t* __restrict__ pix_obs) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int32_t k = key[t];
+    pix_obs[t] = k >= 0 ? glob2obs[k] : -1;
+  }
+}
+
+hipError_t launch_obs_index(const int32_t* key, int64_t n, const int32_t* obs2glob, int64_t n_obs,
+                            int32_t* glob2obs, int64_t n_keys, int32_t* pix_obs, hipStream_t s) {
+  hipError_t e = launch_fill_i32(glob2obs, -1, n_keys, s);
+  if (e != hipSuccess) return e;
+  if (n_obs > 0) {
+    hipLaunchKernelGGL(k_invert_obs, grid_for(n_obs), dim3(256), 0, s, obs2glob, n_obs, glob2obs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_obs_index, grid_for(n), dim3(256), 0, s, key, n, glob2obs, pix_obs);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_layout(const uint32_t* keys, const int32_t* vals, const uint32_t* seg_id,
                                int64_t n, uint32_t n_pix, const float* w, int ns, int64_t* pix_ptr,
-                               int32_t* obs2glob, int32_t* pix_obs, float* w_pm, int32_t* perm,
-                               hipStream_t s) {
+                               int32_t* obs2glob, float* w_pm, int32_t* perm, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_layout, grid_for(n), dim3(256), 0, s, keys, vals, seg_id, n, n_pix,
-                     (const float2*)w, ns, pix_ptr, obs2glob, pix_obs, (float2*)w_pm, perm);
+                     (const float2*)w, ns, pix_ptr, obs2glob, (float2*)w_pm, perm);
   return hipGetLastError();
 }
 

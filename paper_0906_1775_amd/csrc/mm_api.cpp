@@ -677,9 +677,11 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
     L.obs2glob = P->alloc<int32_t>(L.n_obs);
     L.perm = P->alloc<int32_t>(L.n_valid);
     if (ns == 3) L.w_pm = P->alloc<float>(2 * L.n_valid);
-    hipchk(launch_build_layout(keys, vals, seg, n, (uint32_t)n_keys, d_w, ns, L.ptr, L.obs2glob, L.obs_idx,
-                               L.w_pm, L.perm, s),
+    hipchk(launch_build_layout(keys, vals, seg, n, (uint32_t)n_keys, d_w, ns, L.ptr, L.obs2glob, L.w_pm, L.perm, s),
            "pointing layout");
+    int32_t* glob2obs = P->alloc<int32_t>(n_keys);
+    hipchk(launch_obs_index(d_key, n, L.obs2glob, L.n_obs, glob2obs, n_keys, L.obs_idx, s), "observed index");
+    P->release(glob2obs);
     hipchk(hipMemcpyAsync(L.ptr + L.n_obs, &L.n_valid, 8, hipMemcpyHostToDevice, s), "copy");
     // released blocks are only reused by later work on this stream: no wait needed
     P->release(keys);

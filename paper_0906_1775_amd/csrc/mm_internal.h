@@ -151,11 +151,14 @@ hipError_t launch_segment_flags(const uint32_t* keys, int64_t n, uint32_t n_pix,
 // out[0] = number of sorted keys below n_pix (out[0] must be 0 beforehand)
 hipError_t launch_find_nvalid(const uint32_t* keys, int64_t n, uint32_t n_pix, int64_t* out,
                               hipStream_t s);
-// pix_ptr, obs2glob, pix_obs, w_pm, perm from the sorted order
+// pix_ptr, obs2glob, w_pm, perm from the sorted order
 hipError_t launch_build_layout(const uint32_t* keys, const int32_t* vals, const uint32_t* seg_id,
                                int64_t n, uint32_t n_pix, const float* w, int ns, int64_t* pix_ptr,
-                               int32_t* obs2glob, int32_t* pix_obs, float* w_pm, int32_t* perm,
-                               hipStream_t s);
+                               int32_t* obs2glob, float* w_pm, int32_t* perm, hipStream_t s);
+// time-major observed index pix_obs[t] (-1 for excised samples) through the inverse map
+// glob2obs [n_keys] (scratch) of obs2glob; the keys must be in [-1, n_keys)
+hipError_t launch_obs_index(const int32_t* key, int64_t n, const int32_t* obs2glob, int64_t n_obs,
+                            int32_t* glob2obs, int64_t n_keys, int32_t* pix_obs, hipStream_t s);
 
 // out[b] = sum over interval b of u_t v_t (one workgroup per interval, fixed order)
 hipError_t launch_interval_dots(const double* u, const double* v, const int64_t* iv_start, int n_iv,
