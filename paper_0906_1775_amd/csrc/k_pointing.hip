@@ -268,23 +268,55 @@ __global__ void k_sell_widths(const int64_t* __restrict__ pix_ptr, int64_t n_obs
   slice_len[s] = (uint32_t)min(w * 64, (int64_t)0xFFFFFFFF);   // saturates; the host rejects it
 }
 
-__global__ void k_sell_fill(const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm,
-                            const float2* __restrict__ w_pm, int64_t n_obs,
-                            const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
-                            int32_t* __restrict__ sell_t, float2* __restrict__ sell_w, int ns) {
+// Fill of the sliced layout, a transpose of each slice's pixel-major runs: one
+// workgroup per slice, whose wavefronts take interleaved tiles of kFillRows rows
+// and stage each tile in LDS.  Reads take 16
+// consecutive entries of 4 pixels per instruction (16 lanes per pixel); writes
+// take a whole row (64 pixels) per instruction.  Rows are padded to kFillRows + 1
+// entries so that both LDS access patterns are free of bank conflicts.
+constexpr int kFillRows = 16;
+constexpr int kFillWaves = 4;
+
+__global__ __launch_bounds__(64 * kFillWaves) void k_sell_fill(
+    const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm, const float2* __restrict__ w_pm,
+    int64_t n_obs, const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
+    int32_t* __restrict__ sell_t, float2* __restrict__ sell_w, int ns) {
+  __shared__ int32_t s_t[kFillWaves][64][kFillRows + 1];
+  __shared__ float2 s_w[kFillWaves][64][kFillRows + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sub = lane / kFillRows, jj = lane % kFillRows;   // stage 1: pixel sub-index and row
   const int64_t n_sl = (n_obs + 63) / 64;
-  const int lane = threadIdx.x & 63;
-  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / 64);
-  for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; s < n_sl; s += wstride) {
+  for (int64_t s = blockIdx.x; s < n_sl; s += gridDim.x) {
     const int64_t base = (int64_t)slice_end[s] - slice_len[s];
-    const int64_t width = slice_len[s] / 64;
+    const int width = (int)(slice_len[s] / 64);
     const int64_t o = s * 64 + lane;
-    const int64_t k0 = o < n_obs ? pix_ptr[o] : 0, k1 = o < n_obs ? pix_ptr[o + 1] : 0;
-    for (int64_t j = 0; j < width; ++j) {
-      const int64_t e = base + j * 64 + lane;
-      const bool hit = k0 + j < k1;
-      sell_t[e] = hit ? perm[k0 + j] : -1;
-      if (ns == 3) sell_w[e] = hit ? w_pm[k0 + j] : make_float2(0.f, 0.f);
+    const int64_t my_k0 = o < n_obs ? pix_ptr[o] : 0;
+    const int my_cnt = o < n_obs ? (int)(pix_ptr[o + 1] - my_k0) : 0;
+    for (int j0 = wv * kFillRows; j0 < width; j0 += kFillWaves * kFillRows) {   // uniform per wavefront
+      // stage 1: pixel L = 4 q + sub, row j0 + jj
+#pragma unroll 4
+      for (int q = 0; q < 64 / (64 / kFillRows); ++q) {
+        const int L = q * (64 / kFillRows) + sub;
+        const int64_t k0 = __shfl(my_k0, L, 64);
+        const int cnt = __shfl(my_cnt, L, 64);
+        const int j = j0 + jj;
+        if (j < cnt) {
+          s_t[wv][L][jj] = perm[k0 + j];
+          if (ns == 3) s_w[wv][L][jj] = w_pm[k0 + j];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // stage 2: row j0 + r, pixel = lane
+      const int rows = width - j0 < kFillRows ? width - j0 : kFillRows;
+      for (int r = 0; r < rows; ++r) {
+        const int64_t e = base + (int64_t)(j0 + r) * 64 + lane;
+        const bool hit = j0 + r < my_cnt;
+        sell_t[e] = hit ? s_t[wv][lane][r] : -1;
+        if (ns == 3) sell_w[e] = hit ? s_w[wv][lane][r] : make_float2(0.f, 0.f);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
   }
 }
@@ -301,10 +333,9 @@ hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const f
                             float* sell_w, int ns, hipStream_t s) {
   const int64_t n_sl = (n_obs + 63) / 64;
   if (n_sl == 0) return hipSuccess;
-  int64_t nb = (n_sl + 3) / 4;
-  if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)nb), dim3(256), 0, s, pix_ptr, perm, (const float2*)w_pm, n_obs,
-                     slice_end, slice_len, sell_t, (float2*)sell_w, ns);
+  const int64_t nb = n_sl < 65536 ? n_sl : 65536;
+  hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)nb), dim3(64 * kFillWaves), 0, s, pix_ptr, perm,
+                     (const float2*)w_pm, n_obs, slice_end, slice_len, sell_t, (float2*)sell_w, ns);
   return hipGetLastError();
 }
 
