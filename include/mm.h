@@ -239,8 +239,12 @@ typedef struct {
   double tol;                   /* stop when ||r||_2 / ||b||_2 <= tol (paper default 1e-6) */
   int32_t max_iter;             /* at most this many H applications (paper default 50) */
   int32_t fixed_iters;          /* > 0: run exactly this many iterations, ignore tol */
-  int32_t check_every;          /* iterations between host convergence checks (>= 1) */
-  int32_t use_graph;            /* capture each block of check_every iterations in a hipGraph */
+  int32_t check_every;          /* iterations between host convergence checks (>= 1); a block
+                                   is shortened when every active RHS is predicted (from its
+                                   residual rate since the last check) to reach tol sooner */
+  int32_t use_graph;            /* replay each full block of check_every iterations as a hipGraph,
+                                   captured once per plan at its second solve (a plan's first
+                                   solve launches directly: capture costs more than it saves then) */
   int32_t true_residual;        /* recompute ||b - H x_best|| / ||b|| in float64 at exit */
   const double* d_x0;           /* optional initial map [n_rhs][n_pix][n_stokes]; NULL = 0 */
   int32_t refine;               /* MM_MIXED only: 1 = reliable updates: the iterate and the CG

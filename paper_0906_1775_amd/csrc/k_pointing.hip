@@ -42,6 +42,11 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
                                                 Ty* __restrict__ y, int64_t n_t, int64_t ys, int n_rhs,
                                                 const CgState* __restrict__ st) {
   constexpr int U = kGatherUnroll;
+  if (st) {   // every RHS has stopped: nothing to read
+    bool any = false;
+    for (int r = 0; r < n_rhs; ++r) any = any || st[r].active != 0;
+    if (!any) return;
+  }
   const int64_t step = (int64_t)gridDim.x * 256 * U;
   for (int64_t t0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; t0 < n_t; t0 += step) {
     int32_t o[U];
@@ -130,6 +135,11 @@ __global__ __launch_bounds__(256) void k_gather4(const int32_t* __restrict__ pix
                                                  int64_t n_t, int n_rhs, const CgState* __restrict__ st,
                                                  bool vec_out) {
   constexpr int U = kGather4Unroll;
+  if (st) {   // every RHS has stopped: nothing to read
+    bool any = false;
+    for (int r = 0; r < n_rhs; ++r) any = any || st[r].active != 0;
+    if (!any) return;
+  }
   const int64_t n_q = n_t >> 2;
   const int64_t step = (int64_t)gridDim.x * 256 * U;
   for (int64_t q0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; q0 < n_q; q0 += step) {

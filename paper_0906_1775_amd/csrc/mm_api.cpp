@@ -257,6 +257,7 @@ struct mm_plan_s {
   int precision = MM_FP64, precond = MM_PRECOND_BLOCK, R = 1;
   int nf_req = 0;
   int shape_req = 0;            // requested transform shape (0 = default)
+  int solves = 0;               // solves completed with this plan
   int64_t lag_len = 0;
   double f_samp = 0;
   std::vector<int64_t> iv_start;
@@ -1035,9 +1036,11 @@ std::vector<double> dots(mm_plan_s* P, const double* x, const double* y, int R, 
 }
 
 // queue `step` PCG iterations; a full block of k iterations runs as one hipGraph,
-// captured once per plan (and k)
+// captured once per plan (and k) from the plan's second solve on: a plan solved
+// once gains nothing from the capture, and at the sizes where launches cost more
+// than the kernels the capture is paid back by the second solve
 void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph) {
-  if (use_graph && step == k && k > 0) {
+  if (use_graph && step == k && k > 0 && P->solves > 0) {
     if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
       if (P->graph) {
         hipchk(hipGraphExecDestroy(P->graph), "graph destroy");
@@ -1063,6 +1066,34 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
     for (int i = 0; i < step; ++i) enqueue_iteration(P, s);
   }
 }
+
+// Iterations in the next block between host checks: a full block of k, or fewer when
+// every active RHS is predicted to reach tol sooner from its residual rate since the
+// previous check (a shorter block saves the launches past convergence; the estimate is
+// padded, since a block that ends short costs another check).
+struct BlockSizer {
+  std::vector<double> rel;
+  std::vector<int> iter;
+  explicit BlockSizer(int R) : rel(R, 0.0), iter(R, -1) {}
+  int next(const CgState* st, int k, double tol) {
+    int need = 0;
+    bool any = false;
+    for (size_t r = 0; r < rel.size(); ++r) {
+      const CgState& c = st[r];
+      if (!c.active) continue;
+      any = true;
+      int est = k;
+      if (tol > 0 && iter[r] >= 0 && c.iter > iter[r] && c.rel > tol && rel[r] > c.rel && c.rel > 0) {
+        const double rate = std::log(c.rel / rel[r]) / (double)(c.iter - iter[r]);   // per iteration, < 0
+        est = (int)std::ceil(1.25 * std::log(tol / c.rel) / rate) + 1;
+      }
+      need = std::max(need, est);
+      rel[r] = c.rel;
+      iter[r] = c.iter;
+    }
+    return any ? std::max(1, std::min(k, need)) : k;
+  }
+};
 
 // PCG on H x = vb (observed layout) in the iteration precision of fs_main.
 // vb must hold the right-hand sides; x0 is read from vx when have_x0.  On
@@ -1101,8 +1132,9 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
   int done = 0;
   bool finished = all_done();
   const int k = std::min(check_every, std::max(1, n_max));
+  BlockSizer sizer(R);
   while (!finished && done < n_max) {
-    const int step = std::min(k, n_max - done);
+    const int step = std::min(fixed ? k : sizer.next(P->st_host, k, tol), n_max - done);
     iterate_block(P, s, step, k, use_graph);
     done += step;
     finished = all_done();
@@ -1286,8 +1318,9 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
         if (P->st_host[r].active) return true;
       return false;
     };
+    BlockSizer sizer(R);
     while (any_active() && done < n_max) {
-      const int step = std::min(k, n_max - done);
+      const int step = std::min(sizer.next(P->st_host, k, o.tol), n_max - done);
       iterate_block(P, s, step, k, o.use_graph != 0);
       done += step;
       hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
@@ -1583,6 +1616,7 @@ mm_status_t mm_solve(mm_plan_t P, const void* d_tod, int32_t tod_dtype, double* 
     src.tod = d_tod;
     src.tod64 = tod_dtype == MM_F64;
     solve_impl(P, src, d_x, opts, info, as_stream(stream), &result);
+    ++P->solves;
   });
   return st != MM_OK ? st : result;
 }
@@ -1595,6 +1629,7 @@ mm_status_t mm_solve_rhs(mm_plan_t P, const double* d_b, double* d_x, const mm_s
     RhsSource src;
     src.map = d_b;
     solve_impl(P, src, d_x, opts, info, as_stream(stream), &result);
+    ++P->solves;
   });
   return st != MM_OK ? st : result;
 }
