@@ -138,8 +138,9 @@ typedef struct {
   int32_t n_templates;          /* template blocks appended to P, 0 .. 16 */
   const mm_template_t* templates;  /* host [n_templates], or NULL when n_templates = 0 */
   int32_t fft_shape;            /* workgroup shape of the overlap-save transform (n_f / 2 complex
-                                   points): 0 = library default (shape 6 for 2^14 points, else
-                                   1); 1 = 16 points per thread, radix-16 passes (32 points per
+                                   points): 0 = library default (for 2^14 points shape 6 in
+                                   float32, 3 in float64; else 1); 1 = 16 points per thread,
+                                   radix-16 passes (32 points per
                                    thread for 2^15 points); 2 = radix-32 passes, 32 points per
                                    thread (64 for 2^15); 3 = 512 threads x 32 points, radix-16
                                    passes, conjugate pairs of the real-to-complex step in
@@ -148,12 +149,14 @@ typedef struct {
                                    threads x 64 points, radix-32, split exchanges, two
                                    workgroups per CU; 6 = 1024 threads x 16 points, radix-8
                                    passes, pairs in registers; 7 = shape 6 with split exchanges,
-                                   two workgroups per CU.  For 2^15 points shape 3 is 1024
+                                   two workgroups per CU; 8 = 512 threads x 32 points, radix-8
+                                   passes, pairs in registers.  For 2^15 points shape 3 is 1024
                                    threads x 32 points, radix-8 passes, pairs in registers.
                                    Shape 2 exists for float32 transforms of 2^13 .. 2^15 points,
-                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 7 for 2^14
-                                   points (6 also in float64); elsewhere shape 1 is used.  Ignored
-                                   with n_f = -1 (the autotuner tries every shape). */
+                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 8 for 2^14
+                                   points (3, 6 and 8 also in float64); elsewhere shape 1 is
+                                   used.  Ignored with n_f = -1 (the autotuner tries every
+                                   shape). */
 } mm_desc_t;
 
 typedef struct {
@@ -166,7 +169,7 @@ typedef struct {
   int64_t n_sliced;             /* entries of the sliced pixel-major pointing (>= n_valid;
                                    the excess is padding to the widest pixel of each slice) */
   int64_t n_tmpl;               /* template amplitudes per RHS in map-shaped buffers (0 = none) */
-  int32_t fft_shape;            /* transform shape the iterations use (1 .. 7, see mm_desc_t) */
+  int32_t fft_shape;            /* transform shape the iterations use (1 .. 8, see mm_desc_t) */
 } mm_plan_info_t;
 
 /*

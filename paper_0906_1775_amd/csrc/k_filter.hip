@@ -73,9 +73,11 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s) {
 // workgroups share a CU and one's global loads and stores overlap the other's
 // arithmetic.  Variant 4 is 256 threads x 64 points with radix-32 passes, split
 // and two per CU.  Variant 5 is 1024 threads x 16 points with radix-8 passes
-// and the paired layout (the fastest 2^14-point shape measured, in float32 and
-// float64); variant 6 is variant 5 split, two per CU.  BPC: workgroups per CU
-// the register budget is sized for.
+// and the paired layout (the fastest 2^14-point shape measured in float32);
+// variant 6 is variant 5 split, two per CU; variant 7 is 512 threads
+// x 32 points with radix-8 passes, paired.  In float64 the 512-thread shapes
+// (variants 2 and 7) have twice the registers per thread, and variant 2 is the
+// fastest there.  BPC: workgroups per CU the register budget is sized for.
 template <int NT_, int LOGE_, int LOGR_, bool SPLIT_ = false, bool PAIRED_ = false, int BPC_ = 1>
 struct OlsCfg {
   static constexpr int NT = NT_, LOGE = LOGE_, LOGR = LOGR_, BPC = BPC_;
@@ -92,12 +94,13 @@ template <> struct OlsShape<14, 3> : OlsCfg<512, 5, 4, true, true, 2> {};
 template <> struct OlsShape<14, 4> : OlsCfg<256, 6, 5, true, true, 2> {};
 template <> struct OlsShape<14, 5> : OlsCfg<1024, 4, 3, false, true> {};
 template <> struct OlsShape<14, 6> : OlsCfg<1024, 4, 3, true, true, 2> {};
+template <> struct OlsShape<14, 7> : OlsCfg<512, 5, 3, false, true> {};
 template <> struct OlsShape<15, 1> : OlsCfg<512, 6, 5, false, true> {};
 template <> struct OlsShape<15, 2> : OlsCfg<1024, 5, 3, false, true> {};
 
 bool ols_variant_exists(int logn, bool fp64, int v) {
   if (v == 0) return logn >= kMinLogN && logn <= ols_max_logn(fp64);
-  if (v == 5) return logn == 14;
+  if (v == 5 || v == 7 || (v == 2 && logn == 14)) return logn == 14;
   if (fp64) return false;
   return (v == 1 && (logn == 13 || logn == 14 || logn == 15)) || ((v >= 2 && v <= 6) && logn == 14) ||
          (v == 2 && logn == 15);
@@ -138,7 +141,9 @@ int pass_twiddle_count(int logn, bool fp64, int variant) {
   if (variant == 1)
     return logn == 13 ? pass_tw_total_t<float, 13, 1>()
                       : (logn == 14 ? pass_tw_total_t<float, 14, 1>() : pass_tw_total_t<float, 15, 1>());
+  if (variant == 2 && fp64) return pass_tw_total_t<double, 14, 2>();
   if (variant == 2) return logn == 14 ? pass_tw_total_t<float, 14, 2>() : pass_tw_total_t<float, 15, 2>();
+  if (variant == 7) return fp64 ? pass_tw_total_t<double, 14, 7>() : pass_tw_total_t<float, 14, 7>();
   if (variant == 3) return pass_tw_total_t<float, 14, 3>();
   if (variant == 4) return pass_tw_total_t<float, 14, 4>();
   if (variant == 5) return fp64 ? pass_tw_total_t<double, 14, 5>() : pass_tw_total_t<float, 14, 5>();
@@ -165,7 +170,9 @@ hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, i
   if (variant == 1)
     return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s)
                       : (logn == 14 ? pass_tw_launch<float, 14, 1>(tab, s) : pass_tw_launch<float, 15, 1>(tab, s));
+  if (variant == 2 && fp64) return pass_tw_launch<double, 14, 2>(tab, s);
   if (variant == 2) return logn == 14 ? pass_tw_launch<float, 14, 2>(tab, s) : pass_tw_launch<float, 15, 2>(tab, s);
+  if (variant == 7) return fp64 ? pass_tw_launch<double, 14, 7>(tab, s) : pass_tw_launch<float, 14, 7>(tab, s);
   if (variant == 3) return pass_tw_launch<float, 14, 3>(tab, s);
   if (variant == 4) return pass_tw_launch<float, 14, 4>(tab, s);
   if (variant == 5) return fp64 ? pass_tw_launch<double, 14, 5>(tab, s) : pass_tw_launch<float, 14, 5>(tab, s);
@@ -671,6 +678,8 @@ static hipError_t ols_dispatch(int logn, int variant, const void* y_in, void* y_
                                int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s, const CgState* st) {
   if (!ols_variant_exists(logn, sizeof(T) == 8, variant)) return hipErrorInvalidValue;
   if (variant == 5) return ols_launch<T, Tin, 14, 5>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st);
+  if (variant == 7) return ols_launch<T, Tin, 14, 7>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st);
+  if (variant == 2 && logn == 14) return ols_launch<T, Tin, 14, 2>(y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st);
 #define MM_OLS_ARGS y_in, y_out, chunks, n_chunks, spec, ptw, tw2, n_t, n_c, m, n_rhs, s, st
   if constexpr (sizeof(T) == 4) {
     if (variant == 1)

@@ -448,8 +448,9 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
 }
 
 // transform shape used when the descriptor leaves it open: the fastest measured
-// for each length (2^14 points: 1024 threads x 16 points, radix-8 passes, pairs in registers)
-int default_ols_variant(int logn, bool fp64) { (void)fp64; return logn == 14 ? 5 : 0; }
+// for each length (2^14 points: float32 1024 threads x 16 points, radix-8 passes;
+// float64 512 threads x 32 points, radix-16 passes; pairs in registers in both)
+int default_ols_variant(int logn, bool fp64) { return logn == 14 ? (fp64 ? 2 : 5) : 0; }
 
 void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
   const int maxlog = ols_max_logn(fp64);
@@ -859,7 +860,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
   if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
     fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
-  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 7]");
+  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 8]");
   validate_templates(d);
 
   P->ns = d->n_stokes;
