@@ -131,6 +131,89 @@ hipError_t launch_scan_inclusive(const uint32_t* in, uint32_t* out, int64_t n, v
   return scan_impl(in, out, n, (uint32_t*)scratch, 0, s);
 }
 
+// ---------------------------------------------------------------- observed ids
+// seg[i] = number of runs of equal valid keys (key < n_pix) that start at or
+// before i, for the sorted keys: the run-start flags are formed on the fly and
+// scanned block by block (4096 items); the sample after the last valid key
+// writes n_valid.  Keys go through LDS so that global loads and stores stay
+// coalesced while each thread scans 16 consecutive items; LDS slots are padded
+// by one word per 16 so that the per-thread runs spread over the banks.
+__device__ __forceinline__ int seg_pad(int j) { return j + (j >> 4); }
+
+__global__ __launch_bounds__(kScanThreads) void k_seg_scan_block(const uint32_t* __restrict__ keys, int64_t n,
+                                                                 uint32_t n_pix, uint32_t* __restrict__ out,
+                                                                 uint32_t* __restrict__ block_sums,
+                                                                 int64_t* __restrict__ n_valid) {
+  __shared__ uint32_t sk[kScanBlock + kScanBlock / 16 + 2];   // padded keys b0 .. b0 + 4095
+  __shared__ uint32_t sh[kScanThreads];
+  __shared__ uint32_t edge[2];                                 // keys b0 - 1 and b0 + 4096
+  const int tid = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int j = i * kScanThreads + tid;
+    const int64_t idx = b0 + j;
+    sk[seg_pad(j)] = idx < n ? keys[idx] : 0xFFFFFFFFu;
+  }
+  if (tid == 0) {
+    edge[0] = b0 > 0 ? keys[b0 - 1] : 0xFFFFFFFFu;
+    edge[1] = b0 + kScanBlock < n ? keys[b0 + kScanBlock] : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  uint32_t v[kScanItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int j = tid * kScanItems + i;
+    const int64_t idx = b0 + j;
+    const uint32_t k = sk[seg_pad(j)];
+    const uint32_t prev = j > 0 ? sk[seg_pad(j - 1)] : edge[0];
+    const uint32_t next = j + 1 < kScanBlock ? sk[seg_pad(j + 1)] : edge[1];
+    const bool valid = idx < n && k < n_pix;
+    v[i] = (valid && (idx == 0 || prev != k)) ? 1u : 0u;
+    sum += v[i];
+    if (valid && (idx == n - 1 || next >= n_pix)) n_valid[0] = idx + 1;   // unique writer
+  }
+  sh[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t x = tid >= off ? sh[tid - off] : 0u;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  uint32_t run = tid > 0 ? sh[tid - 1] : 0u;
+  if (tid == kScanThreads - 1) block_sums[blockIdx.x] = sh[kScanThreads - 1];
+  // inclusive values back through LDS, then coalesced stores
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    run += v[i];
+    sk[seg_pad(tid * kScanItems + i)] = run;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int j = i * kScanThreads + tid;
+    const int64_t idx = b0 + j;
+    if (idx < n) out[idx] = sk[seg_pad(j)];
+  }
+}
+
+hipError_t launch_segment_scan(const uint32_t* keys, int64_t n, uint32_t n_pix, uint32_t* seg, int64_t* n_valid,
+                               void* scratch, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  uint32_t* sums = (uint32_t*)scratch;
+  hipLaunchKernelGGL(k_seg_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, s, keys, n, n_pix, seg, sums,
+                     n_valid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nb == 1) return e;
+  e = scan_impl(sums, sums, nb, sums + nb + 1, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seg, n, sums);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- radix sort
 __global__ void k_sort_init(const int32_t* __restrict__ pix, int64_t n, uint32_t n_pix,
                             uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
@@ -303,38 +386,7 @@ hipError_t launch_sort_by_pixel(const int32_t* pix, int64_t n, int64_t n_pix, ui
 }
 
 // ---------------------------------------------------------------- observed layout
-__global__ void k_segment_flags(const uint32_t* __restrict__ keys, int64_t n, uint32_t n_pix,
-                                uint32_t* __restrict__ flags) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t k = keys[i];
-    flags[i] = (k < n_pix && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
-  }
-}
-
-__global__ void k_find_nvalid(const uint32_t* __restrict__ keys, int64_t n, uint32_t n_pix,
-                              int64_t* __restrict__ out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    if (keys[i] < n_pix && (i == n - 1 || keys[i + 1] >= n_pix)) out[0] = i + 1;   // unique writer
-  }
-}
-
-hipError_t launch_find_nvalid(const uint32_t* keys, int64_t n, uint32_t n_pix, int64_t* out,
-                              hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_find_nvalid, grid_for(n), dim3(256), 0, s, keys, n, n_pix, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_segment_flags(const uint32_t* keys, int64_t n, uint32_t n_pix, uint32_t* flags,
-                                hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segment_flags, grid_for(n), dim3(256), 0, s, keys, n, n_pix, flags);
-  return hipGetLastError();
-}
-
-// seg_id = inclusive scan of the segment flags (observed id + 1 for valid samples)
+// seg_id = observed id + 1 of each sorted valid sample (launch_segment_scan)
 __global__ void k_build_layout(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals,
                                const uint32_t* __restrict__ seg_id, int64_t n, uint32_t n_pix,
                                const float2* __restrict__ w, int ns, int64_t* __restrict__ pix_ptr,

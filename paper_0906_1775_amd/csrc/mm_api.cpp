@@ -657,14 +657,11 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
     int32_t* vals = P->alloc<int32_t>(n);
     hipchk(launch_sort_by_pixel(d_key, n, n_keys, keys, vals, scratch, s), "sort by pixel");
     P->release(scratch);
-    uint32_t* flags = P->alloc<uint32_t>(n);
     uint32_t* seg = P->alloc<uint32_t>(n);
     char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(n));
     int64_t* nvalid_d = P->alloc<int64_t>(1);
-    hipchk(launch_segment_flags(keys, n, (uint32_t)n_keys, flags, s), "segment flags");
-    hipchk(launch_scan_inclusive(flags, seg, n, sscr, s), "segment scan");
     hipchk(hipMemsetAsync(nvalid_d, 0, sizeof(int64_t), s), "memset");
-    hipchk(launch_find_nvalid(keys, n, (uint32_t)n_keys, nvalid_d, s), "valid count");
+    hipchk(launch_segment_scan(keys, n, (uint32_t)n_keys, seg, nvalid_d, sscr, s), "observed ids");
     uint32_t nobs_h = 0;
     int64_t nvalid_h = 0;
     int32_t hflag = 0;
@@ -688,7 +685,6 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
     // released blocks are only reused by later work on this stream: no wait needed
     P->release(keys);
     P->release(vals);
-    P->release(flags);
     P->release(seg);
     P->release(sscr);
     P->release(nvalid_d);
@@ -1036,6 +1032,27 @@ std::vector<double> dots(mm_plan_s* P, const double* x, const double* y, int R, 
   return out;
 }
 
+// per-RHS x.y and x.z with one host round trip
+void dots2(mm_plan_s* P, const double* x, const double* y, const double* z, int R, hipStream_t s,
+           std::vector<double>& xy, std::vector<double>& xz) {
+  const int64_t nu = P->nu();
+  std::vector<double> h((size_t)2 * R * kDotBlocks);
+  hipchk(launch_dot(x, y, nu, R, P->part1, s), "dot");
+  hipchk(launch_dot(x, z, nu, R, P->part2, s), "dot");
+  hipchk(hipMemcpyAsync(h.data(), P->part1, sizeof(double) * R * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
+  hipchk(hipMemcpyAsync(h.data() + (size_t)R * kDotBlocks, P->part2, sizeof(double) * R * kDotBlocks,
+                        hipMemcpyDeviceToHost, s),
+         "copy");
+  hipchk(hipStreamSynchronize(s), "dot");
+  xy.assign(R, 0.0);
+  xz.assign(R, 0.0);
+  for (int r = 0; r < R; ++r)
+    for (int i = 0; i < kDotBlocks; ++i) {
+      xy[r] += h[(size_t)r * kDotBlocks + i];
+      xz[r] += h[(size_t)(R + r) * kDotBlocks + i];
+    }
+}
+
 // queue `step` PCG iterations; a full block of k iterations runs as one hipGraph,
 // captured once per plan (and k) from the plan's second solve on: a plan solved
 // once gains nothing from the capture, and at the sizes where launches cost more
@@ -1281,8 +1298,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
           any_restart = true;
         }
       if (any_restart) sync_p32(P, s);
-      const std::vector<double> rr = dots(P, P->vr, P->vr, R, s);
-      const std::vector<double> rz = dots(P, P->vr, P->vz, R, s);
+      std::vector<double> rr, rz;
+      dots2(P, P->vr, P->vr, P->vz, R, s, rr, rz);
       for (int r : rows) {
         CgState& c = P->st_host[r];
         const double tr = c.bnorm > 0 ? std::sqrt(rr[r]) / c.bnorm : 0.0;

@@ -146,11 +146,11 @@ size_t scan_scratch_bytes(int64_t n);
 hipError_t launch_scan_inclusive(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
                                  hipStream_t s);
 // flags[i] = 1 where a new pixel segment starts (i < n_valid)
-hipError_t launch_segment_flags(const uint32_t* keys, int64_t n, uint32_t n_pix, uint32_t* flags,
-                                hipStream_t s);
-// out[0] = number of sorted keys below n_pix (out[0] must be 0 beforehand)
-hipError_t launch_find_nvalid(const uint32_t* keys, int64_t n, uint32_t n_pix, int64_t* out,
-                              hipStream_t s);
+// seg[i] = observed id + 1 of sorted sample i (runs of equal keys below n_pix counted
+// up to i), and n_valid[0] = number of keys below n_pix (n_valid[0] must be 0
+// beforehand); scratch of scan_scratch_bytes(n) bytes
+hipError_t launch_segment_scan(const uint32_t* keys, int64_t n, uint32_t n_pix, uint32_t* seg, int64_t* n_valid,
+                               void* scratch, hipStream_t s);
 // pix_ptr, obs2glob, w_pm, perm from the sorted order
 hipError_t launch_build_layout(const uint32_t* keys, const int32_t* vals, const uint32_t* seg_id,
                                int64_t n, uint32_t n_pix, const float* w, int ns, int64_t* pix_ptr,
