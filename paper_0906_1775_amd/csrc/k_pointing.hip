@@ -20,10 +20,13 @@
 namespace mm {
 
 // Each block covers kGatherUnroll x 256 consecutive samples; a thread takes
-// samples tid, tid + 256, ... of its block, issuing all pointing loads, then
-// all map loads, before any store, so several independent chains are in
-// flight while every load instruction stays coalesced across the wavefront.
-constexpr int kGatherUnroll = 4;
+// samples tid, tid + 256, ... of its block, so every load and store instruction
+// covers 64 consecutive samples of the wavefront.  A thread issues all its
+// pointing loads, then all its map lookups, before any store: the lookups of
+// one instruction then fall on the pixels of 64 consecutive samples, which a
+// scan keeps within a few cache lines, and many independent chains are in
+// flight per wavefront.
+constexpr int kGatherUnroll = 8;
 
 // one 8-byte nontemporal load of a (sin, cos) pair
 __device__ __forceinline__ float2 load_nt(const float2* p) {
@@ -33,8 +36,25 @@ __device__ __forceinline__ float2 load_nt(const float2* p) {
   return r;
 }
 
+// The (I, Q, U) values of one pixel, read as one load
+template <typename Tp> struct Stokes3 { Tp v[3]; };
+
+// y_t = sum_s w_ts p_{pix_t, s} for the samples of row r; o must be a valid pixel:
+// excised samples are clamped to pixel 0 by the caller and their value discarded,
+// so that no lookup waits behind a branch.
+template <int NS, typename Tp>
+__device__ __forceinline__ double sky_value(const Tp* __restrict__ row, int32_t o, float s, float c) {
+  if constexpr (NS == 1) {
+    return (double)row[o];
+  } else {
+    const Stokes3<Tp> m = *reinterpret_cast<const Stokes3<Tp>*>(row + (int64_t)o * 3);
+    return 0.5 * ((double)m.v[0] + (double)s * (double)m.v[1] + (double)c * (double)m.v[2]);
+  }
+}
+
 // Tp: element type of the map (float64, or the float32 copy of the search
-// direction that mixed-precision iterations gather from)
+// direction that mixed-precision iterations gather from); y rows have stride ys.
+// Requires n_obs >= 1 (pixel 0 exists).
 template <typename Ty, int NS, typename Tp>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
                                                 const float2* __restrict__ w,
@@ -53,26 +73,22 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
     float2 sc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t t = t0 + u * 256;
+      // a slot past the last sample re-reads the last sample and is discarded;
       // the pointing streams are read once per pass: nontemporal, so they do not
       // evict the map (and the TOD rows other kernels re-read) from the caches
-      o[u] = t < n_t ? __builtin_nontemporal_load(pix_obs + t) : -1;
-      if (NS == 3) sc[u] = t < n_t ? load_nt(w + t) : make_float2(0.f, 0.f);
+      const int64_t t = t0 + u * 256 < n_t ? t0 + u * 256 : n_t - 1;
+      o[u] = __builtin_nontemporal_load(pix_obs + t);
+      if (NS == 3) sc[u] = load_nt(w + t);
+      else sc[u] = make_float2(0.f, 0.f);
     }
     for (int r = 0; r < n_rhs; ++r) {
       if (st && !st[r].active) continue;   // this RHS has stopped iterating
+      const Tp* __restrict__ row = p + (int64_t)r * vs;
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        v[u] = 0.0;
-        if (o[u] >= 0) {
-          if (NS == 1) {
-            v[u] = (double)p[(int64_t)r * vs + o[u]];
-          } else {
-            const Tp* m = p + (int64_t)r * vs + (int64_t)o[u] * 3;
-            v[u] = 0.5 * ((double)m[0] + (double)sc[u].x * (double)m[1] + (double)sc[u].y * (double)m[2]);
-          }
-        }
+        const double val = sky_value<NS, Tp>(row, o[u] >= 0 ? o[u] : 0, sc[u].x, sc[u].y);
+        v[u] = o[u] >= 0 ? val : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -83,17 +99,19 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_
   }
 }
 
-// per-sample gather of n samples into rows of stride ys
-static hipError_t launch_gather_samples(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
-                                        const double* p, int64_t vs, void* y, int64_t n_t, int64_t ys,
-                                        int n_rhs, hipStream_t s, const CgState* st, const float* p32,
-                                        int64_t vs32) {
+hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
+                         const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
+                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32) {
   if (n_t == 0) return hipSuccess;
+  if (n_obs == 0)   // every sample excised: the TOD rows are zero (a fill kernel, safe under graph capture)
+    return out_f64 ? launch_fill_f64((double*)y, 0.0, n_t * n_rhs, s)
+                   : launch_fill_i32((int32_t*)y, 0, n_t * n_rhs, s);   // float32 zero = all bits zero
   int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
   if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
-#define MM_GA(TY, NS, TP, PP, VS) hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, ys, n_rhs, st)
+#define MM_GA(TY, NS, TP, PP, VS) \
+  hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, n_t, n_rhs, st)
   if (p32) {
     if (out_f64) { if (ns == 1) MM_GA(double, 1, float, p32, vs32); else MM_GA(double, 3, float, p32, vs32); }
     else { if (ns == 1) MM_GA(float, 1, float, p32, vs32); else MM_GA(float, 3, float, p32, vs32); }
@@ -103,131 +121,6 @@ static hipError_t launch_gather_samples(bool out_f64, int ns, const int32_t* pix
   }
 #undef MM_GA
   return hipGetLastError();
-}
-
-// Four consecutive samples per thread: the pointing is read with 16-byte loads
-// (4 pixel ids, then 2 x 2 (sin, cos) pairs) and, when every TOD row starts on a
-// 4-sample boundary, the TOD is written with 16-byte (float32) or 2 x 16-byte
-// (float64) stores.  Same values as k_gather; used when the pointing streams
-// are 16-byte aligned.  The n_t mod 4 trailing samples go through k_gather's
-// per-sample path (one block).
-typedef int32_t v4i __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double v2d __attribute__((ext_vector_type(2)));
-constexpr int kGather4Unroll = 2;
-
-// o must be a valid pixel: excised samples are clamped to pixel 0 by the caller and
-// their value discarded, so that no load sits behind a branch.
-template <int NS, typename Tp>
-__device__ __forceinline__ double sky_value(const Tp* __restrict__ row, int32_t o, float s, float c) {
-  if constexpr (NS == 1) {
-    return (double)row[o];
-  } else {
-    const Tp* m = row + (int64_t)o * 3;
-    return 0.5 * ((double)m[0] + (double)s * (double)m[1] + (double)c * (double)m[2]);
-  }
-}
-
-// requires n_obs >= 1 (pixel 0 exists) and n_t >= 4
-template <typename Ty, int NS, typename Tp>
-__global__ __launch_bounds__(256) void k_gather4(const int32_t* __restrict__ pix_obs, const float* __restrict__ w,
-                                                 const Tp* __restrict__ p, int64_t vs, Ty* __restrict__ y,
-                                                 int64_t n_t, int n_rhs, const CgState* __restrict__ st,
-                                                 bool vec_out) {
-  constexpr int U = kGather4Unroll;
-  if (st) {   // every RHS has stopped: nothing to read
-    bool any = false;
-    for (int r = 0; r < n_rhs; ++r) any = any || st[r].active != 0;
-    if (!any) return;
-  }
-  const int64_t n_q = n_t >> 2;
-  const int64_t step = (int64_t)gridDim.x * 256 * U;
-  for (int64_t q0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; q0 < n_q; q0 += step) {
-    v4i o[U];
-    v4f sc0[U], sc1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // an idle slot (past the last group) loads the last group and is discarded
-      const int64_t q = q0 + u * 256 < n_q ? q0 + u * 256 : n_q - 1;
-      o[u] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(pix_obs) + q);
-      if (NS == 3) {
-        const v4f* wq = reinterpret_cast<const v4f*>(w) + 2 * q;
-        sc0[u] = __builtin_nontemporal_load(wq);
-        sc1[u] = __builtin_nontemporal_load(wq + 1);
-      } else {
-        sc0[u] = sc1[u] = v4f{0.f, 0.f, 0.f, 0.f};
-      }
-    }
-    for (int r = 0; r < n_rhs; ++r) {
-      if (st && !st[r].active) continue;   // this RHS has stopped iterating
-      const Tp* __restrict__ row = p + (int64_t)r * vs;
-      double v[U][4];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t oo[4] = {o[u].x, o[u].y, o[u].z, o[u].w};
-        const float ss[4] = {sc0[u].x, sc0[u].z, sc1[u].x, sc1[u].z};
-        const float cc[4] = {sc0[u].y, sc0[u].w, sc1[u].y, sc1[u].w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double val = sky_value<NS, Tp>(row, oo[k] >= 0 ? oo[k] : 0, ss[k], cc[k]);
-          v[u][k] = oo[k] >= 0 ? val : 0.0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t q = q0 + u * 256;
-        if (q >= n_q) continue;
-        Ty* __restrict__ yr = y + (int64_t)r * n_t + 4 * q;
-        if (vec_out) {
-          if constexpr (sizeof(Ty) == 4) {
-            *reinterpret_cast<v4f*>(yr) = v4f{(float)v[u][0], (float)v[u][1], (float)v[u][2], (float)v[u][3]};
-          } else {
-            reinterpret_cast<v2d*>(yr)[0] = v2d{v[u][0], v[u][1]};
-            reinterpret_cast<v2d*>(yr)[1] = v2d{v[u][2], v[u][3]};
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) yr[k] = (Ty)v[u][k];
-        }
-      }
-    }
-  }
-}
-
-hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
-                         const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
-                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32) {
-  if (n_t == 0) return hipSuccess;
-  const bool aligned = n_obs > 0 && n_t >= 4 && (reinterpret_cast<uintptr_t>(pix_obs) & 15) == 0 &&
-                       (ns == 1 || (reinterpret_cast<uintptr_t>(w) & 15) == 0);
-  if (aligned) {
-    const int64_t n_q = n_t >> 2;
-    const bool vec_out = (n_t & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 31) == 0;
-    if (n_q > 0) {
-      int64_t nb = (n_q + 256 * kGather4Unroll - 1) / (256 * kGather4Unroll);
-      if (nb > 65536) nb = 65536;
-      const dim3 g((unsigned)nb), b(256);
-#define MM_G4(TY, NS, TP, PP, VS) \
-  hipLaunchKernelGGL((k_gather4<TY, NS, TP>), g, b, 0, s, pix_obs, w, PP, VS, (TY*)y, n_t, n_rhs, st, vec_out)
-      if (p32) {
-        if (out_f64) { if (ns == 1) MM_G4(double, 1, float, p32, vs32); else MM_G4(double, 3, float, p32, vs32); }
-        else { if (ns == 1) MM_G4(float, 1, float, p32, vs32); else MM_G4(float, 3, float, p32, vs32); }
-      } else {
-        if (out_f64) { if (ns == 1) MM_G4(double, 1, double, p, vs); else MM_G4(double, 3, double, p, vs); }
-        else { if (ns == 1) MM_G4(float, 1, double, p, vs); else MM_G4(float, 3, double, p, vs); }
-      }
-#undef MM_G4
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    const int64_t t0 = n_q * 4;
-    if (t0 == n_t) return hipSuccess;
-    // trailing samples: the per-sample kernel on the last n_t - t0 samples (one block)
-    const size_t yb = out_f64 ? sizeof(double) : sizeof(float);
-    return launch_gather_samples(out_f64, ns, pix_obs + t0, w ? w + 2 * t0 : nullptr, p, vs,
-                                 (char*)y + t0 * yb, n_t - t0, n_t, n_rhs, s, st, p32, vs32);
-  }
-  return launch_gather_samples(out_f64, ns, pix_obs, w, p, vs, y, n_t, n_t, n_rhs, s, st, p32, vs32);
 }
 
 // dst[r * dst_stride + i] = (float)src[r * src_stride + i], i < n
