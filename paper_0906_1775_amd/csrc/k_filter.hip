@@ -557,14 +557,23 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
     const T* __restrict__ spec, const cx<T>* __restrict__ ptw, const cx<T>* __restrict__ tw2,
     int64_t n_t, int n_c, int m, const CgState* __restrict__ st) {
   using F = ShapeFFT<T, LOGN, V>;
-  if (st && !st[blockIdx.y].active) return;   // this RHS has stopped iterating
+  // Workgroups are dealt to the 8 XCDs round-robin in linear (x-fastest) order, so
+  // XCD x takes workgroups x, x + 8, ...; give it a contiguous run of (RHS, chunk)
+  // pairs instead, so that neighbouring chunks, whose windows overlap by 2 n_c
+  // samples, read the shared samples through the same L2.
+  const int64_t n_wg = (int64_t)gridDim.x * gridDim.y;
+  const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
+  const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
+  const int rhs = (int)(job / gridDim.x);
+  if (st && !st[rhs].active) return;   // this RHS has stopped iterating
   using PI = typename Pair<Tin>::type;
   using PO = typename Pair<T>::type;
   __shared__ __align__(16) char lds[F::LDS_BYTES];
   constexpr int N = F::N, E = F::E, NT = F::NT;
   const int t = threadIdx.x;
-  const OlsChunk ch = chunks[blockIdx.x];
-  const int64_t roff = (int64_t)blockIdx.y * n_t;
+  const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
+  const int64_t roff = (int64_t)rhs * n_t;
   const int64_t s0 = ch.out_start - n_c;
   const int64_t lo = ch.iv_lo, hi = ch.iv_hi;
   const Tin* __restrict__ src = yin + roff;
