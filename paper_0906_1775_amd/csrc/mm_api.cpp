@@ -56,6 +56,10 @@ mm_status_t guarded(F&& f) {
 }
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+// pinned staging slots of a plan (8 bytes each) and its dot-partial buffer
+constexpr int kPinSlots = 8;
+enum PinSlot { kPinFlag = 0, kPinObs, kPinValid, kPinTotal, kPinSingular };
+
 int ilog2(int64_t x) {
   int l = 0;
   while ((int64_t(1) << l) < x) ++l;
@@ -305,8 +309,13 @@ struct mm_plan_s {
   double *vb64 = nullptr, *vxbest = nullptr;   // mixed refinement: b and the best iterate in float64
   double* vxacc = nullptr;                      // accumulated map of the restarted correction
   CgState* st = nullptr;
-  CgState* st_host = nullptr;
+  CgState* st_host = nullptr;     // pinned: the CG states, then the staging slots below
+  char* pin = nullptr;            // pinned staging of scalar readbacks (kPinSlots 8-byte slots) and dot partials
+  template <typename T>
+  T* slot(int k) { return reinterpret_cast<T*>(pin + 8 * k); }
+  double* pin_dots() { return reinterpret_cast<double*>(pin + kPinSlots * 8); }
   double* hist = nullptr;
+  double* hist_host = nullptr;    // pinned copy target of hist
   int hist_cap = 0;
 
   // cached graph of check_every iterations
@@ -368,6 +377,7 @@ struct mm_plan_s {
     for (auto& a : allocs) cache_put(device, a.first, a.second);
     for (auto& a : spare) cache_put(device, a.first, a.second);
     if (st_host) (void)hipHostFree(st_host);
+    if (hist_host) (void)hipHostFree(hist_host);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (own) stream_put(device, own);
@@ -646,10 +656,9 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
   hipchk(launch_check_pix(d_key, n, n_keys, flag, s), "index check");
   L.obs_idx = P->alloc<int32_t>(n);
   if (n == 0) {
-    int32_t hflag = 0;
-    hipchk(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
+    hipchk(hipMemcpyAsync(P->slot<int32_t>(kPinFlag), flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
     hipchk(hipStreamSynchronize(s), "index check");
-    if (hflag) fail(MM_EINVAL, range_msg);
+    if (*P->slot<int32_t>(kPinFlag)) fail(MM_EINVAL, range_msg);
   }
   if (n > 0) {
     char* scratch = P->alloc<char>((int64_t)sort_scratch_bytes(n));
@@ -662,16 +671,13 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
     int64_t* nvalid_d = P->alloc<int64_t>(1);
     hipchk(hipMemsetAsync(nvalid_d, 0, sizeof(int64_t), s), "memset");
     hipchk(launch_segment_scan(keys, n, (uint32_t)n_keys, seg, nvalid_d, sscr, s), "observed ids");
-    uint32_t nobs_h = 0;
-    int64_t nvalid_h = 0;
-    int32_t hflag = 0;
-    hipchk(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
-    hipchk(hipMemcpyAsync(&nobs_h, seg + (n - 1), 4, hipMemcpyDeviceToHost, s), "copy");
-    hipchk(hipMemcpyAsync(&nvalid_h, nvalid_d, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(P->slot<int32_t>(kPinFlag), flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
+    hipchk(hipMemcpyAsync(P->slot<uint32_t>(kPinObs), seg + (n - 1), 4, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(P->slot<int64_t>(kPinValid), nvalid_d, 8, hipMemcpyDeviceToHost, s), "copy");
     hipchk(hipStreamSynchronize(s), "observed count");
-    if (hflag) fail(MM_EINVAL, range_msg);
-    L.n_obs = nobs_h;
-    L.n_valid = nvalid_h;
+    if (*P->slot<int32_t>(kPinFlag)) fail(MM_EINVAL, range_msg);
+    L.n_obs = *P->slot<uint32_t>(kPinObs);
+    L.n_valid = *P->slot<int64_t>(kPinValid);
     L.ptr = P->alloc<int64_t>(L.n_obs + 1);
     L.obs2glob = P->alloc<int32_t>(L.n_obs);
     L.perm = P->alloc<int32_t>(L.n_valid);
@@ -711,8 +717,9 @@ void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
   if (n_sl > 0) {
     hipchk(launch_sell_widths(L.ptr, L.n_obs, len, s), "slice widths");
     hipchk(launch_scan_inclusive(len, end, n_sl, sscr, s), "slice offsets");
-    hipchk(hipMemcpyAsync(&total, end + (n_sl - 1), 4, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(P->slot<uint32_t>(kPinTotal), end + (n_sl - 1), 4, hipMemcpyDeviceToHost, s), "copy");
     hipchk(hipStreamSynchronize(s), "slices");
+    total = *P->slot<uint32_t>(kPinTotal);
     // the 32-bit slice sizes and their prefix sum are exact while the padded total
     // stays below 2^32 - 1 (a saturated size also trips this test).  A slice holds at
     // most 64 x its pixels' hits, so the total is at most 64 n_valid: only larger
@@ -899,7 +906,13 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->own = stream_take(P->device);
   hipchk(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming), "event");
   hipchk(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming), "event");
-  hipchk(hipHostMalloc((void**)&P->st_host, sizeof(CgState) * P->R, hipHostMallocDefault), "pinned state");
+  // one pinned block: the CG states, scalar slots, and the dot partials of dots2
+  // (device-to-host copies into pageable memory are staged and serialise)
+  const size_t st_bytes = (sizeof(CgState) * P->R + 255) & ~(size_t)255;
+  hipchk(hipHostMalloc((void**)&P->st_host, st_bytes + kPinSlots * 8 + sizeof(double) * 2 * P->R * kDotBlocks,
+                       hipHostMallocDefault),
+         "pinned state");
+  P->pin = reinterpret_cast<char*>(P->st_host) + st_bytes;
 
   const int64_t n = P->n_t;
   // ---- pointing: range check, sort by pixel, observed layout
@@ -943,10 +956,9 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
                                 P->n_iv, P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
            "preconditioner");
     hipchk(launch_count_nonzero(sing, P->n_obs, nullptr, cnt, s), "singular count");
-    double hc = 0;
-    hipchk(hipMemcpyAsync(&hc, cnt, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(P->slot<double>(kPinSingular), cnt, 8, hipMemcpyDeviceToHost, s), "copy");
     hipchk(hipStreamSynchronize(s), "preconditioner");
-    P->n_singular = (int)hc;
+    P->n_singular = (int)*P->slot<double>(kPinSingular);
     P->release(sing);
     P->release(cnt);
   }
@@ -1023,9 +1035,10 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
 // per-RHS sums of x.y over [R][nu] vectors (float64, fixed order)
 std::vector<double> dots(mm_plan_s* P, const double* x, const double* y, int R, hipStream_t s) {
   const int64_t nu = P->nu();
-  std::vector<double> h((size_t)R * kDotBlocks), out(R, 0.0);
+  std::vector<double> out(R, 0.0);
+  const double* h = P->pin_dots();
   hipchk(launch_dot(x, y, nu, R, P->part1, s), "dot");
-  hipchk(hipMemcpyAsync(h.data(), P->part1, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s), "copy");
+  hipchk(hipMemcpyAsync(P->pin_dots(), P->part1, sizeof(double) * R * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
   hipchk(hipStreamSynchronize(s), "dot");
   for (int r = 0; r < R; ++r)
     for (int i = 0; i < kDotBlocks; ++i) out[r] += h[(size_t)r * kDotBlocks + i];
@@ -1036,11 +1049,11 @@ std::vector<double> dots(mm_plan_s* P, const double* x, const double* y, int R, 
 void dots2(mm_plan_s* P, const double* x, const double* y, const double* z, int R, hipStream_t s,
            std::vector<double>& xy, std::vector<double>& xz) {
   const int64_t nu = P->nu();
-  std::vector<double> h((size_t)2 * R * kDotBlocks);
+  double* h = P->pin_dots();
   hipchk(launch_dot(x, y, nu, R, P->part1, s), "dot");
   hipchk(launch_dot(x, z, nu, R, P->part2, s), "dot");
-  hipchk(hipMemcpyAsync(h.data(), P->part1, sizeof(double) * R * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
-  hipchk(hipMemcpyAsync(h.data() + (size_t)R * kDotBlocks, P->part2, sizeof(double) * R * kDotBlocks,
+  hipchk(hipMemcpyAsync(h, P->part1, sizeof(double) * R * kDotBlocks, hipMemcpyDeviceToHost, s), "copy");
+  hipchk(hipMemcpyAsync(h + (size_t)R * kDotBlocks, P->part2, sizeof(double) * R * kDotBlocks,
                         hipMemcpyDeviceToHost, s),
          "copy");
   hipchk(hipStreamSynchronize(s), "dot");
@@ -1217,8 +1230,14 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
 
   if (P->hist_cap < n_max + 1) {
     if (P->hist) P->release(P->hist);
+    if (P->hist_host) {
+      hipchk(hipHostFree(P->hist_host), "pinned history");
+      P->hist_host = nullptr;
+    }
     P->hist_cap = n_max + 1;
     P->hist = P->alloc<double>((int64_t)R * P->hist_cap);
+    hipchk(hipHostMalloc((void**)&P->hist_host, sizeof(double) * R * P->hist_cap, hipHostMallocDefault),
+           "pinned history");
   }
 
   std::vector<int> iters(R, 0), best_iter(R, 0);
@@ -1230,8 +1249,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     make_rhs(P, src, P->fs_main, 0, R, P->vb, P->y2, s);
     if (o.d_x0) to_obs(P, o.d_x0, P->vx, R, s);
     run_pcg(P, s, o.tol, n_max, fixed, o.check_every, o.use_graph != 0, o.d_x0 != nullptr);
-    std::vector<double> hh((size_t)R * P->hist_cap);
-    hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+    const double* hh = P->hist_host;
+    hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * P->hist_cap, hipMemcpyDeviceToHost, s), "copy");
     hipchk(hipStreamSynchronize(s), "history");
     for (int r = 0; r < R; ++r) {
       const CgState& c = P->st_host[r];
@@ -1328,7 +1347,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       hipchk(hipMemcpyAsync(P->st, P->st_host, sizeof(CgState) * R, hipMemcpyHostToDevice, s), "state copy");
     };
 
-    std::vector<double> hh((size_t)R * P->hist_cap);
+    const double* hh = P->hist_host;
     const int k = std::min(std::max(o.check_every, 1), std::max(1, n_max));
     int done = 0;
     auto any_active = [&]() {
@@ -1342,7 +1361,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       iterate_block(P, s, step, k, o.use_graph != 0);
       done += step;
       hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
-      hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * P->hist_cap, hipMemcpyDeviceToHost, s), "copy");
       hipchk(hipStreamSynchronize(s), "solve");
       std::vector<int> rows;
       for (int r = 0; r < R; ++r) {
@@ -1395,7 +1414,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
         hist_out[(size_t)r * (n_max + 1)] = rel[r];
       }
     }
-    std::vector<double> hh((size_t)R * P->hist_cap);
+    const double* hh = P->hist_host;
     for (int outer = 0; outer < 30; ++outer) {
       // right-hand sides of the correction equation; RHS already converged get 0
       double worst = 0.0;
@@ -1417,7 +1436,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       int budget = 0;
       for (int r = 0; r < R; ++r) budget = std::max(budget, n_max - iters[r]);
       run_pcg(P, s, tau, budget, false, o.check_every, o.use_graph != 0, false);
-      hipchk(hipMemcpyAsync(hh.data(), P->hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * P->hist_cap, hipMemcpyDeviceToHost, s), "copy");
       hipchk(hipStreamSynchronize(s), "history");
       // x += d (rows of converged RHS add 0)
       hipchk(launch_axpby(P->vxacc, P->vxb, 1.0, 1.0, (int64_t)R * nu, s), "accumulate");

@@ -82,6 +82,11 @@ def test_every_sample_excised():
     m, info = mm.solve(tod_tensor(p), tol=1e-8)
     assert info["status"] == "MM_OK"
     assert torch.all(m == 0)
+    # P x of any map is zero TOD, in either precision
+    x = torch.randn((1, p.n_pix, 1), dtype=torch.float64, device=dev)
+    for dt in (torch.float32, torch.float64):
+        y = mm.unpoint(x, dtype=dt)
+        assert y.shape == (1, p.pix.size) and y.dtype == dt and torch.all(y == 0)
 
 
 def test_empty_intervals_change_nothing():
