@@ -295,6 +295,7 @@ struct mm_plan_s {
   // preconditioner
   double* minv = nullptr;
   int n_singular = 0;
+  hipEvent_t ev_singular = nullptr;   // recorded after n_singular's copy to its pinned slot (null once read)
 
   // work
   void* y1 = nullptr;            // [R][n_t] of the iteration precision
@@ -380,6 +381,7 @@ struct mm_plan_s {
     if (hist_host) (void)hipHostFree(hist_host);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_singular) (void)hipEventDestroy(ev_singular);
     if (own) stream_put(device, own);
   }
 
@@ -389,6 +391,18 @@ struct mm_plan_s {
   int64_t ng() const { return n_pix * ns + n_tglob; }    // API map-shaped row
   bool main_fp64() const { return precision == MM_FP64; }
 };
+
+// preconditioner blocks flagged singular (the count is copied back without a wait
+// at plan time and read here when first needed)
+int singular_count(mm_plan_s* P) {
+  if (P->ev_singular) {
+    hipchk(hipEventSynchronize(P->ev_singular), "preconditioner");
+    P->n_singular = (int)*P->slot<double>(kPinSingular);
+    hipchk(hipEventDestroy(P->ev_singular), "event");
+    P->ev_singular = nullptr;
+  }
+  return P->n_singular;
+}
 
 namespace {
 
@@ -525,8 +539,7 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   fs.spec = P->alloc<char>((int64_t)P->n_filt * (fs.N + 1) * esz);
   char* sscr = P->alloc<char>((int64_t)spectra_scratch_bytes(logn));
   hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, sscr, s), "filter spectra");
-  hipchk(hipStreamSynchronize(s), "filter setup");
-  P->release(sscr);
+  P->release(sscr);   // later work on this stream may reuse it (the chunk upload above was staged)
   fs.ready = true;
 }
 
@@ -956,9 +969,10 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
                                 P->n_iv, P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
            "preconditioner");
     hipchk(launch_count_nonzero(sing, P->n_obs, nullptr, cnt, s), "singular count");
+    // read when first needed (plan info, end of a solve), not here: no wait in the plan build
     hipchk(hipMemcpyAsync(P->slot<double>(kPinSingular), cnt, 8, hipMemcpyDeviceToHost, s), "copy");
-    hipchk(hipStreamSynchronize(s), "preconditioner");
-    P->n_singular = (int)*P->slot<double>(kPinSingular);
+    hipchk(hipEventCreateWithFlags(&P->ev_singular, hipEventDisableTiming), "event");
+    hipchk(hipEventRecord(P->ev_singular, s), "event");
     P->release(sing);
     P->release(cnt);
   }
@@ -1494,7 +1508,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     }
     if (info->history) std::memcpy(info->history, hist_out.data(), sizeof(double) * hist_out.size());
   }
-  if (P->n_singular > 0) {
+  if (singular_count(P) > 0) {
     g_last_error = std::to_string(P->n_singular) + " singular preconditioner block(s)";
     *result = MM_ESINGULAR;
   } else if (notconv) {
@@ -1561,7 +1575,7 @@ mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
     info->n_valid = P->n_valid;
     info->n_f = P->fs_main.nf;
     info->n_chunks = P->fs_main.n_chunks;
-    info->n_singular = P->n_singular;
+    info->n_singular = singular_count(P);
     info->n_sliced = P->px.sell_entries;
     info->n_tmpl = P->n_tglob;
     info->fft_shape = P->fs_main.variant + 1;
