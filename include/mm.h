@@ -252,10 +252,14 @@ typedef struct {
   const double* d_x0;           /* optional initial map [n_rhs][n_pix][n_stokes]; NULL = 0 */
   int32_t refine;               /* MM_MIXED only: 1 = reliable updates: the iterate and the CG
                                    vectors are float64 and H is applied in float32; at the host's
-                                   check points each RHS whose recurrence residual fell tenfold
-                                   since its last replacement (or reached tol) gets its residual
-                                   replaced by the float64 true residual b - H x (float64 filter)
-                                   and CG continues along the same direction; tol is tested on
+                                   check points each RHS whose recurrence residual fell a
+                                   thousandfold since its last replacement (or reached tol) gets
+                                   its residual replaced by the float64 true residual b - H x
+                                   (float64 filter) and CG continues along the same direction;
+                                   once the convergence rate is known, blocks between checks
+                                   may grow to 2 check_every iterations while the residual is
+                                   predicted to stay within 4.5 decades of the last float64
+                                   one; tol is tested on
                                    those true residuals and the iterate with the lowest one is
                                    returned, so the map reaches float64 accuracy.  0 = plain
                                    mixed iterations.  Ignored with fixed_iters. */

@@ -56,6 +56,13 @@ mm_status_t guarded(F&& f) {
 }
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+// Mixed solver: a check replaces the residual of an RHS whose recurrence residual fell
+// below kMixedReplaceFall x its float64 residual at the last replacement, and blocks
+// are sized so that it is not predicted to fall more than kMixedMaxDrop decades below
+// that residual before the next check.
+constexpr double kMixedReplaceFall = 1e-3;
+constexpr double kMixedMaxDrop = 4.5;
+
 // pinned staging slots of a plan (8 bytes each) and its dot-partial buffer
 constexpr int kPinSlots = 8;
 enum PinSlot { kPinFlag = 0, kPinObs, kPinValid, kPinTotal, kPinSingular };
@@ -1115,28 +1122,41 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
 // Iterations in the next block between host checks: a full block of k, or fewer when
 // every active RHS is predicted to reach tol sooner from its residual rate since the
 // previous check (a shorter block saves the launches past convergence; the estimate is
-// padded, since a block that ends short costs another check).
+// padded, since a block that ends short costs another check).  For the mixed solver
+// (ref_rel = each RHS's float64 residual at its last replacement) a block may run up
+// to k_long iterations once the rate is known, but only as long as the residual is
+// predicted to stay within max_drop decades of ref_rel: the float32 recurrence
+// residual is trusted that far below the last float64 one, and fewer, longer blocks
+// mean fewer float64 replacements.
 struct BlockSizer {
   std::vector<double> rel;
   std::vector<int> iter;
   explicit BlockSizer(int R) : rel(R, 0.0), iter(R, -1) {}
-  int next(const CgState* st, int k, double tol) {
-    int need = 0;
-    bool any = false;
+  int next(const CgState* st, int k, double tol, int k_long = 0, double max_drop = 0.0,
+           const double* ref_rel = nullptr) {
+    int need = 0, cap = std::max(k, k_long);
+    bool any = false, all_rates = true;
     for (size_t r = 0; r < rel.size(); ++r) {
       const CgState& c = st[r];
       if (!c.active) continue;
       any = true;
       int est = k;
-      if (tol > 0 && iter[r] >= 0 && c.iter > iter[r] && c.rel > tol && rel[r] > c.rel && c.rel > 0) {
+      if (iter[r] >= 0 && c.iter > iter[r] && rel[r] > c.rel && c.rel > 0) {
         const double rate = std::log(c.rel / rel[r]) / (double)(c.iter - iter[r]);   // per iteration, < 0
-        est = (int)std::ceil(1.25 * std::log(tol / c.rel) / rate) + 1;
+        if (tol > 0 && c.rel > tol) est = (int)std::ceil(1.25 * std::log(tol / c.rel) / rate) + 1;
+        if (max_drop > 0 && ref_rel) {
+          const double left = max_drop * std::log(10.0) - std::log(std::max(ref_rel[r], c.rel) / c.rel);
+          cap = std::min(cap, std::max(1, (int)(left / -rate)));
+        }
+      } else {
+        all_rates = false;
       }
       need = std::max(need, est);
       rel[r] = c.rel;
       iter[r] = c.iter;
     }
-    return any ? std::max(1, std::min(k, need)) : k;
+    const int longest = (max_drop > 0 && ref_rel && all_rates) ? cap : k;
+    return any ? std::max(1, std::min(longest, need)) : k;
   }
 };
 
@@ -1278,11 +1298,13 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
   } else if (P->tmpl.empty()) {
     // Mixed precision with reliable updates (float64 residual replacement): the
     // iterate and every CG vector are float64 and H is applied in float32; at the
-    // host's check points, for each RHS whose recurrence residual fell tenfold
+    // host's check points, for each RHS whose recurrence residual fell a thousandfold
     // since its last replacement (or reached tol, or stopped), the residual is
     // replaced by the float64 true residual b - H64 x, z = M r and rho = r.z are
-    // recomputed, and CG continues along the same direction p (no restart).  The
-    // iterate with the lowest true residual is returned.
+    // recomputed, and CG continues along the same direction p (no restart).  Blocks
+    // between checks are sized (BlockSizer) so that the recurrence residual is not
+    // predicted to fall more than kMixedMaxDrop decades below the last float64 one.
+    // The iterate with the lowest true residual is returned.
     ensure_fp64_path(P, s);
     ensure_refine_vectors(P);
     for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
@@ -1371,7 +1393,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     };
     BlockSizer sizer(R);
     while (any_active() && done < n_max) {
-      const int step = std::min(sizer.next(P->st_host, k, o.tol), n_max - done);
+      const int step = std::min(sizer.next(P->st_host, k, o.tol, 2 * k, kMixedMaxDrop, last_true.data()), n_max - done);
       iterate_block(P, s, step, k, o.use_graph != 0);
       done += step;
       hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
@@ -1383,7 +1405,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
         for (int i = rep_iter[r] + 1; i <= c.iter && i <= n_max; ++i)
           hist_out[(size_t)r * (n_max + 1) + i] = hh[(size_t)r * P->hist_cap + i];
         if (c.bnorm > 0 && (c.iter > rep_iter[r] || (c.breakdown && restarted[r] != c.iter)) &&
-            (!c.active || c.rel <= o.tol || c.rel <= 0.1 * last_true[r] || done >= n_max))
+            (!c.active || c.rel <= o.tol || c.rel <= kMixedReplaceFall * last_true[r] || done >= n_max))
           rows.push_back(r);
       }
       if (!rows.empty()) replace(rows);
