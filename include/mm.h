@@ -256,10 +256,10 @@ typedef struct {
                                    thousandfold since its last replacement (or reached tol) gets
                                    its residual replaced by the float64 true residual b - H x
                                    (float64 filter) and CG continues along the same direction;
-                                   once the convergence rate is known, blocks between checks
-                                   may grow to 2 check_every iterations while the residual is
-                                   predicted to stay within 4.5 decades of the last float64
-                                   one; tol is tested on
+                                   blocks between checks are at most min(check_every, 8)
+                                   iterations until the convergence rate is known, then up to
+                                   2 check_every while the residual is predicted to stay within
+                                   4.5 decades of the last float64 one; tol is tested on
                                    those true residuals and the iterate with the lowest one is
                                    returned, so the map reaches float64 accuracy.  0 = plain
                                    mixed iterations.  Ignored with fixed_iters. */

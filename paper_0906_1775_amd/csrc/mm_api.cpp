@@ -62,6 +62,7 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 // that residual before the next check.
 constexpr double kMixedReplaceFall = 1e-3;
 constexpr double kMixedMaxDrop = 4.5;
+constexpr int kMixedFirstBlock = 8;
 
 // pinned staging slots of a plan (8 bytes each) and its dot-partial buffer
 constexpr int kPinSlots = 8;
@@ -1127,7 +1128,8 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
 // to k_long iterations once the rate is known, but only as long as the residual is
 // predicted to stay within max_drop decades of ref_rel: the float32 recurrence
 // residual is trusted that far below the last float64 one, and fewer, longer blocks
-// mean fewer float64 replacements.
+// mean fewer float64 replacements.  Until the rate is known such a block is at most
+// kMixedFirstBlock iterations.
 struct BlockSizer {
   std::vector<double> rel;
   std::vector<int> iter;
@@ -1155,7 +1157,9 @@ struct BlockSizer {
       rel[r] = c.rel;
       iter[r] = c.iter;
     }
-    const int longest = (max_drop > 0 && ref_rel && all_rates) ? cap : k;
+    // without a rate (first block, or a residual that rose) a mixed block is at most
+    // kMixedFirstBlock iterations, whatever check_every asks
+    const int longest = (max_drop > 0 && ref_rel) ? (all_rates ? cap : std::min(k, kMixedFirstBlock)) : k;
     return any ? std::max(1, std::min(longest, need)) : k;
   }
 };
