@@ -373,8 +373,9 @@ template <int NS, int G>
 __global__ __launch_bounds__(256) void k_precond_build(
     int kind, const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm,
     const float2* __restrict__ w_pm, const int64_t* __restrict__ iv_start, int n_iv,
-    const int32_t* __restrict__ iv_filter, const double* __restrict__ lags, int n_c, int64_t n_obs,
-    double* __restrict__ minv, int32_t* __restrict__ singular) {
+    const int32_t* __restrict__ iv_hint, int hint_shift, const int32_t* __restrict__ iv_filter,
+    const double* __restrict__ lags, int n_c, int64_t n_obs, double* __restrict__ minv,
+    int32_t* __restrict__ singular) {
   constexpr int NM = NS == 1 ? 1 : 6;
   constexpr int GPB = 256 / G;
   const int lane = threadIdx.x % G;
@@ -386,12 +387,9 @@ __global__ __launch_bounds__(256) void k_precond_build(
         double wgt = 1.0;
         if (kind == 0) {
           const int64_t t = perm[k];
-          int lo = 0, hi = n_iv;   // last interval with iv_start <= t
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (iv_start[mid] <= t) lo = mid; else hi = mid;
-          }
-          wgt = lags[(int64_t)iv_filter[lo] * n_c];
+          int b = iv_hint[t >> hint_shift];   // then the last interval with iv_start <= t
+          while (b + 1 < n_iv && iv_start[b + 1] <= t) ++b;
+          wgt = lags[(int64_t)iv_filter[b] * n_c];
         }
         if (NS == 1) {
           B[0] += wgt;
@@ -442,11 +440,11 @@ __global__ __launch_bounds__(256) void k_precond_build(
 template <int NS>
 static hipError_t precond_g(int group, dim3 g, hipStream_t s, int kind, const int64_t* pp,
                             const int32_t* perm, const float2* w, const int64_t* ivs, int n_iv,
-                            const int32_t* ivf, const double* lags, int n_c, int64_t n_obs,
-                            double* minv, int32_t* sing) {
+                            const int32_t* hint, int hsh, const int32_t* ivf, const double* lags, int n_c,
+                            int64_t n_obs, double* minv, int32_t* sing) {
   const dim3 b(256);
   switch (group) {
-#define MM_PCB(G) case G: hipLaunchKernelGGL((k_precond_build<NS, G>), g, b, 0, s, kind, pp, perm, w, ivs, n_iv, ivf, lags, n_c, n_obs, minv, sing); break;
+#define MM_PCB(G) case G: hipLaunchKernelGGL((k_precond_build<NS, G>), g, b, 0, s, kind, pp, perm, w, ivs, n_iv, hint, hsh, ivf, lags, n_c, n_obs, minv, sing); break;
     MM_PCB(4) MM_PCB(8) MM_PCB(16) MM_PCB(32) MM_PCB(64)
 #undef MM_PCB
     default: return hipErrorInvalidValue;
@@ -455,16 +453,18 @@ static hipError_t precond_g(int group, dim3 g, hipStream_t s, int kind, const in
 }
 
 hipError_t launch_precond_build(int ns, int kind, int group, const int64_t* pix_ptr, const int32_t* perm,
-                                const float* w_pm, const int64_t* iv_start, int n_iv,
-                                const int32_t* iv_filter, const double* lags, int n_c,
+                                const float* w_pm, const int64_t* iv_start, int n_iv, const int32_t* iv_hint,
+                                int hint_shift, const int32_t* iv_filter, const double* lags, int n_c,
                                 int64_t n_obs, double* minv, int32_t* singular, hipStream_t s) {
   if (n_obs == 0) return hipSuccess;
   int64_t nb = (n_obs * group + 255) / 256;
   if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb);
   const float2* w = (const float2*)w_pm;
-  return ns == 1 ? precond_g<1>(group, g, s, kind, pix_ptr, perm, w, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular)
-                 : precond_g<3>(group, g, s, kind, pix_ptr, perm, w, iv_start, n_iv, iv_filter, lags, n_c, n_obs, minv, singular);
+  return ns == 1 ? precond_g<1>(group, g, s, kind, pix_ptr, perm, w, iv_start, n_iv, iv_hint, hint_shift, iv_filter,
+                                 lags, n_c, n_obs, minv, singular)
+                 : precond_g<3>(group, g, s, kind, pix_ptr, perm, w, iv_start, n_iv, iv_hint, hint_shift, iv_filter,
+                                 lags, n_c, n_obs, minv, singular);
 }
 
 __global__ __launch_bounds__(256) void k_interval_dots(const double* __restrict__ u,
@@ -486,19 +486,23 @@ hipError_t launch_interval_dots(const double* u, const double* v, const int64_t*
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void k_count_nonzero(const int32_t* __restrict__ flags, int64_t n,
-                                                        double* __restrict__ out) {
-  __shared__ double sh[1024 / 64];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += flags[i] != 0 ? 1.0 : 0.0;
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[0] = s;
+// number of nonzero flags, added to *out (an exact integer count, whatever the order)
+__global__ __launch_bounds__(256) void k_count_nonzero(const int32_t* __restrict__ flags, int64_t n,
+                                                       unsigned long long* __restrict__ out) {
+  unsigned int c = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) c += flags[i] != 0 ? 1u : 0u;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c != 0) atomicAdd(out, (unsigned long long)c);
 }
 
-hipError_t launch_count_nonzero(const int32_t* flags, int64_t n, double* partial, double* out,
-                                hipStream_t s) {
-  (void)partial;
-  hipLaunchKernelGGL(k_count_nonzero, dim3(1), dim3(1024), 0, s, flags, n, out);
+hipError_t launch_count_nonzero(const int32_t* flags, int64_t n, unsigned long long* out, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), s);   // plan time only, never captured
+  if (e != hipSuccess || n == 0) return e;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_count_nonzero, dim3((unsigned)nb), dim3(256), 0, s, flags, n, out);
   return hipGetLastError();
 }
 

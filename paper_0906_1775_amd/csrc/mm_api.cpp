@@ -297,6 +297,8 @@ struct mm_plan_s {
   double* lags = nullptr;
   double* d_params = nullptr;    // [n_filters][3] (sigma, f_knee, alpha) when given
   int64_t* d_iv_start = nullptr;
+  int32_t* d_iv_hint = nullptr;   // coarse index of the interval table (build_interval_hint)
+  int iv_hint_shift = 0;
   int32_t* d_iv_filter = nullptr;
   FilterSetup fs_main, fs64;
 
@@ -405,7 +407,7 @@ struct mm_plan_s {
 int singular_count(mm_plan_s* P) {
   if (P->ev_singular) {
     hipchk(hipEventSynchronize(P->ev_singular), "preconditioner");
-    P->n_singular = (int)*P->slot<double>(kPinSingular);
+    P->n_singular = (int)*P->slot<unsigned long long>(kPinSingular);
     hipchk(hipEventDestroy(P->ev_singular), "event");
     P->ev_singular = nullptr;
   }
@@ -840,6 +842,32 @@ void setup_templates(mm_plan_s* P, const mm_desc_t* d, hipStream_t s) {
 
 // Diagonal preconditioner of the template amplitudes: diag(B^T W^-1 B)^-1
 // (block), diag(B^T B)^-1 (Jacobi) or 1; 0 for an all-zero column.
+// Coarse index of the interval table for sample -> interval lookups on the device:
+// hint[c] = the last interval starting at or before sample c << shift.  Buckets are
+// no longer than the shortest non-empty interval (while the table stays within 2^20
+// entries), so a sample lies at most a few interval starts past its bucket's hint.
+void build_interval_hint(mm_plan_s* P, hipStream_t s) {
+  int64_t lmin = std::max<int64_t>(P->n_t, 1);
+  for (int b = 0; b < P->n_iv; ++b) {
+    const int64_t len = P->iv_start[b + 1] - P->iv_start[b];
+    if (len > 0) lmin = std::min(lmin, len);
+  }
+  int sh = 0;
+  while ((int64_t(2) << sh) <= lmin) ++sh;
+  while ((P->n_t >> sh) + 1 > (int64_t(1) << 20)) ++sh;
+  const int64_t nb = (P->n_t >> sh) + 1;
+  std::vector<int32_t> hint((size_t)nb);
+  int b = 0;
+  for (int64_t c = 0; c < nb; ++c) {
+    const int64_t t0 = c << sh;
+    while (b + 1 < P->n_iv && P->iv_start[b + 1] <= t0) ++b;
+    hint[(size_t)c] = b;
+  }
+  P->iv_hint_shift = sh;
+  P->d_iv_hint = P->alloc<int32_t>(nb);
+  hipchk(hipMemcpyAsync(P->d_iv_hint, hint.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s), "copy");
+}
+
 void build_template_precond(mm_plan_s* P, hipStream_t s) {
   P->minv_t = P->alloc<double>(std::max<int64_t>(P->n_tunk, 1));
   for (Template& T : P->tmpl) {
@@ -848,7 +876,8 @@ void build_template_precond(mm_plan_s* P, hipStream_t s) {
       if (T.lay.n_obs == 0) continue;
       int32_t* sing = P->alloc<int32_t>(T.lay.n_obs);
       hipchk(launch_precond_build(1, P->precond, T.lay.group, T.lay.ptr, T.lay.perm, nullptr, P->d_iv_start,
-                                  P->n_iv, P->d_iv_filter, P->lags, P->n_c, T.lay.n_obs, dst, sing, s),
+                                  P->n_iv, P->d_iv_hint, P->iv_hint_shift, P->d_iv_filter, P->lags, P->n_c,
+                                  T.lay.n_obs, dst, sing, s),
              "template preconditioner");
       hipchk(hipStreamSynchronize(s), "template preconditioner");
       P->release(sing);
@@ -968,17 +997,19 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->d_iv_filter = P->alloc<int32_t>(P->n_iv);
   hipchk(hipMemcpyAsync(P->d_iv_start, P->iv_start.data(), 8 * (P->n_iv + 1), hipMemcpyHostToDevice, s), "copy");
   hipchk(hipMemcpyAsync(P->d_iv_filter, P->iv_filter.data(), 4 * P->n_iv, hipMemcpyHostToDevice, s), "copy");
+  build_interval_hint(P, s);
   const int nm = P->ns == 1 ? 1 : 6;
   P->minv = P->alloc<double>(P->n_obs * nm);
   {
     int32_t* sing = P->alloc<int32_t>(P->n_obs);
-    double* cnt = P->alloc<double>(1);
+    unsigned long long* cnt = P->alloc<unsigned long long>(1);
     hipchk(launch_precond_build(P->ns, P->precond, P->px.group, P->px.ptr, P->px.perm, P->px.w_pm, P->d_iv_start,
-                                P->n_iv, P->d_iv_filter, P->lags, P->n_c, P->n_obs, P->minv, sing, s),
+                                P->n_iv, P->d_iv_hint, P->iv_hint_shift, P->d_iv_filter, P->lags, P->n_c, P->n_obs,
+                                P->minv, sing, s),
            "preconditioner");
-    hipchk(launch_count_nonzero(sing, P->n_obs, nullptr, cnt, s), "singular count");
+    hipchk(launch_count_nonzero(sing, P->n_obs, cnt, s), "singular count");
     // read when first needed (plan info, end of a solve), not here: no wait in the plan build
-    hipchk(hipMemcpyAsync(P->slot<double>(kPinSingular), cnt, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipchk(hipMemcpyAsync(P->slot<unsigned long long>(kPinSingular), cnt, 8, hipMemcpyDeviceToHost, s), "copy");
     hipchk(hipEventCreateWithFlags(&P->ev_singular, hipEventDisableTiming), "event");
     hipchk(hipEventRecord(P->ev_singular, s), "event");
     P->release(sing);

@@ -165,12 +165,14 @@ hipError_t launch_interval_dots(const double* u, const double* v, const int64_t*
                                 double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- CG (k_cg.hip)
+// iv_hint[t >> hint_shift]: an interval starting at or before sample t, at most a few
+// interval starts before the one that holds t
 hipError_t launch_precond_build(int ns, int kind, int group, const int64_t* pix_ptr, const int32_t* perm,
-                                const float* w_pm, const int64_t* iv_start, int n_iv,
-                                const int32_t* iv_filter, const double* lags, int n_c,
+                                const float* w_pm, const int64_t* iv_start, int n_iv, const int32_t* iv_hint,
+                                int hint_shift, const int32_t* iv_filter, const double* lags, int n_c,
                                 int64_t n_obs, double* minv, int32_t* singular, hipStream_t s);
-hipError_t launch_count_nonzero(const int32_t* flags, int64_t n, double* partial, double* out,
-                                hipStream_t s);
+// *out = number of nonzero flags[0..n) (out is cleared first; plan time only)
+hipError_t launch_count_nonzero(const int32_t* flags, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_dot(const double* x, const double* y, int64_t nu, int n_rhs, double* partial,
                       hipStream_t s);
 hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* partial_rr,
