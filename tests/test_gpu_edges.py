@@ -108,6 +108,27 @@ def test_empty_intervals_change_nothing():
     assert rel_err(ma.cpu().numpy()[0], o.to_global(x)) <= 1e-10
 
 
+def test_many_short_intervals_with_alternating_filters():
+    """Stationary intervals of 1 to 300 samples, alternating between two noise filters:
+    the per-sample interval lookup of the preconditioner build (a coarse index plus a
+    few steps) and the per-interval filtering give the oracle's PCG iterates."""
+    p = _small(filters=((1.0, 0.4, 1.5), (2.0, 0.1, 1.2)))
+    rng = np.random.default_rng(5)
+    cuts = [0]
+    while cuts[-1] < p.pix.size:
+        cuts.append(min(p.pix.size, cuts[-1] + int(rng.integers(1, 301))))
+    iv = np.asarray(cuts, dtype=np.int64)
+    flt = (np.arange(iv.size - 1) % 2).astype(np.int32)
+    o = Oracle(p.pix, p.w, p.n_pix, 3, iv, flt, p.filter_params, p.f_samp, p.n_c, L_K=L_K)
+    from paper_0906_1775_amd import MapMaker
+    dev = torch.device("cuda:0")
+    mm = MapMaker(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.w).to(dev), p.n_pix, 3, iv, flt,
+                  filter_lags=o.lag_tab, n_c=p.n_c)
+    m, _ = mm.solve(tod_tensor(p), fixed_iters=6)
+    x, _ = o.pcg(o.rhs(p.tod[0]), fixed_iters=6)
+    assert rel_err(m.cpu().numpy()[0], o.to_global(x)) <= 1e-10
+
+
 def test_sixty_four_right_hand_sides():
     p = _small(n_stokes=1, n_rhs=64, det_lens=(1500,), seed=5)
     o = oracle_for(p, L_K)
