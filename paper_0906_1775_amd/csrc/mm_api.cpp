@@ -106,6 +106,7 @@ struct FilterSetup {
   void* ptw = nullptr;     // per-pass twiddle tables of the transform
   void* spec = nullptr;
   OlsChunk* chunks = nullptr;
+  std::vector<OlsChunk> chunks_host;   // source of the asynchronous upload of chunks, kept with the setup
   int n_chunks = 0;
 };
 
@@ -298,6 +299,7 @@ struct mm_plan_s {
   double* d_params = nullptr;    // [n_filters][3] (sigma, f_knee, alpha) when given
   int64_t* d_iv_start = nullptr;
   int32_t* d_iv_hint = nullptr;   // coarse index of the interval table (build_interval_hint)
+  std::vector<int32_t> iv_hint;   // its host copy, the source of the asynchronous upload
   int iv_hint_shift = 0;
   int32_t* d_iv_filter = nullptr;
   FilterSetup fs_main, fs64;
@@ -528,7 +530,8 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   fs.m = fs.nf - 2 * P->n_c;
   if (fs.m <= 0) fail(MM_EINVAL, "n_f must exceed 2 n_c");
 
-  std::vector<OlsChunk> ch;
+  std::vector<OlsChunk>& ch = fs.chunks_host;
+  ch.clear();
   for (int b = 0; b < P->n_iv; ++b) {
     const int64_t a = P->iv_start[b], e = P->iv_start[b + 1];
     for (int64_t o = a; o < e; o += fs.m) ch.push_back(OlsChunk{o, a, e, P->iv_filter[b], 0});
@@ -549,7 +552,7 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   fs.spec = P->alloc<char>((int64_t)P->n_filt * (fs.N + 1) * esz);
   char* sscr = P->alloc<char>((int64_t)spectra_scratch_bytes(logn));
   hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, sscr, s), "filter spectra");
-  P->release(sscr);   // later work on this stream may reuse it (the chunk upload above was staged)
+  P->release(sscr);   // later work on this stream may reuse it
   fs.ready = true;
 }
 
@@ -840,8 +843,6 @@ void setup_templates(mm_plan_s* P, const mm_desc_t* d, hipStream_t s) {
   P->n_tunk = ooff;
 }
 
-// Diagonal preconditioner of the template amplitudes: diag(B^T W^-1 B)^-1
-// (block), diag(B^T B)^-1 (Jacobi) or 1; 0 for an all-zero column.
 // Coarse index of the interval table for sample -> interval lookups on the device:
 // hint[c] = the last interval starting at or before sample c << shift.  Buckets are
 // no longer than the shortest non-empty interval (while the table stays within 2^20
@@ -856,7 +857,8 @@ void build_interval_hint(mm_plan_s* P, hipStream_t s) {
   while ((int64_t(2) << sh) <= lmin) ++sh;
   while ((P->n_t >> sh) + 1 > (int64_t(1) << 20)) ++sh;
   const int64_t nb = (P->n_t >> sh) + 1;
-  std::vector<int32_t> hint((size_t)nb);
+  std::vector<int32_t>& hint = P->iv_hint;
+  hint.assign((size_t)nb, 0);
   int b = 0;
   for (int64_t c = 0; c < nb; ++c) {
     const int64_t t0 = c << sh;
@@ -868,6 +870,8 @@ void build_interval_hint(mm_plan_s* P, hipStream_t s) {
   hipchk(hipMemcpyAsync(P->d_iv_hint, hint.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s), "copy");
 }
 
+// Diagonal preconditioner of the template amplitudes: diag(B^T W^-1 B)^-1
+// (block), diag(B^T B)^-1 (Jacobi) or 1; 0 for an all-zero column.
 void build_template_precond(mm_plan_s* P, hipStream_t s) {
   P->minv_t = P->alloc<double>(std::max<int64_t>(P->n_tunk, 1));
   for (Template& T : P->tmpl) {
