@@ -284,7 +284,6 @@ struct mm_plan_s {
   int64_t n_obs = 0, n_valid = 0;
   const float* w = nullptr;     // caller's (sin, cos) pairs, time-major
   Layout px;                    // sky pointing
-  std::vector<std::pair<int, float>> tuned;   // (n_f * kOlsVariants + shape, ms per filter pass) tried by the autotuner
 
   // templates
   std::vector<Template> tmpl;
@@ -448,7 +447,6 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
   void* yb = P->alloc<char>(std::max<int64_t>(P->n_t, 1) * esz);
   hipchk(hipMemsetAsync(ya, 0, std::max<int64_t>(P->n_t, 1) * esz, s), "memset");
   float best_ms = 0;
-  P->tuned.clear();
   for (; ilog2(nf) - 1 <= maxlog; nf <<= 1) {
     for (int v = 0; v < kOlsVariants; ++v) {
       if (!ols_variant_exists(ilog2(nf) - 1, fp64, v)) continue;
@@ -466,7 +464,6 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
       hipchk(hipEventSynchronize(e1), "autotune");
       float ms = 0;
       hipchk(hipEventElapsedTime(&ms, e0, e1), "event time");
-      P->tuned.push_back({(int)nf * kOlsVariants + v, ms / 3.0f});
       if (!fs.ready || ms < best_ms) {
         if (fs.ready) release_filter(P, fs);
         fs = cand;
