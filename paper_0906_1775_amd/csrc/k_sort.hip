@@ -4,13 +4,14 @@
 // The paper keeps three pixel index schemes (Implementation section, pixel
 // indexing) and re-indexes with binary searches every time the pointing is
 // rebuilt.  Here the pointing stays resident, so the re-indexing happens once:
-// a stable least-significant-digit radix sort (8-bit digits) orders the
+// a stable least-significant-digit radix sort (8-bit digits, or 9-bit ones where
+// they save a pass) orders the
 // samples by pixel; the first sample of each run of equal pixels opens an
 // observed pixel, which gives the observed ids, the pixel-major CSR offsets,
 // hit counts and the time-major observed index used by the gather.
 //
 // Sort tile: 256 threads x 16 rounds = 4096 keys.  Within a round, lanes of a
-// wavefront holding the same digit find each other with eight ballots; the
+// wavefront holding the same digit find each other with one ballot per digit bit; the
 // per-wave counts in LDS order the four waves; rounds run in key order, so
 // the sort is stable and every output position is computed, not raced for.
 // Each tile is ordered by digit in LDS before it is written out.
@@ -225,43 +226,57 @@ __global__ void k_sort_init(const int32_t* __restrict__ pix, int64_t n, uint32_t
   }
 }
 
+// Digit counts of one tile (digits of BITS bits at `shift`), digit-major:
+// counts[d * n_tiles + tile].
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              int64_t n, int shift, int64_t n_tiles,
                                                              uint32_t* __restrict__ counts) {
-  __shared__ uint32_t h[256];
+  constexpr int NB = 1 << BITS, PER = NB / kSortThreads;
+  __shared__ uint32_t h[NB];
   const int tid = threadIdx.x;
-  h[tid] = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) h[q * kSortThreads + tid] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
   for (int i = 0; i < kSortRounds; ++i) {
     const int64_t idx = base + (int64_t)i * kSortThreads + tid;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (NB - 1)], 1u);
   }
   __syncthreads();
-  counts[(int64_t)tid * n_tiles + blockIdx.x] = h[tid];
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    counts[(int64_t)(q * kSortThreads + tid) * n_tiles + blockIdx.x] = h[q * kSortThreads + tid];
 }
 
 // Stable scatter of one tile by digit.  Ranks are formed round by round as keys
-// come (lanes of a wavefront with the same digit find each other with eight
+// come (lanes of a wavefront with the same digit find each other with BITS
 // ballots; per-wave counts order the four waves; a running count per digit
 // carries over rounds), then the tile is placed in LDS in (digit, rank) order
 // and written out in that order, so each digit's keys leave as one contiguous
 // run at offsets[digit][tile] instead of one scattered word per key.
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n, int shift,
     int64_t n_tiles, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
     int32_t* __restrict__ vals_out) {
+  constexpr int NB = 1 << BITS, PER = NB / kSortThreads;   // digits per thread in the per-digit loops
   __shared__ uint32_t s_key[kSortTile];
   __shared__ int32_t s_val[kSortTile];
-  __shared__ uint32_t gbase[256];                   // output offset of this tile's digit d
-  __shared__ uint32_t lcnt[256];                    // keys of digit d seen so far in the tile
-  __shared__ uint32_t lstart[256];                  // first LDS slot of digit d
-  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  __shared__ uint32_t gbase[NB];                    // output offset of this tile's digit d
+  __shared__ uint32_t lcnt[NB];                     // keys of digit d seen so far in the tile
+  __shared__ uint32_t lstart[NB];                   // first LDS slot of digit d
+  __shared__ uint32_t wcnt[kSortThreads / 64][NB];
+  __shared__ uint32_t tsum[kSortThreads];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  gbase[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
-  lcnt[tid] = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int d = q * kSortThreads + tid;
+    gbase[d] = offsets[(int64_t)d * n_tiles + blockIdx.x];
+    lcnt[d] = 0;
+  }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
   const int n_here = (int)((n - tile0) < kSortTile ? (n - tile0) : kSortTile);
@@ -270,16 +285,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 #pragma unroll
   for (int i = 0; i < kSortRounds; ++i) {
 #pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w)
+#pragma unroll
+      for (int q = 0; q < PER; ++q) wcnt[w][q * kSortThreads + tid] = 0;
     __syncthreads();
     const int j = i * kSortThreads + tid;
     const bool valid = j < n_here;
     key[i] = valid ? keys_in[tile0 + j] : 0u;
     val[i] = valid ? vals_in[tile0 + j] : 0;
-    const uint32_t d = (key[i] >> shift) & 255u;
+    const uint32_t d = (key[i] >> shift) & (NB - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -291,33 +308,45 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int w = 0; w < wave; ++w) r += wcnt[w][d];
     rk[i] = r;
     __syncthreads();
-    uint32_t add = 0;
 #pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][tid];
-    lcnt[tid] += add;
+    for (int q = 0; q < PER; ++q) {
+      uint32_t add = 0;
+#pragma unroll
+      for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][q * kSortThreads + tid];
+      lcnt[q * kSortThreads + tid] += add;
+    }
   }
   __syncthreads();
-  // exclusive scan of the tile's digit counts (256 entries, one per thread)
+  // exclusive scan of the tile's NB digit counts: thread tid owns the PER consecutive
+  // digits tid * PER ..; a scan of the 256 thread sums orders them
   {
-    uint32_t v = lcnt[tid];
-    lstart[tid] = v;
+    uint32_t c[PER], tot = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      c[q] = lcnt[tid * PER + q];
+      tot += c[q];
+    }
+    tsum[tid] = tot;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const uint32_t x = tid >= off ? lstart[tid - off] : 0u;
+    for (int off = 1; off < kSortThreads; off <<= 1) {
+      const uint32_t x = tid >= off ? tsum[tid - off] : 0u;
       __syncthreads();
-      lstart[tid] += x;
+      tsum[tid] += x;
       __syncthreads();
     }
-    const uint32_t incl = lstart[tid];
-    __syncthreads();
-    lstart[tid] = incl - v;
+    uint32_t run = tsum[tid] - tot;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      lstart[tid * PER + q] = run;
+      run += c[q];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortRounds; ++i) {
     const int j = i * kSortThreads + tid;
     if (j < n_here) {
-      const uint32_t pos = lstart[(key[i] >> shift) & 255u] + rk[i];
+      const uint32_t pos = lstart[(key[i] >> shift) & (NB - 1)] + rk[i];
       s_key[pos] = key[i];
       s_val[pos] = val[i];
     }
@@ -328,7 +357,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int j = i * kSortThreads + tid;
     if (j < n_here) {
       const uint32_t k = s_key[j];
-      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t d = (k >> shift) & (NB - 1);
       const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
       keys_out[pos] = k;
       vals_out[pos] = s_val[j];
@@ -336,9 +365,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
 }
 
+// widest digit of a pass (9-bit digits are used where they save a pass)
+constexpr int kSortMaxBits = 9;
+
 size_t sort_scratch_bytes(int64_t n) {
   const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
-  const int64_t m = 256 * n_tiles;
+  const int64_t m = (int64_t(1) << kSortMaxBits) * n_tiles;
   return (size_t)n * 8 * 2                      // two key/value buffers
          + (size_t)m * sizeof(uint32_t)          // digit counts / offsets
          + scan_scratch_bytes(m) + 256;
@@ -348,19 +380,25 @@ hipError_t launch_sort_by_pixel(const int32_t* pix, int64_t n, int64_t n_pix, ui
                                 int32_t* vals_out, void* scratch, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
-  const int64_t m = 256 * n_tiles;
   char* p = (char*)scratch;
   uint32_t* ka = (uint32_t*)p; p += (size_t)n * 4;
   int32_t* va = (int32_t*)p;   p += (size_t)n * 4;
   uint32_t* kb = (uint32_t*)p; p += (size_t)n * 4;
   int32_t* vb = (int32_t*)p;   p += (size_t)n * 4;
-  uint32_t* counts = (uint32_t*)p; p += (size_t)m * 4;
+  uint32_t* counts = (uint32_t*)p; p += (size_t)((int64_t(1) << kSortMaxBits) * n_tiles) * 4;
   uint32_t* scan_tmp = (uint32_t*)p;
 
   int bits = 0;
   while (bits < 32 && (((uint64_t)n_pix) >> bits) != 0) ++bits;   // keys lie in [0, n_pix]
+  // 8-bit digits, or 9-bit ones where they save a pass of up to three (keys of 9, 17 or
+  // 18 bits: the pass they save sorts one or two bits).  A tile of 4,096 keys spread
+  // over 512 digits leaves in runs of 8 keys, half the write runs of 256 digits, so
+  // for wider keys (a 2^30-sample, 26-bit sort: 3 x 9 bits took 104 ms against 96 ms
+  // for 4 x 8) the fourth 8-bit pass is the cheaper choice.
   int passes = (bits + 7) / 8;
   if (passes == 0) passes = 1;
+  const int dbits = (passes > 1 && passes <= 3 && (passes - 1) * kSortMaxBits >= bits) ? kSortMaxBits : 8;
+  if (dbits == kSortMaxBits) passes -= 1;
 
   hipLaunchKernelGGL(k_sort_init, grid_for(n), dim3(256), 0, s, pix, n, (uint32_t)n_pix, ka, va);
   hipError_t e = hipGetLastError();
@@ -368,16 +406,25 @@ hipError_t launch_sort_by_pixel(const int32_t* pix, int64_t n, int64_t n_pix, ui
   uint32_t *kin = ka, *kout = kb;
   int32_t *vin = va, *vout = vb;
   for (int ps = 0; ps < passes; ++ps) {
-    const int shift = 8 * ps;
+    const int shift = dbits * ps;
     const bool last = ps == passes - 1;
     uint32_t* ko = last ? keys_out : kout;
     int32_t* vo = last ? vals_out : vout;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin, n,
-                       shift, n_tiles, counts);
+    const int64_t m = (int64_t(1) << dbits) * n_tiles;
+    if (dbits == 8)
+      hipLaunchKernelGGL(k_radix_hist<8>, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin, n, shift, n_tiles,
+                         counts);
+    else
+      hipLaunchKernelGGL(k_radix_hist<kSortMaxBits>, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin, n, shift,
+                         n_tiles, counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_impl(counts, counts, m, scan_tmp, 1, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin,
-                       vin, n, shift, n_tiles, counts, ko, vo);
+    if (dbits == 8)
+      hipLaunchKernelGGL(k_radix_scatter<8>, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin, vin, n, shift,
+                         n_tiles, counts, ko, vo);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<kSortMaxBits>, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, kin, vin, n,
+                         shift, n_tiles, counts, ko, vo);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     uint32_t* tk = kin; kin = kout; kout = tk;
     int32_t* tv = vin; vin = vout; vout = tv;
