@@ -196,16 +196,30 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_sell_fill(
     const int64_t my_k0 = o < n_obs ? pix_ptr[o] : 0;
     const int my_cnt = o < n_obs ? (int)(pix_ptr[o + 1] - my_k0) : 0;
     for (int j0 = wv * kFillRows; j0 < width; j0 += kFillWaves * kFillRows) {   // uniform per wavefront
-      // stage 1: pixel L = 4 q + sub, row j0 + jj
-#pragma unroll 4
-      for (int q = 0; q < 64 / (64 / kFillRows); ++q) {
+      // stage 1: pixel L = 4 q + sub, row j0 + jj; every load of the tile is issued
+      // before the first LDS store (a slot past its pixel's hits re-reads the pixel's
+      // first entry and is not stored), so they are all in flight together
+      constexpr int NQ = 64 / (64 / kFillRows);
+      int32_t tv[NQ];
+      float2 wv2[NQ];
+      bool in[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
         const int L = q * (64 / kFillRows) + sub;
         const int64_t k0 = __shfl(my_k0, L, 64);
         const int cnt = __shfl(my_cnt, L, 64);
         const int j = j0 + jj;
-        if (j < cnt) {
-          s_t[wv][L][jj] = perm[k0 + j];
-          if (ns == 3) s_w[wv][L][jj] = w_pm[k0 + j];
+        in[q] = j < cnt;
+        const int64_t k = in[q] ? k0 + j : k0;
+        tv[q] = cnt > 0 ? perm[k] : 0;
+        if (ns == 3) wv2[q] = cnt > 0 ? w_pm[k] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int L = q * (64 / kFillRows) + sub;
+        if (in[q]) {
+          s_t[wv][L][jj] = tv[q];
+          if (ns == 3) s_w[wv][L][jj] = wv2[q];
         }
       }
       __builtin_amdgcn_wave_barrier();
