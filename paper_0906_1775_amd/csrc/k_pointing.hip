@@ -6,10 +6,10 @@
 // samples are zero.
 //
 // Gather streams the time-ordered pointing (observed pixel id, sin/cos pair)
-// coalesced and reads the map through the caches.  Scatter walks a sliced,
-// pixel-major copy of the pointing built by the plan: one lane (of each of
-// the slice's wavefronts) owns one pixel, so every pixel sum is formed in a
-// fixed order and no atomics are needed.  The scatter can also return
+// coalesced and reads the map through the caches.  Scatter walks the
+// pixel-major pointing built by the plan (as it is, a group of lanes per pixel,
+// for pixels with many hits; else a sliced copy, one lane per pixel), so every
+// pixel sum is formed in a fixed order and no atomics are needed.  The scatter can also return
 // the per-block partial sums of p.q for the CG step length.  Maps are float64
 // rows [R][vs] whose first n_obs * ns values are the observed pixels (the rest
 // of a row holds template amplitudes).
@@ -390,20 +390,150 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
   }
 }
 
+// q = P^T y over the plain pixel-major layout: a wavefront takes 64 / kSegLanes
+// pixels at a time, kSegLanes lanes per pixel reading consecutive hits, which
+// for a raster scan are runs of consecutive TOD samples, so each TOD load
+// touches a few cache lines (the sliced layout reads the j-th hit of 64
+// different pixels, one dwell apart in time).  For pixels with hundreds of
+// hits, where the lanes stay busy.  Each lane sums its hits in order, then the
+// lanes of a pixel are combined by a fixed butterfly in float64, so every
+// (pixel, RHS) sum has a fixed order.
+constexpr int kSegLanes = 16;
+constexpr int kSegBatch = 4;   // loads in flight per lane
+template <typename Ty, int NS, int RG>
+__global__ __launch_bounds__(64 * kBlockWaves) void k_scatter_seg(
+    const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm, const float2* __restrict__ w_pm,
+    const Ty* __restrict__ y, double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs,
+    const double* __restrict__ p, double* __restrict__ pq_part, int pq_stride, int pq_slot,
+    const CgState* __restrict__ st) {
+  constexpr int NW = kBlockWaves, G = kSegLanes, PPW = 64 / G;
+  __shared__ double sh[NW][RG];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int gl = lane % G;   // lane within its pixel's group
+  for (int r0 = 0; r0 < n_rhs; r0 += RG) {
+    bool act[RG];
+    bool any = false;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      act[g] = r0 + g < n_rhs && !(st && !st[r0 + g].active);   // RHS that stopped iterating are skipped
+      any = any || act[g];
+    }
+    if (!any) continue;                    // uniform over the block
+    double pq[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) pq[g] = 0.0;
+    for (int64_t o0 = ((int64_t)blockIdx.x * NW + wv) * PPW; o0 < n_obs; o0 += (int64_t)gridDim.x * NW * PPW) {
+      const int64_t o = o0 + lane / G;
+      const bool ov = o < n_obs;
+      const int64_t k0 = ov ? pix_ptr[o] : 0, k1 = ov ? pix_ptr[o + 1] : 0;   // k1 > k0 for an observed pixel
+      int span = (int)(k1 - k0);            // the wavefront walks its longest pixel
+#pragma unroll
+      for (int off = G; off < 64; off <<= 1) span = max(span, __shfl_xor(span, off, 64));
+      Acc<Ty> a[RG][NS];
+      for (int64_t j0 = 0; j0 < span; j0 += G * kSegBatch) {
+        // loads issued unconditionally (a slot past the pixel's hits re-reads its
+        // last one; a lane past the last pixel reads entry 0) and masked afterwards
+        int32_t tt[kSegBatch];
+        float2 ww[kSegBatch];
+#pragma unroll
+        for (int b = 0; b < kSegBatch; ++b) {
+          const int64_t k = k0 + j0 + b * G + gl;
+          const bool in = k < k1;
+          const int64_t kk = in ? k : (k1 > 0 ? k1 - 1 : 0);
+          const int32_t tv = __builtin_nontemporal_load(perm + kk);
+          tt[b] = in ? tv : -1;
+          if (NS == 3) ww[b] = load_nt(w_pm + kk);
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          if (!act[g]) continue;
+          const Ty* __restrict__ yr = y + (int64_t)(r0 + g) * n_t;
+          Ty vv[kSegBatch];
+#pragma unroll
+          for (int b = 0; b < kSegBatch; ++b) {
+            const Ty yv = yr[tt[b] >= 0 ? tt[b] : 0];
+            vv[b] = tt[b] >= 0 ? yv : (Ty)0;
+          }
+#pragma unroll
+          for (int b = 0; b < kSegBatch; ++b) {
+            if (tt[b] < 0) continue;
+            if (NS == 1) {
+              a[g][0].add(vv[b]);
+            } else {
+              const Ty h = (Ty)0.5 * vv[b];
+              a[g][0].add(h);
+              a[g][1].add(h * (Ty)ww[b].x);
+              a[g][2].add(h * (Ty)ww[b].y);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        if (!act[g]) continue;
+        const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+          double v = a[g][c].value();
+#pragma unroll
+          for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);   // same sum on the group's lanes
+          if (ov && gl == c) q[i + c] = v;
+          if (p && ov && gl == 0) pq[g] += p[i + c] * v;
+        }
+      }
+    }
+    if (p) {   // block sums of the p.q contributions, fixed order
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        double v = pq[g];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sh[wv][g] = v;
+      }
+      __syncthreads();
+      if (tid < RG && act[tid]) {
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += sh[w][tid];
+        pq_part[(int64_t)(r0 + tid) * pq_stride + pq_slot + blockIdx.x] = sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 int scatter_blocks(int64_t n_obs, int wps) {
+  if (wps == 0) {
+    const int64_t ppb = (int64_t)kBlockWaves * (64 / kSegLanes);   // pixels per block and step
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n_obs + ppb - 1) / ppb, kScatterBlocks));
+  }
   const int64_t n_sl = (n_obs + 63) / 64;
   const int64_t spb = kBlockWaves / std::max(1, wps);
   return (int)std::max<int64_t>(1, std::min<int64_t>((n_sl + spb - 1) / spb, kScatterBlocks));
 }
 
 // wavefronts per slice for a layout whose pixels have `avg` entries on average
-int scatter_waves_per_slice(double avg) { return avg >= 128 ? 8 : avg >= 64 ? 4 : avg >= 32 ? 2 : 1; }
+int scatter_waves_per_slice(double avg) { return avg >= 128 ? 0 : avg >= 64 ? 4 : avg >= 32 ? 2 : 1; }
 
 hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
                           double* pq_part, int pq_stride, int pq_slot, const CgState* st) {
   if (n_obs == 0) return hipSuccess;
   const dim3 g((unsigned)scatter_blocks(n_obs, L.wps)), b(64 * kBlockWaves);
+  if (L.wps == 0) {
+    const float2* w = (const float2*)L.w_pm;
+#define MM_SG(T, NS, RG) hipLaunchKernelGGL((k_scatter_seg<T, NS, RG>), g, b, 0, s, L.ptr, L.perm, w, (const T*)y, q, \
+                                            vs, n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot, st)
+    if (in_f64) {
+      if (ns == 1) { if (n_rhs == 1) MM_SG(double, 1, 1); else MM_SG(double, 1, 4); }
+      else { if (n_rhs == 1) MM_SG(double, 3, 1); else MM_SG(double, 3, 4); }
+    } else {
+      if (ns == 1) { if (n_rhs == 1) MM_SG(float, 1, 1); else MM_SG(float, 1, 4); }
+      else { if (n_rhs == 1) MM_SG(float, 3, 1); else MM_SG(float, 3, 4); }
+    }
+#undef MM_SG
+    return hipGetLastError();
+  }
   const float2* w = (const float2*)L.w;
 #define MM_SC(T, NS, RG, WPS) hipLaunchKernelGGL((k_scatter<T, NS, RG, WPS>), g, b, 0, s, L.end, L.len, L.t, w, \
                                                  (const T*)y, q, vs, n_obs, n_t, n_rhs, p, pq_part, pq_stride, \

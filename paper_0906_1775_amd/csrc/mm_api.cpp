@@ -732,6 +732,15 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
 
 // Sliced copy of a layout for the scatter; the plain pixel-major copy is dropped.
 void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
+  const int wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
+  if (wps == 0) {   // pixels with many hits: the scatter reads the pixel-major arrays as they are
+    L.sell_entries = L.n_valid;
+    L.sell.wps = 0;
+    L.sell.ptr = L.ptr;
+    L.sell.perm = L.perm;
+    L.sell.w_pm = L.w_pm;
+    return;
+  }
   const int64_t n_sl = (L.n_obs + 63) / 64;
   uint32_t* len = P->alloc<uint32_t>(n_sl);
   uint32_t* end = P->alloc<uint32_t>(n_sl);
@@ -764,7 +773,7 @@ void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
   L.sell.len = len;
   L.sell.t = st;
   L.sell.w = sw;
-  L.sell.wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
+  L.sell.wps = wps;
   P->release(L.perm);
   L.perm = nullptr;
   P->release(L.w_pm);
@@ -1018,7 +1027,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   }
   build_template_precond(P, s);
 
-  // ---- sliced pointing for the scatters; the plain pixel-major copies are then dropped
+  // ---- scatter layouts: the pixel-major arrays as they are, or a sliced copy that replaces them
   build_sell(P, P->px, P->ns, s);
   for (Template& T : P->tmpl)
     if (T.kind == MM_TMPL_ONEHOT) build_sell(P, T.lay, 1, s);

@@ -102,7 +102,11 @@ struct SellLayout {
   const uint32_t* len = nullptr;   // [n_slices] entries of each slice (64 x its widest pixel)
   const int32_t* t = nullptr;      // sample index per entry, -1 = padding
   const float* w = nullptr;        // (sin, cos) per entry (polarisation only)
-  int wps = 8;                     // wavefronts per slice in the scatter (1, 2, 4 or 8)
+  int wps = 8;                     // wavefronts per slice in the scatter (1, 2, 4 or 8); 0 = no
+                                   // slices: one wavefront per pixel over the pixel-major arrays
+  const int64_t* ptr = nullptr;    // pixel-major layout (wps = 0): [n_obs + 1] offsets,
+  const int32_t* perm = nullptr;   // [n_valid] sample ids
+  const float* w_pm = nullptr;     // [n_valid][2] (sin, cos) (polarisation only)
 };
 hipError_t launch_sell_widths(const int64_t* pix_ptr, int64_t n_obs, uint32_t* slice_len, hipStream_t s);
 hipError_t launch_sell_fill(const int64_t* pix_ptr, const int32_t* perm, const float* w_pm, int64_t n_obs,
@@ -117,7 +121,7 @@ hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* 
                           int pq_slot = 0, const CgState* st = nullptr);
 // blocks (= p.q partial sums) of a scatter over n_obs pixels with wps wavefronts per slice
 int scatter_blocks(int64_t n_obs, int wps);
-int scatter_waves_per_slice(double avg_entries_per_pixel);
+int scatter_waves_per_slice(double avg_entries_per_pixel);   // 0: pixel-major, no slices
 hipError_t launch_convert(bool in_f64, bool out_f64, const void* in, void* out, int64_t n,
                           hipStream_t s);
 // observed <-> global layout of n_rhs rows (strides obs_stride, glob_stride in doubles)

@@ -99,6 +99,29 @@ def test_unpoint_and_point(which, dtype, T, TQU):
     assert max_rel(xm[0], ref) < (1e-13 if dtype == torch.float64 else 1e-6)
 
 
+# 24,000 TQU samples on grids of 144, 256, 576 and 2304 pixels: about 167, 94, 42 and
+# 10 hits per observed pixel, so the scatter reads the plain pixel-major layout
+# (128 or more on average) and the sliced one with 4, 2 and 1 wavefronts per slice
+@pytest.mark.parametrize("grid", [(12, 12), (16, 16), (24, 24), (48, 48)])
+@pytest.mark.parametrize("n_rhs", [1, 3])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_point_on_every_scatter_layout(grid, n_rhs, dtype):
+    p = with_excised(synth.make_custom(
+        3, grid=grid, det_lens=(9000, 7000, 5000, 3000),
+        interval_lens=[[4000, 5000], [7000], [1, 2, 997, 4000], [3000]],
+        filters=((1.0, 0.3, 1.6),), n_c=100, f_samp=20.0, n_rhs=n_rhs, seed=33))
+    o = oracle_for(p, L_K)
+    mm = plan_for(p, lag_dft_len=L_K)
+    info = mm.info()
+    assert (info["n_sliced"] == info["n_valid"]) == (info["n_valid"] >= 128 * info["n_obs"])
+    yy = np.random.default_rng(12).standard_normal((n_rhs, p.n_samples))
+    yt = torch.from_numpy(yy).to(dtype).cuda()
+    xm = mm.point(yt).cpu().numpy()
+    for r in range(n_rhs):
+        ref = o.to_global(o.apply_At(yt[r].cpu().double().numpy()))
+        assert max_rel(xm[r], ref) < (1e-13 if dtype == torch.float64 else 1e-6)
+
+
 @pytest.mark.parametrize("which", ["T", "TQU"])
 @pytest.mark.parametrize("n_f", [0, 256, 512, 2048])
 def test_weight_fp64(which, n_f, T, TQU):

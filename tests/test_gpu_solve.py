@@ -90,11 +90,15 @@ def test_converged_mixed(which, refine, T, TQU, C1):
         assert err <= 1e-5
 
 
-def test_sliced_layout_covers_every_sample(TQU):
-    p, _ = TQU
-    info = plan_for(p, lag_dft_len=L_K).info()
-    assert info["n_sliced"] >= info["n_valid"]
-    assert info["n_sliced"] % 64 == 0
+def test_scatter_layout_covers_every_sample(TQU, C1):
+    # TQU: about 167 hits per pixel, the plain pixel-major layout; C1: 64, sliced
+    for p, _ in (TQU, C1):
+        info = plan_for(p, lag_dft_len=L_K if p is TQU[0] else 0).info()
+        if info["n_valid"] >= 128 * info["n_obs"]:
+            assert info["n_sliced"] == info["n_valid"]
+        else:
+            assert info["n_sliced"] >= info["n_valid"]
+            assert info["n_sliced"] % 64 == 0
 
 
 def test_mixed_refine_multi_rhs(T):
