@@ -395,7 +395,9 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
 // for a raster scan are runs of consecutive TOD samples, so each TOD load
 // touches a few cache lines (the sliced layout reads the j-th hit of 64
 // different pixels, one dwell apart in time).  For pixels with hundreds of
-// hits, where the lanes stay busy.  Each lane sums its hits in order, then the
+// hits, where the lanes stay busy, and a TOD small enough for the last-level
+// cache (neighbouring pixels' hits share TOD lines that this layout reads from
+// different wavefronts).  Each lane sums its hits in order, then the
 // lanes of a pixel are combined by a fixed butterfly in float64, so every
 // (pixel, RHS) sum has a fixed order.
 constexpr int kSegLanes = 16;
@@ -513,6 +515,7 @@ int scatter_blocks(int64_t n_obs, int wps) {
 }
 
 // wavefronts per slice for a layout whose pixels have `avg` entries on average
+// (the plan may still choose 8 wavefronts per slice over 0 for a large TOD)
 int scatter_waves_per_slice(double avg) { return avg >= 128 ? 0 : avg >= 64 ? 4 : avg >= 32 ? 2 : 1; }
 
 hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,

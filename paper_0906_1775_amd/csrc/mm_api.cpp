@@ -731,8 +731,18 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
 }
 
 // Sliced copy of a layout for the scatter; the plain pixel-major copy is dropped.
+// Largest TOD one scatter pass reads (rows of up to 4 RHS) for which the pixel-major
+// scatter is used.  A TOD cache line holds hits of several neighbouring pixels,
+// which that scatter reads from different wavefronts (the sliced one from one):
+// measured faster while those re-reads stay in the 256 MiB last-level cache
+// (64 MiB of float32 TOD: 7 % less time per iteration) and slower beyond it
+// (1 GiB: 5 % more).
+constexpr int64_t kSegTodBytes = int64_t(128) << 20;
+
 void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
-  const int wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
+  int wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
+  const int64_t pass_bytes = P->n_t * (P->main_fp64() ? 8 : 4) * std::min(P->R, 4);
+  if (wps == 0 && pass_bytes > kSegTodBytes) wps = 8;
   if (wps == 0) {   // pixels with many hits: the scatter reads the pixel-major arrays as they are
     L.sell_entries = L.n_valid;
     L.sell.wps = 0;

@@ -101,7 +101,8 @@ def test_unpoint_and_point(which, dtype, T, TQU):
 
 # 24,000 TQU samples on grids of 144, 256, 576 and 2304 pixels: about 167, 94, 42 and
 # 10 hits per observed pixel, so the scatter reads the plain pixel-major layout
-# (128 or more on average) and the sliced one with 4, 2 and 1 wavefronts per slice
+# (128 or more on average; a TOD this small is far below the plan's size bound for it)
+# and the sliced one with 4, 2 and 1 wavefronts per slice
 @pytest.mark.parametrize("grid", [(12, 12), (16, 16), (24, 24), (48, 48)])
 @pytest.mark.parametrize("n_rhs", [1, 3])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
