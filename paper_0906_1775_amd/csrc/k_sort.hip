@@ -250,33 +250,38 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
     counts[(int64_t)(q * kSortThreads + tid) * n_tiles + blockIdx.x] = h[q * kSortThreads + tid];
 }
 
-// Stable scatter of one tile by digit.  Ranks are formed round by round as keys
-// come (lanes of a wavefront with the same digit find each other with BITS
-// ballots; per-wave counts order the four waves; a running count per digit
-// carries over rounds), then the tile is placed in LDS in (digit, rank) order
-// and written out in that order, so each digit's keys leave as one contiguous
-// run at offsets[digit][tile] instead of one scattered word per key.
+// Stable scatter of one tile by digit.  Each wavefront ranks its own quarter
+// of the tile (keys in tile order, 64 per round) against running per-digit
+// counts that only it touches, so the rounds need no block barrier: lanes with
+// the same digit find each other with BITS ballots.  The per-wave counts then
+// give each wave its offset within every digit, the tile is placed in LDS in
+// (digit, rank) order and written out in that order, so each digit's keys
+// leave as one contiguous run at offsets[digit][tile] instead of one scattered
+// word per key.
 template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n, int shift,
     int64_t n_tiles, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
     int32_t* __restrict__ vals_out) {
   constexpr int NB = 1 << BITS, PER = NB / kSortThreads;   // digits per thread in the per-digit loops
+  constexpr int NW = kSortThreads / 64, KPW = kSortTile / NW;   // wavefronts, keys per wavefront
   __shared__ uint32_t s_key[kSortTile];
   __shared__ int32_t s_val[kSortTile];
   __shared__ uint32_t gbase[NB];                    // output offset of this tile's digit d
-  __shared__ uint32_t lcnt[NB];                     // keys of digit d seen so far in the tile
   __shared__ uint32_t lstart[NB];                   // first LDS slot of digit d
-  __shared__ uint32_t wcnt[kSortThreads / 64][NB];
-  __shared__ uint32_t tsum[kSortThreads];
+  __shared__ uint32_t wcnt[NW][NB];                 // keys of digit d in wave w's quarter, then the
+                                                    // keys of digit d in the quarters before it
+  __shared__ uint32_t tsum[NW];                     // wave totals of the digit scan
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int d = q * kSortThreads + tid;
     gbase[d] = offsets[(int64_t)d * n_tiles + blockIdx.x];
-    lcnt[d] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][d] = 0;
   }
+  __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
   const int n_here = (int)((n - tile0) < kSortTile ? (n - tile0) : kSortTile);
@@ -284,15 +289,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   int32_t val[kSortRounds];
 #pragma unroll
   for (int i = 0; i < kSortRounds; ++i) {
-#pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w)
-#pragma unroll
-      for (int q = 0; q < PER; ++q) wcnt[w][q * kSortThreads + tid] = 0;
-    __syncthreads();
-    const int j = i * kSortThreads + tid;
+    const int j = wave * KPW + i * 64 + lane;
     const bool valid = j < n_here;
     key[i] = valid ? keys_in[tile0 + j] : 0u;
     val[i] = valid ? vals_in[tile0 + j] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < kSortRounds; ++i) {
+    const int j = wave * KPW + i * 64 + lane;
+    const bool valid = j < n_here;
     const uint32_t d = (key[i] >> shift) & (NB - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -302,39 +307,45 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       peers &= bit ? m : ~m;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    uint32_t r = lcnt[d] + rank;
-    for (int w = 0; w < wave; ++w) r += wcnt[w][d];
-    rk[i] = r;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      uint32_t add = 0;
-#pragma unroll
-      for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][q * kSortThreads + tid];
-      lcnt[q * kSortThreads + tid] += add;
-    }
+    const uint32_t before = wcnt[wave][d];
+    rk[i] = before + rank;
+    // every lane has read its count before the digit's first lane writes the new one
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
-  // exclusive scan of the tile's NB digit counts: thread tid owns the PER consecutive
-  // digits tid * PER ..; a scan of the 256 thread sums orders them
+  // per digit: the waves' counts become offsets within the digit; exclusive scan of
+  // the tile's NB digit totals: thread tid owns the PER consecutive digits tid * PER ..;
+  // a scan of the 256 thread sums (within each wavefront, then across the four) orders them
   {
     uint32_t c[PER], tot = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      c[q] = lcnt[tid * PER + q];
-      tot += c[q];
+      const int d = tid * PER + q;
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t x = wcnt[w][d];
+        wcnt[w][d] = run;
+        run += x;
+      }
+      c[q] = run;
+      tot += run;
     }
-    tsum[tid] = tot;
+    // inclusive scan of the thread sums within the wavefront, then the wave totals
+    uint32_t incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    if (lane == 63) tsum[wave] = incl;
     __syncthreads();
-    for (int off = 1; off < kSortThreads; off <<= 1) {
-      const uint32_t x = tid >= off ? tsum[tid - off] : 0u;
-      __syncthreads();
-      tsum[tid] += x;
-      __syncthreads();
-    }
-    uint32_t run = tsum[tid] - tot;
+    uint32_t run = incl - tot;
+    for (int w = 0; w < wave; ++w) run += tsum[w];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       lstart[tid * PER + q] = run;
@@ -344,9 +355,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kSortRounds; ++i) {
-    const int j = i * kSortThreads + tid;
+    const int j = wave * KPW + i * 64 + lane;
     if (j < n_here) {
-      const uint32_t pos = lstart[(key[i] >> shift) & (NB - 1)] + rk[i];
+      const uint32_t d = (key[i] >> shift) & (NB - 1);
+      const uint32_t pos = lstart[d] + wcnt[wave][d] + rk[i];
       s_key[pos] = key[i];
       s_val[pos] = val[i];
     }
