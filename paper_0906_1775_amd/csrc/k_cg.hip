@@ -125,9 +125,9 @@ template <int NS, int RG>
 __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     double* __restrict__ x, const double* __restrict__ p, double* __restrict__ rv,
     const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ minv,
-    CgState* __restrict__ st, int64_t n_obs, int64_t vs, const double* __restrict__ minv_t, int64_t n_tail,
-    int n_rhs, const double* __restrict__ pq_part, int n_pq, double* __restrict__ prz,
-    double* __restrict__ prr) {
+    CgState* __restrict__ st, CgState* __restrict__ st_prev, int64_t n_obs, int64_t vs,
+    const double* __restrict__ minv_t, int64_t n_tail, int n_rhs, const double* __restrict__ pq_part, int n_pq,
+    double* __restrict__ prz, double* __restrict__ prr) {
   __shared__ double sh[kDotThreads / 64];
   __shared__ double s_alpha[RG];
   constexpr int NM = NS == 1 ? 1 : 6;
@@ -156,8 +156,12 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
       }
       s_alpha[g] = al;
       if (blockIdx.x == 0) {
+        CgState v = st[r];
+        v.alpha = al;
+        v.breakdown = brk ? 1 : 0;
         st[r].alpha = al;            // read by no other block of this kernel
-        st[r].breakdown = brk ? 1 : 0;
+        st[r].breakdown = v.breakdown;
+        st_prev[r] = v;              // the state before the step, for the scalar step that follows
       }
     }
     __syncthreads();
@@ -220,14 +224,14 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
 }
 
 hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
-                            double* z, const double* minv, CgState* st, int64_t n_obs,
+                            double* z, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s) {
   const dim3 b(kDotThreads);
 #define MM_UPD(NS, RG)                                                                                     \
   hipLaunchKernelGGL((k_cg_update<NS, RG>), dim3(kDotBlocks, (n_rhs + RG - 1) / RG), b, 0, s, x, p, r, q, z, \
-                     minv, st, n_obs, vs, minv_t, n_tail, n_rhs, pq_part, n_pq, partial_rz, partial_rr)
+                     minv, st, st_prev, n_obs, vs, minv_t, n_tail, n_rhs, pq_part, n_pq, partial_rz, partial_rr)
   if (n_rhs == 1) {
     if (ns == 1) MM_UPD(1, 1); else MM_UPD(3, 1);
   } else {
@@ -237,23 +241,17 @@ hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const
   return hipGetLastError();
 }
 
-__global__ void k_cg_finalize(CgState* st, const double* __restrict__ prz,
-                              const double* __restrict__ prr, double* __restrict__ history,
-                              int hist_stride) {
-  const int r = blockIdx.x;
-  const double rz = fold_partials(prz, r);
-  const double rr = fold_partials(prr, r);
-  if (threadIdx.x != 0) return;
-  CgState s = st[r];
-  if (!s.active || s.breakdown) {   // stopped, or p.q <= 0: no step was taken
+// The scalar step of RHS s after an update: iteration count, relative residual,
+// best iterate, convergence, beta and rho from the folded r.z and r.r.  Returns
+// false when no step was taken (stopped, or p.q <= 0).
+__device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr) {
+  if (!s.active || s.breakdown) {
     s.copy_best = 0;
     s.active = 0;
-    st[r] = s;
-    return;
+    return false;
   }
   s.iter += 1;
   s.rel = sqrt(rr) / s.bnorm;
-  if (history) history[(int64_t)r * hist_stride + s.iter] = s.rel;
   if (s.rel < s.best_rel) {
     s.best_rel = s.rel;
     s.best_iter = s.iter;
@@ -264,25 +262,33 @@ __global__ void k_cg_finalize(CgState* st, const double* __restrict__ prz,
   if (!s.fixed && s.rel <= s.tol) s.active = 0;
   s.beta = rz / s.rho;
   s.rho = rz;
-  st[r] = s;
+  return true;
 }
 
-hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
-                              int n_rhs, double* history, int hist_stride, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_finalize, dim3(n_rhs), dim3(64), 0, s, st, partial_rz, partial_rr,
-                     history, hist_stride);
-  return hipGetLastError();
-}
-
-__global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z,
-                          const double* __restrict__ x, double* __restrict__ xbest,
-                          const CgState* __restrict__ st, int64_t nu, float* __restrict__ p32, int64_t n32,
-                          int64_t vs32) {
+// Scalar step, then p = z + beta p (active RHS) and x_best = x (RHS whose
+// iterate became the best), in one launch: every block folds the partial sums in
+// the same fixed order and derives the same new state from st_prev (written by
+// the update, read-only here); block 0 of each RHS stores it in st, which no
+// block of this kernel reads.
+__global__ void k_cg_step_next(double* __restrict__ p, const double* __restrict__ z,
+                               const double* __restrict__ x, double* __restrict__ xbest,
+                               CgState* __restrict__ st, const CgState* __restrict__ st_prev,
+                               const double* __restrict__ prz, const double* __restrict__ prr,
+                               double* __restrict__ history, int hist_stride, int64_t nu,
+                               float* __restrict__ p32, int64_t n32, int64_t vs32) {
   const int r = blockIdx.y;
-  const bool upd = st[r].active != 0;
-  const bool best = st[r].copy_best != 0;
+  const double rz = fold_partials(prz, r);
+  const double rr = fold_partials(prr, r);
+  CgState s = st_prev[r];
+  const bool stepped = cg_scalar_step(s, rz, rr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[r] = s;
+    if (stepped && history) history[(int64_t)r * hist_stride + s.iter] = s.rel;
+  }
+  const bool upd = s.active != 0;
+  const bool best = s.copy_best != 0;
   if (!upd && !best) return;
-  const double beta = st[r].beta;
+  const double beta = s.beta;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
     const int64_t j = (int64_t)r * nu + i;
@@ -295,12 +301,14 @@ __global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z,
   }
 }
 
-hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
-                          const CgState* st, int64_t nu, int n_rhs, hipStream_t s, float* p32, int64_t n32,
-                          int64_t vs32) {
+hipError_t launch_cg_step_next(double* p, const double* z, const double* x, double* xbest, CgState* st,
+                               const CgState* st_prev, const double* partial_rz, const double* partial_rr,
+                               double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
+                               float* p32, int64_t n32, int64_t vs32) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
-  hipLaunchKernelGGL(k_cg_next, g, dim3(256), 0, s, p, z, x, xbest, st, nu, p32, n32, vs32);
+  hipLaunchKernelGGL(k_cg_step_next, g, dim3(256), 0, s, p, z, x, xbest, st, st_prev, partial_rz, partial_rr,
+                     history, hist_stride, nu, p32, n32, vs32);
   return hipGetLastError();
 }
 

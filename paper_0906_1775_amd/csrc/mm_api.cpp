@@ -321,6 +321,7 @@ struct mm_plan_s {
   double *vb64 = nullptr, *vxbest = nullptr;   // mixed refinement: b and the best iterate in float64
   double* vxacc = nullptr;                      // accumulated map of the restarted correction
   CgState* st = nullptr;
+  CgState* st_prev = nullptr;    // state before the current step (written by the update)
   CgState* st_host = nullptr;     // pinned: the CG states, then the staging slots below
   char* pin = nullptr;            // pinned staging of scalar readbacks (kPinSlots 8-byte slots) and dot partials
   template <typename T>
@@ -1083,6 +1084,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->part3 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part_pq = P->alloc<double>((int64_t)P->R * std::max(P->n_pq, 1));
   P->st = P->alloc<CgState>(P->R);
+  P->st_prev = P->alloc<CgState>(P->R);
   // mixed iterations gather the search direction from a float32 copy of its map part
   // (half the map bytes; the gathered TOD is float32 anyway)
   if (!P->main_fp64()) P->vp32 = P->alloc<float>((int64_t)P->R * std::max<int64_t>(P->vs32(), 1));
@@ -1097,12 +1099,12 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s, P->st, P->vp32);
   weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s, P->st);
   scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp, P->st);
-  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->n_obs, P->nu(), P->minv_t,
-                          P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
+  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->st_prev, P->n_obs, P->nu(),
+                          P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
-  hipchk(launch_cg_finalize(P->st, P->part2, P->part3, R, P->hist, P->hist_cap, s), "finalize");
-  hipchk(launch_cg_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
-         "next direction");
+  hipchk(launch_cg_step_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->st_prev, P->part2, P->part3, P->hist,
+                             P->hist_cap, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
+         "scalar step and next direction");
 }
 
 // per-RHS sums of x.y over [R][nu] vectors (float64, fixed order)

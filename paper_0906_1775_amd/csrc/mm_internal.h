@@ -186,19 +186,21 @@ hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* p
 // n_pq partial sums of p.q; writes the r.z and r.r partial sums
 // Vectors are rows of stride vs: n_obs pixel blocks, then n_tail template
 // amplitudes preconditioned by the diagonal minv_t.
+// (also copies the state before the step, alpha and breakdown included, to st_prev)
 hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
-                            double* z, const double* minv, CgState* st, int64_t n_obs,
+                            double* z, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s);
-hipError_t launch_cg_finalize(CgState* st, const double* partial_rz, const double* partial_rr,
-                              int n_rhs, double* history, int hist_stride, hipStream_t s);
-// p = z + beta p (active RHS) and x_best = x (RHS whose iterate became the best);
-// p32 (optional): also a float32 copy of the first n32 entries of each row of p
-// (rows of stride vs32)
-hipError_t launch_cg_next(double* p, const double* z, const double* x, double* xbest,
-                          const CgState* st, int64_t nu, int n_rhs, hipStream_t s,
-                          float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
+// The scalar step (new rho, beta, residual, best iterate, convergence; st from
+// st_prev and the update's partial sums; history[r * hist_stride + iter] = rel),
+// then p = z + beta p (active RHS) and x_best = x (RHS whose iterate became the
+// best); p32 (optional): also a float32 copy of the first n32 entries of each
+// row of p (rows of stride vs32)
+hipError_t launch_cg_step_next(double* p, const double* z, const double* x, double* xbest, CgState* st,
+                               const CgState* st_prev, const double* partial_rz, const double* partial_rr,
+                               double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
+                               float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
 hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
                                 int64_t n_obs, int64_t vs, const double* minv_t, int64_t n_tail,
                                 int n_rhs, hipStream_t s);
