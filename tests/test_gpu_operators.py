@@ -123,6 +123,22 @@ def test_point_on_every_scatter_layout(grid, n_rhs, dtype):
         assert max_rel(xm[r], ref) < (1e-13 if dtype == torch.float64 else 1e-6)
 
 
+# Plans built again from the same pointing scatter bit-identically: the radix sort,
+# the layouts and every summation order are fixed, so nothing depends on timing.  The
+# 2^24-sample workload sorts 4,096 tiles in two 9-bit passes (pixel-major scatter);
+# the small TQU problem is sorted in one pass.
+@pytest.mark.parametrize("which", ["TQU", "c2"])
+def test_plans_scatter_bit_identically(which, TQU):
+    p = TQU[0] if which == "TQU" else synth.make_problem("c2")
+    y = torch.from_numpy(np.random.default_rng(13).standard_normal((1, p.n_samples)).astype(np.float32)).cuda()
+    outs = []
+    for _ in range(3):
+        mm = plan_for(p, n_rhs=1, precision="mixed", lag_dft_len=L_K if which == "TQU" else 0)
+        outs.append(mm.point(y).cpu().numpy())
+        mm.close()
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
 @pytest.mark.parametrize("which", ["T", "TQU"])
 @pytest.mark.parametrize("n_f", [0, 256, 512, 2048])
 def test_weight_fp64(which, n_f, T, TQU):
