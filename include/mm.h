@@ -168,7 +168,7 @@ typedef struct {
   int64_t device_bytes;         /* device memory held by the plan */
   int64_t n_sliced;             /* entries of the scatter's pixel-major pointing: n_valid when
                                    it is read as is (128 or more hits per observed pixel on
-                                   average and at most 128 MiB of TOD per scatter pass), else
+                                   average and at most 256 MiB of TOD per scatter pass), else
                                    the sliced copy's (a multiple of 64, >= n_valid; the excess
                                    is padding to the widest pixel of each slice) */
   int64_t n_tmpl;               /* template amplitudes per RHS in map-shaped buffers (0 = none) */

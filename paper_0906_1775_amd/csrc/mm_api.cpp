@@ -735,10 +735,11 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
 // Largest TOD one scatter pass reads (rows of up to 4 RHS) for which the pixel-major
 // scatter is used.  A TOD cache line holds hits of several neighbouring pixels,
 // which that scatter reads from different wavefronts (the sliced one from one):
-// measured faster while those re-reads stay in the 256 MiB last-level cache
-// (64 MiB of float32 TOD: 7 % less time per iteration; 128 MiB of float64 TOD:
-// 4 % less) and slower beyond it (1 GiB: 5 % more).
-constexpr int64_t kSegTodBytes = int64_t(128) << 20;
+// measured faster while those re-reads mostly stay in the 256 MiB last-level
+// cache (64 MiB of float32 TOD: 7 % less time per iteration; 128 MiB of float64
+// TOD: 4 % less; 4 RHS x 64 MiB: 6 % less) and slower beyond it (512 MiB: 6 %
+// more; 1 GiB: 5 % more).
+constexpr int64_t kSegTodBytes = int64_t(256) << 20;
 
 void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
   int wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
