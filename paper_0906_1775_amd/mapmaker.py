@@ -130,7 +130,9 @@ class MapMaker:
         L.check(self._lib.mm_plan_create(ctypes.byref(d), _ptr(pix), _ptr(w), _stream(), ctypes.byref(h)),
                 self._lib)
         self._h = h
-        self.n_tmpl = int(self.info()["n_tmpl"])
+        # (plan info waits for the plan's last counts: asked only when templates add amplitudes,
+        # so that the caller can queue work behind an unfinished plan)
+        self.n_tmpl = int(self.info()["n_tmpl"]) if self.templates else 0
         self._map_shape = (self.n_rhs, self.n_pix, self.n_stokes) if self.n_tmpl == 0 else \
             (self.n_rhs, self.n_pix * self.n_stokes + self.n_tmpl)
 
