@@ -69,6 +69,22 @@ def test_convolution_off_by_one_is_caught(monkeypatch):
     _fails(pn.test_ninv_fft_equals_direct_equals_dense_toeplitz, [257, 31, 33, 2])
 
 
+def test_single_sample_window_off_by_one_is_caught(monkeypatch):
+    def short_window(y_window, t, a, e, f):
+        n_c = f.shape[0]
+        lo, hi = max(a, t - n_c + 1), min(e, t + n_c - 1)
+        ys = np.asarray(y_window(lo, hi), dtype=np.float64)
+        return float(np.dot(f[np.abs(np.arange(lo, hi) - t)], ys))
+    monkeypatch.setattr(noise, "apply_ninv_at", short_window)
+    _fails(pn.test_single_sample_ninv_matches_direct_and_dense_toeplitz, 16)
+
+
+def test_single_sample_wrong_interval_edge_is_caught(monkeypatch):
+    orig = noise.apply_ninv_at
+    monkeypatch.setattr(noise, "apply_ninv_at", lambda y_window, t, a, e, f: orig(y_window, t, max(a - 1, 0), e, f))
+    _fails(pn.test_single_sample_ninv_matches_direct_and_dense_toeplitz, 16)
+
+
 def test_pcg_beta_sign_error_is_caught(monkeypatch):
     def bad_pcg(self, b, tol=1e-6, max_iter=50, precond="block", **kw):
         M = self.preconditioner(precond)

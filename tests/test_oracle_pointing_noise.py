@@ -144,6 +144,35 @@ def test_ninv_fft_equals_direct_equals_dense_toeplitz(lens):
     assert np.allclose(b, c, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("n_c", [1, 16, 64])
+def test_single_sample_ninv_matches_direct_and_dense_toeplitz(n_c):
+    """apply_ninv_at (one output sample from the banded-Toeplitz definition) at every
+    sample of ragged intervals, including lengths 1, 2, n_c - 1, n_c, n_c + 1 and an
+    empty interval, against the direct convolution and the dense block-Toeplitz product."""
+    rng = np.random.default_rng(11 + n_c)
+    tabs = np.stack([noise.lags(n_c, 50.0, 1.0, 0.3, 1.2, L=1 << 12),
+                     noise.lags(n_c, 50.0, 0.7, 1.0, 1.9, L=1 << 12)])
+    lens = sorted({1, 2, max(n_c - 1, 1), n_c, n_c + 1, 3 * n_c + 5}) + [0, 7]
+    iv = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    filt = np.arange(len(lens)) % 2
+    y = rng.standard_normal(int(iv[-1]))
+    direct = noise.apply_ninv_direct(y, iv, filt, tabs)
+    blocks = []
+    for k, n in enumerate(lens):
+        col = np.zeros(n)
+        m = min(n, n_c)
+        col[:m] = tabs[filt[k]][:m]
+        blocks.append(scipy.linalg.toeplitz(col) if n else np.zeros((0, 0)))
+    dense = scipy.linalg.block_diag(*blocks) @ y
+    at = np.empty_like(y)
+    for b in range(len(lens)):
+        a, e = int(iv[b]), int(iv[b + 1])
+        for t in range(a, e):
+            at[t] = noise.apply_ninv_at(lambda lo, hi: y[lo:hi], t, a, e, tabs[filt[b]])
+    assert np.allclose(at, direct, rtol=0, atol=1e-13)
+    assert np.allclose(at, dense, rtol=0, atol=1e-13)
+
+
 def test_ninv_batches_rows_independently():
     rng = np.random.default_rng(6)
     f = noise.lags(32, 50.0, 1.0, 0.3, 1.2, L=1 << 12)[None, :]
