@@ -26,11 +26,18 @@
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are device (HBM) pointers on the current HIP device;
- *     all others are host pointers.  The caller owns every buffer it passes;
- *     the library owns only the plan and what the plan allocates.
+ *     all others are host pointers.  The caller owns every buffer it passes.
+ *     A plan's device memory is one workspace: the caller's (mm_plan, sized by
+ *     mm_plan_workspace_size) or one block mm_plan_create allocates; the plan
+ *     allocates no other device memory in any later call.
  *   - `stream` is a hipStream_t (passed as void*); NULL means the default
- *     stream.  Work is enqueued on it; entry points that must read results
- *     on the host (plan creation, mm_solve) synchronise that stream.
+ *     stream.  Work is enqueued on it.  Plan construction returns once its work
+ *     is queued (it waits only for the counts it needs on the host); every later
+ *     call on the plan orders its work after that build, whatever its stream.
+ *     Entry points that read results on the host (mm_filter_lags, mm_solve,
+ *     mm_solve_rhs, mm_noise_gradient) return with their results complete.
+ *     Calls on one plan share its work buffers: the caller must not let them
+ *     overlap in time (one stream per plan, or its own synchronisation).
  *   - Maps cross the boundary in global pixel layout, float64,
  *     [n_rhs][n_pix][n_stokes] (Stokes fastest).  Pixels never observed are
  *     written as 0.  With templates every map-shaped buffer is the extended
@@ -96,7 +103,7 @@ enum { MM_TMPL_ONEHOT = 1,   /* B[t, idx_t] = 1: synchronous bins, destriping of
  *     and map).  Amplitudes: 32 per segment, segment-major.
  * Template rows do not depend on the pointing index: a sample with pixel -1
  * still carries its template columns.  d_idx and d_omega are read by every
- * operator and must stay allocated and unchanged until mm_plan_destroy.
+ * operator and must stay allocated and unchanged until mm_destroy.
  * Amplitude preconditioner: diag(B^T W^-1 B)^-1 (MM_PRECOND_BLOCK),
  * diag(B^T B)^-1 (MM_PRECOND_JACOBI) or 1, with 0 for an all-zero column.
  */
@@ -165,7 +172,7 @@ typedef struct {
   int32_t n_f;                  /* FFT length the iterations use */
   int32_t n_chunks;             /* overlap-save transforms per TOD pass and RHS */
   int32_t n_singular;           /* preconditioner blocks flagged singular */
-  int64_t device_bytes;         /* device memory held by the plan */
+  int64_t device_bytes;         /* bytes of the workspace in use (at most the bound) */
   int64_t n_sliced;             /* entries of the scatter's pixel-major pointing: n_valid when
                                    it is read as is (128 or more hits per observed pixel on
                                    average and at most 256 MiB of TOD per scatter pass), else
@@ -176,47 +183,69 @@ typedef struct {
 } mm_plan_info_t;
 
 /*
- * Build a plan: validate the descriptor, range-check the pointing, compact
- * the observed pixels (Implementation section, observed index scheme), sort
- * samples by pixel for the pixel-major scatter, build the noise filters
- * (lags f(tau) and overlap-save spectra) and the preconditioner.
- *   d_pix: device int32 [n_samples], pixel of each sample, -1 = no pixel
- *          (excised sample; its row of P is zero).
- *   d_w:   device float32 [n_samples][2] = (sin 2a_t, cos 2a_t); required
- *          when n_stokes == 3, ignored (may be NULL) when n_stokes == 1.
- *          d_w must stay allocated and unchanged until mm_plan_destroy.
+ * Device bytes a plan of this descriptor needs in its workspace (an upper bound
+ * computed from the descriptor alone: it holds for any pointing the descriptor
+ * admits).  The plan holds the time-major observed index and the pixel-major
+ * (or sliced) pointing of the pixel-indexing scheme (Implementation section),
+ * the lags and overlap-save spectra of N^-1 (Weighting section), the block
+ * preconditioner (Implementation section), and the TOD and CG work vectors of
+ * the PCG iteration (Algorithm section, eq. pcgSystem).  Host-only.
+ * Errors: MM_EINVAL (descriptor), MM_EUNSUPPORTED (forced n_f longer than the
+ * on-chip transforms).
+ */
+mm_status_t mm_plan_workspace_size(const mm_desc_t* desc, size_t* bytes);
+
+/*
+ * Build a plan in the caller's workspace: validate the descriptor, range-check
+ * the pointing, compact the observed pixels (Implementation section, observed
+ * index scheme), sort samples by pixel for the pixel-major scatter, build the
+ * noise filters (lags f(tau) and overlap-save spectra, Weighting section) and
+ * the preconditioner (Implementation section).
+ *   d_pix:  device int32 [n_samples], pixel of each sample, -1 = no pixel
+ *           (excised sample; its row of P is zero).  Read during the build.
+ *   d_w:    device float32 [n_samples][2] = (sin 2a_t, cos 2a_t); required
+ *           when n_stokes == 3, ignored (may be NULL) when n_stokes == 1.
+ *           d_w must stay allocated and unchanged until mm_destroy.
+ *   d_ws:   device workspace of ws_bytes >= mm_plan_workspace_size(desc),
+ *           256-byte aligned, owned by the caller; the plan uses it until
+ *           mm_destroy and never frees it.  Its contents on entry do not matter.
  * With n_c = 1 (white noise) N^-1 is applied as the diagonal f_b(0) without
  * transforms (the destriping case of the "Using MADmap" section).
- * Errors: MM_EINVAL (descriptor, pixel or template index out of range),
- * MM_ENOMEM, MM_EDEVICE, MM_EUNSUPPORTED (forced n_f longer than the on-chip
- * transforms).  A
- * singular preconditioner block does not fail the plan; it is counted in
- * mm_plan_info_t.n_singular and makes mm_solve return MM_ESINGULAR.
+ * Errors: MM_EINVAL (descriptor, pixel or template index out of range, NULL or
+ * misaligned workspace, ws_bytes below the bound), MM_EDEVICE, MM_EUNSUPPORTED
+ * (forced n_f longer than the on-chip transforms).  A singular preconditioner
+ * block does not fail the plan; it is counted in mm_plan_info_t.n_singular and
+ * makes mm_solve return MM_ESINGULAR.
  */
+mm_status_t mm_plan(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* d_ws,
+                    size_t ws_bytes, void* stream, mm_plan_t* out_plan);
+
+/* mm_plan in a workspace the library allocates (hipMalloc of the bound) and
+ * mm_destroy frees.  Errors as mm_plan, and MM_ENOMEM. */
 mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w,
                            void* stream, mm_plan_t* out_plan);
-/* Destroy a plan (waits for the device to be idle).  Its device memory is kept by the
- * library for later plans of the process, up to the device's cache limit (16 GiB unless
- * changed with mm_set_cache_limit); the rest is freed. */
+
+/* Destroy a plan: waits for the device to be idle, so that the caller may free or
+ * reuse its workspace at once.  NULL is a no-op.  mm_plan_destroy is the same call. */
+mm_status_t mm_destroy(mm_plan_t plan);
 mm_status_t mm_plan_destroy(mm_plan_t plan);
 
-/* Device memory kept for later plans (plan-memory cache).  Freed device memory is
- * cleared by the driver before it is handed out again, at a few tens of GB/s, so a
- * process that re-plans problems of hundreds of GB spends seconds per plan unless
- * the blocks are reused; the cache keeps them.  Sets the limit of HIP device
- * `device` (0 .. device count - 1) to `bytes` (>= 0) and frees cached blocks above
- * it at once (bytes = 0 empties the cache); the previous limit goes to *previous
- * (may be NULL).  Blocks held by live plans are not affected.  Cached blocks are
- * not available to other allocators of the process (a failed plan allocation
- * empties the cache and retries).  Errors: MM_EINVAL (device out of range,
- * bytes < 0), MM_EDEVICE. */
-mm_status_t mm_set_cache_limit(int32_t device, int64_t bytes, int64_t* previous);
+/* Sizes the plan found: observed pixels and pointed samples (pixel-indexing
+ * scheme, Implementation section), FFT length and transforms per TOD pass of the
+ * overlap-save N^-1 (Weighting section, eq. FFTcomplexityFunction), singular
+ * preconditioner blocks (Implementation section), workspace bytes in use.  Waits
+ * for the preconditioner's singular-block count when first called. */
 mm_status_t mm_plan_get_info(mm_plan_t plan, mm_plan_info_t* info);
 
-/* Hit count of every global pixel: device int32 [n_pix] (exact integers). */
+/* Hit count of every global pixel, the number of samples pointing at it (the
+ * pixel-indexing scheme of the Implementation section; for temperature the
+ * diagonal of P^T P): device int32 [n_pix], exact integers, unobserved pixels 0. */
 mm_status_t mm_hits(mm_plan_t plan, int32_t* d_hits, void* stream);
 
-/* The plan's lags f(tau): host float64 [n_filters][n_c] (synchronises). */
+/* The lags f(tau), tau = 0 .. n_c - 1, of each filter's banded Toeplitz block of
+ * N^-1 (Weighting section; built from p(f) of the Algorithm section when the plan
+ * has filter_params): host float64 [n_filters][n_c].  Copies on `stream` after
+ * the plan's build and synchronises that stream. */
 mm_status_t mm_filter_lags(mm_plan_t plan, double* lags_out, void* stream);
 
 /* y = P x: device map [n_rhs][n_pix][n_stokes] float64 -> TOD [n_rhs][n_samples]
@@ -245,7 +274,8 @@ typedef struct {
   double tol;                   /* stop when ||r||_2 / ||b||_2 <= tol (paper default 1e-6) */
   int32_t max_iter;             /* at most this many H applications (paper default 50) */
   int32_t fixed_iters;          /* > 0: run exactly this many iterations, ignore tol */
-  int32_t check_every;          /* iterations between host convergence checks (>= 1); a block
+  int32_t check_every;          /* iterations between host convergence checks (1 .. 256; larger
+                                   values are taken as 256); a block
                                    is shortened when every active RHS is predicted (from its
                                    residual rate since the last check) to reach tol sooner */
   int32_t use_graph;            /* replay each full block of check_every iterations as a hipGraph,
@@ -307,19 +337,26 @@ mm_status_t mm_solve_rhs(mm_plan_t plan, const double* d_b, double* d_x,
                          const mm_solve_opts_t* opts, mm_solve_info_t* info, void* stream);
 
 /*
- * Gradient of a map loss with respect to the noise parameters.  For
- * m = H^-1 P^T N^-1 d and lambda = H^-1 dL/dm, dL/dtheta = u^T (dN^-1/dtheta) v
- * with u = P lambda and v = d - P m, where dN^-1/dtheta is the banded Toeplitz
- * operator whose lags are the theta-derivative of f(tau) (the lag construction
- * of the plan differentiated under the inverse DFT), restricted to the intervals
- * of each filter.
- *   d_u, d_v: TOD [n_rhs][n_samples] of tod_dtype.
- *   grad_out: host float64 [n_rhs][n_filters][3] = dL/d(sigma, f_knee, alpha).
- * Computed in float64 whatever the plan's precision; synchronises.  Returns
- * MM_EUNSUPPORTED for plans built from explicit lags.
+ * Gradient of a map loss with respect to the noise parameters theta = (sigma,
+ * f_knee, alpha) of p(f) (Algorithm section).  The map m = H^-1 P^T N^-1 d
+ * (eq. eMLM) depends on theta only through N^-1; with lambda = H^-1 dL/dm (the
+ * adjoint solve: H is symmetric, Algorithm section, so mm_solve_rhs gives it),
+ *     dL/dtheta = sum over RHS r of (P lambda_r)^T (dN^-1/dtheta) (d_r - P m_r),
+ * where dN^-1/dtheta is the banded Toeplitz operator (Weighting section) whose
+ * lags are the theta-derivative of f(tau) (the plan's lag construction
+ * differentiated under the inverse DFT), restricted to the intervals of each
+ * filter.  The parameters are shared by the RHS, so their terms are summed.
+ *   d_tod:    TOD d [n_rhs][n_samples] of tod_dtype (the solve's data).
+ *   d_m:      the map m [n_rhs][n_pix][n_stokes] float64 (map-shaped; with
+ *             templates the extended vector).
+ *   d_lambda: the adjoint lambda, same layout as d_m.
+ *   grad_out: host float64 [n_filters][3] = dL/d(sigma, f_knee, alpha).
+ * P m, P lambda, d - P m and the filtered products are formed on the device in
+ * float64 whatever the plan's precision; synchronises.  Returns MM_EUNSUPPORTED
+ * for plans built from explicit lags.
  */
-mm_status_t mm_noise_gradient(mm_plan_t plan, const void* d_u, const void* d_v, int32_t tod_dtype,
-                              double* grad_out, void* stream);
+mm_status_t mm_noise_gradient(mm_plan_t plan, const void* d_tod, int32_t tod_dtype, const double* d_m,
+                              const double* d_lambda, double* grad_out, void* stream);
 
 /* FFT length by the paper's halving rule (Weighting section, eq. FFTcomplexityFunction):
  * start at the smallest power of two >= longest, halve while h'(n_f/2) >= 0 and

@@ -29,14 +29,12 @@ class _MapSolve(torch.autograd.Function):
         tod, m = ctx.saved_tensors
         plan = ctx.plan
         lam, _ = plan.solve_rhs(g.detach().to(torch.float64).contiguous(), tol=ctx.tol, max_iter=ctx.max_iter)
-        u = plan.unpoint(lam, dtype=torch.float64)                       # P lambda
         grad_tod = grad_params = None
         if ctx.needs_input_grad[0]:
+            u = plan.unpoint(lam, dtype=torch.float64)                    # P lambda
             grad_tod = plan.weight(u.to(tod.dtype))                       # N^-1 P lambda
         if ctx.needs_input_grad[1]:
-            v = tod.detach().to(torch.float64) - plan.unpoint(m, dtype=torch.float64)   # d - P m
-            gp = plan.noise_gradient(u, v).sum(axis=0)                    # noise parameters shared by the RHS
-            grad_params = torch.from_numpy(gp)
+            grad_params = torch.from_numpy(plan.noise_gradient(tod.detach().contiguous(), m, lam))
         return grad_tod, grad_params, None, None, None
 
 

@@ -265,7 +265,7 @@ __device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr)
   return true;
 }
 
-// Scalar step, then p = z + beta p (active RHS) and x_best = x (RHS whose
+// Scalar step, then p = z + beta p (RHS that stepped) and x_best = x (RHS whose
 // iterate became the best), in one launch: every block folds the partial sums in
 // the same fixed order and derives the same new state from st_prev (written by
 // the update, read-only here); block 0 of each RHS stores it in st, which no
@@ -283,9 +283,11 @@ __global__ void k_cg_step_next(double* __restrict__ p, const double* __restrict_
   const bool stepped = cg_scalar_step(s, rz, rr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st[r] = s;
-    if (stepped && history) history[(int64_t)r * hist_stride + s.iter] = s.rel;
+    if (stepped && history) history[(int64_t)r * hist_stride + s.iter % hist_stride] = s.rel;
   }
-  const bool upd = s.active != 0;
+  // p advances on every step taken, also the one on which an RHS stops: a later
+  // residual replacement that finds it above tol continues it along this direction
+  const bool upd = stepped;
   const bool best = s.copy_best != 0;
   if (!upd && !best) return;
   const double beta = s.beta;

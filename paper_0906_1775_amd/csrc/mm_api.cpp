@@ -110,99 +110,21 @@ struct FilterSetup {
   int n_chunks = 0;
 };
 
-// Device memory and streams of destroyed plans, kept per device for later
-// plans of the process: hipFree synchronises the whole device and hipMalloc of
-// large blocks maps pages, which together cost more than the plan's kernels.
-// Freed VRAM is also cleared by the driver before it is handed out again, at a
-// few tens of GB/s, so re-planning a problem of hundreds of GB pays seconds unless
-// the blocks are reused.  At most cap[dev] bytes (default kCacheCap, changed with
-// mm_set_cache_limit) stay cached per device; a failed hipMalloc empties the
-// cache and retries once.
-constexpr size_t kCacheCap = size_t(16) << 30;
-
-struct DeviceCache {
+// Streams of destroyed plans, kept per device for later plans of the process
+// (creating a stream costs more than the small plans' kernels).
+struct StreamPool {
   std::mutex mu;
-  std::vector<std::pair<size_t, void*>> blocks[64];
-  size_t held[64] = {};
-  size_t cap[64];
   std::vector<hipStream_t> streams[64];
-  DeviceCache() {
-    for (size_t& c : cap) c = kCacheCap;
-  }
 };
 
-DeviceCache& cache() {
-  static DeviceCache* c = new DeviceCache();   // never destroyed: blocks outlive static teardown
+StreamPool& stream_pool() {
+  static StreamPool* c = new StreamPool();   // never destroyed: streams outlive static teardown
   return *c;
-}
-
-// smallest cached block of at least b bytes and at most b + b/8 + 1 MiB
-void* cache_take(int dev, size_t b, size_t* got) {
-  if (dev < 0 || dev >= 64) return nullptr;
-  DeviceCache& c = cache();
-  std::lock_guard<std::mutex> lk(c.mu);
-  auto& v = c.blocks[dev];
-  const size_t hi = b + b / 8 + (size_t(1) << 20);
-  size_t best = v.size();
-  for (size_t i = 0; i < v.size(); ++i)
-    if (v[i].first >= b && v[i].first <= hi && (best == v.size() || v[i].first < v[best].first)) best = i;
-  if (best == v.size()) return nullptr;
-  void* p = v[best].second;
-  *got = v[best].first;
-  c.held[dev] -= v[best].first;
-  v.erase(v.begin() + best);
-  return p;
-}
-
-void cache_put(int dev, size_t b, void* p) {
-  DeviceCache& c = cache();
-  {
-    std::lock_guard<std::mutex> lk(c.mu);
-    if (dev >= 0 && dev < 64 && c.held[dev] + b <= c.cap[dev]) {
-      c.blocks[dev].push_back({b, p});
-      c.held[dev] += b;
-      return;
-    }
-  }
-  (void)hipFree(p);   // teardown: nothing to report to
-}
-
-void cache_flush(int dev) {
-  if (dev < 0 || dev >= 64) return;
-  std::vector<std::pair<size_t, void*>> v;
-  {
-    DeviceCache& c = cache();
-    std::lock_guard<std::mutex> lk(c.mu);
-    v.swap(c.blocks[dev]);
-    c.held[dev] = 0;
-  }
-  for (auto& e : v) (void)hipFree(e.second);
-}
-
-// set the cap of device dev; blocks above the new cap are freed (largest first)
-size_t cache_set_cap(int dev, size_t cap) {
-  std::vector<void*> drop;
-  size_t prev;
-  {
-    DeviceCache& c = cache();
-    std::lock_guard<std::mutex> lk(c.mu);
-    prev = c.cap[dev];
-    c.cap[dev] = cap;
-    auto& v = c.blocks[dev];
-    std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
-    while (c.held[dev] > cap && !v.empty()) {
-      c.held[dev] -= v.back().first;
-      drop.push_back(v.back().second);
-      v.pop_back();
-    }
-  }
-  for (void* p : drop) hipchk(hipFree(p), "hipFree");
-  return prev;
 }
 
 hipStream_t stream_take(int dev) {
   if (dev >= 0 && dev < 64) {
-    DeviceCache& c = cache();
+    StreamPool& c = stream_pool();
     std::lock_guard<std::mutex> lk(c.mu);
     if (!c.streams[dev].empty()) {
       hipStream_t st = c.streams[dev].back();
@@ -217,7 +139,7 @@ hipStream_t stream_take(int dev) {
 
 void stream_put(int dev, hipStream_t st) {
   if (dev >= 0 && dev < 64) {
-    DeviceCache& c = cache();
+    StreamPool& c = stream_pool();
     std::lock_guard<std::mutex> lk(c.mu);
     if (c.streams[dev].size() < 16) {
       c.streams[dev].push_back(st);
@@ -226,6 +148,22 @@ void stream_put(int dev, hipStream_t st) {
   }
   (void)hipStreamDestroy(st);
 }
+
+// Device memory of a plan: one block, the caller's workspace (mm_plan) or one the
+// library allocated (mm_plan_create), cut into two regions.  Persistent data
+// (pointing layouts, filters, preconditioner, scalars) are bumped from the start,
+// up to a limit the descriptor bounds; the work region after it holds the TOD and
+// CG work vectors.  Temporaries are stacked over the work region: during the build
+// from its start (the work vectors are not in use before the build has finished,
+// and every entry point waits for it), afterwards above the two TOD work buffers.
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+inline size_t block_bytes(int64_t count, size_t elem) { return align_up((size_t)std::max<int64_t>(count, 1) * elem); }
+
+// Entries of the device history ring of every RHS: the host copies it after each
+// block of iterations, and blocks are shorter than the ring.
+constexpr int kHistRing = 1024;
+constexpr int kMaxCheckEvery = 256;   // blocks are at most 2 x check_every iterations
 
 // Pixel-major layout of one pointing matrix with one non-zero per row: the sky
 // pointing, or a one-hot template read as a temperature-only pointing.
@@ -237,6 +175,7 @@ struct Layout {
   int32_t* perm = nullptr;       // [n_valid] sample ids, pixel-major (released once sliced)
   float* w_pm = nullptr;         // [n_valid][2] (sin, cos), pixel-major (released once sliced)
   int group = 8;                 // lanes per pixel in the plan-time preconditioner build
+  int wps = 0;                   // wavefronts per slice of the scatter (0: pixel-major arrays as they are)
   SellLayout sell;               // sliced pointing of the scatter
   int64_t sell_entries = 0;
 };
@@ -327,73 +266,84 @@ struct mm_plan_s {
   template <typename T>
   T* slot(int k) { return reinterpret_cast<T*>(pin + 8 * k); }
   double* pin_dots() { return reinterpret_cast<double*>(pin + kPinSlots * 8); }
-  double* hist = nullptr;
+  double* hist = nullptr;         // [R][kHistRing] residual per iteration (ring, index iter % kHistRing)
   double* hist_host = nullptr;    // pinned copy target of hist
-  int hist_cap = 0;
 
   // cached graph of check_every iterations
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
-  const double* graph_hist = nullptr;
 
-  // live device blocks, and blocks the plan released: the plan's own work is
-  // stream-ordered, so a released block is reused by its later allocations at once
-  std::vector<std::pair<size_t, void*>> allocs, spare;
-  int64_t bytes = 0;
+  hipEvent_t ev_ready = nullptr;  // recorded on the build stream when the plan's build work is queued
 
+  // ---- device memory (see align_up): ws[0, pers_lim) persistent, ws[pers_lim, ws_size) work region
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  bool ws_owned = false;          // allocated by mm_plan_create (freed by mm_destroy)
+  size_t pers_lim = 0, pers_top = 0;
+  size_t work_top = 0;            // work vectors, bumped from pers_lim
+  size_t tmp_base = 0;            // temporaries are stacked from here
+  size_t tmp_peak = 0;            // highest end of a temporary so far
+  struct Tmp {
+    size_t off, bytes;
+    bool live;
+  };
+  std::vector<Tmp> tmps;
+
+  size_t tmp_top() const { return tmps.empty() ? tmp_base : tmps.back().off + tmps.back().bytes; }
+  [[noreturn]] void exhausted(const char* what, size_t need) {
+    fail(MM_ENOMEM, std::string("workspace too small for the plan's ") + what + " (" + std::to_string(need) +
+                        " bytes past the end of its region; the bound from mm_plan_workspace_size was exceeded)");
+  }
+  // persistent block (lives as long as the plan)
   template <typename T>
   T* alloc(int64_t count) {
-    if (count <= 0) count = 1;
-    const size_t b = (size_t)count * sizeof(T);
-    void* p = nullptr;
-    const size_t hi = b + b / 8 + (size_t(1) << 20);
-    size_t best = spare.size();
-    for (size_t i = 0; i < spare.size(); ++i)
-      if (spare[i].first >= b && spare[i].first <= hi && (best == spare.size() || spare[i].first < spare[best].first))
-        best = i;
-    size_t got = b;
-    if (best < spare.size()) {
-      got = spare[best].first;
-      p = spare[best].second;
-      spare.erase(spare.begin() + best);
-    } else if ((p = cache_take(device, b, &got)) != nullptr) {
-    } else {
-      hipError_t e = hipMalloc(&p, b);
-      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
-        (void)hipGetLastError();
-        for (auto& s : spare) (void)hipFree(s.second);
-        spare.clear();
-        cache_flush(device);
-        e = hipMalloc(&p, b);
-      }
-      hipchk(e, "hipMalloc");
-    }
-    allocs.push_back({got, p});
-    bytes += (int64_t)got;
-    return (T*)p;
+    const size_t b = block_bytes(count, sizeof(T));
+    if (pers_top + b > pers_lim) exhausted("persistent data", pers_top + b - pers_lim);
+    T* p = reinterpret_cast<T*>(ws + pers_top);
+    pers_top += b;
+    return p;
   }
-  void release(void* p) {
+  // work vector (from the end of the build on)
+  template <typename T>
+  T* work(int64_t count) {
+    const size_t b = block_bytes(count, sizeof(T));
+    if (work_top + b > ws_size) exhausted("work vectors", work_top + b - ws_size);
+    T* p = reinterpret_cast<T*>(ws + work_top);
+    work_top += b;
+    return p;
+  }
+  // temporary block, released with release(): the stack pops released blocks from its top
+  template <typename T>
+  T* temp(int64_t count) {
+    const size_t b = block_bytes(count, sizeof(T));
+    const size_t off = tmp_top();
+    if (off + b > ws_size) exhausted("temporaries", off + b - ws_size);
+    tmps.push_back(Tmp{off, b, true});
+    tmp_peak = std::max(tmp_peak, off + b);
+    return reinterpret_cast<T*>(ws + off);
+  }
+  void release(const void* p) {
     if (!p) return;
-    for (size_t i = 0; i < allocs.size(); ++i)
-      if (allocs[i].second == p) {
-        spare.push_back(allocs[i]);
-        bytes -= (int64_t)allocs[i].first;
-        allocs.erase(allocs.begin() + i);
-        return;
-      }
+    const size_t off = (size_t)((const char*)p - ws);
+    for (Tmp& t : tmps)
+      if (t.live && t.off == off) t.live = false;
+    while (!tmps.empty() && !tmps.back().live) tmps.pop_back();
   }
+  // device bytes in use: persistent data, then the larger of the work vectors and the temporaries
+  int64_t bytes() const { return (int64_t)(std::max(work_top, tmp_peak)); }
+
   ~mm_plan_s() {
     if (graph) (void)hipGraphExecDestroy(graph);   // destructor: statuses are discarded
-    // work the caller queued on its own streams may still read the blocks: drain
-    // the device once before they become available to other plans
+    // work the caller queued on its own streams may still read the workspace: drain
+    // the device before the caller may reuse it
     (void)hipDeviceSynchronize();
-    for (auto& a : allocs) cache_put(device, a.first, a.second);
-    for (auto& a : spare) cache_put(device, a.first, a.second);
+    if (ws_owned && ws) (void)hipFree(ws);
     if (st_host) (void)hipHostFree(st_host);
     if (hist_host) (void)hipHostFree(hist_host);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (ev_singular) (void)hipEventDestroy(ev_singular);
+    if (ev_ready) (void)hipEventDestroy(ev_ready);
     if (own) stream_put(device, own);
   }
 
@@ -420,7 +370,12 @@ namespace {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
-void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant = 0);
+// order work on `stream` after the plan's build (the build may have run on another stream)
+void wait_ready(mm_plan_s* P, hipStream_t stream) {
+  if (P->ev_ready) hipchk(hipStreamWaitEvent(stream, P->ev_ready, 0), "event wait");
+}
+
+void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant, bool tmp);
 
 void release_filter(mm_plan_s* P, FilterSetup& fs) {
   P->release(fs.chunks);
@@ -430,29 +385,48 @@ void release_filter(mm_plan_s* P, FilterSetup& fs) {
   fs = FilterSetup();
 }
 
-// Autotuner: build every admissible on-chip transform (length x workgroup shape)
-// and keep the one whose overlap-save pass over the plan's own intervals runs fastest.
-void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
-  const int maxlog = ols_max_logn(fp64);
+int64_t longest_interval(const std::vector<int64_t>& iv_start) {
   int64_t longest = 1;
-  for (int b = 0; b < P->n_iv; ++b) longest = std::max<int64_t>(longest, P->iv_start[b + 1] - P->iv_start[b]);
+  for (size_t b = 0; b + 1 < iv_start.size(); ++b) longest = std::max<int64_t>(longest, iv_start[b + 1] - iv_start[b]);
+  return longest;
+}
+
+// Lengths the autotuner tries: every on-chip power of two above 2 n_c, up to the first
+// one whose half already covers twice the longest interval (longer ones only add padding).
+std::vector<int64_t> autotune_lengths(int n_c, int64_t longest, bool fp64) {
+  const int maxlog = ols_max_logn(fp64);
   int64_t nf = 1;
-  while (nf <= 2 * (int64_t)P->n_c) nf <<= 1;
+  while (nf <= 2 * (int64_t)n_c) nf <<= 1;
   nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
   if (ilog2(nf) - 1 > maxlog) fail(MM_EUNSUPPORTED, "n_c too large for the on-chip transforms");
+  std::vector<int64_t> out;
+  for (; ilog2(nf) - 1 <= maxlog; nf <<= 1) {
+    out.push_back(nf);
+    if ((nf >> 1) >= 2 * longest) break;
+  }
+  return out;
+}
+
+// Autotuner: build every admissible on-chip transform (length x workgroup shape) as a
+// temporary, time its overlap-save pass over the plan's own intervals, and build the
+// fastest one for the plan.
+void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
+  const std::vector<int64_t> lens = autotune_lengths(P->n_c, longest_interval(P->iv_start), fp64);
   hipEvent_t e0, e1;
   hipchk(hipEventCreate(&e0), "event");
   hipchk(hipEventCreate(&e1), "event");
   const int esz = fp64 ? 8 : 4;
-  void* ya = P->alloc<char>(std::max<int64_t>(P->n_t, 1) * esz);
-  void* yb = P->alloc<char>(std::max<int64_t>(P->n_t, 1) * esz);
+  void* ya = P->temp<char>(std::max<int64_t>(P->n_t, 1) * esz);
+  void* yb = P->temp<char>(std::max<int64_t>(P->n_t, 1) * esz);
   hipchk(hipMemsetAsync(ya, 0, std::max<int64_t>(P->n_t, 1) * esz, s), "memset");
   float best_ms = 0;
-  for (; ilog2(nf) - 1 <= maxlog; nf <<= 1) {
+  int64_t best_nf = 0;
+  int best_v = 0;
+  for (int64_t nf : lens) {
     for (int v = 0; v < kOlsVariants; ++v) {
       if (!ols_variant_exists(ilog2(nf) - 1, fp64, v)) continue;
       FilterSetup cand;
-      build_filter_nf(P, cand, fp64, nf, s, v);
+      build_filter_nf(P, cand, fp64, nf, s, v, true);
       hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw, cand.tw2,
                         P->n_t, P->n_c, cand.m, 1, s, v),
              "autotune warm-up");
@@ -465,20 +439,19 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
       hipchk(hipEventSynchronize(e1), "autotune");
       float ms = 0;
       hipchk(hipEventElapsedTime(&ms, e0, e1), "event time");
-      if (!fs.ready || ms < best_ms) {
-        if (fs.ready) release_filter(P, fs);
-        fs = cand;
+      if (best_nf == 0 || ms < best_ms) {
         best_ms = ms;
-      } else {
-        release_filter(P, cand);
+        best_nf = nf;
+        best_v = v;
       }
+      release_filter(P, cand);
     }
-    if ((nf >> 1) >= 2 * longest) break;   // longer transforms only add padding
   }
-  P->release(ya);
   P->release(yb);
+  P->release(ya);
   hipchk(hipEventDestroy(e0), "event");
   hipchk(hipEventDestroy(e1), "event");
+  build_filter_nf(P, fs, fp64, best_nf, s, best_v, false);
 }
 
 // transform shape used when the descriptor leaves it open: the fastest measured
@@ -486,32 +459,42 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
 // float64 512 threads x 32 points, radix-16 passes; pairs in registers in both)
 int default_ols_variant(int logn, bool fp64) { return logn == 14 ? (fp64 ? 2 : 5) : 0; }
 
-void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
+// n_f of a filter set-up that is not autotuned (secondary: the float64 filter of a
+// mixed plan, which takes a forced n_f only when it has a float64 transform)
+int64_t choose_nf(int nf_req, int n_c, int64_t longest, bool fp64, bool secondary) {
   const int maxlog = ols_max_logn(fp64);
+  if (nf_req > 0 && !(secondary && ilog2(nf_req) - 1 > maxlog)) return nf_req;
+  int64_t nf = fft_length_rule(n_c, longest);
+  nf = std::min<int64_t>(nf, int64_t(1) << (kPreferredMaxLogN + 1));
+  if (nf <= 2 * (int64_t)n_c) {
+    nf = 1;
+    while (nf <= 2 * (int64_t)n_c) nf <<= 1;
+  }
+  return std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
+}
+
+int choose_variant(int shape_req, int64_t nf, bool fp64) {
+  const int logn = ilog2(nf) - 1;
+  const int v = shape_req > 0 ? shape_req - 1 : default_ols_variant(logn, fp64);
+  return ols_variant_exists(logn, fp64, v) ? v : 0;
+}
+
+void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
   if (P->nf_req < 0 && !secondary) {
     autotune_filter(P, fs, fp64, s);
     return;
   }
-  int64_t nf;
-  if (P->nf_req > 0 && !(secondary && ilog2(P->nf_req) - 1 > maxlog)) {
-    nf = P->nf_req;
-  } else {
-    int64_t longest = 1;
-    for (int b = 0; b < P->n_iv; ++b)
-      longest = std::max<int64_t>(longest, P->iv_start[b + 1] - P->iv_start[b]);
-    nf = fft_length_rule(P->n_c, longest);
-    nf = std::min<int64_t>(nf, int64_t(1) << (kPreferredMaxLogN + 1));
-    if (nf <= 2 * (int64_t)P->n_c) {
-      nf = 1;
-      while (nf <= 2 * (int64_t)P->n_c) nf <<= 1;
-    }
-    nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
-  }
-  const int variant = P->shape_req > 0 ? P->shape_req - 1 : default_ols_variant(ilog2(nf) - 1, fp64);
-  build_filter_nf(P, fs, fp64, nf, s, variant);
+  const int64_t nf = choose_nf(P->nf_req, P->n_c, longest_interval(P->iv_start), fp64, secondary);
+  build_filter_nf(P, fs, fp64, nf, s, choose_variant(P->shape_req, nf, fp64), false);
 }
 
-void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant) {
+int64_t count_chunks(const std::vector<int64_t>& iv_start, int64_t m) {
+  int64_t c = 0;
+  for (size_t b = 0; b + 1 < iv_start.size(); ++b) c += (iv_start[b + 1] - iv_start[b] + m - 1) / m;
+  return c;
+}
+
+void check_transform_length(int64_t nf, bool fp64) {
   const int maxlog = ols_max_logn(fp64);
   const int logn = ilog2(nf) - 1;
   if (logn > maxlog)
@@ -519,7 +502,13 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
                               std::to_string(int64_t(1) << (maxlog + 1)) +
                               (fp64 ? " for float64" : " for float32"));
   if (logn < kMinLogN) fail(MM_EUNSUPPORTED, "FFT length below 128");
+}
+
+void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant, bool tmp) {
+  check_transform_length(nf, fp64);
+  const int logn = ilog2(nf) - 1;
   if (!ols_variant_exists(logn, fp64, variant)) variant = 0;
+  auto get = [&](int64_t bytes) -> char* { return tmp ? P->temp<char>(bytes) : P->alloc<char>(bytes); };
   fs.fp64 = fp64;
   fs.logn = logn;
   fs.variant = variant;
@@ -536,19 +525,19 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   }
   if (ch.size() > (size_t)0x7fffffff) fail(MM_EUNSUPPORTED, "too many overlap-save chunks");
   fs.n_chunks = (int)ch.size();
-  fs.chunks = P->alloc<OlsChunk>((int64_t)ch.size());
+  fs.chunks = reinterpret_cast<OlsChunk*>(get((int64_t)ch.size() * (int64_t)sizeof(OlsChunk)));
   if (!ch.empty())
     hipchk(hipMemcpyAsync(fs.chunks, ch.data(), ch.size() * sizeof(OlsChunk), hipMemcpyHostToDevice, s),
            "chunk table upload");
   const int esz = fp64 ? 8 : 4;
-  fs.tw2 = P->alloc<char>((int64_t)fs.N * 2 * esz);
+  fs.tw2 = get((int64_t)fs.N * 2 * esz);
   hipchk(launch_tw2_table(fs.tw2, logn, fp64, s), "twiddle table");
   const int ntw = pass_twiddle_count(logn, fp64, variant);
   if (ntw < 0) fail(MM_EUNSUPPORTED, "no transform for this FFT length");
-  fs.ptw = P->alloc<char>((int64_t)std::max(ntw, 1) * 2 * esz);
+  fs.ptw = get((int64_t)std::max(ntw, 1) * 2 * esz);
   hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s, variant), "pass twiddle tables");
-  fs.spec = P->alloc<char>((int64_t)P->n_filt * (fs.N + 1) * esz);
-  char* sscr = P->alloc<char>((int64_t)spectra_scratch_bytes(logn));
+  fs.spec = get((int64_t)P->n_filt * (fs.N + 1) * esz);
+  char* sscr = P->temp<char>((int64_t)spectra_scratch_bytes(logn));
   hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, sscr, s), "filter spectra");
   P->release(sscr);   // later work on this stream may reuse it
   fs.ready = true;
@@ -653,46 +642,64 @@ void rhs_obs(mm_plan_s* P, const FilterSetup& fs, const void* tod, bool tod_f64,
   scatter_all(P, fs.fp64, yb, out, R, s);
 }
 
-void ensure_fp64_path(mm_plan_s* P, hipStream_t s) {
-  if (P->main_fp64()) return;
-  if (!P->fs64.ready) build_filter(P, P->fs64, true, s, true);
-  // the float64 residual pass never overlaps the float32 iteration: it reuses
-  // the TOD work buffers, which mixed plans size for one float64 row
-  P->y64a = (double*)P->y1;
-  P->y64b = (double*)P->y2;
-}
 
 void check_tod_dtype(int32_t dt) {
   if (dt != MM_F32 && dt != MM_F64) fail(MM_EINVAL, "tod_dtype must be MM_F32 or MM_F64");
 }
 
+// Largest TOD one scatter pass reads (rows of up to 4 RHS) for which the pixel-major
+// scatter is used.  A TOD cache line holds hits of several neighbouring pixels,
+// which that scatter reads from different wavefronts (the sliced one from one):
+// measured faster while those re-reads mostly stay in the 256 MiB last-level
+// cache (64 MiB of float32 TOD: 7 % less time per iteration; 128 MiB of float64
+// TOD: 4 % less; 4 RHS x 64 MiB: 6 % less) and slower beyond it (512 MiB: 6 %
+// more; 1 GiB: 5 % more).
+constexpr int64_t kSegTodBytes = int64_t(256) << 20;
+
+// Wavefronts per slice of the scatter over a layout (0 = no slices: the scatter reads
+// the pixel-major arrays as they are)
+int layout_waves(int64_t n_t, bool fp64, int R, int64_t n_obs, int64_t n_valid) {
+  int wps = scatter_waves_per_slice(n_obs > 0 ? (double)n_valid / (double)n_obs : 1.0);
+  const int64_t pass_bytes = n_t * (fp64 ? 8 : 4) * std::min(R, 4);
+  if (wps == 0 && pass_bytes > kSegTodBytes) wps = 8;
+  return wps;
+}
+
+// Entries the sliced copy of a layout with n_valid samples may take (padding to the
+// widest pixel of each slice included); a layout whose slices need more keeps the
+// pixel-major arrays for the scatter.  Bounds the workspace from the descriptor alone.
+int64_t sliced_allowance(int64_t n_valid) { return (2 * n_valid / 64 + 1) * 64; }
+
 // Pixel-major layout of a pointing with one non-zero per row: range check,
 // stable sort of the samples by key, observed compaction (Implementation
 // section, observed index scheme).  Keys lie in [-1, n_keys); -1 = no column.
+// The pixel-major sample ids and weights are temporaries when the scatter will
+// read a sliced copy of them (build_sell), else they are kept.
 void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, const float* d_w, Layout& L,
                   hipStream_t s, const char* range_msg) {
   const int64_t n = P->n_t;
   // The range check is read at the first synchronisation below: the sort and the
   // layout kernels stay in bounds whatever the indices (an index outside the range
   // only misplaces its sample, and the plan fails before anything uses the result).
-  int32_t* flag = P->alloc<int32_t>(1);
+  int32_t* flag = P->temp<int32_t>(1);
   hipchk(launch_fill_i32(flag, 0, 1, s), "fill");
   hipchk(launch_check_pix(d_key, n, n_keys, flag, s), "index check");
   L.obs_idx = P->alloc<int32_t>(n);
+  L.wps = 0;
   if (n == 0) {
     hipchk(hipMemcpyAsync(P->slot<int32_t>(kPinFlag), flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
     hipchk(hipStreamSynchronize(s), "index check");
     if (*P->slot<int32_t>(kPinFlag)) fail(MM_EINVAL, range_msg);
   }
   if (n > 0) {
-    char* scratch = P->alloc<char>((int64_t)sort_scratch_bytes(n));
-    uint32_t* keys = P->alloc<uint32_t>(n);
-    int32_t* vals = P->alloc<int32_t>(n);
+    char* scratch = P->temp<char>((int64_t)sort_scratch_bytes(n));
+    uint32_t* keys = P->temp<uint32_t>(n);
+    int32_t* vals = P->temp<int32_t>(n);
     hipchk(launch_sort_by_pixel(d_key, n, n_keys, keys, vals, scratch, s), "sort by pixel");
     P->release(scratch);
-    uint32_t* seg = P->alloc<uint32_t>(n);
-    char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(n));
-    int64_t* nvalid_d = P->alloc<int64_t>(1);
+    uint32_t* seg = P->temp<uint32_t>(n);
+    char* sscr = P->temp<char>((int64_t)scan_scratch_bytes(n));
+    int64_t* nvalid_d = P->temp<int64_t>(1);
     hipchk(hipMemsetAsync(nvalid_d, 0, sizeof(int64_t), s), "memset");
     hipchk(launch_segment_scan(keys, n, (uint32_t)n_keys, seg, nvalid_d, sscr, s), "observed ids");
     hipchk(hipMemcpyAsync(P->slot<int32_t>(kPinFlag), flag, 4, hipMemcpyDeviceToHost, s), "index check copy");
@@ -702,13 +709,19 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
     if (*P->slot<int32_t>(kPinFlag)) fail(MM_EINVAL, range_msg);
     L.n_obs = *P->slot<uint32_t>(kPinObs);
     L.n_valid = *P->slot<int64_t>(kPinValid);
+    L.wps = layout_waves(n, P->main_fp64(), P->R, L.n_obs, L.n_valid);
     L.ptr = P->alloc<int64_t>(L.n_obs + 1);
     L.obs2glob = P->alloc<int32_t>(L.n_obs);
-    L.perm = P->alloc<int32_t>(L.n_valid);
-    if (ns == 3) L.w_pm = P->alloc<float>(2 * L.n_valid);
+    if (L.wps > 0) {
+      L.perm = P->temp<int32_t>(L.n_valid);
+      if (ns == 3) L.w_pm = P->temp<float>(2 * L.n_valid);
+    } else {
+      L.perm = P->alloc<int32_t>(L.n_valid);
+      if (ns == 3) L.w_pm = P->alloc<float>(2 * L.n_valid);
+    }
     hipchk(launch_build_layout(keys, vals, seg, n, (uint32_t)n_keys, d_w, ns, L.ptr, L.obs2glob, L.w_pm, L.perm, s),
            "pointing layout");
-    int32_t* glob2obs = P->alloc<int32_t>(n_keys);
+    int32_t* glob2obs = P->temp<int32_t>(n_keys);
     hipchk(launch_obs_index(d_key, n, L.obs2glob, L.n_obs, glob2obs, n_keys, L.obs_idx, s), "observed index");
     P->release(glob2obs);
     hipchk(hipMemcpyAsync(L.ptr + L.n_obs, &L.n_valid, 8, hipMemcpyHostToDevice, s), "copy");
@@ -731,33 +744,27 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
   L.group = g;
 }
 
-// Sliced copy of a layout for the scatter; the plain pixel-major copy is dropped.
-// Largest TOD one scatter pass reads (rows of up to 4 RHS) for which the pixel-major
-// scatter is used.  A TOD cache line holds hits of several neighbouring pixels,
-// which that scatter reads from different wavefronts (the sliced one from one):
-// measured faster while those re-reads mostly stay in the 256 MiB last-level
-// cache (64 MiB of float32 TOD: 7 % less time per iteration; 128 MiB of float64
-// TOD: 4 % less; 4 RHS x 64 MiB: 6 % less) and slower beyond it (512 MiB: 6 %
-// more; 1 GiB: 5 % more).
-constexpr int64_t kSegTodBytes = int64_t(256) << 20;
-
+// The scatter's view of a layout: the pixel-major arrays as they are (L.wps = 0), or
+// a sliced copy that replaces them.  A copy that would exceed sliced_allowance
+// entries is not made: the pixel-major arrays are kept instead.
 void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
-  int wps = scatter_waves_per_slice(L.n_obs > 0 ? (double)L.n_valid / (double)L.n_obs : 1.0);
-  const int64_t pass_bytes = P->n_t * (P->main_fp64() ? 8 : 4) * std::min(P->R, 4);
-  if (wps == 0 && pass_bytes > kSegTodBytes) wps = 8;
-  if (wps == 0) {   // pixels with many hits: the scatter reads the pixel-major arrays as they are
+  auto keep_pixel_major = [&]() {
     L.sell_entries = L.n_valid;
     L.sell.wps = 0;
     L.sell.ptr = L.ptr;
     L.sell.perm = L.perm;
     L.sell.w_pm = L.w_pm;
+  };
+  if (L.wps == 0) {   // pixels with many hits: the scatter reads the pixel-major arrays as they are
+    keep_pixel_major();
     return;
   }
   const int64_t n_sl = (L.n_obs + 63) / 64;
   uint32_t* len = P->alloc<uint32_t>(n_sl);
   uint32_t* end = P->alloc<uint32_t>(n_sl);
-  char* sscr = P->alloc<char>((int64_t)scan_scratch_bytes(std::max<int64_t>(n_sl, 1)));
+  char* sscr = P->temp<char>((int64_t)scan_scratch_bytes(std::max<int64_t>(n_sl, 1)));
   uint32_t total = 0;
+  bool fits = true;
   if (n_sl > 0) {
     hipchk(launch_sell_widths(L.ptr, L.n_obs, len, s), "slice widths");
     hipchk(launch_scan_inclusive(len, end, n_sl, sscr, s), "slice offsets");
@@ -773,10 +780,27 @@ void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
       std::vector<uint32_t> hl(n_sl);
       hipchk(hipMemcpy(hl.data(), len, 4 * n_sl, hipMemcpyDeviceToHost), "copy");
       for (uint32_t v : hl) check += v;
-      if (check >= 4294967295.0) fail(MM_EUNSUPPORTED, "sliced pointing exceeds 2^32 - 1 entries");
+      if (check >= 4294967295.0) fits = false;
     }
+    if ((int64_t)total > sliced_allowance(L.n_valid)) fits = false;
   }
   P->release(sscr);
+  if (!fits) {
+    // move the pixel-major arrays out of the temporaries and scatter over them
+    int32_t* perm = P->alloc<int32_t>(L.n_valid);
+    hipchk(hipMemcpyAsync(perm, L.perm, 4 * L.n_valid, hipMemcpyDeviceToDevice, s), "copy");
+    P->release(L.perm);
+    L.perm = perm;
+    if (ns == 3) {
+      float* w = P->alloc<float>(2 * L.n_valid);
+      hipchk(hipMemcpyAsync(w, L.w_pm, 8 * L.n_valid, hipMemcpyDeviceToDevice, s), "copy");
+      P->release(L.w_pm);
+      L.w_pm = w;
+    }
+    L.wps = 0;
+    keep_pixel_major();
+    return;
+  }
   L.sell_entries = total;
   int32_t* st = P->alloc<int32_t>(std::max<int64_t>(total, 1));
   float* sw = ns == 3 ? P->alloc<float>(2 * std::max<int64_t>(total, 1)) : nullptr;
@@ -785,11 +809,11 @@ void build_sell(mm_plan_s* P, Layout& L, int ns, hipStream_t s) {
   L.sell.len = len;
   L.sell.t = st;
   L.sell.w = sw;
-  L.sell.wps = wps;
-  P->release(L.perm);
-  L.perm = nullptr;
+  L.sell.wps = L.wps;
   P->release(L.w_pm);
   L.w_pm = nullptr;
+  P->release(L.perm);
+  L.perm = nullptr;
 }
 
 // Validate the descriptor's templates and build their layouts ("Using MADmap" section).
@@ -865,15 +889,20 @@ void setup_templates(mm_plan_s* P, const mm_desc_t* d, hipStream_t s) {
 // hint[c] = the last interval starting at or before sample c << shift.  Buckets are
 // no longer than the shortest non-empty interval (while the table stays within 2^20
 // entries), so a sample lies at most a few interval starts past its bucket's hint.
-void build_interval_hint(mm_plan_s* P, hipStream_t s) {
-  int64_t lmin = std::max<int64_t>(P->n_t, 1);
-  for (int b = 0; b < P->n_iv; ++b) {
-    const int64_t len = P->iv_start[b + 1] - P->iv_start[b];
+int interval_hint_shift(const std::vector<int64_t>& iv_start, int64_t n_t) {
+  int64_t lmin = std::max<int64_t>(n_t, 1);
+  for (size_t b = 0; b + 1 < iv_start.size(); ++b) {
+    const int64_t len = iv_start[b + 1] - iv_start[b];
     if (len > 0) lmin = std::min(lmin, len);
   }
   int sh = 0;
   while ((int64_t(2) << sh) <= lmin) ++sh;
-  while ((P->n_t >> sh) + 1 > (int64_t(1) << 20)) ++sh;
+  while ((n_t >> sh) + 1 > (int64_t(1) << 20)) ++sh;
+  return sh;
+}
+
+void build_interval_hint(mm_plan_s* P, hipStream_t s) {
+  const int sh = interval_hint_shift(P->iv_start, P->n_t);
   const int64_t nb = (P->n_t >> sh) + 1;
   std::vector<int32_t>& hint = P->iv_hint;
   hint.assign((size_t)nb, 0);
@@ -896,7 +925,7 @@ void build_template_precond(mm_plan_s* P, hipStream_t s) {
     double* dst = P->minv_t + T.ooff;
     if (T.kind == MM_TMPL_ONEHOT) {
       if (T.lay.n_obs == 0) continue;
-      int32_t* sing = P->alloc<int32_t>(T.lay.n_obs);
+      int32_t* sing = P->temp<int32_t>(T.lay.n_obs);
       hipchk(launch_precond_build(1, P->precond, T.lay.group, T.lay.ptr, T.lay.perm, nullptr, P->d_iv_start,
                                   P->n_iv, P->d_iv_hint, P->iv_hint_shift, P->d_iv_filter, P->lags, P->n_c,
                                   T.lay.n_obs, dst, sing, s),
@@ -906,7 +935,7 @@ void build_template_precond(mm_plan_s* P, hipStream_t s) {
     } else if (P->precond == MM_PRECOND_NONE) {
       hipchk(launch_fill_f64(dst, 1.0, T.n_unk, s), "fill");
     } else {
-      double* diag = P->alloc<double>(T.n_unk);
+      double* diag = P->temp<double>(T.n_unk);
       hipchk(launch_hwp_diag(P->precond == MM_PRECOND_BLOCK ? 0 : 1, T.tiles, T.n_tiles, T.d_seg_tile, T.n_seg,
                              T.d_seg, T.omega, P->d_iv_start, P->n_iv, P->d_iv_filter, P->lags, P->n_c, T.partial,
                              diag, s),
@@ -918,7 +947,9 @@ void build_template_precond(mm_plan_s* P, hipStream_t s) {
   }
 }
 
-void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const float* d_w, hipStream_t s) {
+// Host-side checks of a descriptor (before any device work); the interval table
+// and filter parameters are checked as well.
+void validate_desc(const mm_desc_t* d) {
   if (!d) fail(MM_EINVAL, "descriptor is NULL");
   if (d->n_stokes != 1 && d->n_stokes != 3) fail(MM_EINVAL, "n_stokes must be 1 or 3");
   if (d->n_pix < 1 || d->n_pix >= (int64_t(1) << 31) - 1) fail(MM_EINVAL, "n_pix must be in [1, 2^31 - 1)");
@@ -931,12 +962,178 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   if (d->precision != MM_FP64 && d->precision != MM_MIXED) fail(MM_EINVAL, "precision must be MM_FP64 or MM_MIXED");
   if (d->precond < MM_PRECOND_BLOCK || d->precond > MM_PRECOND_NONE) fail(MM_EINVAL, "unknown preconditioner");
   if (d->n_rhs < 1 || d->n_rhs > 64) fail(MM_EINVAL, "n_rhs must be in [1, 64]");
-  if (d->n_samples > 0 && !d_pix) fail(MM_EINVAL, "d_pix is NULL");
-  if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
   if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
     fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
   if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 8]");
   validate_templates(d);
+  if (d->iv_start[0] != 0 || d->iv_start[d->n_intervals] != d->n_samples)
+    fail(MM_EINVAL, "intervals must start at 0 and end at n_samples");
+  for (int b = 0; b < d->n_intervals; ++b) {
+    if (d->iv_start[b + 1] < d->iv_start[b]) fail(MM_EINVAL, "iv_start must be non-decreasing");
+    if (d->iv_filter[b] < 0 || d->iv_filter[b] >= d->n_filters) fail(MM_EINVAL, "iv_filter out of range");
+  }
+  const int ncp = 1 << std::max(kMinLogN, ilog2(d->n_c));
+  const int64_t lag_len = d->lag_dft_len ? d->lag_dft_len : (1 << 20);
+  if (d->filter_params) {
+    if (!(d->f_samp > 0)) fail(MM_EINVAL, "f_samp must be positive");
+    if (!is_pow2(lag_len) || lag_len < 4 * (int64_t)ncp) fail(MM_EINVAL, "lag_dft_len must be a power of two >= 4 n_c");
+    if (ncp > (1 << ols_max_logn(true))) fail(MM_EUNSUPPORTED, "n_c too large for the lag construction");
+    for (int f = 0; f < d->n_filters; ++f) {
+      const double sg = d->filter_params[3 * f], fk = d->filter_params[3 * f + 1], al = d->filter_params[3 * f + 2];
+      if (!(sg > 0) || !(fk >= 0) || !(al > 0) || !std::isfinite(sg) || !std::isfinite(fk) || !std::isfinite(al))
+        fail(MM_EINVAL, "filter parameters need sigma > 0, f_knee >= 0, alpha > 0");
+    }
+  }
+}
+
+int64_t y_bytes(bool fp64, int R, int64_t n) { return fp64 ? (int64_t)R * n * 8 : std::max<int64_t>((int64_t)R * 4, 8) * n; }
+
+// Device bytes of a filter set-up (chunk table, twiddles, spectra) and of the
+// spectra build's scratch
+size_t filter_bytes(const std::vector<int64_t>& iv_start, int n_filt, int n_c, int64_t nf, int variant, bool fp64) {
+  const int logn = ilog2(nf) - 1;
+  const int64_t N = int64_t(1) << logn;
+  const int esz = fp64 ? 8 : 4;
+  const int ntw = pass_twiddle_count(logn, fp64, variant);
+  return block_bytes(count_chunks(iv_start, nf - 2 * n_c) * (int64_t)sizeof(OlsChunk), 1) +
+         block_bytes(N * 2 * esz, 1) + block_bytes((int64_t)std::max(ntw, 1) * 2 * esz, 1) +
+         block_bytes((int64_t)n_filt * (N + 1) * esz, 1);
+}
+
+// Upper bounds of a plan's device memory from its descriptor alone: persistent data,
+// work vectors, the build's temporaries (stacked over the work region) and the
+// temporaries of later calls (stacked above the TOD work buffers).  Every count the
+// data decide is bounded: observed pixels by min(n_pix, n_samples) (one-hot
+// amplitudes by min(n_amp, n_samples)), pointed samples by n_samples, a sliced
+// scatter layout by sliced_allowance, the p.q partial sums by kScatterBlocks per
+// scatter.
+struct PlanBounds {
+  size_t pers = 0, work = 0, temps = 0, call_temps = 0;
+  size_t total() const { return pers + std::max(work + call_temps, temps) + kAlign; }
+};
+
+PlanBounds plan_bounds(const mm_desc_t* d) {
+  validate_desc(d);
+  PlanBounds B;
+  const int64_t n = d->n_samples;
+  const int ns = d->n_stokes, R = d->n_rhs, nf_filt = d->n_filters, n_c = d->n_c;
+  const bool fp64 = d->precision == MM_FP64;
+  const std::vector<int64_t> iv(d->iv_start, d->iv_start + d->n_intervals + 1);
+  const int64_t longest = longest_interval(iv);
+  // pixel-major layout of a pointing with one non-zero per row (build_layout, build_sell)
+  auto layout = [&](int64_t n_keys, int lns, int64_t* n_obs_out) {
+    const int64_t n_obs = std::min<int64_t>(n_keys, n);
+    *n_obs_out = n_obs;
+    B.pers += block_bytes(n, 4);
+    B.temps += block_bytes(1, 4);
+    if (n == 0) {
+      B.pers += block_bytes(1, 8) + 2 * block_bytes(1, 4);
+      return;
+    }
+    const int64_t n_sl = (n_obs + 63) / 64;
+    const int64_t allow = sliced_allowance(n);
+    const size_t csr = block_bytes(n, 4) + (lns == 3 ? block_bytes(2 * n, 4) : 0);
+    const size_t sliced = block_bytes(allow, 4) + (lns == 3 ? block_bytes(2 * allow, 4) : 0);
+    B.pers += block_bytes(n_obs + 1, 8) + block_bytes(n_obs, 4) + 2 * block_bytes(n_sl, 4) + std::max(csr, sliced);
+    B.temps += block_bytes((int64_t)sort_scratch_bytes(n), 1) + 3 * block_bytes(n, 4) +
+               block_bytes((int64_t)scan_scratch_bytes(n), 1) + block_bytes(1, 8) + csr + block_bytes(n_keys, 4) +
+               block_bytes((int64_t)scan_scratch_bytes(std::max<int64_t>(n_sl, 1)), 1);
+  };
+  int64_t n_obs = 0;
+  layout(d->n_pix, ns, &n_obs);
+  int64_t n_tunk = 0, n_pq = n_obs > 0 ? kScatterBlocks : 0;
+  for (int k = 0; k < d->n_templates; ++k) {
+    const mm_template_t& D = d->templates[k];
+    if (D.kind == MM_TMPL_ONEHOT) {
+      int64_t n_amp_obs = 0;
+      layout(D.n_amp, 1, &n_amp_obs);
+      n_tunk += n_amp_obs;
+      n_pq += kScatterBlocks;
+      B.temps += block_bytes(n_amp_obs, 4);                       // preconditioner flags
+    } else {
+      int64_t n_tiles = 0;
+      for (int g = 0; g < D.n_seg; ++g) n_tiles += (D.seg_start[g + 1] - D.seg_start[g] + kTileSamples - 1) / kTileSamples;
+      B.pers += block_bytes(n_tiles, sizeof(SampleTile)) + block_bytes(D.n_seg + 1, 8) + block_bytes(D.n_seg + 1, 4) +
+                block_bytes(std::max<int64_t>(n_tiles, 1) * R * kHwpColumns, 8);
+      n_tunk += (int64_t)kHwpColumns * D.n_seg;
+      n_pq += 1;
+      B.temps += block_bytes((int64_t)kHwpColumns * D.n_seg, 8);  // preconditioner diagonal
+    }
+  }
+  // noise filters
+  const int64_t lag_len = d->lag_dft_len ? d->lag_dft_len : (1 << 20);
+  const int batch = std::max(1, std::min(nf_filt, 16));
+  B.pers += block_bytes((int64_t)nf_filt * n_c, 8);
+  if (d->filter_params) {
+    B.pers += block_bytes(3 * (int64_t)nf_filt, 8);
+    B.temps += block_bytes((int64_t)lags_scratch_bytes(n_c, lag_len, batch), 1);
+  }
+  int logn64 = 0;   // transform of the float64 filter (noise gradient)
+  if (d->n_f < 0) {
+    size_t most = 0, most_tmp = 0;
+    for (int64_t nf : autotune_lengths(n_c, longest, fp64))
+      for (int v = 0; v < kOlsVariants; ++v) {
+        if (!ols_variant_exists(ilog2(nf) - 1, fp64, v)) continue;
+        const size_t fb = filter_bytes(iv, nf_filt, n_c, nf, v, fp64);
+        most = std::max(most, fb);
+        most_tmp = std::max(most_tmp, fb + block_bytes((int64_t)spectra_scratch_bytes(ilog2(nf) - 1), 1));
+        if (fp64) logn64 = std::max(logn64, ilog2(nf) - 1);
+      }
+    B.pers += most;
+    B.temps += 2 * block_bytes(std::max<int64_t>(n, 1) * (fp64 ? 8 : 4), 1) + most_tmp + most;
+  } else {
+    const int64_t nf = choose_nf(d->n_f, n_c, longest, fp64, false);
+    const int logn = ilog2(nf) - 1;
+    check_transform_length(nf, fp64);
+    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, fp64), fp64);
+    B.temps += block_bytes((int64_t)spectra_scratch_bytes(logn), 1);
+    if (fp64) logn64 = logn;
+  }
+  if (!fp64) {
+    const int64_t nf = choose_nf(d->n_f, n_c, longest, true, true);
+    logn64 = ilog2(nf) - 1;
+    check_transform_length(nf, true);
+    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, true), true);
+    B.temps += block_bytes((int64_t)spectra_scratch_bytes(logn64), 1);
+  }
+  // interval tables and their coarse index
+  const int sh = interval_hint_shift(iv, n);
+  B.pers += block_bytes(d->n_intervals + 1, 8) + block_bytes(d->n_intervals, 4) + block_bytes((n >> sh) + 1, 4);
+  // preconditioner
+  B.pers += block_bytes(n_obs * (ns == 1 ? 1 : 6), 8) + block_bytes(std::max<int64_t>(n_tunk, 1), 8);
+  B.temps += block_bytes(n_obs, 4) + block_bytes(1, 8);
+  if (n_c == 1) {
+    int64_t n_wt = 0;
+    for (int b = 0; b < d->n_intervals; ++b) n_wt += (iv[b + 1] - iv[b] + kTileSamples - 1) / kTileSamples;
+    B.pers += block_bytes(n_wt, sizeof(SampleTile));
+  }
+  // scalars, partial sums, residual ring
+  B.pers += 3 * block_bytes((int64_t)R * kDotBlocks, 8) + block_bytes((int64_t)R * std::max<int64_t>(n_pq, 1), 8) +
+            2 * block_bytes(R, sizeof(CgState)) + block_bytes((int64_t)R * kHistRing, 8);
+  // work vectors
+  const int64_t nu = n_obs * ns + n_tunk;
+  B.work = 2 * block_bytes(y_bytes(fp64, R, n), 1) + 7 * block_bytes((int64_t)R * nu, 8);
+  if (!fp64)
+    B.work += block_bytes((int64_t)R * std::max<int64_t>(n_obs * ns, 1), 4) + 2 * block_bytes((int64_t)R * nu, 8) +
+              (d->n_templates > 0 ? block_bytes((int64_t)R * nu, 8) : 0);
+  // noise gradient
+  if (d->filter_params) {
+    const int64_t N64 = int64_t(1) << logn64;
+    B.call_temps = block_bytes(std::max<int64_t>(n, 1), 8) + block_bytes((int64_t)nf_filt * n_c, 8) +
+                   block_bytes(3 * (int64_t)nf_filt * (N64 + 1), 8) + block_bytes(3 * (int64_t)std::max(d->n_intervals, 1), 8) +
+                   block_bytes((int64_t)std::max(lags_scratch_bytes(n_c, lag_len, batch),
+                                                 spectra_scratch_bytes(logn64)), 1);
+  }
+  return B;
+}
+
+// Build a plan in the workspace ws of ws_bytes (the caller's), or, with ws = NULL,
+// in one block of the bound's size that the plan allocates and frees itself.
+void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const float* d_w, void* ws,
+                size_t ws_bytes, hipStream_t s) {
+  const PlanBounds bounds = plan_bounds(d);
+  if (d->n_samples > 0 && !d_pix) fail(MM_EINVAL, "d_pix is NULL");
+  if (d->n_stokes == 3 && d->n_samples > 0 && !d_w) fail(MM_EINVAL, "d_w is NULL for polarised pointing");
 
   P->ns = d->n_stokes;
   P->n_pix = d->n_pix;
@@ -953,26 +1150,24 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   P->w = d_w;
   P->iv_start.assign(d->iv_start, d->iv_start + d->n_intervals + 1);
   P->iv_filter.assign(d->iv_filter, d->iv_filter + d->n_intervals);
-  if (P->iv_start[0] != 0 || P->iv_start[P->n_iv] != P->n_t)
-    fail(MM_EINVAL, "intervals must start at 0 and end at n_samples");
-  for (int b = 0; b < P->n_iv; ++b) {
-    if (P->iv_start[b + 1] < P->iv_start[b]) fail(MM_EINVAL, "iv_start must be non-decreasing");
-    if (P->iv_filter[b] < 0 || P->iv_filter[b] >= P->n_filt) fail(MM_EINVAL, "iv_filter out of range");
-  }
-  int ncp = 1 << std::max(kMinLogN, ilog2(P->n_c));
   P->lag_len = d->lag_dft_len ? d->lag_dft_len : (1 << 20);
-  if (d->filter_params) {
-    if (!(d->f_samp > 0)) fail(MM_EINVAL, "f_samp must be positive");
-    if (!is_pow2(P->lag_len) || P->lag_len < 4 * (int64_t)ncp)
-      fail(MM_EINVAL, "lag_dft_len must be a power of two >= 4 n_c");
-    if (ncp > (1 << ols_max_logn(true))) fail(MM_EUNSUPPORTED, "n_c too large for the lag construction");
-    P->params.assign(d->filter_params, d->filter_params + 3 * (size_t)P->n_filt);
-    for (int f = 0; f < P->n_filt; ++f) {
-      const double sg = P->params[3 * f], fk = P->params[3 * f + 1], al = P->params[3 * f + 2];
-      if (!(sg > 0) || !(fk >= 0) || !(al > 0) || !std::isfinite(sg) || !std::isfinite(fk) || !std::isfinite(al))
-        fail(MM_EINVAL, "filter parameters need sigma > 0, f_knee >= 0, alpha > 0");
-    }
+  if (d->filter_params) P->params.assign(d->filter_params, d->filter_params + 3 * (size_t)P->n_filt);
+
+  const size_t need = bounds.total();
+  if (ws) {
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+      fail(MM_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " + std::to_string(need) +
+                          " bytes mm_plan_workspace_size gives for this descriptor");
+    P->ws = static_cast<char*>(ws);
+    P->ws_size = ws_bytes;
+  } else {
+    hipchk(hipMalloc((void**)&P->ws, need), "hipMalloc of the plan's device memory");
+    P->ws_owned = true;
+    P->ws_size = need;
   }
+  P->pers_lim = bounds.pers;
+  P->work_top = P->tmp_base = P->tmp_peak = P->pers_lim;
 
   hipchk(hipGetDevice(&P->device), "hipGetDevice");
   P->own = stream_take(P->device);
@@ -981,10 +1176,11 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   // one pinned block: the CG states, scalar slots, and the dot partials of dots2
   // (device-to-host copies into pageable memory are staged and serialise)
   const size_t st_bytes = (sizeof(CgState) * P->R + 255) & ~(size_t)255;
-  hipchk(hipHostMalloc((void**)&P->st_host, st_bytes + kPinSlots * 8 + sizeof(double) * 2 * P->R * kDotBlocks,
-                       hipHostMallocDefault),
-         "pinned state");
+  const size_t pin_bytes = st_bytes + kPinSlots * 8 + sizeof(double) * 2 * P->R * kDotBlocks;
+  hipchk(hipHostMalloc((void**)&P->st_host, pin_bytes, hipHostMallocDefault), "pinned state");
   P->pin = reinterpret_cast<char*>(P->st_host) + st_bytes;
+  hipchk(hipHostMalloc((void**)&P->hist_host, sizeof(double) * P->R * kHistRing, hipHostMallocDefault),
+         "pinned history");
 
   const int64_t n = P->n_t;
   // ---- pointing: range check, sort by pixel, observed layout
@@ -1007,12 +1203,14 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
            "parameter upload");
     const int batch = std::max(1, std::min(P->n_filt, 16));
     const size_t sb = lags_scratch_bytes(P->n_c, P->lag_len, batch);
-    char* scr = P->alloc<char>((int64_t)sb);
+    char* scr = P->temp<char>((int64_t)sb);
     hipchk(launch_lags(dparams, P->n_filt, P->f_samp, P->n_c, P->lag_len, P->lags, scr, sb, s),
            "lag construction");
     P->release(scr);
   }
   build_filter(P, P->fs_main, P->main_fp64(), s);
+  // mixed plans: the float64 filter of the right-hand side and the residual replacements
+  if (!P->main_fp64()) build_filter(P, P->fs64, true, s, true);
 
   // ---- preconditioner
   P->d_iv_start = P->alloc<int64_t>(P->n_iv + 1);
@@ -1023,8 +1221,8 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   const int nm = P->ns == 1 ? 1 : 6;
   P->minv = P->alloc<double>(P->n_obs * nm);
   {
-    int32_t* sing = P->alloc<int32_t>(P->n_obs);
-    unsigned long long* cnt = P->alloc<unsigned long long>(1);
+    int32_t* sing = P->temp<int32_t>(P->n_obs);
+    unsigned long long* cnt = P->temp<unsigned long long>(1);
     hipchk(launch_precond_build(P->ns, P->precond, P->px.group, P->px.ptr, P->px.perm, P->px.w_pm, P->d_iv_start,
                                 P->n_iv, P->d_iv_hint, P->iv_hint_shift, P->d_iv_filter, P->lags, P->n_c, P->n_obs,
                                 P->minv, sing, s),
@@ -1068,27 +1266,42 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
     hipchk(hipStreamSynchronize(s), "tiles");
   }
 
-  // ---- work buffers
-  const int64_t ybytes = P->main_fp64() ? (int64_t)P->R * n * 8 : std::max<int64_t>((int64_t)P->R * 4, 8) * n;
-  P->y1 = P->alloc<char>(ybytes);
-  P->y2 = P->alloc<char>(ybytes);
-  const int64_t vn = (int64_t)P->R * P->nu();
-  P->vx = P->alloc<double>(vn);
-  P->vp = P->alloc<double>(vn);
-  P->vr = P->alloc<double>(vn);
-  P->vz = P->alloc<double>(vn);
-  P->vq = P->alloc<double>(vn);
-  P->vxb = P->alloc<double>(vn);
-  P->vb = P->alloc<double>(vn);
+  // ---- work vectors: the build's temporaries are all released, the region is free
+  if (!P->tmps.empty()) fail(MM_EDEVICE, "internal: plan temporaries outlive the build");
   P->part1 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part2 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part3 = P->alloc<double>((int64_t)P->R * kDotBlocks);
   P->part_pq = P->alloc<double>((int64_t)P->R * std::max(P->n_pq, 1));
   P->st = P->alloc<CgState>(P->R);
   P->st_prev = P->alloc<CgState>(P->R);
-  // mixed iterations gather the search direction from a float32 copy of its map part
-  // (half the map bytes; the gathered TOD is float32 anyway)
-  if (!P->main_fp64()) P->vp32 = P->alloc<float>((int64_t)P->R * std::max<int64_t>(P->vs32(), 1));
+  P->hist = P->alloc<double>((int64_t)P->R * kHistRing);
+  const int64_t ybytes = y_bytes(P->main_fp64(), P->R, n);
+  P->y1 = P->work<char>(ybytes);
+  P->y2 = P->work<char>(ybytes);
+  const int64_t vn = (int64_t)P->R * P->nu();
+  P->vx = P->work<double>(vn);
+  P->vp = P->work<double>(vn);
+  P->vr = P->work<double>(vn);
+  P->vz = P->work<double>(vn);
+  P->vq = P->work<double>(vn);
+  P->vxb = P->work<double>(vn);
+  P->vb = P->work<double>(vn);
+  if (!P->main_fp64()) {
+    // mixed iterations gather the search direction from a float32 copy of its map part
+    // (half the map bytes; the gathered TOD is float32 anyway); reliable updates keep b
+    // and the best iterate in float64, and the float64 residual passes reuse the TOD
+    // work buffers, sized for one float64 row
+    P->vp32 = P->work<float>((int64_t)P->R * std::max<int64_t>(P->vs32(), 1));
+    P->vb64 = P->work<double>(vn);
+    P->vxbest = P->work<double>(vn);
+    if (!P->tmpl.empty()) P->vxacc = P->work<double>(vn);
+    P->y64a = (double*)P->y1;
+    P->y64b = (double*)P->y2;
+  }
+  // later temporaries (noise gradient) are stacked above the work vectors
+  P->tmp_base = P->work_top;
+  hipchk(hipEventCreateWithFlags(&P->ev_ready, hipEventDisableTiming), "event");
+  hipchk(hipEventRecord(P->ev_ready, s), "event");
 }
 
 // queue one PCG iteration for every RHS
@@ -1104,7 +1317,7 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
                           P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
   hipchk(launch_cg_step_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->st_prev, P->part2, P->part3, P->hist,
-                             P->hist_cap, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
+                             kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
          "scalar step and next direction");
 }
 
@@ -1148,7 +1361,7 @@ void dots2(mm_plan_s* P, const double* x, const double* y, const double* z, int 
 // than the kernels the capture is paid back by the second solve
 void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph) {
   if (use_graph && step == k && k > 0 && P->solves > 0) {
-    if (!P->graph || P->graph_k != k || P->graph_hist != P->hist) {
+    if (!P->graph || P->graph_k != k) {
       if (P->graph) {
         hipchk(hipGraphExecDestroy(P->graph), "graph destroy");
         P->graph = nullptr;
@@ -1166,7 +1379,6 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
       hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
       hipchk(hipGraphDestroy(g), "graph destroy");
       P->graph_k = k;
-      P->graph_hist = P->hist;
     }
     hipchk(hipGraphLaunch(P->graph, s), "graph launch");
   } else {
@@ -1218,11 +1430,26 @@ struct BlockSizer {
   }
 };
 
+// Copy the device's residual ring after a block and append the iterations the host
+// has not seen yet to hseq [R][n_max + 1] (blocks are shorter than the ring).
+void read_history(mm_plan_s* P, int n_max, std::vector<int>& seen, std::vector<double>& hseq, double scale = 1.0,
+                  const std::vector<int>* offset = nullptr) {
+  for (int r = 0; r < P->R; ++r) {
+    const CgState& c = P->st_host[r];
+    const int base = offset ? (*offset)[r] : 0;
+    for (int i = seen[r] + 1; i <= c.iter; ++i)
+      if (base + i <= n_max)
+        hseq[(size_t)r * (n_max + 1) + base + i] = scale * P->hist_host[(size_t)r * kHistRing + i % kHistRing];
+    seen[r] = std::max(seen[r], c.iter);
+  }
+}
+
 // PCG on H x = vb (observed layout) in the iteration precision of fs_main.
 // vb must hold the right-hand sides; x0 is read from vx when have_x0.  On
-// exit vxb holds the lowest-residual iterate and st_host the final states.
+// exit vxb holds the lowest-residual iterate and st_host the final states;
+// hseq [R][n_max + 1] the relative residual per iteration (entry 0 = start).
 void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int check_every,
-             bool use_graph, bool have_x0) {
+             bool use_graph, bool have_x0, std::vector<double>& hseq) {
   const int R = P->R;
   const int64_t nu = P->nu();
   if (have_x0) {
@@ -1240,13 +1467,17 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
   hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
   hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
   hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
-  hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, tol, fixed ? 1 : 0, R, P->hist,
-                        P->hist_cap, s),
+  hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, tol, fixed ? 1 : 0, R, P->hist, kHistRing, s),
          "init");
 
+  hseq.assign((size_t)R * (n_max + 1), std::nan(""));
+  std::vector<int> seen(R, -1);
   auto all_done = [&]() {
     hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
+    hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * kHistRing, hipMemcpyDeviceToHost, s),
+           "history copy");
     hipchk(hipStreamSynchronize(s), "solve");
+    read_history(P, n_max, seen, hseq);
     for (int r = 0; r < R; ++r)
       if (P->st_host[r].active) return false;
     return true;
@@ -1254,7 +1485,7 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
 
   int done = 0;
   bool finished = all_done();
-  const int k = std::min(check_every, std::max(1, n_max));
+  const int k = std::min({check_every, std::max(1, n_max), kMaxCheckEvery});
   BlockSizer sizer(R);
   while (!finished && done < n_max) {
     const int step = std::min(fixed ? k : sizer.next(P->st_host, k, tol), n_max - done);
@@ -1262,13 +1493,6 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
     done += step;
     finished = all_done();
   }
-}
-
-void ensure_refine_vectors(mm_plan_s* P) {
-  if (P->vb64) return;
-  const int64_t vn = (int64_t)P->R * P->nu();
-  P->vb64 = P->alloc<double>(vn);
-  P->vxbest = P->alloc<double>(vn);
 }
 
 // out_r = b64_r - H64 x_r for RHS r, in float64 (through the float64 filter)
@@ -1316,21 +1540,10 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
   const bool refine = !P->main_fp64() && o.refine && !fixed;
   hipStream_t s = P->own;
 
-  // order the plan stream after the caller's work
+  // order the plan stream after the plan's build and the caller's work
+  wait_ready(P, s);
   hipchk(hipEventRecord(P->ev_in, caller), "event");
   hipchk(hipStreamWaitEvent(s, P->ev_in, 0), "event wait");
-
-  if (P->hist_cap < n_max + 1) {
-    if (P->hist) P->release(P->hist);
-    if (P->hist_host) {
-      hipchk(hipHostFree(P->hist_host), "pinned history");
-      P->hist_host = nullptr;
-    }
-    P->hist_cap = n_max + 1;
-    P->hist = P->alloc<double>((int64_t)R * P->hist_cap);
-    hipchk(hipHostMalloc((void**)&P->hist_host, sizeof(double) * R * P->hist_cap, hipHostMallocDefault),
-           "pinned history");
-  }
 
   std::vector<int> iters(R, 0), best_iter(R, 0);
   std::vector<double> best_rel(R, 0.0), tres(R, std::nan(""));
@@ -1340,16 +1553,12 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
   if (!refine) {
     make_rhs(P, src, P->fs_main, 0, R, P->vb, P->y2, s);
     if (o.d_x0) to_obs(P, o.d_x0, P->vx, R, s);
-    run_pcg(P, s, o.tol, n_max, fixed, o.check_every, o.use_graph != 0, o.d_x0 != nullptr);
-    const double* hh = P->hist_host;
-    hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * P->hist_cap, hipMemcpyDeviceToHost, s), "copy");
-    hipchk(hipStreamSynchronize(s), "history");
+    run_pcg(P, s, o.tol, n_max, fixed, o.check_every, o.use_graph != 0, o.d_x0 != nullptr, hist_out);
     for (int r = 0; r < R; ++r) {
       const CgState& c = P->st_host[r];
       iters[r] = c.iter;
       best_iter[r] = c.best_iter;
       best_rel[r] = c.best_rel;
-      for (int i = 0; i <= c.iter && i <= n_max; ++i) hist_out[(size_t)r * (n_max + 1) + i] = hh[(size_t)r * P->hist_cap + i];
       if (!fixed && c.bnorm > 0 && !(c.rel <= o.tol) && !(c.best_rel <= o.tol)) notconv = true;
     }
     to_glob(P, P->vxb, d_x, R, s);
@@ -1363,8 +1572,6 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     // between checks are sized (BlockSizer) so that the recurrence residual is not
     // predicted to fall more than kMixedMaxDrop decades below the last float64 one.
     // The iterate with the lowest true residual is returned.
-    ensure_fp64_path(P, s);
-    ensure_refine_vectors(P);
     for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
     hipchk(hipMemcpyAsync(P->vb, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     if (o.d_x0) {
@@ -1382,7 +1589,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
     hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
     hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
-    hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, o.tol, 0, R, P->hist, P->hist_cap, s), "init");
+    hipchk(launch_cg_init(P->st, P->part1, P->part2, P->part3, o.tol, 0, R, P->hist, kHistRing, s), "init");
     hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
     hipchk(hipStreamSynchronize(s), "init");
     std::vector<double> last_true(R), best_true(R);
@@ -1441,8 +1648,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       hipchk(hipMemcpyAsync(P->st, P->st_host, sizeof(CgState) * R, hipMemcpyHostToDevice, s), "state copy");
     };
 
-    const double* hh = P->hist_host;
-    const int k = std::min(std::max(o.check_every, 1), std::max(1, n_max));
+    std::vector<int> seen(R, 0);   // iterations whose residual the host has read
+    const int k = std::min({std::max(o.check_every, 1), std::max(1, n_max), kMaxCheckEvery});
     int done = 0;
     auto any_active = [&]() {
       for (int r = 0; r < R; ++r)
@@ -1455,13 +1662,13 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       iterate_block(P, s, step, k, o.use_graph != 0);
       done += step;
       hipchk(hipMemcpyAsync(P->st_host, P->st, sizeof(CgState) * R, hipMemcpyDeviceToHost, s), "state copy");
-      hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * P->hist_cap, hipMemcpyDeviceToHost, s), "copy");
+      hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * kHistRing, hipMemcpyDeviceToHost, s),
+             "history copy");
       hipchk(hipStreamSynchronize(s), "solve");
+      read_history(P, n_max, seen, hist_out);
       std::vector<int> rows;
       for (int r = 0; r < R; ++r) {
         const CgState& c = P->st_host[r];
-        for (int i = rep_iter[r] + 1; i <= c.iter && i <= n_max; ++i)
-          hist_out[(size_t)r * (n_max + 1) + i] = hh[(size_t)r * P->hist_cap + i];
         if (c.bnorm > 0 && (c.iter > rep_iter[r] || (c.breakdown && restarted[r] != c.iter)) &&
             (!c.active || c.rel <= o.tol || c.rel <= kMixedReplaceFall * last_true[r] || done >= n_max))
           rows.push_back(r);
@@ -1484,9 +1691,6 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     // the lowest true residual is kept.  (One long float32-operator CG, as in the
     // reliable updates, drifts along directions the float64 H nearly annihilates:
     // invisible in the residual, not in the fitted TOD.)
-    ensure_fp64_path(P, s);
-    ensure_refine_vectors(P);
-    if (!P->vxacc) P->vxacc = P->alloc<double>((int64_t)R * nu);
     double* const vr64 = P->vb;   // the true residual is the correction equation's right-hand side
     for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
     if (o.d_x0) {
@@ -1508,7 +1712,6 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
         hist_out[(size_t)r * (n_max + 1)] = rel[r];
       }
     }
-    const double* hh = P->hist_host;
     for (int outer = 0; outer < 30; ++outer) {
       // right-hand sides of the correction equation; RHS already converged get 0
       double worst = 0.0;
@@ -1529,9 +1732,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       const double tau = std::max(o.tol / worst, 1e-5);
       int budget = 0;
       for (int r = 0; r < R; ++r) budget = std::max(budget, n_max - iters[r]);
-      run_pcg(P, s, tau, budget, false, o.check_every, o.use_graph != 0, false);
-      hipchk(hipMemcpyAsync(P->hist_host, P->hist, sizeof(double) * R * P->hist_cap, hipMemcpyDeviceToHost, s), "copy");
-      hipchk(hipStreamSynchronize(s), "history");
+      std::vector<double> inner;   // the correction solve's residuals, relative to its right-hand side
+      run_pcg(P, s, tau, budget, false, o.check_every, o.use_graph != 0, false, inner);
       // x += d (rows of converged RHS add 0)
       hipchk(launch_axpby(P->vxacc, P->vxb, 1.0, 1.0, (int64_t)R * nu, s), "accumulate");
       for (int r = 0; r < R; ++r) residual64_row(P, P->vxacc, vr64, r, s);
@@ -1540,7 +1742,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
         const CgState& c = P->st_host[r];
         const double scale = rel[r];
         for (int i = 1; i <= c.iter && iters[r] + i <= n_max; ++i)
-          hist_out[(size_t)r * (n_max + 1) + iters[r] + i] = scale * hh[(size_t)r * P->hist_cap + i];
+          hist_out[(size_t)r * (n_max + 1) + iters[r] + i] = scale * inner[(size_t)r * (budget + 1) + i];
         iters[r] += c.iter;
         rel[r] = bn[r] > 0 ? std::sqrt(rr[r]) / bn[r] : 0.0;
         if (iters[r] <= n_max) hist_out[(size_t)r * (n_max + 1) + iters[r]] = rel[r];
@@ -1561,7 +1763,6 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
 
   if (o.true_residual && P->n_obs > 0 && !refine) {
     // ||b - H x|| / ||b|| in float64, one RHS at a time
-    if (!P->main_fp64()) ensure_fp64_path(P, s);
     const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
     void* ya = P->main_fp64() ? P->y1 : (void*)P->y64a;
     void* yb = P->main_fp64() ? P->y2 : (void*)P->y64b;
@@ -1599,6 +1800,30 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
 
 }  // namespace
 
+namespace {
+
+mm_status_t plan_impl(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* ws, size_t ws_bytes,
+                      void* stream, mm_plan_t* out_plan) {
+  if (!out_plan) {
+    g_last_error = "out_plan is NULL";
+    return MM_EINVAL;
+  }
+  *out_plan = nullptr;
+  mm_plan_s* P = nullptr;
+  const mm_status_t st = guarded([&] {
+    P = new mm_plan_s();
+    build_plan(P, desc, d_pix, d_w, ws, ws_bytes, as_stream(stream));
+  });
+  if (st != MM_OK) {
+    delete P;
+    return st;
+  }
+  *out_plan = P;
+  return MM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void mm_solve_opts_default(mm_solve_opts_t* o) {
@@ -1613,40 +1838,34 @@ void mm_solve_opts_default(mm_solve_opts_t* o) {
   o->refine = 1;
 }
 
-mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* stream,
-                           mm_plan_t* out_plan) {
-  if (!out_plan) {
-    g_last_error = "out_plan is NULL";
-    return MM_EINVAL;
-  }
-  *out_plan = nullptr;
-  mm_plan_s* P = nullptr;
-  const mm_status_t st = guarded([&] {
-    P = new mm_plan_s();
-    build_plan(P, desc, d_pix, d_w, as_stream(stream));
+
+mm_status_t mm_plan_workspace_size(const mm_desc_t* desc, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) fail(MM_EINVAL, "bytes is NULL");
+    *bytes = plan_bounds(desc).total();
   });
-  if (st != MM_OK) {
-    delete P;
-    return st;
-  }
-  *out_plan = P;
-  return MM_OK;
 }
 
-mm_status_t mm_plan_destroy(mm_plan_t plan) {
+mm_status_t mm_plan(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* d_ws, size_t ws_bytes,
+                    void* stream, mm_plan_t* out_plan) {
+  if (!d_ws) {
+    g_last_error = "d_ws is NULL";
+    if (out_plan) *out_plan = nullptr;
+    return MM_EINVAL;
+  }
+  return plan_impl(desc, d_pix, d_w, d_ws, ws_bytes, stream, out_plan);
+}
+
+mm_status_t mm_plan_create(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* stream,
+                           mm_plan_t* out_plan) {
+  return plan_impl(desc, d_pix, d_w, nullptr, 0, stream, out_plan);
+}
+
+mm_status_t mm_destroy(mm_plan_t plan) {
   return guarded([&] { delete plan; });
 }
 
-mm_status_t mm_set_cache_limit(int32_t device, int64_t bytes, int64_t* previous) {
-  return guarded([&] {
-    int n = 0;
-    hipchk(hipGetDeviceCount(&n), "device count");
-    if (device < 0 || device >= n || device >= 64) fail(MM_EINVAL, "device out of range");
-    if (bytes < 0) fail(MM_EINVAL, "bytes must be >= 0");
-    const size_t prev = cache_set_cap(device, (size_t)bytes);
-    if (previous) *previous = (int64_t)prev;
-  });
-}
+mm_status_t mm_plan_destroy(mm_plan_t plan) { return mm_destroy(plan); }
 
 mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
   return guarded([&] {
@@ -1659,24 +1878,27 @@ mm_status_t mm_plan_get_info(mm_plan_t P, mm_plan_info_t* info) {
     info->n_sliced = P->px.sell_entries;
     info->n_tmpl = P->n_tglob;
     info->fft_shape = P->fs_main.variant + 1;
-    info->device_bytes = P->bytes;
+    info->device_bytes = P->bytes();
   });
 }
 
 mm_status_t mm_hits(mm_plan_t P, int32_t* d_hits, void* stream) {
   return guarded([&] {
     if (!P || !d_hits) fail(MM_EINVAL, "NULL argument");
-    hipchk(launch_hits(P->px.ptr, P->px.obs2glob, d_hits, P->n_obs, P->n_pix, as_stream(stream)), "hits");
+    hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
+    hipchk(launch_hits(P->px.ptr, P->px.obs2glob, d_hits, P->n_obs, P->n_pix, s), "hits");
   });
 }
 
 mm_status_t mm_filter_lags(mm_plan_t P, double* lags_out, void* stream) {
-  (void)stream;
   return guarded([&] {
     if (!P || !lags_out) fail(MM_EINVAL, "NULL argument");
-    // the lags were complete when the plan was returned (its build waits on later work)
-    hipchk(hipMemcpy(lags_out, P->lags, sizeof(double) * (size_t)P->n_filt * P->n_c, hipMemcpyDeviceToHost),
+    hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
+    hipchk(hipMemcpyAsync(lags_out, P->lags, sizeof(double) * (size_t)P->n_filt * P->n_c, hipMemcpyDeviceToHost, s),
            "lag download");
+    hipchk(hipStreamSynchronize(s), "lag download");
   });
 }
 
@@ -1685,6 +1907,7 @@ mm_status_t mm_unpoint(mm_plan_t P, const double* d_x, void* d_y, int32_t tod_dt
     if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
     to_obs(P, d_x, P->vq, P->R, s);
     gather_all(P, tod_dtype == MM_F64, P->vq, d_y, P->R, s);
   });
@@ -1695,6 +1918,7 @@ mm_status_t mm_point(mm_plan_t P, const void* d_y, int32_t tod_dtype, double* d_
     if (!P || !d_x || (!d_y && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
     scatter_all(P, tod_dtype == MM_F64, d_y, P->vq, P->R, s);
     to_glob(P, P->vq, d_x, P->R, s);
   });
@@ -1706,6 +1930,7 @@ mm_status_t mm_weight(mm_plan_t P, const void* d_y_in, void* d_y_out, int32_t to
     check_tod_dtype(tod_dtype);
     if (d_y_in == d_y_out && P->n_t > 0) fail(MM_EINVAL, "y_out must not alias y_in");
     hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
     const bool in64 = tod_dtype == MM_F64;
     const bool t64 = P->main_fp64();
     if (in64 == t64) {
@@ -1721,6 +1946,7 @@ mm_status_t mm_apply_A(mm_plan_t P, const double* d_x, double* d_y, void* stream
   return guarded([&] {
     if (!P || !d_x || !d_y) fail(MM_EINVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
     to_obs(P, d_x, P->vz, P->R, s);
     apply_H_obs(P, P->fs_main, P->vz, P->vq, P->y1, P->y2, P->R, s);
     to_glob(P, P->vq, d_y, P->R, s);
@@ -1732,6 +1958,7 @@ mm_status_t mm_rhs(mm_plan_t P, const void* d_tod, int32_t tod_dtype, double* d_
     if (!P || !d_b || (!d_tod && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     hipStream_t s = as_stream(stream);
+    wait_ready(P, s);
     rhs_obs(P, P->fs_main, d_tod, tod_dtype == MM_F64, P->vq, P->y2, P->R, s);
     to_glob(P, P->vq, d_b, P->R, s);
   });
@@ -1765,57 +1992,70 @@ mm_status_t mm_solve_rhs(mm_plan_t P, const double* d_b, double* d_x, const mm_s
   return st != MM_OK ? st : result;
 }
 
-mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_u, const void* d_v, int32_t tod_dtype,
-                              double* grad_out, void* stream) {
+mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_tod, int32_t tod_dtype, const double* d_m,
+                              const double* d_lambda, double* grad_out, void* stream) {
   return guarded([&] {
-    if (!P || !grad_out || ((!d_u || !d_v) && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
+    if (!P || !grad_out || !d_m || !d_lambda || (!d_tod && P->n_t > 0)) fail(MM_EINVAL, "NULL argument");
     check_tod_dtype(tod_dtype);
     if (!P->d_params) fail(MM_EUNSUPPORTED, "the plan was built from explicit lags: no noise parameters");
     hipStream_t s = as_stream(stream);
-    ensure_fp64_path(P, s);
+    wait_ready(P, s);
     const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
-    double* ya = P->main_fp64() ? (double*)P->y1 : P->y64a;   // u_r in float64
+    double* ya = P->main_fp64() ? (double*)P->y1 : P->y64a;   // d, then u = P lambda_r, in float64
     double* yb = P->main_fp64() ? (double*)P->y2 : P->y64b;   // dN^-1/dtheta v_r
     const bool in64 = tod_dtype == MM_F64;
     const int esz = in64 ? 8 : 4;
-    double* dlags = P->alloc<double>((int64_t)P->n_filt * P->n_c);
-    double* dspec = P->alloc<double>((int64_t)P->n_filt * (f64.N + 1));
-    double* ivd = P->alloc<double>(std::max(P->n_iv, 1));
-    const int batch = std::max(1, std::min(P->n_filt, 16));
+    const int nfl = P->n_filt, n_iv = std::max(P->n_iv, 1);
+    const int64_t spec_n = (int64_t)nfl * (f64.N + 1);
+    const int batch = std::max(1, std::min(nfl, 16));
     const size_t lsb = lags_scratch_bytes(P->n_c, P->lag_len, batch);
-    char* lscr = P->alloc<char>((int64_t)std::max(lsb, spectra_scratch_bytes(f64.logn)));
-    std::vector<double> hd(std::max(P->n_iv, 1));
-    std::vector<double> grad((size_t)P->R * P->n_filt * 3, 0.0);
+    // temporaries above the work vectors, released in reverse order on every exit
+    double* v64 = P->temp<double>(std::max<int64_t>(P->n_t, 1));               // v_r = d_r - P m_r
+    double* dlags = P->temp<double>((int64_t)nfl * P->n_c);
+    double* dspec = P->temp<double>(3 * spec_n);                                   // one symbol per theta
+    double* ivd = P->temp<double>(3 * (int64_t)n_iv);
+    char* lscr = P->temp<char>((int64_t)std::max(lsb, spectra_scratch_bytes(f64.logn)));
+    auto release_all = [&]() {
+      P->release(lscr);
+      P->release(ivd);
+      P->release(dspec);
+      P->release(dlags);
+      P->release(v64);
+    };
+    std::vector<double> hd(3 * (size_t)n_iv);
+    std::vector<double> grad((size_t)nfl * 3, 0.0);
     try {
       for (int mode = 1; mode <= 3; ++mode) {
-        hipchk(launch_lags(P->d_params, P->n_filt, P->f_samp, P->n_c, P->lag_len, dlags, lscr, lsb, s, mode),
+        hipchk(launch_lags(P->d_params, nfl, P->f_samp, P->n_c, P->lag_len, dlags, lscr, lsb, s, mode),
                "derivative lags");
-        hipchk(launch_spectra(dlags, P->n_filt, P->n_c, f64.logn, true, dspec, lscr, s), "derivative spectra");
-        for (int r = 0; r < P->R; ++r) {
-          const void* u_r = (const char*)d_u + (size_t)r * P->n_t * esz;
-          const void* v_r = (const char*)d_v + (size_t)r * P->n_t * esz;
-          hipchk(launch_ols(true, in64, f64.logn, v_r, yb, f64.chunks, f64.n_chunks, dspec, f64.ptw, f64.tw2,
-                            P->n_t, P->n_c, f64.m, 1, s, f64.variant),
+        hipchk(launch_spectra(dlags, nfl, P->n_c, f64.logn, true, dspec + (mode - 1) * spec_n, lscr, s),
+               "derivative spectra");
+      }
+      for (int r = 0; r < P->R; ++r) {
+        // v_r = d_r - P m_r and u_r = P lambda_r, both in float64
+        to_obs(P, d_m + (int64_t)r * P->ng(), P->vz, 1, s);
+        gather_all(P, true, P->vz, v64, 1, s);
+        hipchk(launch_convert(in64, true, (const char*)d_tod + (size_t)r * P->n_t * esz, ya, P->n_t, s), "convert");
+        hipchk(launch_sub(v64, ya, v64, P->n_t, s), "residual TOD");
+        to_obs(P, d_lambda + (int64_t)r * P->ng(), P->vz, 1, s);
+        gather_all(P, true, P->vz, ya, 1, s);
+        for (int mode = 0; mode < 3; ++mode) {
+          hipchk(launch_ols(true, true, f64.logn, v64, yb, f64.chunks, f64.n_chunks, dspec + mode * spec_n, f64.ptw,
+                            f64.tw2, P->n_t, P->n_c, f64.m, 1, s, f64.variant),
                  "derivative filter");
-          hipchk(launch_convert(in64, true, u_r, ya, P->n_t, s), "convert");
-          hipchk(launch_interval_dots(ya, yb, P->d_iv_start, P->n_iv, ivd, s), "interval dots");
-          hipchk(hipMemcpyAsync(hd.data(), ivd, sizeof(double) * P->n_iv, hipMemcpyDeviceToHost, s), "copy");
-          hipchk(hipStreamSynchronize(s), "noise gradient");
-          for (int b = 0; b < P->n_iv; ++b)
-            grad[((size_t)r * P->n_filt + P->iv_filter[b]) * 3 + (mode - 1)] += hd[b];
+          hipchk(launch_interval_dots(ya, yb, P->d_iv_start, P->n_iv, ivd + (int64_t)mode * n_iv, s),
+                 "interval dots");
         }
+        hipchk(hipMemcpyAsync(hd.data(), ivd, sizeof(double) * 3 * n_iv, hipMemcpyDeviceToHost, s), "copy");
+        hipchk(hipStreamSynchronize(s), "noise gradient");
+        for (int mode = 0; mode < 3; ++mode)
+          for (int b = 0; b < P->n_iv; ++b) grad[(size_t)P->iv_filter[b] * 3 + mode] += hd[(size_t)mode * n_iv + b];
       }
     } catch (...) {
-      P->release(dlags);
-      P->release(dspec);
-      P->release(ivd);
-      P->release(lscr);
+      release_all();
       throw;
     }
-    P->release(dlags);
-    P->release(dspec);
-    P->release(ivd);
-    P->release(lscr);
+    release_all();
     std::memcpy(grad_out, grad.data(), sizeof(double) * grad.size());
   });
 }

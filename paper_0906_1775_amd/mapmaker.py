@@ -42,15 +42,6 @@ def fft_length_rule(n_c: int, longest: int) -> int:
     return int(L.load().mm_fft_length_rule(int(n_c), int(longest)))
 
 
-def set_cache_limit(nbytes: int, device: int = 0) -> int:
-    """Limit of the device memory destroyed plans leave to later plans of the process
-    (mm_set_cache_limit); 0 empties the cache.  Returns the previous limit."""
-    lib = L.load()
-    prev = ctypes.c_int64(0)
-    L.check(lib.mm_set_cache_limit(int(device), int(nbytes), ctypes.byref(prev)), lib)
-    return int(prev.value)
-
-
 class MapMaker:
     """A plan of the map-making operators for one pointing and noise model."""
 
@@ -126,9 +117,13 @@ class MapMaker:
             d.templates = ctypes.cast(arr, ctypes.POINTER(L.MMTemplate))
             self._tmpl_keep.append(arr)
         self.precision = precision
+        # the plan's device memory: one workspace from torch's allocator, sized by the library
+        nbytes = ctypes.c_size_t(0)
+        L.check(self._lib.mm_plan_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), self._lib)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=pix.device)
         h = ctypes.c_void_p()
-        L.check(self._lib.mm_plan_create(ctypes.byref(d), _ptr(pix), _ptr(w), _stream(), ctypes.byref(h)),
-                self._lib)
+        L.check(self._lib.mm_plan(ctypes.byref(d), _ptr(pix), _ptr(w), _ptr(self.workspace),
+                                  ctypes.c_size_t(self.workspace.numel()), _stream(), ctypes.byref(h)), self._lib)
         self._h = h
         # (plan info waits for the plan's last counts: asked only when templates add amplitudes,
         # so that the caller can queue work behind an unfinished plan)
@@ -138,9 +133,11 @@ class MapMaker:
 
     # ------------------------------------------------------------------ lifecycle
     def close(self):
+        """Destroy the plan (the library waits for the device) and release its workspace."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            self._lib.mm_plan_destroy(self._h)
+            self._lib.mm_destroy(self._h)
             self._h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -272,13 +269,13 @@ class MapMaker:
         return self._solve_call(self._lib.mm_solve_rhs, (_ptr(b),), tol, max_iter, fixed_iters, check_every,
                                 use_graph, true_residual, x0, out, raise_on_notconv, refine)
 
-    def noise_gradient(self, u: torch.Tensor, v: torch.Tensor) -> np.ndarray:
-        """u^T (dN^-1/dtheta) v per RHS and filter: float64 array [n_rhs, n_filters, 3]."""
-        du = self._check_tod(u)
-        dv = self._check_tod(v)
-        if du != dv:
-            raise TypeError("u and v must have the same dtype")
-        out = np.zeros((self.n_rhs, self.n_filters, 3))
-        L.check(self._lib.mm_noise_gradient(self._h, _ptr(u), _ptr(v), du,
+    def noise_gradient(self, tod: torch.Tensor, m: torch.Tensor, lam: torch.Tensor) -> np.ndarray:
+        """dL/d(sigma, f_knee, alpha) per filter, float64 array [n_filters, 3]: the sum over
+        RHS of (P lam)^T (dN^-1/dtheta) (tod - P m), for the map m and the adjoint lam of a loss."""
+        dt = self._check_tod(tod)
+        self._check_map(m)
+        self._check_map(lam)
+        out = np.zeros((self.n_filters, 3))
+        L.check(self._lib.mm_noise_gradient(self._h, _ptr(tod), dt, _ptr(m), _ptr(lam),
                                             out.ctypes.data_as(ctypes.c_void_p), _stream()), self._lib)
         return out

@@ -169,3 +169,90 @@ def test_ctypes_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def _ws_size(lib, d):
+    n = ctypes.c_size_t(0)
+    st = lib.mm_plan_workspace_size(ctypes.byref(d), ctypes.byref(n))
+    return st, int(n.value)
+
+
+def _big_desc(n_t, n_pix, R, precision, ns=3, n_c=8192, iv_len=1 << 20, n_f=0):
+    from paper_0906_1775_amd import _lib
+    iv = np.arange(0, n_t + 1, iv_len, dtype=np.int64)
+    if iv[-1] != n_t:
+        iv = np.append(iv, n_t)
+    fl = np.zeros(iv.shape[0] - 1, np.int32)
+    fp = np.array([1.0, 0.2, 1.7])
+    d = _lib.MMDesc()
+    d.n_stokes, d.n_pix, d.n_samples, d.n_intervals = ns, n_pix, n_t, fl.shape[0]
+    d.iv_start = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    d.iv_filter = fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.n_filters = 1
+    d.filter_params = fp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.f_samp, d.n_c, d.n_rhs, d.precision, d.n_f = 200.0, n_c, R, precision, n_f
+    return d, (iv, fl, fp)
+
+
+def test_workspace_bound_is_host_only_and_grows_with_the_problem(lib):
+    from paper_0906_1775_amd import _lib
+    sizes = {}
+    for R in (1, 4):
+        for prec in (_lib.MM_FP64, _lib.MM_MIXED):
+            d, keep = _big_desc(1 << 24, 1 << 16, R, prec)
+            st, n = _ws_size(lib, d)
+            assert st == _lib.MM_OK, lib.mm_last_error()
+            sizes[(R, prec)] = n
+    # every bound holds at least the two TOD work buffers and the pointing index
+    assert sizes[(1, _lib.MM_MIXED)] >= 2 * 8 * (1 << 24) + 4 * (1 << 24)
+    assert sizes[(4, _lib.MM_FP64)] > sizes[(1, _lib.MM_FP64)]
+    assert sizes[(4, _lib.MM_MIXED)] > sizes[(1, _lib.MM_MIXED)]
+    assert sizes[(4, _lib.MM_FP64)] > sizes[(4, _lib.MM_MIXED)]   # float64 TOD work buffers
+
+
+def test_workspace_bound_of_the_largest_workload_fits_one_device(lib):
+    """2^30 samples, 12 x 2048^2 pixels x TQU, 8 RHS, mixed precision: the plan's bound plus its
+    inputs (index, polarisation pair, 8 float32 TOD rows) stays within one MI355X's 288 GB."""
+    from paper_0906_1775_amd import _lib
+    n_t = 1 << 30
+    d, keep = _big_desc(n_t, 12 * 2048 * 2048, 8, _lib.MM_MIXED, iv_len=1 << 20)
+    st, n = _ws_size(lib, d)
+    assert st == _lib.MM_OK, lib.mm_last_error()
+    inputs = n_t * (4 + 8 + 8 * 4)
+    assert n + inputs < 270e9, (n, inputs)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_stokes", 2, "n_stokes"), ("n_rhs", 65, "n_rhs"), ("n_f", 24, "n_f"), ("f_samp", 0.0, "f_samp"),
+])
+def test_workspace_size_validates_the_descriptor(lib, field, value, msg):
+    from paper_0906_1775_amd import _lib
+    d, keep = _desc(**{field: value})
+    st, n = _ws_size(lib, d)
+    assert st == _lib.MM_EINVAL and msg in lib.mm_last_error().decode()
+    assert lib.mm_plan_workspace_size(None, None) == _lib.MM_EINVAL
+
+
+def test_forced_transform_beyond_the_chip_is_unsupported_in_the_bound(lib):
+    from paper_0906_1775_amd import _lib
+    d, keep = _big_desc(1 << 20, 1024, 1, _lib.MM_MIXED, n_f=1 << 20)
+    st, _ = _ws_size(lib, d)
+    assert st == _lib.MM_EUNSUPPORTED
+
+
+def test_workspace_checks_fail_before_touching_the_device(lib):
+    from paper_0906_1775_amd import _lib
+    d, keep = _desc()
+    st, need = _ws_size(lib, d)
+    assert st == _lib.MM_OK and need > 0
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced: the checks fail first
+    h = ctypes.c_void_p()
+    assert lib.mm_plan(ctypes.byref(d), fake, None, None, need, None, ctypes.byref(h)) == _lib.MM_EINVAL
+    assert "d_ws" in lib.mm_last_error().decode() and not h.value
+    assert lib.mm_plan(ctypes.byref(d), fake, None, ctypes.c_void_p(0x100000), need - 1, None,
+                       ctypes.byref(h)) == _lib.MM_EINVAL
+    assert "below" in lib.mm_last_error().decode() and not h.value
+    assert lib.mm_plan(ctypes.byref(d), fake, None, ctypes.c_void_p(0x100001), need, None,
+                       ctypes.byref(h)) == _lib.MM_EINVAL
+    assert "aligned" in lib.mm_last_error().decode() and not h.value
+    assert lib.mm_destroy(None) == _lib.MM_OK

@@ -175,25 +175,3 @@ def test_scatter_widths_match_the_oracle(grid, wps, n_rhs):
     m, _ = mm.solve(tod_tensor(p), fixed_iters=5)
     x, _ = o.pcg(o.rhs(p.tod[n_rhs - 1]), fixed_iters=5)
     assert rel_err(m.cpu().numpy()[n_rhs - 1], o.to_global(x)) <= 1e-10
-
-
-def test_cache_limit_set_empty_and_restore():
-    from paper_0906_1775_amd import MMError, set_cache_limit
-    prev = set_cache_limit(1 << 30)
-    assert prev == 16 << 30                     # the library's default
-    try:
-        p = _small()
-        a = plan_for(p, lag_dft_len=L_K)
-        m1, _ = a.solve(tod_tensor(p), fixed_iters=4)
-        a.close()
-        b = plan_for(p, lag_dft_len=L_K)        # built from cached blocks
-        m2, _ = b.solve(tod_tensor(p), fixed_iters=4)
-        b.close()
-        assert torch.equal(m1, m2)
-        assert set_cache_limit(0) == 1 << 30    # empties the cache
-        with pytest.raises(MMError, match="EINVAL"):
-            set_cache_limit(-1)
-        with pytest.raises(MMError, match="EINVAL"):
-            set_cache_limit(1 << 20, device=torch.cuda.device_count())
-    finally:
-        set_cache_limit(prev)
