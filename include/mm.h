@@ -358,6 +358,29 @@ mm_status_t mm_solve_rhs(mm_plan_t plan, const double* d_b, double* d_x,
 mm_status_t mm_noise_gradient(mm_plan_t plan, const void* d_tod, int32_t tod_dtype, const double* d_m,
                               const double* d_lambda, double* grad_out, void* stream);
 
+/*
+ * The lags of the inverse-noise filter from the noise parameters, without a plan:
+ * f(tau), tau = 0 .. n_c - 1, of the banded Toeplitz N^-1 (Weighting section) for
+ * p(f) = sigma^2 (1 + (f_knee/f)^alpha) (Algorithm section): the inverse DFT of
+ * 1/p(nu_j) on lag_dft_len frequencies nu_j = j f_samp / lag_dft_len (1/p at nu = 0
+ * being its limit), tapered by (1 - tau/n_c); with deriv = 1, 2, 3 the same
+ * construction applied to the derivative of 1/p with respect to sigma, f_knee,
+ * alpha.  The plan builds its lags the same way (filter_params).
+ *   d_params: device float64 [n_filters][3] = (sigma, f_knee, alpha), sigma > 0,
+ *             f_knee >= 0, alpha > 0 (other values give non-finite lags).
+ *   d_lags:   device float64 [n_filters][n_c], written.
+ *   d_ws:     device scratch of ws_bytes >= mm_noise_lags_workspace_size(n_c,
+ *             lag_dft_len), 256-byte aligned, the caller's; a larger one lets more
+ *             filters share a launch.  Its contents on entry do not matter.
+ * n_c <= 2^14; lag_dft_len a power of two in [4 n_c, 2^30].  Asynchronous on
+ * `stream`.  Errors: MM_EINVAL (arguments, workspace), MM_EUNSUPPORTED (n_c),
+ * MM_EDEVICE.
+ */
+mm_status_t mm_noise_lags_workspace_size(int32_t n_c, int64_t lag_dft_len, size_t* bytes);
+mm_status_t mm_noise_lags(const double* d_params, int32_t n_filters, double f_samp, int32_t n_c,
+                          int64_t lag_dft_len, int32_t deriv, double* d_lags, void* d_ws, size_t ws_bytes,
+                          void* stream);
+
 /* FFT length by the paper's halving rule (Weighting section, eq. FFTcomplexityFunction):
  * start at the smallest power of two >= longest, halve while h'(n_f/2) >= 0 and
  * n_f/2 > 2 n_c.  Returns 0 for invalid arguments. */

@@ -299,7 +299,8 @@ hipError_t launch_lags(const double* params, int n_filters, double f_samp, int n
   const size_t per_filter = (size_t)R * n_c * sizeof(cx<double>);
   if (scratch_bytes < lag_tw_bytes(logn) + per_filter) return hipErrorInvalidValue;
   const size_t avail = scratch_bytes - lag_tw_bytes(logn);
-  int batch = (int)(avail / per_filter);
+  const size_t fit = avail / per_filter;
+  const int batch = (int)(fit < 65535 ? fit : 65535);   // filters per launch (grid y)
   hipError_t e = launch_pass_twiddles(ptw, logn, true, s);
   if (e != hipSuccess) return e;
   for (int f0 = 0; f0 < n_filters; f0 += batch) {

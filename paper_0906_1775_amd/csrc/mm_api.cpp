@@ -1802,6 +1802,26 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
 
 namespace {
 
+// Arguments of the plan-free lag construction; returns its smallest scratch (one
+// filter per batch).
+size_t check_lag_args(const double* d_params, int32_t n_filters, double f_samp, int32_t n_c, int64_t lag_len,
+                      int32_t deriv, const double* d_lags) {
+  if (!d_params || !d_lags) fail(MM_EINVAL, "NULL argument");
+  if (n_filters < 1) fail(MM_EINVAL, "n_filters must be >= 1");
+  if (n_c < 1) fail(MM_EINVAL, "n_c must be >= 1");
+  if (!(f_samp > 0) || !std::isfinite(f_samp)) fail(MM_EINVAL, "f_samp must be positive");
+  if (deriv < 0 || deriv > 3) fail(MM_EINVAL, "deriv must be 0 (lags) or 1 .. 3 (d/dsigma, d/df_knee, d/dalpha)");
+  const int ncp = 1 << std::max(kMinLogN, ilog2(n_c));
+  if (ncp > (1 << ols_max_logn(true))) fail(MM_EUNSUPPORTED, "n_c too large for the lag construction");
+  if (!is_pow2(lag_len) || lag_len < 4 * (int64_t)ncp || lag_len > (int64_t(1) << 30))
+    fail(MM_EINVAL, "lag_dft_len must be a power of two in [4 n_c, 2^30]");
+  return lags_scratch_bytes(n_c, lag_len, 1);
+}
+
+}  // namespace
+
+namespace {
+
 mm_status_t plan_impl(const mm_desc_t* desc, const int32_t* d_pix, const float* d_w, void* ws, size_t ws_bytes,
                       void* stream, mm_plan_t* out_plan) {
   if (!out_plan) {
@@ -2057,6 +2077,29 @@ mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_tod, int32_t tod_dtype,
     }
     release_all();
     std::memcpy(grad_out, grad.data(), sizeof(double) * grad.size());
+  });
+}
+
+mm_status_t mm_noise_lags_workspace_size(int32_t n_c, int64_t lag_dft_len, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) fail(MM_EINVAL, "bytes is NULL");
+    static const double dummy = 0;
+    *bytes = check_lag_args(&dummy, 1, 1.0, n_c, lag_dft_len, 0, &dummy);
+  });
+}
+
+mm_status_t mm_noise_lags(const double* d_params, int32_t n_filters, double f_samp, int32_t n_c,
+                          int64_t lag_dft_len, int32_t deriv, double* d_lags, void* d_ws, size_t ws_bytes,
+                          void* stream) {
+  return guarded([&] {
+    const size_t need = check_lag_args(d_params, n_filters, f_samp, n_c, lag_dft_len, deriv, d_lags);
+    if (!d_ws) fail(MM_EINVAL, "d_ws is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+      fail(MM_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " + std::to_string(need) +
+                          " bytes mm_noise_lags_workspace_size gives");
+    hipchk(launch_lags(d_params, n_filters, f_samp, n_c, lag_dft_len, d_lags, d_ws, ws_bytes, as_stream(stream), deriv),
+           "lag construction");
   });
 }
 

@@ -42,6 +42,24 @@ def fft_length_rule(n_c: int, longest: int) -> int:
     return int(L.load().mm_fft_length_rule(int(n_c), int(longest)))
 
 
+def noise_lags(params: torch.Tensor, f_samp: float, n_c: int, lag_dft_len: int = 1 << 20,
+               deriv: int = 0) -> torch.Tensor:
+    """Lags f(tau) [n_filters, n_c] (or their derivative, deriv = 1 .. 3 for sigma, f_knee,
+    alpha) of the inverse-noise filter for the parameters ``params`` (float64 CUDA tensor
+    [n_filters, 3] = sigma, f_knee, alpha), computed by mm_noise_lags in a torch workspace."""
+    lib = L.load()
+    if not params.is_cuda or params.dtype != torch.float64 or not params.is_contiguous() \
+            or params.dim() != 2 or params.shape[1] != 3:
+        raise ValueError("params must be a contiguous float64 CUDA tensor [n_filters, 3]")
+    n = ctypes.c_size_t(0)
+    L.check(lib.mm_noise_lags_workspace_size(int(n_c), int(lag_dft_len), ctypes.byref(n)), lib)
+    ws = torch.empty(int(n.value), dtype=torch.uint8, device=params.device)
+    out = torch.empty((params.shape[0], int(n_c)), dtype=torch.float64, device=params.device)
+    L.check(lib.mm_noise_lags(_ptr(params), int(params.shape[0]), float(f_samp), int(n_c), int(lag_dft_len),
+                              int(deriv), _ptr(out), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream()), lib)
+    return out
+
+
 class MapMaker:
     """A plan of the map-making operators for one pointing and noise model."""
 

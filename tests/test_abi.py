@@ -256,3 +256,20 @@ def test_workspace_checks_fail_before_touching_the_device(lib):
                        ctypes.byref(h)) == _lib.MM_EINVAL
     assert "aligned" in lib.mm_last_error().decode() and not h.value
     assert lib.mm_destroy(None) == _lib.MM_OK
+
+
+def test_lag_construction_arguments_fail_before_touching_the_device(lib):
+    from paper_0906_1775_amd import _lib
+    n = ctypes.c_size_t(0)
+    assert lib.mm_noise_lags_workspace_size(8192, 1 << 20, ctypes.byref(n)) == _lib.MM_OK
+    assert n.value >= 128 * 8192 * 16          # one filter's 2^20 / 2^13 partial transforms of 8192 points
+    assert lib.mm_noise_lags_workspace_size(8192, 1 << 14, ctypes.byref(n)) == _lib.MM_EINVAL   # < 4 n_c
+    assert lib.mm_noise_lags_workspace_size(1 << 15, 1 << 20, ctypes.byref(n)) == _lib.MM_EUNSUPPORTED
+    fake = ctypes.c_void_p(0x1000)              # never dereferenced: the checks fail first
+    cases = [dict(n_filters=0), dict(n_c=0), dict(f_samp=0.0), dict(deriv=4), dict(lag=3 << 18),
+             dict(ws=None), dict(ws_bytes=16), dict(ws=ctypes.c_void_p(0x1001))]
+    for c in cases:
+        st = lib.mm_noise_lags(fake, c.get("n_filters", 2), c.get("f_samp", 200.0), c.get("n_c", 64),
+                               c.get("lag", 1 << 14), c.get("deriv", 0), fake, c.get("ws", fake),
+                               c.get("ws_bytes", 1 << 30), None)
+        assert st == _lib.MM_EINVAL, (c, lib.mm_last_error())
