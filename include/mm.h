@@ -381,6 +381,21 @@ mm_status_t mm_noise_lags(const double* d_params, int32_t n_filters, double f_sa
                           int64_t lag_dft_len, int32_t deriv, double* d_lags, void* d_ws, size_t ws_bytes,
                           void* stream);
 
+/*
+ * mm_noise_lags for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * lags, with no workspace argument and no allocation.  Its scratch is a static
+ * device array of 64 MiB that each device the library runs on holds until the
+ * process ends; arguments whose scratch need (mm_noise_lags_workspace_size)
+ * exceeds 64 MiB are rejected with MM_EINVAL (for n_c = 8192 the 2^20-point
+ * construction needs 16 MiB per filter).  Every call on a device uses that
+ * device's one array: calls that overlap in time on one device race, so the
+ * caller serialises them (one stream, or its own synchronisation).  Nothing in
+ * the array needs to start at zero.  Arguments and errors as mm_noise_lags.
+ */
+mm_status_t mm_noise_lags_noalloc(const double* d_params, int32_t n_filters, double f_samp, int32_t n_c,
+                                  int64_t lag_dft_len, int32_t deriv, double* d_lags, void* stream);
+
 /* FFT length by the paper's halving rule (Weighting section, eq. FFTcomplexityFunction):
  * start at the smallest power of two >= longest, halve while h'(n_f/2) >= 0 and
  * n_f/2 > 2 n_c.  Returns 0 for invalid arguments. */

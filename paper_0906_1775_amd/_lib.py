@@ -20,7 +20,8 @@ MM_TMPL_ONEHOT, MM_TMPL_HWP = 1, 2
 EXPORTED = ["mm_plan_workspace_size", "mm_plan", "mm_plan_create", "mm_destroy", "mm_plan_destroy",
             "mm_plan_get_info", "mm_hits", "mm_filter_lags", "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A",
             "mm_rhs", "mm_solve_opts_default", "mm_solve", "mm_solve_rhs", "mm_noise_gradient",
-            "mm_noise_lags_workspace_size", "mm_noise_lags", "mm_fft_length_rule", "mm_last_error",
+            "mm_noise_lags_workspace_size", "mm_noise_lags", "mm_noise_lags_noalloc", "mm_fft_length_rule",
+            "mm_last_error",
             "mm_version"]
 
 
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.mm_noise_gradient.argtypes = [P, P, c_int32, P, P, P, P]
     lib.mm_noise_lags_workspace_size.argtypes = [c_int32, c_int64, POINTER(ctypes.c_size_t)]
     lib.mm_noise_lags.argtypes = [P, c_int32, c_double, c_int32, c_int64, c_int32, P, P, ctypes.c_size_t, P]
+    lib.mm_noise_lags_noalloc.argtypes = [P, c_int32, c_double, c_int32, c_int64, c_int32, P, P]
     lib.mm_fft_length_rule.argtypes = [c_int32, c_int64]
     lib.mm_fft_length_rule.restype = c_int32
     lib.mm_last_error.restype = c_char_p
@@ -103,7 +105,8 @@ def load(path: str = LIB_PATH):
     for name in ("mm_plan_workspace_size", "mm_plan", "mm_plan_create", "mm_destroy", "mm_plan_destroy",
                  "mm_plan_get_info", "mm_hits", "mm_filter_lags",
                  "mm_unpoint", "mm_point", "mm_weight", "mm_apply_A", "mm_rhs", "mm_solve",
-                 "mm_solve_rhs", "mm_noise_gradient", "mm_noise_lags_workspace_size", "mm_noise_lags"):
+                 "mm_solve_rhs", "mm_noise_gradient", "mm_noise_lags_workspace_size", "mm_noise_lags",
+                 "mm_noise_lags_noalloc"):
         getattr(lib, name).restype = c_int32
     _LIB = lib
     return lib

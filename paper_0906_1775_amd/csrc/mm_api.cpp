@@ -1818,6 +1818,27 @@ size_t check_lag_args(const double* d_params, int32_t n_filters, double f_samp, 
   return lags_scratch_bytes(n_c, lag_len, 1);
 }
 
+// The allocation-free lag construction's scratch: one array per device, taken by
+// every mm_noise_lags_noalloc call on that device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per device.
+void* noalloc_scratch() {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipchk(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) fail(MM_EUNSUPPORTED, "device id above 63");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    hipchk(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    addr[dev] = p;
+  }
+  return addr[dev];
+}
+
 }  // namespace
 
 namespace {
@@ -2099,6 +2120,19 @@ mm_status_t mm_noise_lags(const double* d_params, int32_t n_filters, double f_sa
       fail(MM_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " + std::to_string(need) +
                           " bytes mm_noise_lags_workspace_size gives");
     hipchk(launch_lags(d_params, n_filters, f_samp, n_c, lag_dft_len, d_lags, d_ws, ws_bytes, as_stream(stream), deriv),
+           "lag construction");
+  });
+}
+
+mm_status_t mm_noise_lags_noalloc(const double* d_params, int32_t n_filters, double f_samp, int32_t n_c,
+                                  int64_t lag_dft_len, int32_t deriv, double* d_lags, void* stream) {
+  return guarded([&] {
+    const size_t need = check_lag_args(d_params, n_filters, f_samp, n_c, lag_dft_len, deriv, d_lags);
+    if (need > kNoAllocScratchBytes)
+      fail(MM_EINVAL, "this n_c and lag_dft_len need " + std::to_string(need) + " bytes of scratch, above the " +
+                          std::to_string(kNoAllocScratchBytes) + " bytes of the allocation-free variant");
+    hipchk(launch_lags(d_params, n_filters, f_samp, n_c, lag_dft_len, d_lags, noalloc_scratch(), kNoAllocScratchBytes,
+                       as_stream(stream), deriv),
            "lag construction");
   });
 }
