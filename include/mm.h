@@ -296,6 +296,11 @@ typedef struct {
                                    those true residuals and the iterate with the lowest one is
                                    returned, so the map reaches float64 accuracy.  0 = plain
                                    mixed iterations.  Ignored with fixed_iters. */
+  int32_t map_error;            /* 1 = estimate each returned map's distance to the exact
+                                   float64 solution (mm_solve_info_t.map_error): the residual
+                                   b - H x is formed in float64 and H e = b - H x is solved by
+                                   PCG with the plan's operator to 1e-2 of its right-hand
+                                   side (at most 50 iterations); costs those iterations */
 } mm_solve_opts_t;
 
 typedef struct {
@@ -309,6 +314,10 @@ typedef struct {
                                    the last iteration); with refine, the recurrence residual
                                    between replacements and the float64 true residual at each
                                    replacement; may be NULL */
+  double* map_error;            /* [n_rhs] with opts.map_error: ||x - x*|| / ||x|| for the returned
+                                   map x and the exact float64 solution x* of H x* = b (map
+                                   error against float64, estimated to about two digits); NaN
+                                   otherwise; may be NULL */
 } mm_solve_info_t;
 
 /* Fill opts with the paper's defaults (tol 1e-6, max_iter 50) and check_every 8, graph on,

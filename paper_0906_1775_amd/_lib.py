@@ -50,13 +50,13 @@ class MMPlanInfo(ctypes.Structure):
 class MMSolveOpts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("max_iter", c_int32), ("fixed_iters", c_int32),
                 ("check_every", c_int32), ("use_graph", c_int32), ("true_residual", c_int32),
-                ("d_x0", c_void_p), ("refine", c_int32)]
+                ("d_x0", c_void_p), ("refine", c_int32), ("map_error", c_int32)]
 
 
 class MMSolveInfo(ctypes.Structure):
     _fields_ = [("iters", POINTER(c_int32)), ("best_iter", POINTER(c_int32)),
                 ("best_rel_res", POINTER(c_double)), ("true_rel_res", POINTER(c_double)),
-                ("history", POINTER(c_double))]
+                ("history", POINTER(c_double)), ("map_error", POINTER(c_double))]
 
 
 class MMError(RuntimeError):

@@ -1776,6 +1776,32 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     }
   }
 
+  std::vector<double> merr(R, std::nan(""));
+  if (o.map_error && nu > 0) {
+    // Distance of the returned map x to the exact float64 solution x* = H^-1 b: the
+    // error e = x* - x solves H e = b - H x, with the residual formed in float64 and
+    // the correction equation solved by PCG with the plan's operator to 1e-2 of its
+    // right-hand side, which gives ||e|| to about two digits.  The float32 operator of
+    // a mixed plan differs from H by far less than that.
+    const double* xs = refine ? P->vxbest : P->vxb;
+    const std::vector<double> xx = dots(P, xs, xs, R, s);
+    if (P->main_fp64()) {
+      for (int r = 0; r < R; ++r) {
+        apply_H_obs(P, P->fs_main, xs + (int64_t)r * nu, P->vq, P->y1, P->y2, 1, s);
+        hipchk(launch_sub(P->vr + (int64_t)r * nu, P->vb + (int64_t)r * nu, P->vq, nu, s), "residual");
+      }
+    } else {
+      if (!refine)
+        for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
+      for (int r = 0; r < R; ++r) residual64_row(P, xs, P->vr, r, s);
+    }
+    hipchk(hipMemcpyAsync(P->vb, P->vr, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
+    std::vector<double> inner;
+    run_pcg(P, s, 1e-2, 50, false, o.check_every, o.use_graph != 0, false, inner);
+    const std::vector<double> ee = dots(P, P->vxb, P->vxb, R, s);
+    for (int r = 0; r < R; ++r) merr[r] = xx[r] > 0 ? std::sqrt(ee[r] / xx[r]) : (ee[r] > 0 ? INFINITY : 0.0);
+  }
+
   hipchk(hipStreamSynchronize(s), "solve end");
   hipchk(hipEventRecord(P->ev_out, s), "event");
   hipchk(hipStreamWaitEvent(caller, P->ev_out, 0), "event wait");
@@ -1786,6 +1812,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       if (info->best_iter) info->best_iter[r] = best_iter[r];
       if (info->best_rel_res) info->best_rel_res[r] = best_rel[r];
       if (info->true_rel_res) info->true_rel_res[r] = tres[r];
+      if (info->map_error) info->map_error[r] = merr[r];
     }
     if (info->history) std::memcpy(info->history, hist_out.data(), sizeof(double) * hist_out.size());
   }
@@ -1877,6 +1904,7 @@ void mm_solve_opts_default(mm_solve_opts_t* o) {
   o->true_residual = 0;
   o->d_x0 = nullptr;
   o->refine = 1;
+  o->map_error = 0;
 }
 
 

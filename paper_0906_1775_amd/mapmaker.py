@@ -238,7 +238,7 @@ class MapMaker:
         return b
 
     def _solve_call(self, fn, rhs_args, tol, max_iter, fixed_iters, check_every, use_graph, true_residual,
-                    x0, out, raise_on_notconv, refine):
+                    x0, out, raise_on_notconv, refine, map_error=False):
         if x0 is not None:
             self._check_map(x0)
         x = out if out is not None else self._map_like()
@@ -249,12 +249,14 @@ class MapMaker:
         o.check_every, o.use_graph, o.true_residual = int(check_every), int(bool(use_graph)), int(bool(true_residual))
         o.d_x0 = None if x0 is None else x0.data_ptr()
         o.refine = int(bool(refine))
+        o.map_error = int(bool(map_error))
         R = self.n_rhs
         n_hist = (fixed_iters if fixed_iters > 0 else max_iter) + 1
         iters = (ctypes.c_int32 * R)()
         best = (ctypes.c_int32 * R)()
         best_rel = (ctypes.c_double * R)()
         true_rel = (ctypes.c_double * R)()
+        merr = (ctypes.c_double * R)()
         hist = np.zeros((R, n_hist))
         inf = L.MMSolveInfo()
         inf.iters = ctypes.cast(iters, ctypes.POINTER(ctypes.c_int32))
@@ -262,21 +264,25 @@ class MapMaker:
         inf.best_rel_res = ctypes.cast(best_rel, ctypes.POINTER(ctypes.c_double))
         inf.true_rel_res = ctypes.cast(true_rel, ctypes.POINTER(ctypes.c_double))
         inf.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        inf.map_error = ctypes.cast(merr, ctypes.POINTER(ctypes.c_double))
         st = fn(self._h, *rhs_args, _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())
         allow = () if raise_on_notconv else (L.MM_ENOTCONV,)
         L.check(st, self._lib, allow=allow)
         info = dict(status=L.STATUS_NAMES[st], iters=list(iters), best_iter=list(best),
-                    best_rel_res=list(best_rel), true_rel_res=list(true_rel), history=hist)
+                    best_rel_res=list(best_rel), true_rel_res=list(true_rel), history=hist,
+                    map_error=list(merr))
         return x, info
 
     def solve(self, tod: torch.Tensor, tol: float = 1e-6, max_iter: int = 50, fixed_iters: int = 0,
               check_every: int = 8, use_graph: bool = True, true_residual: bool = False,
               x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-              raise_on_notconv: bool = False, refine: bool = True):
-        """PCG solve of H m = P^T N^-1 d; returns (map [n_rhs, n_pix, n_stokes], info dict)."""
+              raise_on_notconv: bool = False, refine: bool = True, map_error: bool = False):
+        """PCG solve of H m = P^T N^-1 d; returns (map [n_rhs, n_pix, n_stokes], info dict).
+        map_error: also estimate each map's distance to the exact float64 solution
+        (info["map_error"])."""
         dt = self._check_tod(tod)
         return self._solve_call(self._lib.mm_solve, (_ptr(tod), dt), tol, max_iter, fixed_iters, check_every,
-                                use_graph, true_residual, x0, out, raise_on_notconv, refine)
+                                use_graph, true_residual, x0, out, raise_on_notconv, refine, map_error)
 
     def solve_rhs(self, b: torch.Tensor, tol: float = 1e-6, max_iter: int = 50, fixed_iters: int = 0,
                   check_every: int = 8, use_graph: bool = True, true_residual: bool = False,

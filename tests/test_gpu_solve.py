@@ -229,3 +229,21 @@ def test_c2_mixed_refined_reaches_fp64_accuracy(check_every):
     print(f"C2 mixed+refine: iters {info['iters'][0]} residual {info['true_rel_res'][0]:.3e} oracle {res:.3e}")
     assert info["status"] == "MM_OK"
     assert res < 2e-10
+
+
+@pytest.mark.parametrize("precision,refine,tol", [("mixed", False, 1e-6), ("mixed", True, 1e-9), ("fp64", False, 1e-6)])
+def test_map_error_estimate_against_a_float64_solve(TQU, precision, refine, tol):
+    """The estimated distance to the exact float64 map (opts.map_error) agrees, to within a
+    factor of 3, with the measured distance to a float64 solve converged to 1e-13."""
+    p, _ = TQU
+    ref_plan = plan_for(p, lag_dft_len=L_K)
+    ref, _ = ref_plan.solve(tod_tensor(p), tol=1e-13, max_iter=1000)
+    mm = plan_for(p, precision=precision, lag_dft_len=L_K)
+    m, info = mm.solve(tod_tensor(p), tol=tol, max_iter=1000, refine=refine, map_error=True)
+    actual = float(torch.linalg.norm(m - ref) / torch.linalg.norm(m))
+    est = info["map_error"][0]
+    print(f"{precision} refine={refine} tol={tol:g}: estimated {est:.3e}, measured {actual:.3e}")
+    assert actual > 0 and 1 / 3 <= est / actual <= 3
+    # without the option the field is NaN
+    _, info2 = mm.solve(tod_tensor(p), tol=tol, max_iter=1000, refine=refine)
+    assert np.isnan(info2["map_error"][0])
