@@ -52,66 +52,91 @@ __device__ __forceinline__ double sky_value(const Tp* __restrict__ row, int32_t 
   }
 }
 
+// The samples t0 + u * 256 (u < kGatherUnroll) of one thread, t0 = its tile's first
+// sample + threadIdx.x: y_t for every active RHS.
+template <typename Ty, int NS, typename Tp>
+__device__ __forceinline__ void gather_tile(const int32_t* __restrict__ pix_obs, const float2* __restrict__ w,
+                                            const Tp* __restrict__ p, int64_t vs, Ty* __restrict__ y, int64_t n_t,
+                                            int64_t ys, int n_rhs, const CgState* __restrict__ st, int64_t t0) {
+  constexpr int U = kGatherUnroll;
+  int32_t o[U];
+  float2 sc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    // a slot past the last sample re-reads the last sample and is discarded;
+    // the pointing streams are read once per pass: nontemporal, so they do not
+    // evict the map (and the TOD rows other kernels re-read) from the caches
+    const int64_t t = t0 + u * 256 < n_t ? t0 + u * 256 : n_t - 1;
+    o[u] = __builtin_nontemporal_load(pix_obs + t);
+    if (NS == 3) sc[u] = load_nt(w + t);
+    else sc[u] = make_float2(0.f, 0.f);
+  }
+  for (int r = 0; r < n_rhs; ++r) {
+    if (st && !st[r].active) continue;   // this RHS has stopped iterating
+    const Tp* __restrict__ row = p + (int64_t)r * vs;
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double val = sky_value<NS, Tp>(row, o[u] >= 0 ? o[u] : 0, sc[u].x, sc[u].y);
+      v[u] = o[u] >= 0 ? val : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t t = t0 + u * 256;
+      if (t < n_t) y[(int64_t)r * ys + t] = (Ty)v[u];
+    }
+  }
+}
+
 // Tp: element type of the map (float64, or the float32 copy of the search
 // direction that mixed-precision iterations gather from); y rows have stride ys.
-// Requires n_obs >= 1 (pixel 0 exists).
+// Requires n_obs >= 1 (pixel 0 exists).  Without `order` the blocks stride over
+// the tiles in time order; with it block b takes one tile, the tiles sorted by
+// the pixels they see: the hardware deals blocks to the 8 XCDs in turn, so block b
+// takes sorted position (b mod 8) * ceil(n_tiles / 8) + b / 8, and the blocks an
+// XCD runs at once read the map of one region of the sky through its L2.
 template <typename Ty, int NS, typename Tp>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ pix_obs,
                                                 const float2* __restrict__ w,
                                                 const Tp* __restrict__ p, int64_t vs,
                                                 Ty* __restrict__ y, int64_t n_t, int64_t ys, int n_rhs,
-                                                const CgState* __restrict__ st) {
+                                                const CgState* __restrict__ st,
+                                                const int32_t* __restrict__ order, int64_t n_tiles) {
   constexpr int U = kGatherUnroll;
   if (st) {   // every RHS has stopped: nothing to read
     bool any = false;
     for (int r = 0; r < n_rhs; ++r) any = any || st[r].active != 0;
     if (!any) return;
   }
-  const int64_t step = (int64_t)gridDim.x * 256 * U;
-  for (int64_t t0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; t0 < n_t; t0 += step) {
-    int32_t o[U];
-    float2 sc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // a slot past the last sample re-reads the last sample and is discarded;
-      // the pointing streams are read once per pass: nontemporal, so they do not
-      // evict the map (and the TOD rows other kernels re-read) from the caches
-      const int64_t t = t0 + u * 256 < n_t ? t0 + u * 256 : n_t - 1;
-      o[u] = __builtin_nontemporal_load(pix_obs + t);
-      if (NS == 3) sc[u] = load_nt(w + t);
-      else sc[u] = make_float2(0.f, 0.f);
-    }
-    for (int r = 0; r < n_rhs; ++r) {
-      if (st && !st[r].active) continue;   // this RHS has stopped iterating
-      const Tp* __restrict__ row = p + (int64_t)r * vs;
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double val = sky_value<NS, Tp>(row, o[u] >= 0 ? o[u] : 0, sc[u].x, sc[u].y);
-        v[u] = o[u] >= 0 ? val : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t t = t0 + u * 256;
-        if (t < n_t) y[(int64_t)r * ys + t] = (Ty)v[u];
-      }
-    }
+  if (order) {
+    const int64_t per = (n_tiles + 7) / 8;
+    const int64_t pos = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (pos >= n_tiles) return;
+    gather_tile<Ty, NS, Tp>(pix_obs, w, p, vs, y, n_t, ys, n_rhs, st,
+                            (int64_t)order[pos] * 256 * U + threadIdx.x);
+    return;
   }
+  const int64_t step = (int64_t)gridDim.x * 256 * U;
+  for (int64_t t0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; t0 < n_t; t0 += step)
+    gather_tile<Ty, NS, Tp>(pix_obs, w, p, vs, y, n_t, ys, n_rhs, st, t0);
 }
 
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
-                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32) {
+                         hipStream_t s, const CgState* st, const float* p32, int64_t vs32,
+                         const int32_t* order) {
   if (n_t == 0) return hipSuccess;
   if (n_obs == 0)   // every sample excised: the TOD rows are zero (a fill kernel, safe under graph capture)
     return out_f64 ? launch_fill_f64((double*)y, 0.0, n_t * n_rhs, s)
                    : launch_fill_i32((int32_t*)y, 0, n_t * n_rhs, s);   // float32 zero = all bits zero
-  int64_t nb = (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll);
-  if (nb > 65536) nb = 65536;
+  const int64_t n_tiles = gather_tiles(n_t);
+  int64_t nb = n_tiles;
+  if (order) nb = 8 * ((n_tiles + 7) / 8);
+  else if (nb > 65536) nb = 65536;
   const dim3 g((unsigned)nb), b(256);
   const float2* w2 = (const float2*)w;
 #define MM_GA(TY, NS, TP, PP, VS) \
-  hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, n_t, n_rhs, st)
+  hipLaunchKernelGGL((k_gather<TY, NS, TP>), g, b, 0, s, pix_obs, w2, PP, VS, (TY*)y, n_t, n_t, n_rhs, st, order, n_tiles)
   if (p32) {
     if (out_f64) { if (ns == 1) MM_GA(double, 1, float, p32, vs32); else MM_GA(double, 3, float, p32, vs32); }
     else { if (ns == 1) MM_GA(float, 1, float, p32, vs32); else MM_GA(float, 3, float, p32, vs32); }
@@ -120,6 +145,41 @@ hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const flo
     else { if (ns == 1) MM_GA(float, 1, double, p, vs); else MM_GA(float, 3, double, p, vs); }
   }
 #undef MM_GA
+  return hipGetLastError();
+}
+
+int64_t gather_tiles(int64_t n_t) { return (n_t + 256 * kGatherUnroll - 1) / (256 * kGatherUnroll); }
+
+// key[i] = the smallest observed id among the samples of gather tile i, -1 if it has none
+__global__ __launch_bounds__(256) void k_tile_keys(const int32_t* __restrict__ pix_obs, int64_t n_t,
+                                                   int32_t* __restrict__ key) {
+  constexpr int64_t T = 256 * kGatherUnroll;
+  const int64_t t0 = (int64_t)blockIdx.x * T;
+  const int64_t t1 = t0 + T < n_t ? t0 + T : n_t;
+  int32_t m = 0x7fffffff;
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+    const int32_t o = pix_obs[t];
+    if (o >= 0 && o < m) m = o;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int32_t v = __shfl_xor(m, off, 64);
+    m = v < m ? v : m;
+  }
+  __shared__ int32_t wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t k = wm[0];
+    for (int i = 1; i < 4; ++i) k = wm[i] < k ? wm[i] : k;
+    key[blockIdx.x] = k == 0x7fffffff ? -1 : k;
+  }
+}
+
+hipError_t launch_tile_keys(const int32_t* pix_obs, int64_t n_t, int32_t* key, hipStream_t s) {
+  const int64_t n_tiles = gather_tiles(n_t);
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)n_tiles), dim3(256), 0, s, pix_obs, n_t, key);
   return hipGetLastError();
 }
 

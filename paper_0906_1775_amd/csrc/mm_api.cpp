@@ -223,6 +223,7 @@ struct mm_plan_s {
   int64_t n_obs = 0, n_valid = 0;
   const float* w = nullptr;     // caller's (sin, cos) pairs, time-major
   Layout px;                    // sky pointing
+  int32_t* gather_order = nullptr;   // gather tiles sorted by the pixels they see, or null (time order)
 
   // templates
   std::vector<Template> tmpl;
@@ -564,7 +565,8 @@ void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, 
 void gather_all(mm_plan_s* P, bool y_f64, const double* x, void* y, int R, hipStream_t s,
                 const CgState* st = nullptr, const float* x32 = nullptr) {
   const int64_t vs = P->nu();
-  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s, st, x32, P->vs32()),
+  hipchk(launch_gather(y_f64, P->ns, P->px.obs_idx, P->w, x, vs, y, P->n_t, P->n_obs, R, s, st, x32, P->vs32(),
+                       P->gather_order),
          "gather");
   for (const Template& T : P->tmpl) {
     const int64_t off = P->nmap() + T.ooff;
@@ -742,6 +744,28 @@ void build_layout(mm_plan_s* P, const int32_t* d_key, int64_t n_keys, int ns, co
   int g = 4;
   while (g < 64 && g * 4 < avg) g *= 2;
   L.group = g;
+}
+
+// Map bytes one gather pass looks up (all RHS) above which the gather visits its tiles
+// sorted by pixel rather than in time order: beyond one XCD's 4 MiB L2, the pixels a
+// scan revisits (other detectors, later passes) are gone from the caches by then in
+// time order, while sorted tiles that see the same pixels run together on one XCD.
+constexpr int64_t kGatherOrderMapBytes = int64_t(4) << 20;
+
+// Gather order: the gather tiles sorted (stably) by the smallest observed id each sees.
+void build_gather_order(mm_plan_s* P, hipStream_t s) {
+  const int64_t map_bytes = P->n_obs * P->ns * (P->main_fp64() ? 8 : 4) * (int64_t)P->R;
+  if (P->n_obs == 0 || map_bytes <= kGatherOrderMapBytes) return;
+  const int64_t n_tiles = gather_tiles(P->n_t);
+  int32_t* key = P->temp<int32_t>(n_tiles);
+  hipchk(launch_tile_keys(P->px.obs_idx, P->n_t, key, s), "gather tile keys");
+  uint32_t* sorted = P->temp<uint32_t>(n_tiles);
+  char* scr = P->temp<char>((int64_t)sort_scratch_bytes(n_tiles));
+  P->gather_order = P->alloc<int32_t>(n_tiles);
+  hipchk(launch_sort_by_pixel(key, n_tiles, P->n_obs, sorted, P->gather_order, scr, s), "gather order");
+  P->release(scr);
+  P->release(sorted);
+  P->release(key);
 }
 
 // The scatter's view of a layout: the pixel-major arrays as they are (L.wps = 0), or
@@ -1041,6 +1065,11 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
   };
   int64_t n_obs = 0;
   layout(d->n_pix, ns, &n_obs);
+  {   // gather order (build_gather_order)
+    const int64_t n_tiles = gather_tiles(n);
+    B.pers += block_bytes(n_tiles, 4);
+    B.temps += 2 * block_bytes(n_tiles, 4) + block_bytes((int64_t)sort_scratch_bytes(n_tiles), 1);
+  }
   int64_t n_tunk = 0, n_pq = n_obs > 0 ? kScatterBlocks : 0;
   for (int k = 0; k < d->n_templates; ++k) {
     const mm_template_t& D = d->templates[k];
@@ -1187,6 +1216,7 @@ void build_plan(mm_plan_s* P, const mm_desc_t* d, const int32_t* d_pix, const fl
   build_layout(P, d_pix, P->n_pix, P->ns, d_w, P->px, s, "pointing index outside [-1, n_pix)");
   P->n_obs = P->px.n_obs;
   P->n_valid = P->px.n_valid;
+  build_gather_order(P, s);
   setup_templates(P, d, s);
 
   // ---- noise filters

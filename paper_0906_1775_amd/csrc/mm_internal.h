@@ -88,11 +88,16 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
 // ---------------------------------------------------------------- pointing (k_pointing.hip)
 // y[r][t] = (P p_r)_t; p rows of stride vs (map values first, observed layout)
 // p32 (optional): a float32 copy of the map part of p (rows of stride vs32), read
-// instead of p
+// instead of p; order (optional): the gather tiles (gather_tiles(n_t) runs of
+// consecutive samples) in the order their blocks should run (sorted by pixel)
 hipError_t launch_gather(bool out_f64, int ns, const int32_t* pix_obs, const float* w,
                          const double* p, int64_t vs, void* y, int64_t n_t, int64_t n_obs, int n_rhs,
                          hipStream_t s, const CgState* st = nullptr, const float* p32 = nullptr,
-                         int64_t vs32 = 0);
+                         int64_t vs32 = 0, const int32_t* order = nullptr);
+// runs of consecutive samples the gather assigns to one block
+int64_t gather_tiles(int64_t n_t);
+// key[i] = smallest observed id among the samples of gather tile i, -1 if none
+hipError_t launch_tile_keys(const int32_t* pix_obs, int64_t n_t, int32_t* key, hipStream_t s);
 // dst[r * dst_stride + i] = (float)src[r * src_stride + i], i < n
 hipError_t launch_rows_to_f32(const double* src, int64_t src_stride, float* dst, int64_t dst_stride, int64_t n,
                               int n_rhs, hipStream_t s);
