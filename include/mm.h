@@ -134,9 +134,13 @@ typedef struct {
   int32_t n_f;                  /* overlap-save FFT length: 0 = library default (the
                                    paper's rule capped at 2^14, or the smallest power of
                                    two above 2 n_c when that is longer), -1 = autotune
-                                   (time every on-chip length on the plan's intervals
-                                   and keep the fastest), > 0 = forced power of two with
-                                   n_f > 2 n_c */
+                                   (time every length with a transform on the plan's
+                                   intervals and keep the fastest), > 0 = forced power of
+                                   two with n_f > 2 n_c.  Transforms exist on chip (one
+                                   workgroup) up to 2^16 in float32 and 2^15 in float64,
+                                   and as a batched four-step transform through device
+                                   memory at 2^17 and 2^18 (the paper's length for
+                                   n_c = 8192) in both precisions */
   int32_t lag_dft_len;          /* L_K, frequencies on which 1/p is sampled to build f
                                    from filter_params; 0 = 2^20; power of two >= 4 n_c */
   int32_t precision;            /* MM_FP64 or MM_MIXED */
@@ -190,8 +194,7 @@ typedef struct {
  * the lags and overlap-save spectra of N^-1 (Weighting section), the block
  * preconditioner (Implementation section), and the TOD and CG work vectors of
  * the PCG iteration (Algorithm section, eq. pcgSystem).  Host-only.
- * Errors: MM_EINVAL (descriptor), MM_EUNSUPPORTED (forced n_f longer than the
- * on-chip transforms).
+ * Errors: MM_EINVAL (descriptor), MM_EUNSUPPORTED (forced n_f with no transform).
  */
 mm_status_t mm_plan_workspace_size(const mm_desc_t* desc, size_t* bytes);
 
@@ -213,7 +216,7 @@ mm_status_t mm_plan_workspace_size(const mm_desc_t* desc, size_t* bytes);
  * transforms (the destriping case of the "Using MADmap" section).
  * Errors: MM_EINVAL (descriptor, pixel or template index out of range, NULL or
  * misaligned workspace, ws_bytes below the bound), MM_EDEVICE, MM_EUNSUPPORTED
- * (forced n_f longer than the on-chip transforms).  A singular preconditioner
+ * (forced n_f with no transform).  A singular preconditioner
  * block does not fail the plan; it is counted in mm_plan_info_t.n_singular and
  * makes mm_solve return MM_ESINGULAR.
  */

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmm.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_filter.hip", "k_pointing.hip", "k_sort.hip", "k_cg.hip", "k_template.hip", "mm_api.cpp"]
+SOURCES = ["k_filter.hip", "k_ols_long.hip", "k_pointing.hip", "k_sort.hip", "k_cg.hip", "k_template.hip",
+           "mm_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -466,8 +466,15 @@ __global__ __launch_bounds__(Shape<LOGN>::NT) void k_spectrum_fft(
 }
 
 // Direct-sum form of the same symbol, for transform lengths beyond the largest
-// float64 workgroup transform: cos(2 pi k tau / n_f) from a float64 table of n_f
-// entries indexed by (k tau) mod n_f.
+// float64 workgroup transform.  One thread takes k and N - k together: since
+// cos(2 pi (N - k) tau / n_f) = (-1)^tau cos(2 pi k tau / n_f), F_k = f(0) + 2 (E + O)
+// and F_(N-k) = f(0) + 2 (E - O), E and O the sums over even and odd tau >= 1.  The
+// cosines are the real parts of z_tau = exp(2 pi i k tau / n_f), advanced by one
+// complex rotation per tau and restarted every kDirectRun steps from a float64 table
+// of cos(2 pi j / n_f), j < n_f (indexed by (k tau) mod n_f; the sine is the entry a
+// quarter period earlier), so rounding grows over at most kDirectRun rotations.
+constexpr int kDirectRun = 16;
+
 __global__ void k_cos_table(double* ctab, int nf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < nf) ctab[j] = cospi(2.0 * (double)j / (double)nf);
@@ -476,18 +483,33 @@ __global__ void k_cos_table(double* ctab, int nf) {
 template <typename T>
 __global__ void k_spectrum_direct(const double* __restrict__ lags, int n_c, int N,
                                   const double* __restrict__ ctab, T* __restrict__ spec) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > N) return;
-  const double* f = lags + (int64_t)blockIdx.y * n_c;
-  const int nf = 2 * N;
-  double acc = 0.0;
-  int idx = 0;
-  for (int tau = 1; tau < n_c; ++tau) {
-    idx += k;
-    if (idx >= nf) idx -= nf;
-    acc += f[tau] * ctab[idx];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;   // 0 .. N/2
+  if (k > N / 2) return;
+  const double* __restrict__ f = lags + (int64_t)blockIdx.y * n_c;
+  const int64_t mask = 2 * (int64_t)N - 1, quarter = N / 2;
+  auto unit = [&](int64_t j) -> cx<double> {   // (cos, sin) of 2 pi j / n_f
+    j &= mask;
+    return {ctab[j], ctab[(j - quarter) & mask]};
+  };
+  const cx<double> w = unit(k);
+  double ev = 0.0, od = 0.0;
+  for (int t0 = 0; t0 < n_c; t0 += kDirectRun) {
+    cx<double> z = unit((int64_t)k * t0);
+#pragma unroll
+    for (int i = 0; i < kDirectRun; i += 2) {
+      const int tau = t0 + i;   // even
+      if (tau >= n_c) break;
+      if (tau > 0) ev = fma(f[tau], z.re, ev);
+      z = cmul(z, w);
+      if (tau + 1 >= n_c) break;
+      od = fma(f[tau + 1], z.re, od);
+      z = cmul(z, w);
+    }
   }
-  spec[(int64_t)blockIdx.y * (N + 1) + k] = (T)((f[0] + 2.0 * acc) / (4.0 * (double)N));
+  const double scale = 1.0 / (4.0 * (double)N);
+  T* __restrict__ out = spec + (int64_t)blockIdx.y * (N + 1);
+  out[k] = (T)((f[0] + 2.0 * (ev + od)) * scale);
+  if (N - k != k) out[N - k] = (T)((f[0] + 2.0 * (ev - od)) * scale);
 }
 
 template <typename T, int LOGN>
@@ -513,7 +535,7 @@ hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, 
     hipLaunchKernelGGL(k_cos_table, dim3((nf + 255) / 256), dim3(256), 0, s, ctab, nf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 g((unsigned)((N + 1 + 255) / 256), (unsigned)n_filters);
+    const dim3 g((unsigned)((N / 2 + 1 + 255) / 256), (unsigned)n_filters);
     if (fp64)
       hipLaunchKernelGGL(k_spectrum_direct<double>, g, dim3(256), 0, s, lags, n_c, N, ctab, (double*)spec);
     else

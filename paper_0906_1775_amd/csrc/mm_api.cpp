@@ -103,8 +103,13 @@ struct FilterSetup {
   int variant = 0;         // workgroup shape of the transform (ols_variant_exists)
   int N = 0, nf = 0, m = 0;
   void* tw2 = nullptr;     // exp(-2 pi i k / n_f), k < N (real-to-complex packing)
-  void* ptw = nullptr;     // per-pass twiddle tables of the transform
+  void* ptw = nullptr;     // per-pass twiddle tables of the transform (long: of its 2^8-point columns)
   void* spec = nullptr;
+  bool long_path = false;  // n_f beyond one workgroup: the batched four-step transform (launch_ols_long)
+  void* ptw_b = nullptr;   // long: per-pass twiddle tables of its rows
+  void* ltab = nullptr;    // long: W_N and pairing twiddle tables (launch_long_tables)
+  void* work = nullptr;    // long: intermediates of `batch` jobs
+  int64_t batch = 0;
   OlsChunk* chunks = nullptr;
   std::vector<OlsChunk> chunks_host;   // source of the asynchronous upload of chunks, kept with the setup
   int n_chunks = 0;
@@ -377,12 +382,20 @@ void wait_ready(mm_plan_s* P, hipStream_t stream) {
 }
 
 void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant, bool tmp);
+void build_symbols(const FilterSetup& fs, const double* lags, int n_filt, int n_c, void* out, char* scr,
+                   hipStream_t s);
+size_t symbol_scratch_bytes(int logn, bool fp64, int n_filt);
+void apply_ols(mm_plan_s* P, const FilterSetup& fs, bool in_f64, const void* y_in, void* y_out, const void* spec,
+               int R, hipStream_t s, const CgState* st = nullptr);
 
 void release_filter(mm_plan_s* P, FilterSetup& fs) {
   P->release(fs.chunks);
   P->release(fs.tw2);
   P->release(fs.ptw);
   P->release(fs.spec);
+  P->release(fs.ptw_b);
+  P->release(fs.ltab);
+  P->release(fs.work);
   fs = FilterSetup();
 }
 
@@ -392,19 +405,27 @@ int64_t longest_interval(const std::vector<int64_t>& iv_start) {
   return longest;
 }
 
-// Lengths the autotuner tries: every on-chip power of two above 2 n_c, up to the first
-// one whose half already covers twice the longest interval (longer ones only add padding).
+// Transforms of 2^logn complex points: on-chip (one workgroup, workgroup shape v), or
+// beyond the on-chip limit the batched four-step transform (one shape, v = 0).
+bool transform_long(int logn, bool fp64) { return logn > ols_max_logn(fp64); }
+bool transform_exists(int logn, bool fp64, int v) {
+  return transform_long(logn, fp64) ? (v == 0 && ols_long_exists(logn)) : ols_variant_exists(logn, fp64, v);
+}
+constexpr int kMaxLogNLong = 17;   // n_f = 2^18, the paper's length for n_c = 8192
+
+// Lengths the autotuner tries: every power of two above 2 n_c that has a transform (on-chip,
+// then the long ones), up to the first whose half already covers twice the longest interval
+// (longer ones only add padding).
 std::vector<int64_t> autotune_lengths(int n_c, int64_t longest, bool fp64) {
-  const int maxlog = ols_max_logn(fp64);
   int64_t nf = 1;
   while (nf <= 2 * (int64_t)n_c) nf <<= 1;
   nf = std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
-  if (ilog2(nf) - 1 > maxlog) fail(MM_EUNSUPPORTED, "n_c too large for the on-chip transforms");
   std::vector<int64_t> out;
-  for (; ilog2(nf) - 1 <= maxlog; nf <<= 1) {
-    out.push_back(nf);
+  for (; ilog2(nf) - 1 <= kMaxLogNLong; nf <<= 1) {
+    if (transform_exists(ilog2(nf) - 1, fp64, 0)) out.push_back(nf);
     if ((nf >> 1) >= 2 * longest) break;
   }
+  if (out.empty()) fail(MM_EUNSUPPORTED, "n_c too large for the transforms");
   return out;
 }
 
@@ -425,17 +446,12 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
   int best_v = 0;
   for (int64_t nf : lens) {
     for (int v = 0; v < kOlsVariants; ++v) {
-      if (!ols_variant_exists(ilog2(nf) - 1, fp64, v)) continue;
+      if (!transform_exists(ilog2(nf) - 1, fp64, v)) continue;
       FilterSetup cand;
       build_filter_nf(P, cand, fp64, nf, s, v, true);
-      hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw, cand.tw2,
-                        P->n_t, P->n_c, cand.m, 1, s, v),
-             "autotune warm-up");
+      apply_ols(P, cand, fp64, ya, yb, cand.spec, 1, s);   // warm-up
       hipchk(hipEventRecord(e0, s), "event");
-      for (int rep = 0; rep < 3; ++rep)
-        hipchk(launch_ols(fp64, fp64, cand.logn, ya, yb, cand.chunks, cand.n_chunks, cand.spec, cand.ptw,
-                          cand.tw2, P->n_t, P->n_c, cand.m, 1, s, v),
-               "autotune");
+      for (int rep = 0; rep < 3; ++rep) apply_ols(P, cand, fp64, ya, yb, cand.spec, 1, s);
       hipchk(hipEventRecord(e1, s), "event");
       hipchk(hipEventSynchronize(e1), "autotune");
       float ms = 0;
@@ -477,7 +493,7 @@ int64_t choose_nf(int nf_req, int n_c, int64_t longest, bool fp64, bool secondar
 int choose_variant(int shape_req, int64_t nf, bool fp64) {
   const int logn = ilog2(nf) - 1;
   const int v = shape_req > 0 ? shape_req - 1 : default_ols_variant(logn, fp64);
-  return ols_variant_exists(logn, fp64, v) ? v : 0;
+  return transform_exists(logn, fp64, v) ? v : 0;
 }
 
 void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool secondary = false) {
@@ -498,17 +514,17 @@ int64_t count_chunks(const std::vector<int64_t>& iv_start, int64_t m) {
 void check_transform_length(int64_t nf, bool fp64) {
   const int maxlog = ols_max_logn(fp64);
   const int logn = ilog2(nf) - 1;
-  if (logn > maxlog)
-    fail(MM_EUNSUPPORTED, "FFT length " + std::to_string(nf) + " exceeds the on-chip transform limit " +
-                              std::to_string(int64_t(1) << (maxlog + 1)) +
-                              (fp64 ? " for float64" : " for float32"));
+  if (logn > maxlog && !ols_long_exists(logn))
+    fail(MM_EUNSUPPORTED, "no transform of FFT length " + std::to_string(nf) + (fp64 ? " in float64" : " in float32") +
+                              " (on-chip up to " + std::to_string(int64_t(1) << (maxlog + 1)) +
+                              ", four-step 2^17 and 2^18)");
   if (logn < kMinLogN) fail(MM_EUNSUPPORTED, "FFT length below 128");
 }
 
 void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant, bool tmp) {
   check_transform_length(nf, fp64);
   const int logn = ilog2(nf) - 1;
-  if (!ols_variant_exists(logn, fp64, variant)) variant = 0;
+  if (!transform_exists(logn, fp64, variant)) variant = 0;
   auto get = [&](int64_t bytes) -> char* { return tmp ? P->temp<char>(bytes) : P->alloc<char>(bytes); };
   fs.fp64 = fp64;
   fs.logn = logn;
@@ -533,15 +549,56 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
   const int esz = fp64 ? 8 : 4;
   fs.tw2 = get((int64_t)fs.N * 2 * esz);
   hipchk(launch_tw2_table(fs.tw2, logn, fp64, s), "twiddle table");
-  const int ntw = pass_twiddle_count(logn, fp64, variant);
-  if (ntw < 0) fail(MM_EUNSUPPORTED, "no transform for this FFT length");
-  fs.ptw = get((int64_t)std::max(ntw, 1) * 2 * esz);
-  hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s, variant), "pass twiddle tables");
+  fs.long_path = transform_long(logn, fp64);
+  if (fs.long_path) {   // four-step: twiddles of its 2^8-point columns and 2^(logn - 8)-point rows
+    fs.ptw = get((int64_t)std::max(pass_twiddle_count(8, fp64, 0), 1) * 2 * esz);
+    hipchk(launch_pass_twiddles(fs.ptw, 8, fp64, s, 0), "pass twiddle tables");
+    fs.ptw_b = get((int64_t)std::max(pass_twiddle_count(logn - 8, fp64, 0), 1) * 2 * esz);
+    hipchk(launch_pass_twiddles(fs.ptw_b, logn - 8, fp64, s, 0), "pass twiddle tables");
+    fs.ltab = get((int64_t)ols_long_table_count(logn) * 2 * esz);
+    hipchk(launch_long_tables(logn, fp64, fs.ltab, s), "four-step twiddle tables");
+    fs.batch = std::min<int64_t>(ols_long_batch(logn, fp64), std::max<int64_t>((int64_t)fs.n_chunks * P->R, 1));
+    fs.work = get(fs.batch * (int64_t)fs.N * 2 * esz);
+  } else {
+    const int ntw = pass_twiddle_count(logn, fp64, variant);
+    if (ntw < 0) fail(MM_EUNSUPPORTED, "no transform for this FFT length");
+    fs.ptw = get((int64_t)std::max(ntw, 1) * 2 * esz);
+    hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s, variant), "pass twiddle tables");
+  }
   fs.spec = get((int64_t)P->n_filt * (fs.N + 1) * esz);
-  char* sscr = P->temp<char>((int64_t)spectra_scratch_bytes(logn));
-  hipchk(launch_spectra(P->lags, P->n_filt, P->n_c, logn, fp64, fs.spec, sscr, s), "filter spectra");
+  char* sscr = P->temp<char>((int64_t)symbol_scratch_bytes(logn, fp64, P->n_filt));
+  build_symbols(fs, P->lags, P->n_filt, P->n_c, fs.spec, sscr, s);
   P->release(sscr);   // later work on this stream may reuse it
   fs.ready = true;
+}
+
+// Symbol tables F_b / (4N) of n_filt filters from their lags (launch_spectra), in the
+// order the transform of fs reads them: natural, or row order for the four-step
+// transform (launch_long_symbol_rows); scr: symbol_scratch_bytes
+void build_symbols(const FilterSetup& fs, const double* lags, int n_filt, int n_c, void* out, char* scr,
+                   hipStream_t s) {
+  if (!fs.long_path) {
+    hipchk(launch_spectra(lags, n_filt, n_c, fs.logn, fs.fp64, out, scr, s), "filter spectra");
+    return;
+  }
+  char* nat = scr + block_bytes((int64_t)spectra_scratch_bytes(fs.logn), 1);
+  hipchk(launch_spectra(lags, n_filt, n_c, fs.logn, fs.fp64, nat, scr, s), "filter spectra");
+  hipchk(launch_long_symbol_rows(fs.logn, fs.fp64, nat, out, n_filt, s), "filter spectra in row order");
+}
+
+// y_out = N^-1 y_in by the overlap-save transforms of fs with the symbol table spec
+// (the plan's filters, or their derivatives); R rows; in_f64 = element type of y_in,
+// y_out has the compute type of fs; st (optional): rows of stopped RHS are skipped
+void apply_ols(mm_plan_s* P, const FilterSetup& fs, bool in_f64, const void* y_in, void* y_out, const void* spec,
+               int R, hipStream_t s, const CgState* st) {
+  if (fs.long_path)
+    hipchk(launch_ols_long(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, spec, fs.ptw, fs.ptw_b,
+                           fs.tw2, fs.ltab, fs.work, fs.batch, P->n_t, P->n_c, fs.m, R, s, st),
+           "overlap-save filter (four-step)");
+  else
+    hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, spec, fs.ptw, fs.tw2, P->n_t,
+                      P->n_c, fs.m, R, s, fs.variant, st),
+           "overlap-save filter");
 }
 
 // y_out = N^-1 y_in with the transforms of fs (or the diagonal f_b(0) when
@@ -555,9 +612,7 @@ void weight(mm_plan_s* P, const FilterSetup& fs, const void* y_in, bool in_f64, 
            "white-noise weight");
     return;
   }
-  hipchk(launch_ols(fs.fp64, in_f64, fs.logn, y_in, y_out, fs.chunks, fs.n_chunks, fs.spec, fs.ptw,
-                    fs.tw2, P->n_t, P->n_c, fs.m, R, s, fs.variant, st),
-         "overlap-save filter");
+  apply_ols(P, fs, in_f64, y_in, y_out, fs.spec, R, s, st);
 }
 
 // y_r = [P B] x_r: x in iteration layout (rows of stride nu), y a TOD of type y_f64
@@ -1012,15 +1067,32 @@ void validate_desc(const mm_desc_t* d) {
 
 int64_t y_bytes(bool fp64, int R, int64_t n) { return fp64 ? (int64_t)R * n * 8 : std::max<int64_t>((int64_t)R * 4, 8) * n; }
 
+// Scratch of build_symbols: the spectra's own, then (four-step transform) the tables in
+// natural order before they are put in row order
+size_t symbol_scratch_bytes(int logn, bool fp64, int n_filt) {
+  const size_t b = spectra_scratch_bytes(logn);
+  if (!transform_long(logn, fp64)) return b;
+  return block_bytes((int64_t)b, 1) + (size_t)n_filt * ((size_t(1) << logn) + 1) * (fp64 ? 8 : 4);
+}
+
 // Device bytes of a filter set-up (chunk table, twiddles, spectra) and of the
 // spectra build's scratch
-size_t filter_bytes(const std::vector<int64_t>& iv_start, int n_filt, int n_c, int64_t nf, int variant, bool fp64) {
+size_t filter_bytes(const std::vector<int64_t>& iv_start, int n_filt, int n_c, int64_t nf, int variant, bool fp64,
+                    int R) {
   const int logn = ilog2(nf) - 1;
   const int64_t N = int64_t(1) << logn;
   const int esz = fp64 ? 8 : 4;
-  const int ntw = pass_twiddle_count(logn, fp64, variant);
-  return block_bytes(count_chunks(iv_start, nf - 2 * n_c) * (int64_t)sizeof(OlsChunk), 1) +
-         block_bytes(N * 2 * esz, 1) + block_bytes((int64_t)std::max(ntw, 1) * 2 * esz, 1) +
+  const int64_t n_chunks = count_chunks(iv_start, nf - 2 * n_c);
+  size_t tw;
+  if (transform_long(logn, fp64)) {   // column and row twiddles, intermediates of a batch
+    const int64_t batch = std::min<int64_t>(ols_long_batch(logn, fp64), std::max<int64_t>(n_chunks * R, 1));
+    tw = block_bytes((int64_t)std::max(pass_twiddle_count(8, fp64, 0), 1) * 2 * esz, 1) +
+         block_bytes((int64_t)std::max(pass_twiddle_count(logn - 8, fp64, 0), 1) * 2 * esz, 1) +
+         block_bytes((int64_t)ols_long_table_count(logn) * 2 * esz, 1) + block_bytes(batch * N * 2 * esz, 1);
+  } else {
+    tw = block_bytes((int64_t)std::max(pass_twiddle_count(logn, fp64, variant), 1) * 2 * esz, 1);
+  }
+  return block_bytes(n_chunks * (int64_t)sizeof(OlsChunk), 1) + block_bytes(N * 2 * esz, 1) + tw +
          block_bytes((int64_t)n_filt * (N + 1) * esz, 1);
 }
 
@@ -1102,10 +1174,11 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
     size_t most = 0, most_tmp = 0;
     for (int64_t nf : autotune_lengths(n_c, longest, fp64))
       for (int v = 0; v < kOlsVariants; ++v) {
-        if (!ols_variant_exists(ilog2(nf) - 1, fp64, v)) continue;
-        const size_t fb = filter_bytes(iv, nf_filt, n_c, nf, v, fp64);
+        if (!transform_exists(ilog2(nf) - 1, fp64, v)) continue;
+        const size_t fb = filter_bytes(iv, nf_filt, n_c, nf, v, fp64, R);
         most = std::max(most, fb);
-        most_tmp = std::max(most_tmp, fb + block_bytes((int64_t)spectra_scratch_bytes(ilog2(nf) - 1), 1));
+        most_tmp =
+            std::max(most_tmp, fb + block_bytes((int64_t)symbol_scratch_bytes(ilog2(nf) - 1, fp64, nf_filt), 1));
         if (fp64) logn64 = std::max(logn64, ilog2(nf) - 1);
       }
     B.pers += most;
@@ -1114,16 +1187,16 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
     const int64_t nf = choose_nf(d->n_f, n_c, longest, fp64, false);
     const int logn = ilog2(nf) - 1;
     check_transform_length(nf, fp64);
-    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, fp64), fp64);
-    B.temps += block_bytes((int64_t)spectra_scratch_bytes(logn), 1);
+    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, fp64), fp64, R);
+    B.temps += block_bytes((int64_t)symbol_scratch_bytes(logn, fp64, nf_filt), 1);
     if (fp64) logn64 = logn;
   }
   if (!fp64) {
     const int64_t nf = choose_nf(d->n_f, n_c, longest, true, true);
     logn64 = ilog2(nf) - 1;
     check_transform_length(nf, true);
-    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, true), true);
-    B.temps += block_bytes((int64_t)spectra_scratch_bytes(logn64), 1);
+    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, true), true, R);
+    B.temps += block_bytes((int64_t)symbol_scratch_bytes(logn64, true, nf_filt), 1);
   }
   // interval tables and their coarse index
   const int sh = interval_hint_shift(iv, n);
@@ -1151,7 +1224,7 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
     B.call_temps = block_bytes(std::max<int64_t>(n, 1), 8) + block_bytes((int64_t)nf_filt * n_c, 8) +
                    block_bytes(3 * (int64_t)nf_filt * (N64 + 1), 8) + block_bytes(3 * (int64_t)std::max(d->n_intervals, 1), 8) +
                    block_bytes((int64_t)std::max(lags_scratch_bytes(n_c, lag_len, batch),
-                                                 spectra_scratch_bytes(logn64)), 1);
+                                                 symbol_scratch_bytes(logn64, true, nf_filt)), 1);
   }
   return B;
 }
@@ -2113,7 +2186,7 @@ mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_tod, int32_t tod_dtype,
     double* dlags = P->temp<double>((int64_t)nfl * P->n_c);
     double* dspec = P->temp<double>(3 * spec_n);                                   // one symbol per theta
     double* ivd = P->temp<double>(3 * (int64_t)n_iv);
-    char* lscr = P->temp<char>((int64_t)std::max(lsb, spectra_scratch_bytes(f64.logn)));
+    char* lscr = P->temp<char>((int64_t)std::max(lsb, symbol_scratch_bytes(f64.logn, true, nfl)));
     auto release_all = [&]() {
       P->release(lscr);
       P->release(ivd);
@@ -2127,8 +2200,7 @@ mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_tod, int32_t tod_dtype,
       for (int mode = 1; mode <= 3; ++mode) {
         hipchk(launch_lags(P->d_params, nfl, P->f_samp, P->n_c, P->lag_len, dlags, lscr, lsb, s, mode),
                "derivative lags");
-        hipchk(launch_spectra(dlags, nfl, P->n_c, f64.logn, true, dspec + (mode - 1) * spec_n, lscr, s),
-               "derivative spectra");
+        build_symbols(f64, dlags, nfl, P->n_c, dspec + (mode - 1) * spec_n, lscr, s);
       }
       for (int r = 0; r < P->R; ++r) {
         // v_r = d_r - P m_r and u_r = P lambda_r, both in float64
@@ -2139,9 +2211,7 @@ mm_status_t mm_noise_gradient(mm_plan_t P, const void* d_tod, int32_t tod_dtype,
         to_obs(P, d_lambda + (int64_t)r * P->ng(), P->vz, 1, s);
         gather_all(P, true, P->vz, ya, 1, s);
         for (int mode = 0; mode < 3; ++mode) {
-          hipchk(launch_ols(true, true, f64.logn, v64, yb, f64.chunks, f64.n_chunks, dspec + mode * spec_n, f64.ptw,
-                            f64.tw2, P->n_t, P->n_c, f64.m, 1, s, f64.variant),
-                 "derivative filter");
+          apply_ols(P, f64, true, v64, yb, dspec + mode * spec_n, 1, s);
           hipchk(launch_interval_dots(ya, yb, P->d_iv_start, P->n_iv, ivd + (int64_t)mode * n_iv, s),
                  "interval dots");
         }

@@ -85,6 +85,25 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
                       const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s,
                       int variant = 0, const CgState* st = nullptr);
 
+// ---------------------------------------------------------------- long filter (k_ols_long.hip)
+// The overlap-save N^-1 with transforms of 2^logn complex points beyond one workgroup
+// (logn 16 and 17, n_f = 2^17 and 2^18), as a batched four-step transform: ptw1 / ptw2 =
+// launch_pass_twiddles tables of lengths 2^8 and 2^(logn - 8), tw2 as for launch_ols,
+// work = device buffer of batch jobs x 2^logn complex points of the compute type.
+// spec_rows: the symbol table in row order (launch_long_tables), ltab: its twiddle tables
+bool ols_long_exists(int logn);
+int64_t ols_long_batch(int logn, bool fp64);   // jobs per batch (intermediates of ~64 MiB)
+int ols_long_table_count(int logn);            // complex entries of ltab
+hipError_t launch_long_tables(int logn, bool fp64, void* ltab, hipStream_t s);
+// spec_rows[f] = spec[f] (launch_spectra's tables) in row order: entry k1 N2 + k2 holds
+// k = k1 + N1 k2 (N1 = 2^8, N2 = 2^(logn - 8)), entry N holds k = N; n_filters tables
+hipError_t launch_long_symbol_rows(int logn, bool fp64, const void* spec, void* spec_rows, int n_filters,
+                                   hipStream_t s);
+hipError_t launch_ols_long(bool fp64, bool in_f64, int logn, const void* y_in, void* y_out, const OlsChunk* chunks,
+                           int n_chunks, const void* spec_rows, const void* ptw1, const void* ptw2, const void* tw2,
+                           const void* ltab, void* work, int64_t batch, int64_t n_t, int n_c, int m, int n_rhs,
+                           hipStream_t s, const CgState* st = nullptr);
+
 // ---------------------------------------------------------------- pointing (k_pointing.hip)
 // y[r][t] = (P p_r)_t; p rows of stride vs (map values first, observed layout)
 // p32 (optional): a float32 copy of the map part of p (rows of stride vs32), read

@@ -18,6 +18,8 @@ by one), hits at those pixels are counted exactly, and the converged maps'
 residual H m - b at those pixels is checked against the oracle's H and b.
 """
 
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -34,8 +36,12 @@ TOL = {"fp64": 1e-10, "mixed": 1e-5}
 def _gen(name, **kw):
     from synth.gpu import make_device_problem
     print(f"generating {name} {kw}", flush=True)
+    # start from an empty cache: inputs carved out of an earlier test's cached segments
+    # would pin those segments, and the plan's workspace (up to ~190 GiB) needs the rest
+    gc.collect()
+    torch.cuda.empty_cache()
     p = make_device_problem(name, device="cuda:0", **kw)
-    torch.cuda.empty_cache()          # the plan allocates outside torch's cache
+    torch.cuda.empty_cache()          # generation temporaries
     return p
 
 
@@ -266,3 +272,45 @@ def test_forced_transform_shapes_match_the_oracle(n_f, shape):
     assert max_rel(m64.apply_A(x).cpu().numpy()[0], want) <= TOL["fp64"]
     wy = m64.weight(y.double()).cpu().numpy()[0]
     assert max_rel(wy, o.apply_ninv(y.double().cpu().numpy()[0])) <= 1e-12
+
+
+@pytest.mark.parametrize("n_f", [1 << 17, 1 << 18])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_four_step_transform_lengths_match_the_oracle(n_f, precision):
+    """The paper's FFT lengths beyond one workgroup (batched four-step transform): N^-1 and H x
+    against the oracle at n_f = 2^17 and 2^18, in float32 and float64."""
+    p = _gen("c3", n_det=2, det_len=1 << 18)
+    o = _host_oracle(p)
+    mm = _plan(p, precision, n_f=n_f)
+    assert mm.info()["n_f"] == n_f
+    x = _random_map(1, p.n_pix, 23)
+    hx = mm.apply_A(x).cpu().numpy()[0]
+    want = o.to_global(o.apply_H(o.to_observed(x[0].cpu().numpy())))
+    assert max_rel(hx, want) <= TOL[precision]
+    y = p.tod[:1].contiguous()
+    if precision == "fp64":
+        y = y.double()
+    wy = mm.weight(y).double().cpu().numpy()[0]
+    err = max_rel(wy, o.apply_ninv(y.double().cpu().numpy()[0]))
+    print(f"n_f {n_f} {precision}: N^-1 max rel {err:.3e}", flush=True)
+    assert err <= (1e-5 if precision == "mixed" else 1e-12)
+    m, _ = mm.solve(p.tod, fixed_iters=4, refine=False)
+    b = o.rhs(p.tod.double().cpu().numpy()[0])
+    xo, _ = o.pcg(b, fixed_iters=4)
+    assert max_rel(m.cpu().numpy()[0], o.to_global(xo)) <= TOL[precision]
+
+
+def test_four_step_transform_on_ragged_intervals():
+    """Intervals of 1 to 300,000 samples (one chunk, several chunks, shorter than the halo)
+    through the 2^17-point four-step transform, two filters, against the direct convolution."""
+    import synth
+    from gpu_helpers import plan_for, oracle_for, tod_tensor
+    lens = [[1, 7, 300, 70000, 150000], [131000, 3]]
+    p = synth.make_custom(3, grid=(64, 64), det_lens=tuple(sum(l) for l in lens), interval_lens=lens,
+                          filters=((1.0, 0.3, 1.6), (0.8, 0.1, 1.2)), n_c=512, f_samp=50.0, seed=31)
+    o = oracle_for(p, 1 << 16)
+    for precision, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        mm = plan_for(p, precision=precision, n_f=1 << 17, lag_dft_len=1 << 16)
+        y = tod_tensor(p)
+        wy = mm.weight(y if precision == "fp64" else y.float()).double().cpu().numpy()[0]
+        assert max_rel(wy, o.apply_ninv(p.tod[0])) <= tol, precision
