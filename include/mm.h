@@ -161,10 +161,12 @@ typedef struct {
                                    workgroups per CU; 6 = 1024 threads x 16 points, radix-8
                                    passes, pairs in registers; 7 = shape 6 with split exchanges,
                                    two workgroups per CU; 8 = 512 threads x 32 points, radix-8
-                                   passes, pairs in registers.  For 2^15 points shape 3 is 1024
+                                   passes, pairs in registers; 9 = shape 6 with each exchange
+                                   made in two halves of the index space through half the LDS,
+                                   two workgroups per CU.  For 2^15 points shape 3 is 1024
                                    threads x 32 points, radix-8 passes, pairs in registers.
                                    Shape 2 exists for float32 transforms of 2^13 .. 2^15 points,
-                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 8 for 2^14
+                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 9 for 2^14
                                    points (3, 6 and 8 also in float64); elsewhere shape 1 is
                                    used.  Ignored with n_f = -1 (the autotuner tries every
                                    shape). */
@@ -183,7 +185,7 @@ typedef struct {
                                    the sliced copy's (a multiple of 64, >= n_valid; the excess
                                    is padding to the widest pixel of each slice) */
   int64_t n_tmpl;               /* template amplitudes per RHS in map-shaped buffers (0 = none) */
-  int32_t fft_shape;            /* transform shape the iterations use (1 .. 8, see mm_desc_t) */
+  int32_t fft_shape;            /* transform shape the iterations use (1 .. 9, see mm_desc_t) */
 } mm_plan_info_t;
 
 /*

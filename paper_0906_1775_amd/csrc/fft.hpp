@@ -126,8 +126,14 @@ __device__ __forceinline__ void dft_reg(cx<T>* v) {
 // FORCE_SPLIT: exchange real and imaginary parts separately even when N complex
 // points fit in LDS (half the LDS, so two workgroups can share a CU).
 // PAIRED: the paired layout of the last forward pass (see above).
+// HALF: exchange through an LDS buffer of N/2 complex points, the lower half of the
+// index space first, then the upper half.  Which half a point is written to and read
+// from never depends on the thread (the top index bit comes from the butterfly block
+// or from r), so each half moves as many b64 accesses as the full exchange, at twice
+// the barriers and half the LDS: two workgroups share a CU, one's exchanges overlapping
+// the other's arithmetic.
 template <typename T, int LOGN, int NT_, int LOGE, int LOGR_ = LOGE, bool FORCE_SPLIT = false,
-          bool PAIRED_ = false>
+          bool PAIRED_ = false, bool HALF_ = false>
 struct BlockFFT {
   static constexpr int N = 1 << LOGN;
   static constexpr int NT = NT_;
@@ -148,12 +154,17 @@ struct BlockFFT {
   static constexpr int sc_pad_log = (sizeof(T) == 4) ? 5 : 4;  // 128 B / sizeof T
   static constexpr int cx_bytes = (N + (N >> cx_pad_log)) * 2 * (int)sizeof(T);
   static constexpr int sc_bytes = (N + (N >> sc_pad_log)) * (int)sizeof(T);
-  static constexpr bool SPLIT = FORCE_SPLIT || cx_bytes > kLdsLimit;
+  static constexpr bool HALF = HALF_;
+  static constexpr int half_bytes = (N / 2 + ((N / 2) >> cx_pad_log)) * 2 * (int)sizeof(T);
+  static constexpr bool SPLIT = !HALF && (FORCE_SPLIT || cx_bytes > kLdsLimit);
   static constexpr bool PAIRED = PAIRED_;
   static_assert(!PAIRED || (NP >= 2 && (E >> LOGR_) % 2 == 0), "paired layout needs an even butterfly count");
   // is pass p of a sequence in the paired layout (last forward pass, first reversed pass)
   static constexpr bool pass_paired(bool fwd, int p) { return PAIRED && (fwd ? p == NP - 1 : p == 0); }
-  static constexpr int LDS_BYTES = SPLIT ? sc_bytes : cx_bytes;
+  static constexpr int LDS_BYTES = HALF ? half_bytes : (SPLIT ? sc_bytes : cx_bytes);
+  static_assert(!HALF || (NT * (1 << LOGR_) <= N / 2 && (1 << LOGR_) >= 2 && (LOGN % LOGR_ == 0 || (1 << (LOGN % LOGR_)) >= 2)),
+                "half exchanges need at least two butterflies per thread");
+  static_assert(!HALF || !PAIRED || (E >> LOGR_) == 2, "half exchanges with the paired layout need two butterflies");
   static_assert(LDS_BYTES <= kLdsLimit, "transform does not fit in LDS");
 
   __device__ static __forceinline__ int cpad(int i) { return i + (i >> cx_pad_log); }
@@ -187,6 +198,23 @@ struct BlockFFT {
     const int b = bfly<PAIR>(t, i);
     return ((b >> LOGNS) << (LOGNS + LOGR)) + (b & ((1 << LOGNS) - 1));
   }
+  // Index half (0: below N/2) of the output slot of element (i, r) of a pass (LOGR, LOGNS),
+  // and of the input slot of element (i, r) of a pass of radix 2^LOGR2, for every thread.
+  // Output: below the last pass the top bit is the top bit of the butterfly b < N/R,
+  // i.e. of its block i NT (t < NT <= N/(2R)); the paired layout's odd i own block
+  // NB - i = i (NB = 2).  In the last pass (Ns R = N) it is the top bit of r.  Input:
+  // b < N/R2, so the top bit of b + r N/R2 is that of r.
+  template <int LOGR, int LOGNS>
+  static constexpr int out_half(int i, int r) {
+    if constexpr (LOGNS + LOGR >= LOGN) {
+      return r >> (LOGR - 1);
+    } else {
+      return (i * NT) >> (LOGN - LOGR - 1);
+    }
+  }
+  template <int LOGR2>
+  static constexpr int in_half(int r) { return r >> (LOGR2 - 1); }
+
   // Padded LDS slot of v + (r << LOGC), with the padding of the constant part
   // folded at compile time: v + c and v stay in rows (of 2^PL elements) that
   // differ by exactly floor(c / 2^PL) for every index an exchange forms.  Reads
@@ -243,7 +271,34 @@ struct BlockFFT {
   __device__ static __forceinline__ void exchange(cx<T>* v, void* lds_raw, int t) {
     constexpr int R = 1 << LOGR, NB = E / R;
     constexpr int R2 = 1 << LOGR2, NB2 = E / R2;
-    if constexpr (!SPLIT) {
+    if constexpr (HALF) {
+      // the points read in the first half land in nv, not in v, whose upper-half points
+      // are still to be written (the registers freed by the first writes take them)
+      cx<T>* lds = reinterpret_cast<cx<T>*>(lds_raw);
+      constexpr int HP = N / 2 + ((N / 2) >> cx_pad_log);   // padded slot of N/2
+      cx<T> nv[E];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int vb = out_base<LOGR, LOGNS, PAIR_OUT>(t, i);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (out_half<LOGR, LOGNS>(i, r) == h) lds[padded<cx_pad_log, LOGNS>(vb, r) - h * HP] = v[i * R + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+          const int vb = bfly<PAIR_IN>(t, i);
+#pragma unroll
+          for (int r = 0; r < R2; ++r)
+            if (in_half<LOGR2>(r) == h) nv[i * R2 + r] = lds[padded<cx_pad_log, LOGN - LOGR2>(vb, r) - h * HP];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = nv[e];
+    } else if constexpr (!SPLIT) {
       cx<T>* lds = reinterpret_cast<cx<T>*>(lds_raw);
       __syncthreads();
 #pragma unroll

@@ -75,13 +75,16 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s) {
 // and two per CU.  Variant 5 is 1024 threads x 16 points with radix-8 passes
 // and the paired layout (the fastest 2^14-point shape measured in float32);
 // variant 6 is variant 5 split, two per CU; variant 7 is 512 threads
-// x 32 points with radix-8 passes, paired.  In float64 the 512-thread shapes
+// x 32 points with radix-8 passes, paired; variant 8 is variant 5 with half
+// exchanges (the lower half of the index space, then the upper half, through an
+// LDS buffer of N/2 points), two per CU at 64 VGPRs.  In float64 the 512-thread shapes
 // (variants 2 and 7) have twice the registers per thread, and variant 2 is the
 // fastest there.  BPC: workgroups per CU the register budget is sized for.
-template <int NT_, int LOGE_, int LOGR_, bool SPLIT_ = false, bool PAIRED_ = false, int BPC_ = 1>
+template <int NT_, int LOGE_, int LOGR_, bool SPLIT_ = false, bool PAIRED_ = false, int BPC_ = 1,
+          bool HALF_ = false>
 struct OlsCfg {
   static constexpr int NT = NT_, LOGE = LOGE_, LOGR = LOGR_, BPC = BPC_;
-  static constexpr bool SPLIT = SPLIT_, PAIRED = PAIRED_;
+  static constexpr bool SPLIT = SPLIT_, PAIRED = PAIRED_, HALF = HALF_;
   // minimum wavefronts per SIMD asked of the register allocator
   static constexpr int WPE = (BPC_ * NT_ / 256) > 1 ? (BPC_ * NT_ / 256) : 1;
 };
@@ -95,6 +98,7 @@ template <> struct OlsShape<14, 4> : OlsCfg<256, 6, 5, true, true, 2> {};
 template <> struct OlsShape<14, 5> : OlsCfg<1024, 4, 3, false, true> {};
 template <> struct OlsShape<14, 6> : OlsCfg<1024, 4, 3, true, true, 2> {};
 template <> struct OlsShape<14, 7> : OlsCfg<512, 5, 3, false, true> {};
+template <> struct OlsShape<14, 8> : OlsCfg<1024, 4, 3, false, true, 2, true> {};
 template <> struct OlsShape<15, 1> : OlsCfg<512, 6, 5, false, true> {};
 template <> struct OlsShape<15, 2> : OlsCfg<1024, 5, 3, false, true> {};
 
@@ -103,12 +107,13 @@ bool ols_variant_exists(int logn, bool fp64, int v) {
   if (v == 5 || v == 7 || (v == 2 && logn == 14)) return logn == 14;
   if (fp64) return false;
   return (v == 1 && (logn == 13 || logn == 14 || logn == 15)) || ((v >= 2 && v <= 6) && logn == 14) ||
+         (v == 8 && logn == 14) ||
          (v == 2 && logn == 15);
 }
 
 template <typename T, int LOGN, int V = 0>
 using ShapeFFT = BlockFFT<T, LOGN, OlsShape<LOGN, V>::NT, OlsShape<LOGN, V>::LOGE, OlsShape<LOGN, V>::LOGR,
-                          OlsShape<LOGN, V>::SPLIT, OlsShape<LOGN, V>::PAIRED>;
+                          OlsShape<LOGN, V>::SPLIT, OlsShape<LOGN, V>::PAIRED, OlsShape<LOGN, V>::HALF>;
 
 // per-pass twiddle rows: entry (j, r) of pass p = exp(-2 pi i j r / (Ns R))
 template <typename T, int LOGN, int V>
@@ -148,6 +153,7 @@ int pass_twiddle_count(int logn, bool fp64, int variant) {
   if (variant == 4) return pass_tw_total_t<float, 14, 4>();
   if (variant == 5) return fp64 ? pass_tw_total_t<double, 14, 5>() : pass_tw_total_t<float, 14, 5>();
   if (variant == 6) return pass_tw_total_t<float, 14, 6>();
+  if (variant == 8) return pass_tw_total_t<float, 14, 8>();
 #define MM_PTC(L) case L: return fp64 ? pass_tw_total_t<double, L>() : pass_tw_total_t<float, L>();
   switch (logn) {
     MM_PTC(6) MM_PTC(7) MM_PTC(8) MM_PTC(9) MM_PTC(10) MM_PTC(11) MM_PTC(12) MM_PTC(13) MM_PTC(14)
@@ -177,6 +183,7 @@ hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, i
   if (variant == 4) return pass_tw_launch<float, 14, 4>(tab, s);
   if (variant == 5) return fp64 ? pass_tw_launch<double, 14, 5>(tab, s) : pass_tw_launch<float, 14, 5>(tab, s);
   if (variant == 6) return pass_tw_launch<float, 14, 6>(tab, s);
+  if (variant == 8) return pass_tw_launch<float, 14, 8>(tab, s);
 #define MM_PTL(L) case L: return fp64 ? pass_tw_launch<double, L>(tab, s) : pass_tw_launch<float, L>(tab, s);
   switch (logn) {
     MM_PTL(6) MM_PTL(7) MM_PTL(8) MM_PTL(9) MM_PTL(10) MM_PTL(11) MM_PTL(12) MM_PTL(13) MM_PTL(14)
@@ -721,6 +728,7 @@ static hipError_t ols_dispatch(int logn, int variant, const void* y_in, void* y_
     if (variant == 3) return ols_launch<T, Tin, 14, 3>(MM_OLS_ARGS);
     if (variant == 4) return ols_launch<T, Tin, 14, 4>(MM_OLS_ARGS);
     if (variant == 6) return ols_launch<T, Tin, 14, 6>(MM_OLS_ARGS);
+    if (variant == 8) return ols_launch<T, Tin, 14, 8>(MM_OLS_ARGS);
     if (logn == 15) return ols_launch<T, Tin, 15>(MM_OLS_ARGS);
   }
 #define MM_OLS_CASE(L) case L: return ols_launch<T, Tin, L>(MM_OLS_ARGS);

@@ -1043,7 +1043,7 @@ void validate_desc(const mm_desc_t* d) {
   if (d->n_rhs < 1 || d->n_rhs > 64) fail(MM_EINVAL, "n_rhs must be in [1, 64]");
   if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
     fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
-  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 8]");
+  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 9]");
   validate_templates(d);
   if (d->iv_start[0] != 0 || d->iv_start[d->n_intervals] != d->n_samples)
     fail(MM_EINVAL, "intervals must start at 0 and end at n_samples");

@@ -67,7 +67,7 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s);
 int pass_twiddle_count(int logn, bool fp64, int variant = 0);
 hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, int variant = 0);
 // whether the overlap-save transform of 2^logn points has workgroup shape `variant`
-constexpr int kOlsVariants = 8;
+constexpr int kOlsVariants = 9;
 bool ols_variant_exists(int logn, bool fp64, int variant);
 // lags (mode 0) or their derivative with respect to sigma (1), f_knee (2), alpha (3)
 hipError_t launch_lags(const double* params /*dev [nf][3]*/, int n_filters, double f_samp, int n_c,
