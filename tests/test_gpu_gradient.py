@@ -27,12 +27,12 @@ def C4():
     return p, ref
 
 
-def _loss_and_grads(p, params=None, tod=None, precision="fp64"):
+def _loss_and_grads(p, params=None, tod=None, precision="fp64", n_f=0):
     from paper_0906_1775_amd import MapMaker, solve_map
     prm = p.filter_params if params is None else params
     dev = torch.device("cuda:0")
     mm = MapMaker(torch.from_numpy(p.pix).to(dev), None, p.n_pix, 1, p.iv_start, p.iv_filter,
-                  filter_params=prm, f_samp=p.f_samp, n_c=p.n_c, precision=precision)
+                  filter_params=prm, f_samp=p.f_samp, n_c=p.n_c, precision=precision, n_f=n_f)
     d = (tod_tensor(p) if tod is None else tod).clone().requires_grad_(True)
     th = torch.tensor(prm, dtype=torch.float64, requires_grad=True)
     m = solve_map(d, mm, th, tol=1e-13, max_iter=3000)
@@ -42,9 +42,12 @@ def _loss_and_grads(p, params=None, tod=None, precision="fp64"):
     return float(L), d.grad.detach().cpu().numpy()[0], th.grad.numpy()[0]
 
 
-def test_adjoint_matches_cpu_reference_gradient(C4):
+@pytest.mark.parametrize("n_f", [0, 1 << 17])
+def test_adjoint_matches_cpu_reference_gradient(C4, n_f):
+    """n_f = 2^17: the float64 filter and its derivative symbols run through the
+    four-step transform (symbols in row order)."""
     p, ref = C4
-    L, gd, gth = _loss_and_grads(p)
+    L, gd, gth = _loss_and_grads(p, n_f=n_f)
     assert abs(L - ref["loss"]) <= 1e-10 * abs(ref["loss"])
     assert rel_err(gd, ref["grad_d"]) <= 1e-8
     assert abs(gth[1] - ref["grad_f_knee"][0]) <= 1e-7 * abs(ref["grad_f_knee"][0])

@@ -3,7 +3,7 @@
 * a plan built in a torch-allocated workspace gives bit-identical hits, operators and
   maps to one built in a workspace the library allocates (mm_plan_create);
 * the bound from the descriptor holds for every kind of plan (precisions, Stokes,
-  right-hand sides, templates, white noise, the autotuner), and the workspace's
+  right-hand sides, templates, white noise, the autotuner, the four-step transform), and the workspace's
   contents on entry do not matter;
 * the plan orders every call after its build, whatever the stream: a plan built on one
   side stream and used at once on another gives the same lags and maps.
@@ -160,7 +160,7 @@ def _template_list(p):
 
 
 @pytest.mark.parametrize("case", ["t_fp64", "tqu_mixed_3rhs", "templates_mixed", "white", "autotune_fp64",
-                                  "all_excised"])
+                                  "all_excised", "four_step_mixed", "four_step_fp64"])
 def test_the_bound_holds_in_a_workspace_of_exactly_its_size(case):
     """Every plan kind builds and solves in a workspace of exactly mm_plan_workspace_size
     bytes, pre-filled with NaN bytes, and uses no more of it than the bound."""
@@ -179,6 +179,10 @@ def test_the_bound_holds_in_a_workspace_of_exactly_its_size(case):
         p, kw = _problem(3, n_c=1), dict(precision=0)
     elif case == "autotune_fp64":
         p, kw = _problem(3, n_c=16), dict(precision=0, n_f=-1)
+    elif case == "four_step_mixed":      # the batched four-step transform (2^16 complex points)
+        p, kw = _problem(3, n_rhs=2), dict(precision=1, n_f=1 << 17)
+    elif case == "four_step_fp64":       # 2^17 complex points in float64
+        p, kw = _problem(3), dict(precision=0, n_f=1 << 18)
     else:
         p, kw = _problem(3), dict(precision=1)
         p.pix[:] = -1
