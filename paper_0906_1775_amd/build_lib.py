@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmm.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_filter.hip", "k_ols_long.hip", "k_pointing.hip", "k_sort.hip", "k_cg.hip", "k_template.hip",
+SOURCES = ["k_filter.hip", "k_ols_long.hip", "k_ols_wave.hip", "k_pointing.hip", "k_sort.hip", "k_cg.hip", "k_template.hip",
            "mm_api.cpp"]
 
 FLAGS = [

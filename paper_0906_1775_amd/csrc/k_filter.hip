@@ -77,7 +77,9 @@ hipError_t launch_tw2_table(void* tw2, int logn, bool fp64, hipStream_t s) {
 // variant 6 is variant 5 split, two per CU; variant 7 is 512 threads
 // x 32 points with radix-8 passes, paired; variant 8 is variant 5 with half
 // exchanges (the lower half of the index space, then the upper half, through an
-// LDS buffer of N/2 points), two per CU at 64 VGPRs.  In float64 the 512-thread shapes
+// LDS buffer of N/2 points), two per CU at 64 VGPRs; variant 9 is the four-step
+// transform with wavefront-private inner stages (k_ols_wave.hip; its "pass twiddles"
+// are that kernel's tables and its symbol is read in row order).  In float64 the 512-thread shapes
 // (variants 2 and 7) have twice the registers per thread, and variant 2 is the
 // fastest there.  BPC: workgroups per CU the register budget is sized for.
 template <int NT_, int LOGE_, int LOGR_, bool SPLIT_ = false, bool PAIRED_ = false, int BPC_ = 1,
@@ -104,6 +106,7 @@ template <> struct OlsShape<15, 2> : OlsCfg<1024, 5, 3, false, true> {};
 
 bool ols_variant_exists(int logn, bool fp64, int v) {
   if (v == 0) return logn >= kMinLogN && logn <= ols_max_logn(fp64);
+  if (v == 9) return ols_wave_exists(logn, fp64);
   if (v == 5 || v == 7 || (v == 2 && logn == 14)) return logn == 14;
   if (fp64) return false;
   return (v == 1 && (logn == 13 || logn == 14 || logn == 15)) || ((v >= 2 && v <= 6) && logn == 14) ||
@@ -143,6 +146,7 @@ static int pass_tw_total_t() { return ShapeFFT<T, LOGN, V>::tw_total(); }
 
 int pass_twiddle_count(int logn, bool fp64, int variant) {
   if (!ols_variant_exists(logn, fp64, variant)) return -1;
+  if (variant == 9) return ols_wave_table_count();
   if (variant == 1)
     return logn == 13 ? pass_tw_total_t<float, 13, 1>()
                       : (logn == 14 ? pass_tw_total_t<float, 14, 1>() : pass_tw_total_t<float, 15, 1>());
@@ -173,6 +177,7 @@ static hipError_t pass_tw_launch(void* tab, hipStream_t s) {
 
 hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, int variant) {
   if (!ols_variant_exists(logn, fp64, variant)) return hipErrorInvalidValue;
+  if (variant == 9) return launch_wave_tables(tab, s);
   if (variant == 1)
     return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s)
                       : (logn == 14 ? pass_tw_launch<float, 14, 1>(tab, s) : pass_tw_launch<float, 15, 1>(tab, s));
@@ -747,6 +752,10 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
                       const void* tw2, int64_t n_t, int n_c, int m, int n_rhs, hipStream_t s, int variant,
                       const CgState* st) {
   if (n_chunks == 0 || n_rhs == 0) return hipSuccess;
+  if (variant == 9) {
+    if (fp64 || !ols_wave_exists(logn, fp64)) return hipErrorInvalidValue;
+    return launch_ols_wave(in_f64, y_in, y_out, chunks, n_chunks, spec, ptw, n_t, n_c, m, n_rhs, s, st);
+  }
   if (fp64) {
     return in_f64 ? ols_dispatch<double, double>(logn, variant, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,
                                                  n_t, n_c, m, n_rhs, s, st)

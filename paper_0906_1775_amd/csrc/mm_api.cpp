@@ -384,7 +384,7 @@ void wait_ready(mm_plan_s* P, hipStream_t stream) {
 void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipStream_t s, int variant, bool tmp);
 void build_symbols(const FilterSetup& fs, const double* lags, int n_filt, int n_c, void* out, char* scr,
                    hipStream_t s);
-size_t symbol_scratch_bytes(int logn, bool fp64, int n_filt);
+size_t symbol_scratch_bytes(int logn, bool fp64, int n_filt, int variant = 0);
 void apply_ols(mm_plan_s* P, const FilterSetup& fs, bool in_f64, const void* y_in, void* y_out, const void* spec,
                int R, hipStream_t s, const CgState* st = nullptr);
 
@@ -566,24 +566,29 @@ void build_filter_nf(mm_plan_s* P, FilterSetup& fs, bool fp64, int64_t nf, hipSt
     hipchk(launch_pass_twiddles(fs.ptw, logn, fp64, s, variant), "pass twiddle tables");
   }
   fs.spec = get((int64_t)P->n_filt * (fs.N + 1) * esz);
-  char* sscr = P->temp<char>((int64_t)symbol_scratch_bytes(logn, fp64, P->n_filt));
+  char* sscr = P->temp<char>((int64_t)symbol_scratch_bytes(logn, fp64, P->n_filt, fs.variant));
   build_symbols(fs, P->lags, P->n_filt, P->n_c, fs.spec, sscr, s);
   P->release(sscr);   // later work on this stream may reuse it
   fs.ready = true;
 }
 
 // Symbol tables F_b / (4N) of n_filt filters from their lags (launch_spectra), in the
-// order the transform of fs reads them: natural, or row order for the four-step
-// transform (launch_long_symbol_rows); scr: symbol_scratch_bytes
+// order the transform of fs reads them: natural, or row order for the batched four-step
+// transform (launch_long_symbol_rows) and for the wavefront-private one (variant 9,
+// launch_wave_symbols); scr: symbol_scratch_bytes
 void build_symbols(const FilterSetup& fs, const double* lags, int n_filt, int n_c, void* out, char* scr,
                    hipStream_t s) {
-  if (!fs.long_path) {
+  const bool wave = !fs.long_path && fs.variant == 9;
+  if (!fs.long_path && !wave) {
     hipchk(launch_spectra(lags, n_filt, n_c, fs.logn, fs.fp64, out, scr, s), "filter spectra");
     return;
   }
   char* nat = scr + block_bytes((int64_t)spectra_scratch_bytes(fs.logn), 1);
   hipchk(launch_spectra(lags, n_filt, n_c, fs.logn, fs.fp64, nat, scr, s), "filter spectra");
-  hipchk(launch_long_symbol_rows(fs.logn, fs.fp64, nat, out, n_filt, s), "filter spectra in row order");
+  if (wave)
+    hipchk(launch_wave_symbols(nat, out, n_filt, s), "filter spectra in row order");
+  else
+    hipchk(launch_long_symbol_rows(fs.logn, fs.fp64, nat, out, n_filt, s), "filter spectra in row order");
 }
 
 // y_out = N^-1 y_in by the overlap-save transforms of fs with the symbol table spec
@@ -1043,7 +1048,7 @@ void validate_desc(const mm_desc_t* d) {
   if (d->n_rhs < 1 || d->n_rhs > 64) fail(MM_EINVAL, "n_rhs must be in [1, 64]");
   if (d->n_f != 0 && d->n_f != -1 && (!is_pow2(d->n_f) || d->n_f <= 2 * d->n_c))
     fail(MM_EINVAL, "n_f must be 0, -1 or a power of two above 2 n_c");
-  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 9]");
+  if (d->fft_shape < 0 || d->fft_shape > kOlsVariants) fail(MM_EINVAL, "fft_shape must be in [0, 10]");
   validate_templates(d);
   if (d->iv_start[0] != 0 || d->iv_start[d->n_intervals] != d->n_samples)
     fail(MM_EINVAL, "intervals must start at 0 and end at n_samples");
@@ -1069,9 +1074,9 @@ int64_t y_bytes(bool fp64, int R, int64_t n) { return fp64 ? (int64_t)R * n * 8 
 
 // Scratch of build_symbols: the spectra's own, then (four-step transform) the tables in
 // natural order before they are put in row order
-size_t symbol_scratch_bytes(int logn, bool fp64, int n_filt) {
+size_t symbol_scratch_bytes(int logn, bool fp64, int n_filt, int variant) {
   const size_t b = spectra_scratch_bytes(logn);
-  if (!transform_long(logn, fp64)) return b;
+  if (!transform_long(logn, fp64) && !(variant == 9 && ols_wave_exists(logn, fp64))) return b;
   return block_bytes((int64_t)b, 1) + (size_t)n_filt * ((size_t(1) << logn) + 1) * (fp64 ? 8 : 4);
 }
 
@@ -1178,7 +1183,7 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
         const size_t fb = filter_bytes(iv, nf_filt, n_c, nf, v, fp64, R);
         most = std::max(most, fb);
         most_tmp =
-            std::max(most_tmp, fb + block_bytes((int64_t)symbol_scratch_bytes(ilog2(nf) - 1, fp64, nf_filt), 1));
+            std::max(most_tmp, fb + block_bytes((int64_t)symbol_scratch_bytes(ilog2(nf) - 1, fp64, nf_filt, v), 1));
         if (fp64) logn64 = std::max(logn64, ilog2(nf) - 1);
       }
     B.pers += most;
@@ -1187,8 +1192,9 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
     const int64_t nf = choose_nf(d->n_f, n_c, longest, fp64, false);
     const int logn = ilog2(nf) - 1;
     check_transform_length(nf, fp64);
-    B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, fp64), fp64, R);
-    B.temps += block_bytes((int64_t)symbol_scratch_bytes(logn, fp64, nf_filt), 1);
+    const int v = choose_variant(d->fft_shape, nf, fp64);
+    B.pers += filter_bytes(iv, nf_filt, n_c, nf, v, fp64, R);
+    B.temps += block_bytes((int64_t)symbol_scratch_bytes(logn, fp64, nf_filt, v), 1);
     if (fp64) logn64 = logn;
   }
   if (!fp64) {

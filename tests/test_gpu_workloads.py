@@ -242,14 +242,14 @@ def test_autotuned_transform_length(precision):
     mm = _plan(p, precision, n_f=-1)
     nf = mm.info()["n_f"]
     assert nf & (nf - 1) == 0 and nf > 2 * p.n_c
-    assert mm.info()["fft_shape"] in (tuple(range(1, 10)) if precision == "mixed" else (1, 3, 6, 8))
+    assert mm.info()["fft_shape"] in (tuple(range(1, 11)) if precision == "mixed" else (1, 3, 6, 8))
     x = _random_map(1, p.n_pix, 17)
     hx = mm.apply_A(x).cpu().numpy()[0]
     want = o.to_global(o.apply_H(o.to_observed(x[0].cpu().numpy())))
     assert max_rel(hx, want) <= TOL[precision]
 
 
-@pytest.mark.parametrize("n_f,shape", [(32768, s) for s in range(1, 10)] + [(65536, 1), (65536, 2), (65536, 3)])
+@pytest.mark.parametrize("n_f,shape", [(32768, s) for s in range(1, 11)] + [(65536, 1), (65536, 2), (65536, 3)])
 def test_forced_transform_shapes_match_the_oracle(n_f, shape):
     """Each workgroup shape of the float32 transforms of 2^14 and 2^15 complex points
     gives the oracle's H x; float64 plans use the shapes that exist in float64 (1, 3, 6, 8)
