@@ -149,7 +149,7 @@ typedef struct {
   int32_t n_templates;          /* template blocks appended to P, 0 .. 16 */
   const mm_template_t* templates;  /* host [n_templates], or NULL when n_templates = 0 */
   int32_t fft_shape;            /* workgroup shape of the overlap-save transform (n_f / 2 complex
-                                   points): 0 = library default (for 2^14 points shape 6 in
+                                   points): 0 = library default (for 2^14 points shape 10 in
                                    float32, 3 in float64; else 1); 1 = 16 points per thread,
                                    radix-16 passes (32 points per
                                    thread for 2^15 points); 2 = radix-32 passes, 32 points per
@@ -163,10 +163,13 @@ typedef struct {
                                    two workgroups per CU; 8 = 512 threads x 32 points, radix-8
                                    passes, pairs in registers; 9 = shape 6 with each exchange
                                    made in two halves of the index space through half the LDS,
-                                   two workgroups per CU.  For 2^15 points shape 3 is 1024
+                                   two workgroups per CU; 10 = 1024 threads x 16 points, a
+                                   four-step transform (16 x 1024) whose 1024-point stages
+                                   stay inside one wavefront (exchanges without workgroup
+                                   barriers), float32 only.  For 2^15 points shape 3 is 1024
                                    threads x 32 points, radix-8 passes, pairs in registers.
                                    Shape 2 exists for float32 transforms of 2^13 .. 2^15 points,
-                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 9 for 2^14
+                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 10 for 2^14
                                    points (3, 6 and 8 also in float64); elsewhere shape 1 is
                                    used.  Ignored with n_f = -1 (the autotuner tries every
                                    shape). */
@@ -185,7 +188,7 @@ typedef struct {
                                    the sliced copy's (a multiple of 64, >= n_valid; the excess
                                    is padding to the widest pixel of each slice) */
   int64_t n_tmpl;               /* template amplitudes per RHS in map-shaped buffers (0 = none) */
-  int32_t fft_shape;            /* transform shape the iterations use (1 .. 9, see mm_desc_t) */
+  int32_t fft_shape;            /* transform shape the iterations use (1 .. 10, see mm_desc_t) */
 } mm_plan_info_t;
 
 /*

@@ -40,9 +40,11 @@ constexpr int kTA = 0, kTB = kWN, kTC = kTB + 1024, kTD = kTC + 64, kT2 = kTD + 
 
 // l, opaque to the optimiser: table reads indexed by the result cannot be hoisted to the
 // kernel's start (where they would stay live across the whole transform and spill)
+// (the result is masked back to a lane index so that the compiler still knows its range
+// and forms 32-bit offsets from the uniform table bases)
 __device__ __forceinline__ int opaque(int l) {
   asm volatile("" : "+v"(l));
-  return l;
+  return l & 63;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -59,7 +61,7 @@ __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __r
   l = opaque(l);
   dft_reg<T, 4>(v);
 #pragma unroll
-  for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tab[kTB + k * 64 + l]);
+  for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tab[(uint32_t)(kTB + k * 64 + l)]);
   // private exchange: value (k1, l) to k1 * 64 + l; lane (m, h) = (l & 15, l >> 4) takes
   // k1 = 4h + e and l' = m + 16 lh
   wave_sync();
@@ -76,7 +78,7 @@ __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __r
   for (int e = 0; e < 4; ++e) {
     dft_reg<T, 2>(v + e * 4);
 #pragma unroll
-    for (int c = 1; c < 4; ++c) v[e * 4 + c] = cmul(v[e * 4 + c], tab[kTC + c * 16 + m]);
+    for (int c = 1; c < 4; ++c) v[e * 4 + c] = cmul(v[e * 4 + c], tab[(uint32_t)(kTC + c * 16 + m)]);
   }
   // private exchange: value (k1, c1, m) to (c1 * 16 + k1) * 17 + m; lane mu = c1 * 16 + k1 takes m = 0..15
   wave_sync();
@@ -96,35 +98,16 @@ __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __r
 bool ols_wave_exists(int logn, bool fp64) { return logn == 14 && !fp64; }
 int ols_wave_table_count() { return kTTotal; }
 
-// One workgroup per (chunk, RHS), as k_ols (same XCD-aware order, same outputs).
+// The packed window of one (chunk, RHS) job: thread g gets z[g + 1024 n_o] = u[2n] + i u[2n + 1]
 template <typename Tin>
-__global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, float* __restrict__ yout,
-                                                   const OlsChunk* __restrict__ chunks,
-                                                   const float* __restrict__ spec_w,
-                                                   const cx<float>* __restrict__ tab, int64_t n_t, int n_c, int m,
-                                                   const CgState* __restrict__ st) {
+__device__ __forceinline__ void wave_load(cx<float>* v, const Tin* __restrict__ yin, const OlsChunk& ch, int rhs,
+                                          int64_t n_t, int n_c, int g) {
   using T = float;
-  constexpr int N = kWN;
-  const int64_t n_wg = (int64_t)gridDim.x * gridDim.y;
-  const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
-  const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
-  const int rhs = (int)(job / gridDim.x);
-  if (st && !st[rhs].active) return;   // this RHS has stopped iterating
-  __shared__ __align__(16) cx<T> lds[16 * kWRow];
-  const int g = threadIdx.x, l = g & 63;
-  const int w = __builtin_amdgcn_readfirstlane(g >> 6);   // wavefront index, uniform
-  cx<T>* row = lds + w * kWRow;
-  const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
-  const int64_t roff = (int64_t)rhs * n_t;
+  using PI = typename std::conditional<sizeof(Tin) == 4, float2, double2>::type;
+  const Tin* __restrict__ src = yin + (int64_t)rhs * n_t;
   const int64_t s0 = ch.out_start - n_c;
   const int64_t lo = ch.iv_lo, hi = ch.iv_hi;
-  const Tin* __restrict__ src = yin + roff;
-  using PI = typename std::conditional<sizeof(Tin) == 4, float2, double2>::type;
-
-  // z[g + 1024 n_o] = u[2n] + i u[2n + 1]
-  cx<T> v[16];
-  const bool in_inside = s0 >= lo && s0 + 2 * N <= hi &&
+  const bool in_inside = s0 >= lo && s0 + 2 * kWN <= hi &&
                          ((reinterpret_cast<uintptr_t>(src + s0) & (sizeof(PI) - 1)) == 0);
   if (in_inside) {
     const PI* __restrict__ src2 = reinterpret_cast<const PI*>(src + s0);
@@ -142,11 +125,24 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
       v[no] = {a, b};
     }
   }
+}
 
+// N^-1 of one job whose window is in v (wave_load); writes the job's valid outputs.
+__device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const OlsChunk ch, int rhs,
+                                            float* __restrict__ yout, const float* __restrict__ spec_w,
+                                            const cx<float>* __restrict__ tab, int64_t n_t, int n_c, int m,
+                                            int g_in) {
+  using T = float;
+  constexpr int N = kWN;
+  const int g = g_in, l = g_in & 63;
+  const int w = __builtin_amdgcn_readfirstlane(g_in >> 6);   // wavefront index, uniform
+  cx<T>* row = lds + w * kWRow;
+  const int64_t s0 = ch.out_start - n_c;
+  const int64_t hi = ch.iv_hi;
   // forward, outer stage: 16-point DFTs over n_o (output k_o), twiddle W_N^(g k_o)
   dft_reg<T, 4>(v);
 #pragma unroll
-  for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tab[kTA + k * 1024 + g]);
+  for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tab[(uint32_t)(kTA + k * 1024 + g)]);
   // workgroup exchange: wavefront w takes row k_o = w, lane l the g = l + 64 j
 #pragma unroll
   for (int k = 0; k < 16; ++k) lds[k * kWRow + g] = v[k];
@@ -175,9 +171,9 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
     const cx<T> Ev = cadd(A, B);
     const cx<T> D = csub(A, B);
     const cx<T> O = {D.im, -D.re};
-    const cx<T> W = tab[kT2 + w * 1024 + kin];
+    const cx<T> W = tab[(uint32_t)(kT2 + w * 1024 + kin)];
     const cx<T> WO = cmul(W, O);
-    const T sa = S[w * 1024 + kin];
+    const T sa = S[(uint32_t)(w * 1024 + kin)];
     const cx<T> Y = cscale(cadd(Ev, WO), sa);
     const cx<T> Yp = cscale(csub(Ev, WO), sb);
     const cx<T> sm = cadd(Y, Yp);
@@ -193,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
     if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0);
     const int kin = lp + 64 * c;
     const int kp = w == 0 ? ((1024 - kin) & 1023) : 1023 - kin;   // partner's k_in
-    const T sb = (w == 0 && kin == 0) ? S[N] : S[wp * 1024 + kp];   // F_(N-k); k = 0 pairs with F_N
+    const T sb = (w == 0 && kin == 0) ? S[N] : S[(uint32_t)(wp * 1024 + kp)];   // F_(N-k); k = 0 pairs with F_N
     pair(kin, kp, v[c], prow[kp], sb, v[c], other[c]);
   }
   // k = N/2 (wavefront 0, k_in = 512) is its own partner: lane 0 of wavefront 0
@@ -221,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-    v[c] = cmul(v[c], tab[kTD + w * 1024 + ld + 64 * c]);
+    v[c] = cmul(v[c], tab[(uint32_t)(kTD + w * 1024 + ld + 64 * c)]);
   }
   wave_sync();
 #pragma unroll
@@ -233,7 +229,7 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
   dft_reg<T, 4>(v);
 
   // outputs 2n, 2n + 1 of n = g + 1024 n_b: the conjugate (re, -im)
-  T* __restrict__ dst = yout + roff;
+  T* __restrict__ dst = yout + (int64_t)rhs * n_t;
   const bool out_inside = ((n_c & 1) == 0) && s0 + n_c + m <= hi &&
                           ((reinterpret_cast<uintptr_t>(dst + s0) & (sizeof(float2) - 1)) == 0);
   if (out_inside) {
@@ -252,6 +248,27 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
       if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -v[nb].im;
     }
   }
+}
+
+
+// One workgroup per (chunk, RHS), as k_ols (same XCD-aware order, same outputs).
+template <typename Tin>
+__global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, float* __restrict__ yout,
+                                                   const OlsChunk* __restrict__ chunks,
+                                                   const float* __restrict__ spec_w,
+                                                   const cx<float>* __restrict__ tab, int64_t n_t, int n_c, int m,
+                                                   const CgState* __restrict__ st) {
+  const int64_t n_wg = (int64_t)gridDim.x * gridDim.y;
+  const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
+  const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
+  const int rhs = (int)(job / gridDim.x);
+  if (st && !st[rhs].active) return;   // this RHS has stopped iterating
+  __shared__ __align__(16) cx<float> lds[16 * kWRow];
+  const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
+  cx<float> v[16];
+  wave_load<Tin>(v, yin, ch, rhs, n_t, n_c, threadIdx.x);
+  wave_filter(v, lds, ch, rhs, yout, spec_w, tab, n_t, n_c, m, threadIdx.x);
 }
 
 // Twiddle tables of k_ols_wave, float32 from float64 angles

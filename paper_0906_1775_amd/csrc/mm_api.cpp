@@ -472,9 +472,9 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
 }
 
 // transform shape used when the descriptor leaves it open: the fastest measured
-// for each length (2^14 points: float32 1024 threads x 16 points, radix-8 passes;
-// float64 512 threads x 32 points, radix-16 passes; pairs in registers in both)
-int default_ols_variant(int logn, bool fp64) { return logn == 14 ? (fp64 ? 2 : 5) : 0; }
+// for each length (2^14 points: float32 the four-step transform with wavefront-private
+// inner stages; float64 512 threads x 32 points, radix-16 passes, pairs in registers)
+int default_ols_variant(int logn, bool fp64) { return logn == 14 ? (fp64 ? 2 : 9) : 0; }
 
 // n_f of a filter set-up that is not autotuned (secondary: the float64 filter of a
 // mixed plan, which takes a forced n_f only when it has a float64 transform)
