@@ -53,13 +53,49 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 16-point DFT in registers, natural order in and out, as 4 x 4:
+// X[k1 + 4 k2] = sum_n2 W_4^(n2 k2) [ W_16^(n2 k1) sum_n1 x[n2 + 4 n1] W_4^(n1 k1) ]
+// (8 4-point DFTs and 9 twiddles, one of them -i: 160 VALU operations against 168 for
+// four radix-2 stages)
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+  const cx<T> mt3 = {t3.im, -t3.re};   // -i t3
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, mt3);
+  a3 = csub(t1, mt3);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);   // v[n2 + 4 k1]
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) v[n2 + 4 * k1] = twiddle_const(v[n2 + 4 * k1], n2 * k1, 16);
+  cx<T> y[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+    dft4(a0, a1, a2, a3);
+    y[k1] = a0;
+    y[k1 + 4] = a1;
+    y[k1 + 8] = a2;
+    y[k1 + 12] = a3;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = y[k];
+}
+
 // 1024-point DFT of a wavefront's row: lane l, register j hold a[l + 64 j] on entry;
 // lane mu, register c2 hold A[mu + 64 c2] on exit.  row: this wavefront's LDS row.
 template <typename T>
 __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __restrict__ tab, int l) {
   // a[l + 64 j]: 16-point DFTs over j (output k1), twiddle W_1024^(l k1)
   l = opaque(l);
-  dft_reg<T, 4>(v);
+  dft16<T>(v);
 #pragma unroll
   for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tab[(uint32_t)(kTB + k * 64 + l)]);
   // private exchange: value (k1, l) to k1 * 64 + l; lane (m, h) = (l & 15, l >> 4) takes
@@ -76,7 +112,7 @@ __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __r
   // 4-point DFTs over lh (output c1), twiddle W_64^(m c1)
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    dft_reg<T, 2>(v + e * 4);
+    dft4(v[e * 4], v[e * 4 + 1], v[e * 4 + 2], v[e * 4 + 3]);
 #pragma unroll
     for (int c = 1; c < 4; ++c) v[e * 4 + c] = cmul(v[e * 4 + c], tab[(uint32_t)(kTC + c * 16 + m)]);
   }
@@ -90,7 +126,7 @@ __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __r
 #pragma unroll
   for (int q = 0; q < 16; ++q) v[q] = row[l * 17 + q];
   // 16-point DFTs over m (output c2): index k1 + 16 (c1 + 4 c2) = mu + 64 c2
-  dft_reg<T, 4>(v);
+  dft16<T>(v);
 }
 
 }  // namespace
@@ -140,7 +176,7 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
   const int64_t s0 = ch.out_start - n_c;
   const int64_t hi = ch.iv_hi;
   // forward, outer stage: 16-point DFTs over n_o (output k_o), twiddle W_N^(g k_o)
-  dft_reg<T, 4>(v);
+  dft16<T>(v);
 #pragma unroll
   for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tab[(uint32_t)(kTA + k * 1024 + g)]);
   // workgroup exchange: wavefront w takes row k_o = w, lane l the g = l + 64 j
@@ -174,10 +210,11 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
     const cx<T> W = tab[(uint32_t)(kT2 + w * 1024 + kin)];
     const cx<T> WO = cmul(W, O);
     const T sa = S[(uint32_t)(w * 1024 + kin)];
-    const cx<T> Y = cscale(cadd(Ev, WO), sa);
-    const cx<T> Yp = cscale(csub(Ev, WO), sb);
-    const cx<T> sm = cadd(Y, Yp);
-    const cx<T> Wd = cmul(cconj(W), csub(Y, Yp));
+    // s = Y + Y' = E (sa + sb) + W O (sa - sb), Y - Y' = E (sa - sb) + W O (sa + sb)
+    const T sp = sa + sb, sq = sa - sb;
+    const cx<T> sm = {Ev.re * sp + WO.re * sq, Ev.im * sp + WO.im * sq};
+    const cx<T> df = {Ev.re * sq + WO.re * sp, Ev.im * sq + WO.im * sp};
+    const cx<T> Wd = cmul(cconj(W), df);
     zk = {sm.re - Wd.im, -(sm.im + Wd.re)};
     znk = {sm.re + Wd.im, sm.im - Wd.re};
   };
@@ -226,7 +263,7 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
   // thread g = n_a takes k_o = 0..15; 16-point DFTs over k_o give X[g + 1024 n_b]
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = lds[k * kWRow + g];
-  dft_reg<T, 4>(v);
+  dft16<T>(v);
 
   // outputs 2n, 2n + 1 of n = g + 1024 n_b: the conjugate (re, -im)
   T* __restrict__ dst = yout + (int64_t)rhs * n_t;
