@@ -129,6 +129,50 @@ __device__ __forceinline__ void inner_dft(cx<T>* v, cx<T>* row, const cx<T>* __r
   dft16<T>(v);
 }
 
+// The transpose of inner_dft's factorization, stage by stage in reverse order: lane mu =
+// k1 + 16 c1, register c2 hold a[mu + 64 c2] on entry (inner_dft's output layout); lane l,
+// register j hold A[l + 64 j] on exit.  The inverse transform runs this form, so that in
+// floating point it is the transpose of the forward one and the float32 operator stays as
+// symmetric as the exact one (the same DFT, with the rounding of the forward mirrored).
+template <typename T>
+__device__ __forceinline__ void inner_dft_t(cx<T>* v, cx<T>* row, const cx<T>* __restrict__ tab, int l) {
+  l = opaque(l);
+  // 16-point DFTs over c2 (output m), twiddle W_64^(m c1), c1 = mu >> 4
+  dft16<T>(v);
+  const int c1 = l >> 4;
+#pragma unroll
+  for (int q = 1; q < 16; ++q) v[q] = cmul(v[q], tab[(uint32_t)(kTC + c1 * 16 + q)]);
+  // private exchange: value (k1, c1, m) at (c1 * 16 + k1) * 17 + m; lane (m, h) takes k1 = 4h + e, c1 = 0..3
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) row[l * 17 + q] = v[q];
+  wave_sync();
+  const int m = l & 15, h = l >> 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[e * 4 + c] = row[(c * 16 + 4 * h + e) * 17 + m];
+  // 4-point DFTs over c1 (output lh), twiddle W_1024^(l' k1), l' = m + 16 lh, k1 = 4h + e
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    dft4(v[e * 4], v[e * 4 + 1], v[e * 4 + 2], v[e * 4 + 3]);
+#pragma unroll
+    for (int lh = 0; lh < 4; ++lh)   // (k1 = 0 or l' = 0: the table holds exactly 1)
+      v[e * 4 + lh] = cmul(v[e * 4 + lh], tab[(uint32_t)(kTB + (4 * h + e) * 64 + m + 16 * lh)]);
+  }
+  // private exchange: value (k1, l') at k1 * 64 + l'; lane l takes k1 = 0..15
+  wave_sync();
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int lh = 0; lh < 4; ++lh) row[(4 * h + e) * 64 + m + 16 * lh] = v[e * 4 + lh];
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = row[k * 64 + l];
+  // 16-point DFTs over k1 (output j)
+  dft16<T>(v);
+}
+
 }  // namespace
 
 bool ols_wave_exists(int logn, bool fp64) { return logn == 14 && !fp64; }
@@ -210,11 +254,12 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
     const cx<T> W = tab[(uint32_t)(kT2 + w * 1024 + kin)];
     const cx<T> WO = cmul(W, O);
     const T sa = S[(uint32_t)(w * 1024 + kin)];
-    // s = Y + Y' = E (sa + sb) + W O (sa - sb), Y - Y' = E (sa - sb) + W O (sa + sb)
-    const T sp = sa + sb, sq = sa - sb;
-    const cx<T> sm = {Ev.re * sp + WO.re * sq, Ev.im * sp + WO.im * sq};
-    const cx<T> df = {Ev.re * sq + WO.re * sp, Ev.im * sq + WO.im * sp};
-    const cx<T> Wd = cmul(cconj(W), df);
+    // (Y and Y' are formed with each symbol value on its own: combining sa +- sb first
+    // would round a small F_k, where the 1/f filter suppresses, against a large F_(N-k))
+    const cx<T> Y = cscale(cadd(Ev, WO), sa);
+    const cx<T> Yp = cscale(csub(Ev, WO), sb);
+    const cx<T> sm = cadd(Y, Yp);
+    const cx<T> Wd = cmul(cconj(W), csub(Y, Yp));
     zk = {sm.re - Wd.im, -(sm.im + Wd.re)};
     znk = {sm.re + Wd.im, sm.im - Wd.re};
   };
@@ -247,9 +292,10 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
 #pragma unroll
   for (int c = 8; c < 16; ++c) v[c] = row[l + 64 * c];
 
-  // inverse: forward transform of the conjugated spectrum, inner stage first
-  // (input index k_in = l + 64 j), then twiddle W_N^(n_a k_o) with k_o = w, n_a = mu + 64 c2
-  inner_dft<T>(v, row, tab, l);
+  // inverse: forward transform of the conjugated spectrum, the transpose of the forward
+  // one: inner stage first (input index k_in = mu + 64 c2, output n_a = l + 64 j), then
+  // twiddle W_N^(n_a k_o) with k_o = w
+  inner_dft_t<T>(v, row, tab, l);
   const int ld = opaque(l);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
