@@ -146,7 +146,7 @@ static int pass_tw_total_t() { return ShapeFFT<T, LOGN, V>::tw_total(); }
 
 int pass_twiddle_count(int logn, bool fp64, int variant) {
   if (!ols_variant_exists(logn, fp64, variant)) return -1;
-  if (variant == 9) return ols_wave_table_count();
+  if (variant == 9) return ols_wave_table_count(logn);
   if (variant == 1)
     return logn == 13 ? pass_tw_total_t<float, 13, 1>()
                       : (logn == 14 ? pass_tw_total_t<float, 14, 1>() : pass_tw_total_t<float, 15, 1>());
@@ -177,7 +177,7 @@ static hipError_t pass_tw_launch(void* tab, hipStream_t s) {
 
 hipError_t launch_pass_twiddles(void* tab, int logn, bool fp64, hipStream_t s, int variant) {
   if (!ols_variant_exists(logn, fp64, variant)) return hipErrorInvalidValue;
-  if (variant == 9) return launch_wave_tables(tab, s);
+  if (variant == 9) return launch_wave_tables(logn, tab, s);
   if (variant == 1)
     return logn == 13 ? pass_tw_launch<float, 13, 1>(tab, s)
                       : (logn == 14 ? pass_tw_launch<float, 14, 1>(tab, s) : pass_tw_launch<float, 15, 1>(tab, s));
@@ -754,7 +754,7 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
   if (n_chunks == 0 || n_rhs == 0) return hipSuccess;
   if (variant == 9) {
     if (fp64 || !ols_wave_exists(logn, fp64)) return hipErrorInvalidValue;
-    return launch_ols_wave(in_f64, y_in, y_out, chunks, n_chunks, spec, ptw, n_t, n_c, m, n_rhs, s, st);
+    return launch_ols_wave(logn, in_f64, y_in, y_out, chunks, n_chunks, spec, ptw, n_t, n_c, m, n_rhs, s, st);
   }
   if (fp64) {
     return in_f64 ? ols_dispatch<double, double>(logn, variant, y_in, y_out, chunks, n_chunks, spec, ptw, tw2,

@@ -1,27 +1,30 @@
-// Overlap-save N^-1 with a four-step 2^14-point transform whose inner stages stay
-// inside one wavefront (float32, n_f = 2^15; the paper's transform is the chunked
-// circulant embedding of its Weighting section).
+// Overlap-save N^-1 with four-step transforms of 2^14 and 2^15 points whose inner
+// stages stay inside one wavefront (float32, n_f = 2^15 and 2^16; the paper's transform
+// is the chunked circulant embedding of its Weighting section).
 //
-// The 2^14 packed complex points z_n (n = g + 1024 n_o, thread g of 1024 holds
-// n_o = 0..15) are transformed as
-//   Z[k_o + 16 k_in] = sum_g W_1024^(g k_in) [ W_N^(g k_o) sum_n_o z[g + 1024 n_o] W_16^(n_o k_o) ]:
-// 16-point DFTs in registers, one workgroup exchange that gives wavefront w the
-// row k_o = w, then a 1024-point DFT of that row inside the wavefront (lane l and
-// register j hold index l + 64 j): 16-point DFTs over j, a twiddle, an exchange
-// through the wavefront's own LDS row, 4-point DFTs across lane groups, a twiddle,
-// a second private exchange and 16-point DFTs.  Its output sits at lane mu,
-// register c2 for index mu + 64 c2, which is the input layout of the same stage,
-// so the inverse (a forward transform of the conjugate, read with the decomposition
-// the other way round: 1024-point stage first, twiddle W_N^(n_a k_o), workgroup
-// exchange, 16-point DFTs) reuses it.  Only three exchanges span the workgroup
-// (the outer one of each transform and the real-to-complex pairing); the private
-// ones need no barrier, so the wavefronts of a SIMD drift apart and one's exchanges
-// overlap another's arithmetic.
+// The N = 1024 NO packed complex points z_n (n = g + 1024 n_o, thread g of 1024 holds
+// n_o = 0..NO-1; NO = 16 or 32) are transformed as
+//   Z[k_o + NO k_in] = sum_g W_1024^(g k_in) [ W_N^(g k_o) sum_n_o z[g + 1024 n_o] W_NO^(n_o k_o) ]:
+// NO-point DFTs in registers, a workgroup exchange that gives wavefront w the row k_o = w
+// (and, for NO = 32, the row w + 16: the exchange then runs in two halves), then a
+// 1024-point DFT of each row inside the wavefront (lane l and register j hold index
+// l + 64 j): 16-point DFTs over j, a twiddle, an exchange through the wavefront's own LDS
+// row, 4-point DFTs across lane groups, a twiddle, a second private exchange and 16-point
+// DFTs.  Its output sits at lane mu, register c2 for index mu + 64 c2, which is the input
+// layout of the same stage, so the inverse (a forward transform of the conjugate, read
+// with the decomposition the other way round: 1024-point stage first, twiddle
+// W_N^(n_a k_o), workgroup exchange, NO-point DFTs) reuses it.  Only the outer exchanges
+// of each transform and the real-to-complex pairing span the workgroup; the private ones
+// need no barrier, so the wavefronts of a SIMD drift apart and one's exchanges overlap
+// another's arithmetic.
 //
-// Pairing: Z_k (wavefront w, k_in) meets Z_(N-k) at wavefront 16 - w, 1023 - k_in
-// (w = 0: wavefront 0, (1024 - k_in) mod 1024) through the LDS rows; the side with
-// k_in < 512 forms both new points and writes its partner's back.  The symbol and the packing twiddle are read in the same row
-// order (tables built by launch_wave_tables / launch_wave_symbols).
+// Pairing: Z_k (row k_o, k_in) meets Z_(N-k) at row NO - k_o, 1023 - k_in (row 0: row 0,
+// (1024 - k_in) mod 1024) through the LDS rows.  For NO = 16 the side with k_in < 512
+// forms both new points and writes its partner's back; for NO = 32 wavefront w >= 1 forms
+// every pair of its row w with row 32 - w (wavefront 16 - w's second row, which waits in
+// LDS), and wavefront 0 pairs rows 0 and 16 within themselves.  The symbol and the packing
+// twiddle are read in the same row order (tables built by launch_wave_tables /
+// launch_wave_symbols).
 #include <algorithm>
 #include <type_traits>
 
@@ -32,11 +35,16 @@ namespace mm {
 
 namespace {
 
-constexpr int kWN = 1 << 14;      // complex points
+constexpr int kWN = 1 << 14;      // complex points of the 16 x 1024 transform
+constexpr int kWN32 = 1 << 15;    // complex points of the 32 x 1024 transform
 constexpr int kWRow = 1088;       // LDS row stride (1024 + 64 padding for the second private exchange)
-// table offsets (complex entries): twA[k * 1024 + g] = W_N^(g k), twB[k * 64 + l] = W_1024^(l k),
-// twC[c * 16 + m] = W_64^(m c), twD[w * 1024 + n] = W_N^(w n), tw2[w * 1024 + k_in] = W_2N^(w + 16 k_in)
-constexpr int kTA = 0, kTB = kWN, kTC = kTB + 1024, kTD = kTC + 64, kT2 = kTD + kWN, kTTotal = kT2 + kWN;
+// table offsets (complex entries): twB[k * 64 + l] = W_1024^(l k), twC[c * 16 + m] = W_64^(m c),
+// twA[k * 1024 + g] = W_N^(g k) (k < NO; the forward's outer twiddle and the inverse's),
+// tw2[r * 1024 + k_in] = W_2N^(r + NO k_in) (r < NO)
+constexpr int kTB = 0, kTC = 1024, kTA = 1088;
+constexpr int wave_t2(int logn) { return kTA + (1 << logn); }
+constexpr int wave_table_total(int logn) { return kTA + 2 * (1 << logn); }
+constexpr int kT2 = wave_t2(14);
 
 // l, opaque to the optimiser: table reads indexed by the result cannot be hoisted to the
 // kernel's start (where they would stay live across the whole transform and spill)
@@ -87,6 +95,46 @@ __device__ __forceinline__ void dft16(cx<T>* v) {
   }
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = y[k];
+}
+
+// 32-point DFT in registers, natural order in and out: radix-2 butterflies of n and
+// n + 16 with W_32^n on the differences, then two 16-point DFTs:
+// X[2 k + b] = sum_n W_16^(n k) [ W_32^(n b) (x[n] + (-1)^b x[n + 16]) ]
+template <typename T>
+__device__ __forceinline__ void dft32(cx<T>* v) {
+  cx<T> e[16], o[16];
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    e[n] = cadd(v[n], v[n + 16]);
+    o[n] = twiddle_const(csub(v[n], v[n + 16]), n, 32);
+  }
+  dft16<T>(e);
+  dft16<T>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[2 * k] = e[k];
+    v[2 * k + 1] = o[k];
+  }
+}
+
+// dft32's factorization transposed (the same DFT): 16-point DFTs of the even and odd
+// inputs, W_32^n on the odd ones, radix-2 butterflies X[n], X[n + 16]
+template <typename T>
+__device__ __forceinline__ void dft32_t(cx<T>* v) {
+  cx<T> e[16], o[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    e[k] = v[2 * k];
+    o[k] = v[2 * k + 1];
+  }
+  dft16<T>(e);
+  dft16<T>(o);
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    const cx<T> t = twiddle_const(o[n], n, 32);
+    v[n] = cadd(e[n], t);
+    v[n + 16] = csub(e[n], t);
+  }
 }
 
 // 1024-point DFT of a wavefront's row: lane l, register j hold a[l + 64 j] on entry;
@@ -173,13 +221,10 @@ __device__ __forceinline__ void inner_dft_t(cx<T>* v, cx<T>* row, const cx<T>* _
   dft16<T>(v);
 }
 
-}  // namespace
 
-bool ols_wave_exists(int logn, bool fp64) { return logn == 14 && !fp64; }
-int ols_wave_table_count() { return kTTotal; }
-
-// The packed window of one (chunk, RHS) job: thread g gets z[g + 1024 n_o] = u[2n] + i u[2n + 1]
-template <typename Tin>
+// The packed window of one (chunk, RHS) job: thread g gets z[g + 1024 n_o] = u[2n] + i u[2n + 1],
+// n_o < NO
+template <typename Tin, int NO>
 __device__ __forceinline__ void wave_load(cx<float>* v, const Tin* __restrict__ yin, const OlsChunk& ch, int rhs,
                                           int64_t n_t, int n_c, int g) {
   using T = float;
@@ -187,24 +232,75 @@ __device__ __forceinline__ void wave_load(cx<float>* v, const Tin* __restrict__ 
   const Tin* __restrict__ src = yin + (int64_t)rhs * n_t;
   const int64_t s0 = ch.out_start - n_c;
   const int64_t lo = ch.iv_lo, hi = ch.iv_hi;
-  const bool in_inside = s0 >= lo && s0 + 2 * kWN <= hi &&
+  const bool in_inside = s0 >= lo && s0 + 2 * 1024 * NO <= hi &&
                          ((reinterpret_cast<uintptr_t>(src + s0) & (sizeof(PI) - 1)) == 0);
   if (in_inside) {
     const PI* __restrict__ src2 = reinterpret_cast<const PI*>(src + s0);
 #pragma unroll
-    for (int no = 0; no < 16; ++no) {
+    for (int no = 0; no < NO; ++no) {
       const PI x = src2[(uint32_t)(g + 1024 * no)];
       v[no] = {(T)x.x, (T)x.y};
     }
   } else {
 #pragma unroll
-    for (int no = 0; no < 16; ++no) {
+    for (int no = 0; no < NO; ++no) {
       const int64_t j = s0 + 2 * (int64_t)(g + 1024 * no);
       const T a = (j >= lo && j < hi) ? (T)src[j] : (T)0;
       const T b = (j + 1 >= lo && j + 1 < hi) ? (T)src[j + 1] : (T)0;
       v[no] = {a, b};
     }
   }
+}
+
+// Outputs 2n, 2n + 1 of n = g + 1024 n_b (n_b < NO) of one job: the conjugate (re, -im) of
+// v[n_b], the valid ones [n_c, n_c + m) of the window
+template <int NO>
+__device__ __forceinline__ void wave_store(const cx<float>* v, float* __restrict__ yout, const OlsChunk& ch,
+                                           int rhs, int64_t n_t, int n_c, int m, int g) {
+  using T = float;
+  const int64_t s0 = ch.out_start - n_c;
+  const int64_t hi = ch.iv_hi;
+  T* __restrict__ dst = yout + (int64_t)rhs * n_t;
+  const bool out_inside = ((n_c & 1) == 0) && s0 + n_c + m <= hi &&
+                          ((reinterpret_cast<uintptr_t>(dst + s0) & (sizeof(float2) - 1)) == 0);
+  if (out_inside) {
+    float2* __restrict__ dst2 = reinterpret_cast<float2*>(dst + s0);
+    const int j0 = n_c >> 1, j1 = (n_c + m) >> 1;
+#pragma unroll
+    for (int nb = 0; nb < NO; ++nb) {
+      const int j = g + 1024 * nb;
+      if (j >= j0 && j < j1) dst2[(uint32_t)j] = float2{v[nb].re, -v[nb].im};
+    }
+  } else {
+#pragma unroll
+    for (int nb = 0; nb < NO; ++nb) {
+      const int pos = 2 * (g + 1024 * nb);
+      if (pos >= n_c && pos < n_c + m && s0 + pos < hi) dst[s0 + pos] = v[nb].re;
+      if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -v[nb].im;
+    }
+  }
+}
+
+// One conjugate pair of the real-to-complex step with the filter symbol (as k_ols):
+// A = Z_k, B = conj Z_(N-k), E = A + B, O = -i (A - B), Y = (E + W O) F_k,
+// Y' = (E - W O) F_(N-k), s = Y + Y', d = W^-1 (Y - Y'); the new Z_k is conj(s + i d),
+// the new Z_(N-k) is s - i d.  W = W_2N^k, sa = F_k / (4N), sb = F_(N-k) / (4N).
+// (Y and Y' are formed with each symbol value on its own: combining sa +- sb first
+// would round a small F_k, where the 1/f filter suppresses, against a large F_(N-k).)
+__device__ __forceinline__ void wave_pair(cx<float> A, cx<float> Bp, cx<float> W, float sa, float sb,
+                                          cx<float>& zk, cx<float>& znk) {
+  using T = float;
+  const cx<T> B = cconj(Bp);
+  const cx<T> Ev = cadd(A, B);
+  const cx<T> D = csub(A, B);
+  const cx<T> O = {D.im, -D.re};
+  const cx<T> WO = cmul(W, O);
+  const cx<T> Y = cscale(cadd(Ev, WO), sa);
+  const cx<T> Yp = cscale(csub(Ev, WO), sb);
+  const cx<T> sm = cadd(Y, Yp);
+  const cx<T> Wd = cmul(cconj(W), csub(Y, Yp));
+  zk = {sm.re - Wd.im, -(sm.im + Wd.re)};
+  znk = {sm.re + Wd.im, sm.im - Wd.re};
 }
 
 // N^-1 of one job whose window is in v (wave_load); writes the job's valid outputs.
@@ -217,8 +313,6 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
   const int g = g_in, l = g_in & 63;
   const int w = __builtin_amdgcn_readfirstlane(g_in >> 6);   // wavefront index, uniform
   cx<T>* row = lds + w * kWRow;
-  const int64_t s0 = ch.out_start - n_c;
-  const int64_t hi = ch.iv_hi;
   // forward, outer stage: 16-point DFTs over n_o (output k_o), twiddle W_N^(g k_o)
   dft16<T>(v);
 #pragma unroll
@@ -232,9 +326,7 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
   // forward, inner stage: lane mu, register c2 hold Z[w + 16 (mu + 64 c2)]
   inner_dft<T>(v, row, tab, l);
 
-  // pairing with Z_(N-k) and the filter symbol (as k_ols: A = Z_k, B = conj Z_(N-k),
-  // E = A + B, O = -i (A - B), Y = (E + W O) F_k, Y' = (E - W O) F_(N-k), s = Y + Y',
-  // d = W^-1 (Y - Y'); the new Z_k is conj(s + i d), the new Z_(N-k) is s - i d).
+  // pairing with Z_(N-k) and the filter symbol (wave_pair).
   // Each wavefront forms both members of the pairs whose k_in < 512 (registers 0..7)
   // and writes the partner's member into the partner's row; it then reads its own
   // members with k_in >= 512 from its row.
@@ -247,21 +339,7 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
   const float* __restrict__ S = spec_w + (int64_t)ch.filter * (N + 1);
   const int lp = opaque(l);
   auto pair = [&](int kin, int kp, cx<T> A, cx<T> Bp, T sb, cx<T>& zk, cx<T>& znk) {
-    const cx<T> B = cconj(Bp);
-    const cx<T> Ev = cadd(A, B);
-    const cx<T> D = csub(A, B);
-    const cx<T> O = {D.im, -D.re};
-    const cx<T> W = tab[(uint32_t)(kT2 + w * 1024 + kin)];
-    const cx<T> WO = cmul(W, O);
-    const T sa = S[(uint32_t)(w * 1024 + kin)];
-    // (Y and Y' are formed with each symbol value on its own: combining sa +- sb first
-    // would round a small F_k, where the 1/f filter suppresses, against a large F_(N-k))
-    const cx<T> Y = cscale(cadd(Ev, WO), sa);
-    const cx<T> Yp = cscale(csub(Ev, WO), sb);
-    const cx<T> sm = cadd(Y, Yp);
-    const cx<T> Wd = cmul(cconj(W), csub(Y, Yp));
-    zk = {sm.re - Wd.im, -(sm.im + Wd.re)};
-    znk = {sm.re + Wd.im, sm.im - Wd.re};
+    wave_pair(A, Bp, tab[(uint32_t)(kT2 + w * 1024 + kin)], S[(uint32_t)(w * 1024 + kin)], sb, zk, znk);
   };
   cx<T> other[8];
 #pragma unroll
@@ -300,7 +378,7 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-    v[c] = cmul(v[c], tab[(uint32_t)(kTD + w * 1024 + ld + 64 * c)]);
+    v[c] = cmul(v[c], tab[(uint32_t)(kTA + w * 1024 + ld + 64 * c)]);
   }
   wave_sync();
 #pragma unroll
@@ -311,28 +389,147 @@ __device__ __forceinline__ void wave_filter(cx<float>* v, cx<float>* lds, const 
   for (int k = 0; k < 16; ++k) v[k] = lds[k * kWRow + g];
   dft16<T>(v);
 
-  // outputs 2n, 2n + 1 of n = g + 1024 n_b: the conjugate (re, -im)
-  T* __restrict__ dst = yout + (int64_t)rhs * n_t;
-  const bool out_inside = ((n_c & 1) == 0) && s0 + n_c + m <= hi &&
-                          ((reinterpret_cast<uintptr_t>(dst + s0) & (sizeof(float2) - 1)) == 0);
-  if (out_inside) {
-    float2* __restrict__ dst2 = reinterpret_cast<float2*>(dst + s0);
-    const int j0 = n_c >> 1, j1 = (n_c + m) >> 1;
+  wave_store<16>(v, yout, ch, rhs, n_t, n_c, m, g);
+}
+
+
+// N^-1 of one job of the 32 x 1024 transform whose window is in v[32] (wave_load); writes
+// the job's valid outputs.  Wavefront w holds rows w (va) and w + 16 (vb) between the outer
+// stages; lds has 17 rows (the 17th takes row 0 during the pairing).
+__device__ __forceinline__ void wave_filter32(cx<float>* v, cx<float>* lds, const OlsChunk ch, int rhs,
+                                              float* __restrict__ yout, const float* __restrict__ spec_w,
+                                              const cx<float>* __restrict__ tab, int64_t n_t, int n_c, int m,
+                                              int g_in) {
+  using T = float;
+  constexpr int N = kWN32;
+  constexpr int T2 = wave_t2(15);
+  const int g = g_in, l = g_in & 63;
+  const int w = __builtin_amdgcn_readfirstlane(g_in >> 6);   // wavefront index, uniform
+  cx<T>* row = lds + w * kWRow;
+  // forward, outer stage: 32-point DFTs over n_o (output k_o), twiddle W_N^(g k_o)
+  dft32<T>(v);
 #pragma unroll
-    for (int nb = 0; nb < 16; ++nb) {
-      const int j = g + 1024 * nb;
-      if (j >= j0 && j < j1) dst2[(uint32_t)j] = float2{v[nb].re, -v[nb].im};
+  for (int k = 1; k < 32; ++k) {
+    if (k % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+    v[k] = cmul(v[k], tab[(uint32_t)(kTA + k * 1024 + g)]);
+  }
+  // workgroup exchange in two halves: wavefront w takes row k_o = w, then k_o = w + 16
+  cx<T> va[16], vb[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) lds[k * kWRow + g] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) va[j] = row[l + 64 * j];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) lds[k * kWRow + g] = v[16 + k];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) vb[j] = row[l + 64 * j];
+  // forward, inner stages: lane mu, register c2 hold Z[r + 32 (mu + 64 c2)], r = w, w + 16
+  inner_dft<T>(va, row, tab, l);
+  inner_dft<T>(vb, row, tab, l);
+
+  // pairing with Z_(N-k) and the filter symbol (wave_pair).  The second rows wait in the
+  // LDS rows (wavefront 0 also puts its row 0 in the 17th); wavefront w >= 1 forms every pair
+  // of its row w (k_in) with row 32 - w (k_in' = 1023 - k_in, in wavefront 16 - w's LDS row),
+  // keeps its own members and writes the partner's back; wavefront 0 pairs row 16 (k_in <
+  // 512 with 1023 - k_in) and row 0 (k_in <= 512 with (1024 - k_in) mod 1024) in place.
+  // Every LDS entry of the phase is read and written by one lane only.
+  const float* __restrict__ S = spec_w + (int64_t)ch.filter * (N + 1);
+  cx<T>* row0 = lds + 16 * kWRow;
+  wave_sync();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) row[l + 64 * c] = vb[c];
+  if (w == 0) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) row0[l + 64 * c] = va[c];
+  }
+  __syncthreads();
+  const int lp = opaque(l);
+  if (w != 0) {
+    const int r = w, rp = 32 - w;
+    cx<T>* prow = lds + (16 - w) * kWRow;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      // (four pairs at a time: the scheduler would otherwise hoist every table and
+      // partner load and spill)
+      if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+      const int kin = lp + 64 * c, kp = 1023 - kin;
+      cx<T> znk;
+      wave_pair(va[c], prow[kp], tab[(uint32_t)(T2 + r * 1024 + kin)], S[(uint32_t)(r * 1024 + kin)],
+                S[(uint32_t)(rp * 1024 + kp)], va[c], znk);
+      prow[kp] = znk;
     }
   } else {
 #pragma unroll
-    for (int nb = 0; nb < 16; ++nb) {
-      const int pos = 2 * (g + 1024 * nb);
-      if (pos >= n_c && pos < n_c + m && s0 + pos < hi) dst[s0 + pos] = v[nb].re;
-      if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -v[nb].im;
+    for (int c = 0; c < 8; ++c) {   // row 16 with itself (in this wavefront's LDS row)
+      if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+      const int kin = lp + 64 * c, kp = 1023 - kin;
+      cx<T> zk, znk;
+      wave_pair(row[kin], row[kp], tab[(uint32_t)(T2 + 16 * 1024 + kin)], S[(uint32_t)(16 * 1024 + kin)],
+                S[(uint32_t)(16 * 1024 + kp)], zk, znk);
+      row[kin] = zk;
+      row[kp] = znk;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {   // row 0 with itself; k = 0 pairs with F_N
+      if (c % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+      const int kin = lp + 64 * c, kp = (1024 - kin) & 1023;
+      cx<T> zk, znk;
+      wave_pair(row0[kin], row0[kp], tab[(uint32_t)(T2 + kin)], S[(uint32_t)kin],
+                kin == 0 ? S[N] : S[(uint32_t)kp], zk, znk);
+      row0[kin] = zk;
+      if (kin != 0) row0[kp] = znk;
+    }
+    if (lp == 0) {   // k = N/2 (row 0, k_in = 512) is its own partner
+      const cx<T> a = row0[512];
+      cx<T> zk, unused;
+      wave_pair(a, a, tab[(uint32_t)(T2 + 512)], S[512], S[512], zk, unused);
+      row0[512] = zk;
     }
   }
-}
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) va[c] = row0[l + 64 * c];
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) vb[c] = row[l + 64 * c];
 
+  // inverse: forward transform of the conjugated spectrum, the transpose of the forward
+  // one: inner stages first (input index k_in = mu + 64 c2, output n_a = l + 64 j), twiddle
+  // W_N^(n_a k_o) with k_o = w, w + 16
+  const int ld = opaque(l);
+  inner_dft_t<T>(va, row, tab, l);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+    va[c] = cmul(va[c], tab[(uint32_t)(kTA + w * 1024 + ld + 64 * c)]);
+  }
+  inner_dft_t<T>(vb, row, tab, l);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+    vb[c] = cmul(vb[c], tab[(uint32_t)(kTA + (w + 16) * 1024 + ld + 64 * c)]);
+  }
+  // workgroup exchange in two halves: thread g = n_a takes k_o = 0..15, then 16..31
+  wave_sync();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) row[l + 64 * c] = va[c];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = lds[k * kWRow + g];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) row[l + 64 * c] = vb[c];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[16 + k] = lds[k * kWRow + g];
+  // 32-point DFTs over k_o (the forward's outer factorization transposed) give X[g + 1024 n_b]
+  dft32_t<T>(v);
+  wave_store<32>(v, yout, ch, rhs, n_t, n_c, m, g);
+}
 
 // One workgroup per (chunk, RHS), as k_ols (same XCD-aware order, same outputs).
 template <typename Tin>
@@ -350,58 +547,104 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
   __shared__ __align__(16) cx<float> lds[16 * kWRow];
   const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
   cx<float> v[16];
-  wave_load<Tin>(v, yin, ch, rhs, n_t, n_c, threadIdx.x);
+  wave_load<Tin, 16>(v, yin, ch, rhs, n_t, n_c, threadIdx.x);
   wave_filter(v, lds, ch, rhs, yout, spec_w, tab, n_t, n_c, m, threadIdx.x);
 }
 
-// Twiddle tables of k_ols_wave, float32 from float64 angles
+// One workgroup per (chunk, RHS) of the 32 x 1024 transform, as k_ols_wave
+template <typename Tin>
+__global__ __launch_bounds__(1024) void k_ols_wave32(const Tin* __restrict__ yin, float* __restrict__ yout,
+                                                     const OlsChunk* __restrict__ chunks,
+                                                     const float* __restrict__ spec_w,
+                                                     const cx<float>* __restrict__ tab, int64_t n_t, int n_c,
+                                                     int m, const CgState* __restrict__ st) {
+  const int64_t n_wg = (int64_t)gridDim.x * gridDim.y;
+  const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
+  const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
+  const int rhs = (int)(job / gridDim.x);
+  if (st && !st[rhs].active) return;   // this RHS has stopped iterating
+  __shared__ __align__(16) cx<float> lds[17 * kWRow];
+  const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
+  cx<float> v[32];
+  wave_load<Tin, 32>(v, yin, ch, rhs, n_t, n_c, threadIdx.x);
+  wave_filter32(v, lds, ch, rhs, yout, spec_w, tab, n_t, n_c, m, threadIdx.x);
+}
+
+// Twiddle tables of the 2^LOGN-point transform, float32 from float64 angles
+template <int LOGN>
 __global__ void k_wave_tables(cx<float>* __restrict__ tab) {
+  constexpr int N = 1 << LOGN, NO = N / 1024, T2 = wave_t2(LOGN);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kTTotal) return;
+  if (e >= wave_table_total(LOGN)) return;
   double num, den;   // angle = -2 pi num / den
-  if (e < kTB) { const int k = e / 1024, g = e % 1024; num = (double)g * k; den = kWN; }
-  else if (e < kTC) { const int k = (e - kTB) / 64, l = (e - kTB) % 64; num = (double)l * k; den = 1024; }
-  else if (e < kTD) { const int c = (e - kTC) / 16, m = (e - kTC) % 16; num = (double)m * c; den = 64; }
-  else if (e < kT2) { const int w = (e - kTD) / 1024, n = (e - kTD) % 1024; num = (double)w * n; den = kWN; }
-  else { const int w = (e - kT2) / 1024, kin = (e - kT2) % 1024; num = (double)(w + 16 * kin); den = 2.0 * kWN; }
+  if (e < kTC) { const int k = e / 64, l = e % 64; num = (double)l * k; den = 1024; }
+  else if (e < kTA) { const int c = (e - kTC) / 16, m = (e - kTC) % 16; num = (double)m * c; den = 64; }
+  else if (e < T2) { const int k = (e - kTA) / 1024, g = (e - kTA) % 1024; num = (double)g * k; den = N; }
+  else { const int r = (e - T2) / 1024, kin = (e - T2) % 1024; num = (double)(r + NO * kin); den = 2.0 * N; }
   const double frac = num / den;
   double sn, cs;
   sincospi(2.0 * (frac - floor(frac)), &sn, &cs);
   tab[e] = {(float)cs, (float)(-sn)};
 }
 
-// spec_w[f][w * 1024 + k_in] = spec[f][w + 16 k_in], spec_w[f][N] = spec[f][N]
+// spec_w[f][r * 1024 + k_in] = spec[f][r + NO k_in], spec_w[f][N] = spec[f][N]
+template <int LOGN>
 __global__ void k_wave_symbols(const float* __restrict__ spec, float* __restrict__ spec_w) {
+  constexpr int N = 1 << LOGN, NO = N / 1024;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e > kWN) return;
-  const float* __restrict__ src = spec + (int64_t)blockIdx.y * (kWN + 1);
-  float* __restrict__ dst = spec_w + (int64_t)blockIdx.y * (kWN + 1);
-  dst[e] = e == kWN ? src[kWN] : src[(e >> 10) + 16 * (e & 1023)];
+  if (e > N) return;
+  const float* __restrict__ src = spec + (int64_t)blockIdx.y * (N + 1);
+  float* __restrict__ dst = spec_w + (int64_t)blockIdx.y * (N + 1);
+  dst[e] = e == N ? src[N] : src[(e >> 10) + NO * (e & 1023)];
 }
 
-hipError_t launch_wave_tables(void* tab, hipStream_t s) {
-  hipLaunchKernelGGL(k_wave_tables, dim3((kTTotal + 255) / 256), dim3(256), 0, s, (cx<float>*)tab);
+}  // namespace
+
+bool ols_wave_exists(int logn, bool fp64) { return (logn == 14 || logn == 15) && !fp64; }
+int ols_wave_table_count(int logn) { return wave_table_total(logn); }
+
+hipError_t launch_wave_tables(int logn, void* tab, hipStream_t s) {
+  if (!ols_wave_exists(logn, false)) return hipErrorInvalidValue;
+  const int n = wave_table_total(logn);
+  if (logn == 14)
+    hipLaunchKernelGGL(k_wave_tables<14>, dim3((n + 255) / 256), dim3(256), 0, s, (cx<float>*)tab);
+  else
+    hipLaunchKernelGGL(k_wave_tables<15>, dim3((n + 255) / 256), dim3(256), 0, s, (cx<float>*)tab);
   return hipGetLastError();
 }
 
-hipError_t launch_wave_symbols(const void* spec, void* spec_w, int n_filters, hipStream_t s) {
+hipError_t launch_wave_symbols(int logn, const void* spec, void* spec_w, int n_filters, hipStream_t s) {
+  if (!ols_wave_exists(logn, false)) return hipErrorInvalidValue;
   if (n_filters <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_wave_symbols, dim3((kWN + 1 + 255) / 256, (unsigned)n_filters), dim3(256), 0, s,
-                     (const float*)spec, (float*)spec_w);
+  const dim3 grid(((1 << logn) + 1 + 255) / 256, (unsigned)n_filters);
+  if (logn == 14)
+    hipLaunchKernelGGL(k_wave_symbols<14>, grid, dim3(256), 0, s, (const float*)spec, (float*)spec_w);
+  else
+    hipLaunchKernelGGL(k_wave_symbols<15>, grid, dim3(256), 0, s, (const float*)spec, (float*)spec_w);
   return hipGetLastError();
 }
 
-hipError_t launch_ols_wave(bool in_f64, const void* y_in, void* y_out, const OlsChunk* chunks, int n_chunks,
-                           const void* spec_w, const void* tab, int64_t n_t, int n_c, int m, int n_rhs,
-                           hipStream_t s, const CgState* st) {
+hipError_t launch_ols_wave(int logn, bool in_f64, const void* y_in, void* y_out, const OlsChunk* chunks,
+                           int n_chunks, const void* spec_w, const void* tab, int64_t n_t, int n_c, int m,
+                           int n_rhs, hipStream_t s, const CgState* st) {
+  if (!ols_wave_exists(logn, false)) return hipErrorInvalidValue;
   if (n_chunks == 0 || n_rhs == 0) return hipSuccess;
   const dim3 grid((unsigned)n_chunks, (unsigned)n_rhs);
-  if (in_f64)
-    hipLaunchKernelGGL(k_ols_wave<double>, grid, dim3(1024), 0, s, (const double*)y_in, (float*)y_out, chunks,
-                       (const float*)spec_w, (const cx<float>*)tab, n_t, n_c, m, st);
+  const float* sw = (const float*)spec_w;
+  const cx<float>* tw = (const cx<float>*)tab;
+  if (logn == 14 && in_f64)
+    hipLaunchKernelGGL(k_ols_wave<double>, grid, dim3(1024), 0, s, (const double*)y_in, (float*)y_out, chunks, sw,
+                       tw, n_t, n_c, m, st);
+  else if (logn == 14)
+    hipLaunchKernelGGL(k_ols_wave<float>, grid, dim3(1024), 0, s, (const float*)y_in, (float*)y_out, chunks, sw,
+                       tw, n_t, n_c, m, st);
+  else if (in_f64)
+    hipLaunchKernelGGL(k_ols_wave32<double>, grid, dim3(1024), 0, s, (const double*)y_in, (float*)y_out, chunks,
+                       sw, tw, n_t, n_c, m, st);
   else
-    hipLaunchKernelGGL(k_ols_wave<float>, grid, dim3(1024), 0, s, (const float*)y_in, (float*)y_out, chunks,
-                       (const float*)spec_w, (const cx<float>*)tab, n_t, n_c, m, st);
+    hipLaunchKernelGGL(k_ols_wave32<float>, grid, dim3(1024), 0, s, (const float*)y_in, (float*)y_out, chunks,
+                       sw, tw, n_t, n_c, m, st);
   return hipGetLastError();
 }
 

@@ -472,20 +472,59 @@ void autotune_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s) {
 }
 
 // transform shape used when the descriptor leaves it open: the fastest measured
-// for each length (2^14 points: float32 the four-step transform with wavefront-private
-// inner stages; float64 512 threads x 32 points, radix-16 passes, pairs in registers)
-int default_ols_variant(int logn, bool fp64) { return logn == 14 ? (fp64 ? 2 : 9) : 0; }
+// for each length (2^14 and 2^15 points in float32: the four-step transforms with
+// wavefront-private inner stages; 2^14 in float64: 512 threads x 32 points, radix-16
+// passes, pairs in registers)
+int default_ols_variant(int logn, bool fp64) {
+  if (!fp64 && ols_wave_exists(logn, fp64)) return 9;
+  return logn == 14 && fp64 ? 2 : 0;
+}
+
+int64_t count_chunks(const std::vector<int64_t>& iv_start, int64_t m);
+
+// Compute units of the current device (256 when there is none to ask)
+int compute_units() {
+  static thread_local int cached = 0;
+  if (cached == 0) {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      cached = cu;
+    else
+      cached = 256;
+    (void)hipGetLastError();
+  }
+  return cached;
+}
+
+// Workgroup time of one 2^15-point wavefront-private transform over one 2^14-point one
+// (the float32 filter pass of 2^30 samples x 8 RHS at n_c = 8192: 32.6 ms for 179,088
+// jobs at n_f = 2^16 against 42.7 ms for 529,632 at 2^15)
+constexpr double kWave15Cost = 2.25;
 
 // n_f of a filter set-up that is not autotuned (secondary: the float64 filter of a
-// mixed plan, which takes a forced n_f only when it has a float64 transform)
-int64_t choose_nf(int nf_req, int n_c, int64_t longest, bool fp64, bool secondary) {
+// mixed plan, which takes a forced n_f only when it has a float64 transform).  The
+// length rule, capped at 2^14; where that leaves no valid outputs, the smallest power
+// of two above 2 n_c, or in float32 with the wavefront-private transforms twice that when
+// its chunks (one workgroup each, one workgroup per CU) take less time in full rounds
+// over the chip: fewer chunks, no more than 2.25 times the work each.
+int64_t choose_nf(int nf_req, int n_c, const std::vector<int64_t>& iv_start, int R, int shape_req, bool fp64,
+                  bool secondary) {
   const int maxlog = ols_max_logn(fp64);
   if (nf_req > 0 && !(secondary && ilog2(nf_req) - 1 > maxlog)) return nf_req;
-  int64_t nf = fft_length_rule(n_c, longest);
+  int64_t nf = fft_length_rule(n_c, longest_interval(iv_start));
   nf = std::min<int64_t>(nf, int64_t(1) << (kPreferredMaxLogN + 1));
   if (nf <= 2 * (int64_t)n_c) {
     nf = 1;
     while (nf <= 2 * (int64_t)n_c) nf <<= 1;
+    const bool wave_shape = shape_req == 0 || shape_req == 10;
+    if (!fp64 && wave_shape && ilog2(nf) - 1 == 14 && ols_wave_exists(15, false)) {
+      const double cu = compute_units();
+      auto rounds = [&](int64_t f) {
+        return std::ceil((double)count_chunks(iv_start, f - 2 * (int64_t)n_c) * std::max(R, 1) / cu);
+      };
+      if (kWave15Cost * rounds(2 * nf) < rounds(nf)) nf *= 2;
+    }
   }
   return std::max<int64_t>(nf, int64_t(1) << (kMinLogN + 1));
 }
@@ -501,7 +540,7 @@ void build_filter(mm_plan_s* P, FilterSetup& fs, bool fp64, hipStream_t s, bool 
     autotune_filter(P, fs, fp64, s);
     return;
   }
-  const int64_t nf = choose_nf(P->nf_req, P->n_c, longest_interval(P->iv_start), fp64, secondary);
+  const int64_t nf = choose_nf(P->nf_req, P->n_c, P->iv_start, P->R, P->shape_req, fp64, secondary);
   build_filter_nf(P, fs, fp64, nf, s, choose_variant(P->shape_req, nf, fp64), false);
 }
 
@@ -586,7 +625,7 @@ void build_symbols(const FilterSetup& fs, const double* lags, int n_filt, int n_
   char* nat = scr + block_bytes((int64_t)spectra_scratch_bytes(fs.logn), 1);
   hipchk(launch_spectra(lags, n_filt, n_c, fs.logn, fs.fp64, nat, scr, s), "filter spectra");
   if (wave)
-    hipchk(launch_wave_symbols(nat, out, n_filt, s), "filter spectra in row order");
+    hipchk(launch_wave_symbols(fs.logn, nat, out, n_filt, s), "filter spectra in row order");
   else
     hipchk(launch_long_symbol_rows(fs.logn, fs.fp64, nat, out, n_filt, s), "filter spectra in row order");
 }
@@ -1189,7 +1228,7 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
     B.pers += most;
     B.temps += 2 * block_bytes(std::max<int64_t>(n, 1) * (fp64 ? 8 : 4), 1) + most_tmp + most;
   } else {
-    const int64_t nf = choose_nf(d->n_f, n_c, longest, fp64, false);
+    const int64_t nf = choose_nf(d->n_f, n_c, iv, R, d->fft_shape, fp64, false);
     const int logn = ilog2(nf) - 1;
     check_transform_length(nf, fp64);
     const int v = choose_variant(d->fft_shape, nf, fp64);
@@ -1198,7 +1237,7 @@ PlanBounds plan_bounds(const mm_desc_t* d) {
     if (fp64) logn64 = logn;
   }
   if (!fp64) {
-    const int64_t nf = choose_nf(d->n_f, n_c, longest, true, true);
+    const int64_t nf = choose_nf(d->n_f, n_c, iv, R, d->fft_shape, true, true);
     logn64 = ilog2(nf) - 1;
     check_transform_length(nf, true);
     B.pers += filter_bytes(iv, nf_filt, n_c, nf, choose_variant(d->fft_shape, nf, true), true, R);

@@ -91,17 +91,17 @@ hipError_t launch_ols(bool fp64, bool in_f64, int logn, const void* y_in, void* 
 // launch_pass_twiddles tables of lengths 2^8 and 2^(logn - 8), tw2 as for launch_ols,
 // work = device buffer of batch jobs x 2^logn complex points of the compute type.
 // spec_rows: the symbol table in row order (launch_long_tables), ltab: its twiddle tables
-// four-step 2^14-point transform with wavefront-private inner stages (variant 9, float32):
-// tab = its twiddle tables (ols_wave_table_count complex entries, launch_wave_tables);
-// spec_w[f] = launch_spectra's table in row order (entry w * 1024 + k_in holds k = w + 16 k_in,
-// entry N holds k = N)
+// four-step transforms of 2^14 and 2^15 points (NO x 1024, NO = 16, 32) with wavefront-private
+// inner stages (variant 9, float32): tab = its twiddle tables (ols_wave_table_count complex
+// entries, launch_wave_tables); spec_w[f] = launch_spectra's table in row order (entry
+// r * 1024 + k_in holds k = r + NO k_in, entry N holds k = N)
 bool ols_wave_exists(int logn, bool fp64);
-int ols_wave_table_count();
-hipError_t launch_wave_tables(void* tab, hipStream_t s);
-hipError_t launch_wave_symbols(const void* spec, void* spec_w, int n_filters, hipStream_t s);
-hipError_t launch_ols_wave(bool in_f64, const void* y_in, void* y_out, const OlsChunk* chunks, int n_chunks,
-                           const void* spec_w, const void* tab, int64_t n_t, int n_c, int m, int n_rhs,
-                           hipStream_t s, const CgState* st);
+int ols_wave_table_count(int logn);
+hipError_t launch_wave_tables(int logn, void* tab, hipStream_t s);
+hipError_t launch_wave_symbols(int logn, const void* spec, void* spec_w, int n_filters, hipStream_t s);
+hipError_t launch_ols_wave(int logn, bool in_f64, const void* y_in, void* y_out, const OlsChunk* chunks,
+                           int n_chunks, const void* spec_w, const void* tab, int64_t n_t, int n_c, int m,
+                           int n_rhs, hipStream_t s, const CgState* st);
 bool ols_long_exists(int logn);
 int64_t ols_long_batch(int logn, bool fp64);   // jobs per batch (intermediates of ~64 MiB)
 int ols_long_table_count(int logn);            // complex entries of ltab

@@ -249,7 +249,8 @@ def test_autotuned_transform_length(precision):
     assert max_rel(hx, want) <= TOL[precision]
 
 
-@pytest.mark.parametrize("n_f,shape", [(32768, s) for s in range(1, 11)] + [(65536, 1), (65536, 2), (65536, 3)])
+@pytest.mark.parametrize("n_f,shape", [(32768, s) for s in range(1, 11)] + [(65536, 1), (65536, 2), (65536, 3),
+                                                                          (65536, 10)])
 def test_forced_transform_shapes_match_the_oracle(n_f, shape):
     """Each workgroup shape of the float32 transforms of 2^14 and 2^15 complex points
     gives the oracle's H x; float64 plans use the shapes that exist in float64 (1, 3, 6, 8)
