@@ -222,26 +222,43 @@ __device__ __forceinline__ void inner_dft_t(cx<T>* v, cx<T>* row, const cx<T>* _
 }
 
 
+// Pairs of TOD elements at any element boundary (windows of intervals that start at an
+// odd sample): 4- and 8-byte aligned, where float2 / double2 need 8 and 16 (the loads and
+// stores are still single 8- and 16-byte accesses)
+struct alignas(4) FloatPairU { float x, y; };
+struct alignas(8) DoublePairU { double x, y; };
+
 // The packed window of one (chunk, RHS) job: thread g gets z[g + 1024 n_o] = u[2n] + i u[2n + 1],
-// n_o < NO
+// n_o < NO, u[i] = TOD sample s0 + i inside the chunk's interval, else 0 (s0 = out_start - n_c).
+// Offsets inside the window are 32-bit from its first sample.
 template <typename Tin, int NO>
 __device__ __forceinline__ void wave_load(cx<float>* v, const Tin* __restrict__ yin, const OlsChunk& ch, int rhs,
                                           int64_t n_t, int n_c, int g) {
   using T = float;
-  using PI = typename std::conditional<sizeof(Tin) == 4, float2, double2>::type;
+  using PU = typename std::conditional<sizeof(Tin) == 4, FloatPairU, DoublePairU>::type;
+  constexpr int W = 2048 * NO;   // window samples
   const Tin* __restrict__ src = yin + (int64_t)rhs * n_t;
   const int64_t s0 = ch.out_start - n_c;
   const int64_t lo = ch.iv_lo, hi = ch.iv_hi;
-  const bool in_inside = s0 >= lo && s0 + 2 * 1024 * NO <= hi &&
-                         ((reinterpret_cast<uintptr_t>(src + s0) & (sizeof(PI) - 1)) == 0);
-  if (in_inside) {
-    const PI* __restrict__ src2 = reinterpret_cast<const PI*>(src + s0);
+  if (s0 >= lo && s0 + W <= hi) {   // the whole window inside the interval
+    const PU* __restrict__ b2 = reinterpret_cast<const PU*>(src + s0);
 #pragma unroll
     for (int no = 0; no < NO; ++no) {
-      const PI x = src2[(uint32_t)(g + 1024 * no)];
+      const PU x = b2[(uint32_t)(g + 1024 * no)];
       v[no] = {(T)x.x, (T)x.y};
     }
-  } else {
+  } else if (s0 >= 0) {   // a window cut by an end of the interval: samples [a, b) of it are data
+    const Tin* __restrict__ base = src + s0;
+    const int a = (int)(lo > s0 ? lo - s0 : 0);
+    const int b = (int)(hi - s0 < W ? hi - s0 : W);
+#pragma unroll
+    for (int no = 0; no < NO; ++no) {
+      const int i = 2 * (g + 1024 * no);
+      const T x = (i >= a && i < b) ? (T)base[(uint32_t)i] : (T)0;
+      const T y = (i + 1 >= a && i + 1 < b) ? (T)base[(uint32_t)(i + 1)] : (T)0;
+      v[no] = {x, y};
+    }
+  } else {   // the window starts before the TOD row (the first interval's first chunk)
 #pragma unroll
     for (int no = 0; no < NO; ++no) {
       const int64_t j = s0 + 2 * (int64_t)(g + 1024 * no);
@@ -253,30 +270,26 @@ __device__ __forceinline__ void wave_load(cx<float>* v, const Tin* __restrict__ 
 }
 
 // Outputs 2n, 2n + 1 of n = g + 1024 n_b (n_b < NO) of one job: the conjugate (re, -im) of
-// v[n_b], the valid ones [n_c, n_c + m) of the window
+// v[n_b]; window positions [n_c, n_c + m) are the chunk's outputs, out_start onwards, cut at
+// the interval's end.  Offsets are 32-bit from out_start.
 template <int NO>
 __device__ __forceinline__ void wave_store(const cx<float>* v, float* __restrict__ yout, const OlsChunk& ch,
                                            int rhs, int64_t n_t, int n_c, int m, int g) {
-  using T = float;
-  const int64_t s0 = ch.out_start - n_c;
-  const int64_t hi = ch.iv_hi;
-  T* __restrict__ dst = yout + (int64_t)rhs * n_t;
-  const bool out_inside = ((n_c & 1) == 0) && s0 + n_c + m <= hi &&
-                          ((reinterpret_cast<uintptr_t>(dst + s0) & (sizeof(float2) - 1)) == 0);
-  if (out_inside) {
-    float2* __restrict__ dst2 = reinterpret_cast<float2*>(dst + s0);
-    const int j0 = n_c >> 1, j1 = (n_c + m) >> 1;
+  float* __restrict__ base = yout + (int64_t)rhs * n_t + ch.out_start;
+  const int len = (int)(ch.iv_hi - ch.out_start < m ? ch.iv_hi - ch.out_start : m);   // outputs of this chunk
+  if ((n_c & 1) == 0 && len == m) {   // whole pairs, all inside
+    FloatPairU* __restrict__ b2 = reinterpret_cast<FloatPairU*>(base);
 #pragma unroll
     for (int nb = 0; nb < NO; ++nb) {
-      const int j = g + 1024 * nb;
-      if (j >= j0 && j < j1) dst2[(uint32_t)j] = float2{v[nb].re, -v[nb].im};
+      const int j = 2 * (g + 1024 * nb) - n_c;
+      if (j >= 0 && j < m) b2[(uint32_t)(j >> 1)] = FloatPairU{v[nb].re, -v[nb].im};
     }
   } else {
 #pragma unroll
     for (int nb = 0; nb < NO; ++nb) {
-      const int pos = 2 * (g + 1024 * nb);
-      if (pos >= n_c && pos < n_c + m && s0 + pos < hi) dst[s0 + pos] = v[nb].re;
-      if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -v[nb].im;
+      const int j = 2 * (g + 1024 * nb) - n_c;
+      if (j >= 0 && j < len) base[(uint32_t)j] = v[nb].re;
+      if (j + 1 >= 0 && j + 1 < len) base[(uint32_t)(j + 1)] = -v[nb].im;
     }
   }
 }
@@ -542,7 +555,7 @@ __global__ __launch_bounds__(1024) void k_ols_wave(const Tin* __restrict__ yin, 
   const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
   const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
-  const int rhs = (int)(job / gridDim.x);
+  const int rhs = __builtin_amdgcn_readfirstlane((int)(job / gridDim.x));   // uniform: scalar row offsets
   if (st && !st[rhs].active) return;   // this RHS has stopped iterating
   __shared__ __align__(16) cx<float> lds[16 * kWRow];
   const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
@@ -562,7 +575,7 @@ __global__ __launch_bounds__(1024) void k_ols_wave32(const Tin* __restrict__ yin
   const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
   const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
-  const int rhs = (int)(job / gridDim.x);
+  const int rhs = __builtin_amdgcn_readfirstlane((int)(job / gridDim.x));   // uniform: scalar row offsets
   if (st && !st[rhs].active) return;   // this RHS has stopped iterating
   __shared__ __align__(16) cx<float> lds[17 * kWRow];
   const OlsChunk ch = chunks[job - (int64_t)rhs * gridDim.x];
