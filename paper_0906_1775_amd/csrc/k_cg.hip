@@ -120,11 +120,13 @@ __device__ __forceinline__ void precond_apply(const double* __restrict__ m, cons
 // One block walks a fixed set of pixels for a group of RG right-hand sides, so a
 // pixel's preconditioner block is read once per group instead of once per RHS;
 // every RHS's partial sums keep the order of a one-RHS pass (tail entries, then
-// pixels, in grid-stride order).
-template <int NS, int RG>
+// pixels, in grid-stride order).  Tv: the element type of q and z (float32 in the
+// mixed-precision iteration: q as the scatter rounded it, z rounded after r.z is
+// formed from its float64 value).
+template <int NS, int RG, typename Tv>
 __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     double* __restrict__ x, const double* __restrict__ p, double* __restrict__ rv,
-    const double* __restrict__ q, double* __restrict__ z, const double* __restrict__ minv,
+    const Tv* __restrict__ q, Tv* __restrict__ z, const double* __restrict__ minv,
     CgState* __restrict__ st, CgState* __restrict__ st_prev, int64_t n_obs, int64_t vs,
     const double* __restrict__ minv_t, int64_t n_tail, int n_rhs, const double* __restrict__ pq_part, int n_pq,
     double* __restrict__ prz, double* __restrict__ prr) {
@@ -179,10 +181,10 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
       if (!act[g]) continue;
       const int64_t b = (int64_t)(r0 + g) * vs + n_obs * NS + j;
       x[b] += alpha[g] * p[b];
-      const double rr = rv[b] - alpha[g] * q[b];
+      const double rr = rv[b] - alpha[g] * (double)q[b];
       rv[b] = rr;
       const double zz = mt * rr;
-      z[b] = zz;
+      z[b] = (Tv)zz;
       arz[g] += rr * zz;
       arr[g] += rr * rr;
     }
@@ -199,13 +201,13 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
         x[b + c] += alpha[g] * p[b + c];
-        rr[c] = rv[b + c] - alpha[g] * q[b + c];
+        rr[c] = rv[b + c] - alpha[g] * (double)q[b + c];
         rv[b + c] = rr[c];
       }
       precond_apply<NS>(m, rr, zz);
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
-        z[b + c] = zz[c];
+        z[b + c] = (Tv)zz[c];
         arz[g] += rr[c] * zz[c];
         arr[g] += rr[c] * rr[c];
       }
@@ -223,20 +225,24 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
   }
 }
 
-hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
-                            double* z, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
+hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const void* q, void* z,
+                            bool qz_f32, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s) {
   const dim3 b(kDotThreads);
-#define MM_UPD(NS, RG)                                                                                     \
-  hipLaunchKernelGGL((k_cg_update<NS, RG>), dim3(kDotBlocks, (n_rhs + RG - 1) / RG), b, 0, s, x, p, r, q, z, \
-                     minv, st, st_prev, n_obs, vs, minv_t, n_tail, n_rhs, pq_part, n_pq, partial_rz, partial_rr)
-  if (n_rhs == 1) {
-    if (ns == 1) MM_UPD(1, 1); else MM_UPD(3, 1);
-  } else {
-    if (ns == 1) MM_UPD(1, 8); else MM_UPD(3, 8);
+#define MM_UPD(NS, RG, TV)                                                                                \
+  hipLaunchKernelGGL((k_cg_update<NS, RG, TV>), dim3(kDotBlocks, (n_rhs + RG - 1) / RG), b, 0, s, x, p, r, \
+                     (const TV*)q, (TV*)z, minv, st, st_prev, n_obs, vs, minv_t, n_tail, n_rhs, pq_part, n_pq,   \
+                     partial_rz, partial_rr)
+#define MM_UPD_T(TV)                                     \
+  if (n_rhs == 1) {                                      \
+    if (ns == 1) MM_UPD(1, 1, TV); else MM_UPD(3, 1, TV); \
+  } else {                                               \
+    if (ns == 1) MM_UPD(1, 8, TV); else MM_UPD(3, 8, TV); \
   }
+  if (qz_f32) { MM_UPD_T(float) } else { MM_UPD_T(double) }
+#undef MM_UPD_T
 #undef MM_UPD
   return hipGetLastError();
 }
@@ -270,7 +276,8 @@ __device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr)
 // the same fixed order and derives the same new state from st_prev (written by
 // the update, read-only here); block 0 of each RHS stores it in st, which no
 // block of this kernel reads.
-__global__ void k_cg_step_next(double* __restrict__ p, const double* __restrict__ z,
+template <typename Tz>
+__global__ void k_cg_step_next(double* __restrict__ p, const Tz* __restrict__ z,
                                const double* __restrict__ x, double* __restrict__ xbest,
                                CgState* __restrict__ st, const CgState* __restrict__ st_prev,
                                const double* __restrict__ prz, const double* __restrict__ prr,
@@ -296,21 +303,25 @@ __global__ void k_cg_step_next(double* __restrict__ p, const double* __restrict_
     const int64_t j = (int64_t)r * nu + i;
     if (best) xbest[j] = x[j];
     if (upd) {
-      const double pn = z[j] + beta * p[j];
+      const double pn = (double)z[j] + beta * p[j];
       p[j] = pn;
       if (p32 && i < n32) p32[(int64_t)r * vs32 + i] = (float)pn;
     }
   }
 }
 
-hipError_t launch_cg_step_next(double* p, const double* z, const double* x, double* xbest, CgState* st,
+hipError_t launch_cg_step_next(double* p, const void* z, bool z_f32, const double* x, double* xbest, CgState* st,
                                const CgState* st_prev, const double* partial_rz, const double* partial_rr,
                                double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
                                float* p32, int64_t n32, int64_t vs32) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
-  hipLaunchKernelGGL(k_cg_step_next, g, dim3(256), 0, s, p, z, x, xbest, st, st_prev, partial_rz, partial_rr,
-                     history, hist_stride, nu, p32, n32, vs32);
+  if (z_f32)
+    hipLaunchKernelGGL(k_cg_step_next<float>, g, dim3(256), 0, s, p, (const float*)z, x, xbest, st, st_prev,
+                       partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+  else
+    hipLaunchKernelGGL(k_cg_step_next<double>, g, dim3(256), 0, s, p, (const double*)z, x, xbest, st, st_prev,
+                       partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
   return hipGetLastError();
 }
 

@@ -331,12 +331,14 @@ constexpr int kBatch = 4;
 // split a slice's entries (the plan picks 8 for pixels with hundreds of hits, 1
 // for a few tens, where the cross-wave combine would dominate); a block of 8
 // wavefronts works on 8 / WPS slices at a time.  Every (pixel, RHS) sum has a
-// fixed order for a given WPS.
-template <typename Ty, int NS, int RG, int WPS>
+// fixed order for a given WPS.  Tq: the element type q is stored in (the float64 sum is
+// rounded to it); p (element type Tp, rows of stride ps) times the stored q gives the p.q
+// partial sums.
+template <typename Ty, typename Tq, typename Tp, int NS, int RG, int WPS>
 __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
-    double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs, const double* __restrict__ p,
+    Tq* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs, const Tp* __restrict__ p, int64_t ps,
     double* __restrict__ pq_part, int pq_stride, int pq_slot, const CgState* __restrict__ st) {
   constexpr int NW = kBlockWaves, SPB = NW / WPS;
   __shared__ double part[WPS > 1 ? NW : 1][RG * NS][64];
@@ -414,6 +416,7 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
         for (int g = 0; g < RG; ++g) {
           if (!act[g]) continue;
           const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
+          const int64_t ip = (int64_t)(r0 + g) * ps + o * NS;
 #pragma unroll
           for (int c = 0; c < NS; ++c) {
             double v;
@@ -424,8 +427,9 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
             } else {
               v = a[g][c].value();
             }
-            q[i + c] = v;
-            if (p) pq[g] += p[i + c] * v;
+            const Tq vq = (Tq)v;
+            q[i + c] = vq;
+            if (p) pq[g] += (double)p[ip + c] * (double)vq;
           }
         }
       }
@@ -462,11 +466,11 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
 // (pixel, RHS) sum has a fixed order.
 constexpr int kSegLanes = 16;
 constexpr int kSegBatch = 4;   // loads in flight per lane
-template <typename Ty, int NS, int RG>
+template <typename Ty, typename Tq, typename Tp, int NS, int RG>
 __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter_seg(
     const int64_t* __restrict__ pix_ptr, const int32_t* __restrict__ perm, const float2* __restrict__ w_pm,
-    const Ty* __restrict__ y, double* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs,
-    const double* __restrict__ p, double* __restrict__ pq_part, int pq_stride, int pq_slot,
+    const Ty* __restrict__ y, Tq* __restrict__ q, int64_t vs, int64_t n_obs, int64_t n_t, int n_rhs,
+    const Tp* __restrict__ p, int64_t ps, double* __restrict__ pq_part, int pq_stride, int pq_slot,
     const CgState* __restrict__ st) {
   constexpr int NW = kBlockWaves, G = kSegLanes, PPW = 64 / G;
   __shared__ double sh[NW][RG];
@@ -535,13 +539,15 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter_seg(
       for (int g = 0; g < RG; ++g) {
         if (!act[g]) continue;
         const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
+        const int64_t ip = (int64_t)(r0 + g) * ps + o * NS;
 #pragma unroll
         for (int c = 0; c < NS; ++c) {
           double v = a[g][c].value();
 #pragma unroll
           for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);   // same sum on the group's lanes
-          if (ov && gl == c) q[i + c] = v;
-          if (p && ov && gl == 0) pq[g] += p[i + c] * v;
+          const Tq vq = (Tq)v;
+          if (ov && gl == c) q[i + c] = vq;
+          if (p && ov && gl == 0) pq[g] += (double)p[ip + c] * (double)vq;
         }
       }
     }
@@ -578,47 +584,54 @@ int scatter_blocks(int64_t n_obs, int wps) {
 // (the plan may still choose 8 wavefronts per slice over 0 for a large TOD)
 int scatter_waves_per_slice(double avg) { return avg >= 128 ? 0 : avg >= 64 ? 4 : avg >= 32 ? 2 : 1; }
 
-hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
-                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
-                          double* pq_part, int pq_stride, int pq_slot, const CgState* st) {
+template <typename Ty, typename Tq, typename Tp>
+static hipError_t scatter_typed(int ns, const SellLayout& L, const Ty* y, Tq* q, int64_t vs, int64_t n_obs,
+                                int64_t n_t, int n_rhs, hipStream_t s, const Tp* p, int64_t ps, double* pq_part,
+                                int pq_stride, int pq_slot, const CgState* st) {
   if (n_obs == 0) return hipSuccess;
   const dim3 g((unsigned)scatter_blocks(n_obs, L.wps)), b(64 * kBlockWaves);
   if (L.wps == 0) {
     const float2* w = (const float2*)L.w_pm;
-#define MM_SG(T, NS, RG) hipLaunchKernelGGL((k_scatter_seg<T, NS, RG>), g, b, 0, s, L.ptr, L.perm, w, (const T*)y, q, \
-                                            vs, n_obs, n_t, n_rhs, p, pq_part, pq_stride, pq_slot, st)
-    if (in_f64) {
-      if (ns == 1) { if (n_rhs == 1) MM_SG(double, 1, 1); else MM_SG(double, 1, 4); }
-      else { if (n_rhs == 1) MM_SG(double, 3, 1); else MM_SG(double, 3, 4); }
-    } else {
-      if (ns == 1) { if (n_rhs == 1) MM_SG(float, 1, 1); else MM_SG(float, 1, 4); }
-      else { if (n_rhs == 1) MM_SG(float, 3, 1); else MM_SG(float, 3, 4); }
-    }
+#define MM_SG(NS, RG) hipLaunchKernelGGL((k_scatter_seg<Ty, Tq, Tp, NS, RG>), g, b, 0, s, L.ptr, L.perm, w, y, q, \
+                                         vs, n_obs, n_t, n_rhs, p, ps, pq_part, pq_stride, pq_slot, st)
+    if (ns == 1) { if (n_rhs == 1) MM_SG(1, 1); else MM_SG(1, 4); }
+    else { if (n_rhs == 1) MM_SG(3, 1); else MM_SG(3, 4); }
 #undef MM_SG
     return hipGetLastError();
   }
   const float2* w = (const float2*)L.w;
-#define MM_SC(T, NS, RG, WPS) hipLaunchKernelGGL((k_scatter<T, NS, RG, WPS>), g, b, 0, s, L.end, L.len, L.t, w, \
-                                                 (const T*)y, q, vs, n_obs, n_t, n_rhs, p, pq_part, pq_stride, \
-                                                 pq_slot, st)
-#define MM_SC_W(T, NS, RG)                     \
+#define MM_SC(NS, RG, WPS) hipLaunchKernelGGL((k_scatter<Ty, Tq, Tp, NS, RG, WPS>), g, b, 0, s, L.end, L.len, L.t, \
+                                              w, y, q, vs, n_obs, n_t, n_rhs, p, ps, pq_part, pq_stride, pq_slot, st)
+#define MM_SC_W(NS, RG)                        \
   switch (L.wps) {                             \
-    case 1: MM_SC(T, NS, RG, 1); break;        \
-    case 2: MM_SC(T, NS, RG, 2); break;        \
-    case 4: MM_SC(T, NS, RG, 4); break;        \
-    default: MM_SC(T, NS, RG, 8); break;       \
+    case 1: MM_SC(NS, RG, 1); break;           \
+    case 2: MM_SC(NS, RG, 2); break;           \
+    case 4: MM_SC(NS, RG, 4); break;           \
+    default: MM_SC(NS, RG, 8); break;          \
   }
   // one accumulator set for a single RHS; groups of 4 otherwise
-  if (in_f64) {
-    if (ns == 1) { if (n_rhs == 1) { MM_SC_W(double, 1, 1) } else { MM_SC_W(double, 1, 4) } }
-    else { if (n_rhs == 1) { MM_SC_W(double, 3, 1) } else { MM_SC_W(double, 3, 4) } }
-  } else {
-    if (ns == 1) { if (n_rhs == 1) { MM_SC_W(float, 1, 1) } else { MM_SC_W(float, 1, 4) } }
-    else { if (n_rhs == 1) { MM_SC_W(float, 3, 1) } else { MM_SC_W(float, 3, 4) } }
-  }
+  if (ns == 1) { if (n_rhs == 1) { MM_SC_W(1, 1) } else { MM_SC_W(1, 4) } }
+  else { if (n_rhs == 1) { MM_SC_W(3, 1) } else { MM_SC_W(3, 4) } }
 #undef MM_SC_W
 #undef MM_SC
   return hipGetLastError();
+}
+
+hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* y, double* q, int64_t vs,
+                          int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s, const double* p,
+                          double* pq_part, int pq_stride, int pq_slot, const CgState* st) {
+  if (in_f64)
+    return scatter_typed<double, double, double>(ns, L, (const double*)y, q, vs, n_obs, n_t, n_rhs, s, p, vs,
+                                                 pq_part, pq_stride, pq_slot, st);
+  return scatter_typed<float, double, double>(ns, L, (const float*)y, q, vs, n_obs, n_t, n_rhs, s, p, vs, pq_part,
+                                              pq_stride, pq_slot, st);
+}
+
+hipError_t launch_scatter_q32(int ns, const SellLayout& L, const float* y, float* q, int64_t vs, int64_t n_obs,
+                              int64_t n_t, int n_rhs, hipStream_t s, const float* p32, int64_t vs32,
+                              double* pq_part, int pq_stride, int pq_slot, const CgState* st) {
+  return scatter_typed<float, float, float>(ns, L, y, q, vs, n_obs, n_t, n_rhs, s, p32, vs32, pq_part, pq_stride,
+                                            pq_slot, st);
 }
 
 // ---------------------------------------------------------------- layout helpers

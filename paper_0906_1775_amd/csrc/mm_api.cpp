@@ -355,6 +355,8 @@ struct mm_plan_s {
 
   int64_t nmap() const { return n_obs * ns; }            // map unknowns per RHS
   int64_t vs32() const { return n_obs * ns; }             // row of the float32 copy of p
+  // float32 q and z in the iteration: mixed precision, no template amplitudes
+  bool iter_f32() const { return vp32 != nullptr && !fs_main.fp64 && tmpl.empty(); }
   int64_t nu() const { return n_obs * ns + n_tunk; }     // iteration vector row
   int64_t ng() const { return n_pix * ns + n_tglob; }    // API map-shaped row
   bool main_fp64() const { return precision == MM_FP64; }
@@ -1460,11 +1462,20 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   // the host only every check_every iterations)
   gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s, P->st, P->vp32);
   weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s, P->st);
-  scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp, P->st);
-  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, P->minv, P->st, P->st_prev, P->n_obs, P->nu(),
-                          P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
+  // the mixed-precision iteration without templates keeps q and z in float32 (in the
+  // first half of their float64 buffers): q is a float32 operator's output, and z only
+  // builds the next direction, whose float32 copy the gather reads
+  const bool v32 = P->iter_f32();
+  if (v32)
+    hipchk(launch_scatter_q32(P->ns, P->px.sell, (const float*)P->y2, (float*)P->vq, P->nu(), P->n_obs, P->n_t, R,
+                              s, P->vp32, P->vs32(), P->part_pq, P->n_pq, 0, P->st),
+           "scatter");
+  else
+    scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp, P->st);
+  hipchk(launch_cg_update(P->ns, P->vx, P->vp, P->vr, P->vq, P->vz, v32, P->minv, P->st, P->st_prev, P->n_obs,
+                          P->nu(), P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
-  hipchk(launch_cg_step_next(P->vp, P->vz, P->vx, P->vxb, P->st, P->st_prev, P->part2, P->part3, P->hist,
+  hipchk(launch_cg_step_next(P->vp, P->vz, v32, P->vx, P->vxb, P->st, P->st_prev, P->part2, P->part3, P->hist,
                              kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
          "scalar step and next direction");
 }

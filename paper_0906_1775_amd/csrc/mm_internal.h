@@ -154,6 +154,11 @@ hipError_t launch_scatter(bool in_f64, int ns, const SellLayout& L, const void* 
                           int64_t n_obs, int64_t n_t, int n_rhs, hipStream_t s,
                           const double* p = nullptr, double* pq_part = nullptr, int pq_stride = 0,
                           int pq_slot = 0, const CgState* st = nullptr);
+// The same with float32 y and q, and the p.q partial sums from the float32 copy of p
+// (p32, rows of stride vs32): the mixed-precision iteration's scatter.
+hipError_t launch_scatter_q32(int ns, const SellLayout& L, const float* y, float* q, int64_t vs, int64_t n_obs,
+                              int64_t n_t, int n_rhs, hipStream_t s, const float* p32, int64_t vs32,
+                              double* pq_part, int pq_stride, int pq_slot, const CgState* st);
 // blocks (= p.q partial sums) of a scatter over n_obs pixels with wps wavefronts per slice
 int scatter_blocks(int64_t n_obs, int wps);
 int scatter_waves_per_slice(double avg_entries_per_pixel);   // 0: pixel-major, no slices
@@ -222,8 +227,9 @@ hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* p
 // Vectors are rows of stride vs: n_obs pixel blocks, then n_tail template
 // amplitudes preconditioned by the diagonal minv_t.
 // (also copies the state before the step, alpha and breakdown included, to st_prev)
-hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const double* q,
-                            double* z, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
+// q and z: float64, or float32 when qz_f32 (z rounded after r.z is formed)
+hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const void* q, void* z,
+                            bool qz_f32, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s);
@@ -231,8 +237,8 @@ hipError_t launch_cg_update(int ns, double* x, const double* p, double* r, const
 // st_prev and the update's partial sums; history[r * hist_stride + iter] = rel),
 // then p = z + beta p (active RHS) and x_best = x (RHS whose iterate became the
 // best); p32 (optional): also a float32 copy of the first n32 entries of each
-// row of p (rows of stride vs32)
-hipError_t launch_cg_step_next(double* p, const double* z, const double* x, double* xbest, CgState* st,
+// row of p (rows of stride vs32); z: float64, or float32 when z_f32
+hipError_t launch_cg_step_next(double* p, const void* z, bool z_f32, const double* x, double* xbest, CgState* st,
                                const CgState* st_prev, const double* partial_rz, const double* partial_rr,
                                double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
                                float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
