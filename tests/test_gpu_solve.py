@@ -149,6 +149,24 @@ def test_multi_rhs_stop_independently(T):
         assert rel_err(m.cpu().numpy()[r], ref) <= 1e-7
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+@pytest.mark.parametrize("check_every", [1, 8])
+def test_lowest_residual_iterate_is_returned(T, precision, tol, check_every):
+    """RHS 0's relative residual rises at its second iteration (0.363 -> 0.407 on the
+    oracle): a 2-iteration solve returns its first iterate, which the update of the second
+    iteration copies, and RHS 1 and 2 their second, copied after the last step; with
+    3 iterations every RHS returns its third."""
+    p, o = T
+    mm = plan_for(p, precision=precision, n_rhs=3, lag_dft_len=L_K)
+    for k in (2, 3):
+        m, info = mm.solve(tod_tensor(p), fixed_iters=k, check_every=check_every)
+        for r in range(3):
+            ref, rinfo = _oracle_map(o, p.tod[r], fixed_iters=k)
+            assert info["best_iter"][r] == rinfo.best_iter
+            assert rel_err(m.cpu().numpy()[r], ref) <= tol
+        assert list(info["best_iter"]) == ([1, 2, 2] if k == 2 else [3, 3, 3])
+
+
 def test_graph_and_plain_launches_agree_bitwise(TQU):
     p, _ = TQU
     mm = plan_for(p, n_rhs=1, lag_dft_len=L_K)
