@@ -48,6 +48,15 @@ template <typename T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+// Pairs of TOD elements at any element boundary (windows of intervals that start at an
+// odd sample): 4- and 8-byte aligned, where float2 / double2 need 8 and 16 (the loads and
+// stores are still single 8- and 16-byte accesses)
+struct alignas(4) FloatPairU { float x, y; };
+struct alignas(8) DoublePairU { double x, y; };
+template <typename T> struct PairU;
+template <> struct PairU<float> { using type = FloatPairU; };
+template <> struct PairU<double> { using type = DoublePairU; };
+
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};

@@ -581,9 +581,6 @@ hipError_t launch_spectra(const double* lags, int n_filters, int n_c, int logn, 
 // spectrum of the output, Z'_k = (Y_k + Y_{k+N})/2 + i W^{-k} (Y_k - Y_{k+N})/2,
 // Y = F X.  The table spec holds F/(4N), which absorbs both halvings and the
 // 1/N of the inverse transform; the inverse is conj(FFT(conj Z')).
-template <typename V> struct Pair;
-template <> struct Pair<float> { using type = float2; };
-template <> struct Pair<double> { using type = double2; };
 
 template <typename T, typename Tin, int LOGN, int V>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
@@ -600,10 +597,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
   const int64_t wl = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const int64_t xq = n_wg >> 3, xr = n_wg & 7, xw = wl & 7;
   const int64_t job = xw * xq + (xw < xr ? xw : xr) + (wl >> 3);
-  const int rhs = (int)(job / gridDim.x);
+  const int rhs = __builtin_amdgcn_readfirstlane((int)(job / gridDim.x));   // uniform: scalar row offsets
   if (st && !st[rhs].active) return;   // this RHS has stopped iterating
-  using PI = typename Pair<Tin>::type;
-  using PO = typename Pair<T>::type;
+  using PI = typename PairU<Tin>::type;
+  using PO = typename PairU<T>::type;
   __shared__ __align__(16) char lds[F::LDS_BYTES];
   constexpr int N = F::N, E = F::E, NT = F::NT;
   const int t = threadIdx.x;
@@ -615,9 +612,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
 
   cx<T> v[E];
   constexpr int L0 = F::first_log_fwd(), R0 = 1 << L0;
-  const bool in_inside = s0 >= lo && s0 + 2 * N <= hi &&
-                         ((reinterpret_cast<uintptr_t>(src + s0) & (sizeof(PI) - 1)) == 0);
-  if (in_inside) {
+  // the window: whole inside the interval (pair accesses at any element boundary), cut
+  // by an end of it (32-bit window offsets, samples [a, b) are data), or starting before
+  // the TOD row (the first interval's first chunk)
+  if (s0 >= lo && s0 + 2 * N <= hi) {
     const PI* __restrict__ src2 = reinterpret_cast<const PI*>(src + s0);
 #pragma unroll
     for (int i = 0; i < E / R0; ++i)
@@ -626,6 +624,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
         // 32-bit offsets from the uniform window base: one VGPR per address
         const PI x = src2[(uint32_t)F::template in_index<L0>(t, i, r)];
         v[i * R0 + r] = {(T)x.x, (T)x.y};
+      }
+  } else if (s0 >= 0) {
+    const Tin* __restrict__ base = src + s0;
+    const int a = (int)(lo > s0 ? lo - s0 : 0);
+    const int b = (int)(hi - s0 < 2 * N ? hi - s0 : 2 * N);
+#pragma unroll
+    for (int i = 0; i < E / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int k2 = 2 * F::template in_index<L0>(t, i, r);
+        const T x = (k2 >= a && k2 < b) ? (T)base[(uint32_t)k2] : (T)0;
+        const T y = (k2 + 1 >= a && k2 + 1 < b) ? (T)base[(uint32_t)(k2 + 1)] : (T)0;
+        v[i * R0 + r] = {x, y};
       }
   } else {
 #pragma unroll
@@ -678,30 +689,28 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, OlsShape<LOGN, V>::NT),
   F::forward_rev(v, lds, ptw, t);
 
   constexpr int LZ = F::last_log_rev(), RZ = 1 << LZ;
-  T* __restrict__ dst = yout + roff;
-  const bool out_inside = ((n_c & 1) == 0) && s0 + n_c + m <= hi &&
-                          ((reinterpret_cast<uintptr_t>(dst + s0) & (sizeof(PO) - 1)) == 0);
-  if (out_inside) {
-    PO* __restrict__ dst2 = reinterpret_cast<PO*>(dst + s0);
-    const int j0 = n_c >> 1, j1 = (n_c + m) >> 1;
+  // outputs 2j, 2j + 1 go to out_start + o, o = 2j - n_c, for o in [0, len): 32-bit offsets
+  T* __restrict__ dst = yout + roff + ch.out_start;
+  const int len = (int)(hi - ch.out_start < m ? hi - ch.out_start : m);   // outputs of this chunk
+  if ((n_c & 1) == 0 && len == m) {   // whole pairs, all inside
+    PO* __restrict__ dst2 = reinterpret_cast<PO*>(dst);
 #pragma unroll
     for (int i = 0; i < E / RZ; ++i)
 #pragma unroll
       for (int r = 0; r < RZ; ++r) {
-        const int j = t + i * NT + r * (N >> LZ);
+        const int o = 2 * (t + i * NT + r * (N >> LZ)) - n_c;
         const cx<T> z = v[i * RZ + r];
-        if (j >= j0 && j < j1) dst2[(uint32_t)j] = PO{z.re, -z.im};
+        if (o >= 0 && o < m) dst2[(uint32_t)(o >> 1)] = PO{z.re, -z.im};
       }
   } else {
 #pragma unroll
     for (int i = 0; i < E / RZ; ++i)
 #pragma unroll
       for (int r = 0; r < RZ; ++r) {
-        const int j = t + i * NT + r * (N >> LZ);
-        const int pos = 2 * j;
+        const int o = 2 * (t + i * NT + r * (N >> LZ)) - n_c;
         const cx<T> z = v[i * RZ + r];
-        if (pos >= n_c && pos < n_c + m && s0 + pos < hi) dst[s0 + pos] = z.re;
-        if (pos + 1 >= n_c && pos + 1 < n_c + m && s0 + pos + 1 < hi) dst[s0 + pos + 1] = -z.im;
+        if (o >= 0 && o < len) dst[(uint32_t)o] = z.re;
+        if (o + 1 >= 0 && o + 1 < len) dst[(uint32_t)(o + 1)] = -z.im;
       }
   }
 }

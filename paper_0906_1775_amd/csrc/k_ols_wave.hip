@@ -222,12 +222,6 @@ __device__ __forceinline__ void inner_dft_t(cx<T>* v, cx<T>* row, const cx<T>* _
 }
 
 
-// Pairs of TOD elements at any element boundary (windows of intervals that start at an
-// odd sample): 4- and 8-byte aligned, where float2 / double2 need 8 and 16 (the loads and
-// stores are still single 8- and 16-byte accesses)
-struct alignas(4) FloatPairU { float x, y; };
-struct alignas(8) DoublePairU { double x, y; };
-
 // The packed window of one (chunk, RHS) job: thread g gets z[g + 1024 n_o] = u[2n] + i u[2n + 1],
 // n_o < NO, u[i] = TOD sample s0 + i inside the chunk's interval, else 0 (s0 = out_start - n_c).
 // Offsets inside the window are 32-bit from its first sample.
@@ -235,7 +229,7 @@ template <typename Tin, int NO>
 __device__ __forceinline__ void wave_load(cx<float>* v, const Tin* __restrict__ yin, const OlsChunk& ch, int rhs,
                                           int64_t n_t, int n_c, int g) {
   using T = float;
-  using PU = typename std::conditional<sizeof(Tin) == 4, FloatPairU, DoublePairU>::type;
+  using PU = typename PairU<Tin>::type;
   constexpr int W = 2048 * NO;   // window samples
   const Tin* __restrict__ src = yin + (int64_t)rhs * n_t;
   const int64_t s0 = ch.out_start - n_c;
