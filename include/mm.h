@@ -133,7 +133,11 @@ typedef struct {
   int32_t n_c;                  /* correlation length: f(tau) = 0 for tau >= n_c; >= 1 */
   int32_t n_f;                  /* overlap-save FFT length: 0 = library default (the
                                    paper's rule capped at 2^14, or the smallest power of
-                                   two above 2 n_c when that is longer), -1 = autotune
+                                   two above 2 n_c when that is longer; in float32 with the
+                                   default shape, twice that, 2^16, where the chunks of the
+                                   2^15-point transform take fewer full rounds of one
+                                   workgroup per compute unit at 2.25 times the work each),
+                                   -1 = autotune
                                    (time every length with a transform on the plan's
                                    intervals and keep the fastest), > 0 = forced power of
                                    two with n_f > 2 n_c.  Transforms exist on chip (one
@@ -149,8 +153,9 @@ typedef struct {
   int32_t n_templates;          /* template blocks appended to P, 0 .. 16 */
   const mm_template_t* templates;  /* host [n_templates], or NULL when n_templates = 0 */
   int32_t fft_shape;            /* workgroup shape of the overlap-save transform (n_f / 2 complex
-                                   points): 0 = library default (for 2^14 points shape 10 in
-                                   float32, 3 in float64; else 1); 1 = 16 points per thread,
+                                   points): 0 = library default (for 2^14 and 2^15 points shape
+                                   10 in float32, for 2^14 shape 3 in float64; else 1);
+                                   1 = 16 points per thread,
                                    radix-16 passes (32 points per
                                    thread for 2^15 points); 2 = radix-32 passes, 32 points per
                                    thread (64 for 2^15); 3 = 512 threads x 32 points, radix-16
@@ -166,12 +171,14 @@ typedef struct {
                                    two workgroups per CU; 10 = 1024 threads x 16 points, a
                                    four-step transform (16 x 1024) whose 1024-point stages
                                    stay inside one wavefront (exchanges without workgroup
-                                   barriers), float32 only.  For 2^15 points shape 3 is 1024
-                                   threads x 32 points, radix-8 passes, pairs in registers.
-                                   Shape 2 exists for float32 transforms of 2^13 .. 2^15 points,
-                                   shape 3 for 2^14 and 2^15 points, shapes 4 .. 10 for 2^14
-                                   points (3, 6 and 8 also in float64); elsewhere shape 1 is
-                                   used.  Ignored with n_f = -1 (the autotuner tries every
+                                   barriers), float32 only; for 2^15 points 1024 threads x 32
+                                   points (32 x 1024, two 1024-point rows per wavefront,
+                                   workgroup exchanges in two halves).  For 2^15 points shape
+                                   3 is 1024 threads x 32 points, radix-8 passes, pairs in
+                                   registers.  Shape 2 exists for float32 transforms of
+                                   2^13 .. 2^15 points, shapes 3 and 10 for 2^14 and 2^15
+                                   points, shapes 4 .. 9 for 2^14 points (3, 6 and 8 also in
+                                   float64); elsewhere shape 1 is used.  Ignored with n_f = -1 (the autotuner tries every
                                    shape). */
 } mm_desc_t;
 
