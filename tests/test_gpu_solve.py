@@ -245,6 +245,10 @@ def test_c2_mixed_solve_reaches_the_float64_map_error():
     m_a, i_a = m64.solve(tod, tol=1e-8, max_iter=400)
     e64 = float(torch.linalg.norm(m_a - ref) / torch.linalg.norm(ref))
     mx = plan_for(p, precision="mixed")
+    # 2^24 samples: 352 windows of 2^16 samples would fill 256 CUs less than twice, so the
+    # default keeps n_f = 2^15 (the 16 x 1024 wavefront-private transform)
+    if torch.cuda.get_device_properties(0).multi_processor_count == 256:
+        assert mx.info()["n_f"] == 1 << 15 and mx.info()["fft_shape"] == 10
     m_b, i_b = mx.solve(tod, tol=1e-8 / 3, max_iter=400)
     emx = float(torch.linalg.norm(m_b - ref) / torch.linalg.norm(ref))
     print(f"C2 map error: float64 {e64:.3e} ({i_a['iters'][0]} it), mixed {emx:.3e} ({i_b['iters'][0]} it)")

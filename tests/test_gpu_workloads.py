@@ -130,12 +130,31 @@ def _hit_samples(p, pixels):
     return torch.nonzero(sel).flatten().cpu().numpy()
 
 
+def _default_nf(p, precision):
+    """The library's default FFT length for n_c = 8192 workloads: 2^15 (the smallest power of
+    two above 2 n_c), or in float32 2^16 when its chunks, one 2^15-point workgroup each at
+    2.25 times the work of a 2^14-point one, take fewer full rounds over the compute units."""
+    assert p.n_c == 8192
+    if precision == "fp64":
+        return 1 << 15
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    iv = np.asarray(p.iv_start, dtype=np.int64)
+    lens = iv[1:] - iv[:-1]
+
+    def rounds(nf):
+        m = nf - 2 * p.n_c
+        return -(-int(np.sum((lens + m - 1) // m)) * p.n_rhs // cu)
+    return 1 << 16 if 2.25 * rounds(1 << 16) < rounds(1 << 15) else 1 << 15
+
+
 def _check_full(p, precision, n_f=0):
     lag_tab = onoise.lag_table(p.filter_params, p.f_samp, p.n_c)
     pixels = _pick_pixels(p, 4, 5)
     ts = _hit_samples(p, pixels)
     mm = _plan(p, precision, n_f=n_f)
     print(f"{p.name} full: plan {mm.info()}", flush=True)
+    if n_f == 0:
+        assert mm.info()["n_f"] == _default_nf(p, precision)
     h = mm.hits()[torch.from_numpy(pixels).cuda()].cpu().numpy()
     assert np.array_equal(h, np.array([np.count_nonzero(p.pix[ts].cpu().numpy() == q) for q in pixels]))
     rs = sorted({0, p.n_rhs - 1})
@@ -176,6 +195,8 @@ def _check_full(p, precision, n_f=0):
 def test_batched_uneven_full_size_sampled(precision):
     p = _gen("c3")
     assert p.n_samples == 1 << 28
+    if precision == "mixed":
+        assert _default_nf(p, precision) == 1 << 16   # 5,829 chunks against 16,779 at 2^15
     _check_full(p, precision)
 
 
@@ -229,6 +250,7 @@ def test_full_size_mixed_map_matches_the_fp64_map(name, kw):
 def test_large_batch_full_size_sampled():
     p = _gen("c5")
     assert p.n_samples == 1 << 30 and p.n_rhs == 8
+    assert _default_nf(p, "mixed") == 1 << 16
     _check_full(p, "mixed")
 
 
@@ -265,6 +287,8 @@ def test_forced_transform_shapes_match_the_oracle(n_f, shape):
     assert max_rel(hx, want) <= TOL["mixed"]
     y = p.tod[:1].contiguous()
     wy = mm.weight(y).double().cpu().numpy()[0]
+    assert max_rel(wy, o.apply_ninv(y.double().cpu().numpy()[0])) <= 1e-5
+    wy = mm.weight(y.double()).cpu().numpy()[0]          # float64 TOD into the float32 transform
     assert max_rel(wy, o.apply_ninv(y.double().cpu().numpy()[0])) <= 1e-5
     if n_f == 65536:
         return                          # beyond the largest float64 transform
