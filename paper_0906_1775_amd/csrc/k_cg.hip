@@ -122,13 +122,11 @@ __device__ __forceinline__ void precond_apply(const double* __restrict__ m, cons
 // every RHS's partial sums keep the order of a one-RHS pass (tail entries, then
 // pixels, in grid-stride order).  Tv: the element type of q and z (float32 in the
 // mixed-precision iteration: q as the scatter rounded it, z rounded after r.z is
-// formed from its float64 value).  An RHS whose last step made its iterate the best
-// (copy_best) has that iterate, the x this kernel reads, copied to xbest here, where x
-// is read anyway.
+// formed from its float64 value).  x += alpha p is left to the step kernel, which reads
+// p anyway.
 template <int NS, int RG, typename Tv>
 __global__ __launch_bounds__(kDotThreads) void k_cg_update(
-    double* __restrict__ x, double* __restrict__ xbest, const double* __restrict__ p, double* __restrict__ rv,
-    const Tv* __restrict__ q, Tv* __restrict__ z, const double* __restrict__ minv,
+    double* __restrict__ rv, const Tv* __restrict__ q, Tv* __restrict__ z, const double* __restrict__ minv,
     CgState* __restrict__ st, CgState* __restrict__ st_prev, int64_t n_obs, int64_t vs,
     const double* __restrict__ minv_t, int64_t n_tail, int n_rhs, const double* __restrict__ pq_part, int n_pq,
     double* __restrict__ prz, double* __restrict__ prr) {
@@ -137,17 +135,16 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
   constexpr int NM = NS == 1 ? 1 : 6;
   const int r0 = blockIdx.y * RG;
   const int tid = threadIdx.x;
-  bool act[RG], cb[RG];
+  bool act[RG];
   double alpha[RG];
 #pragma unroll
   for (int g = 0; g < RG; ++g) {
     const int r = r0 + g;
     if (r >= n_rhs) {               // uniform over the block
-      act[g] = cb[g] = false;
+      act[g] = false;
       alpha[g] = 0.0;
       continue;
     }
-    cb[g] = st[r].copy_best != 0;
     double acc = 0.0;
     for (int i = tid; i < n_pq; i += kDotThreads) acc += pq_part[(int64_t)r * n_pq + i];
     const double pq = block_sum(acc, sh);
@@ -181,12 +178,8 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     const double mt = minv_t[j];
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
-      if (!act[g] && !cb[g]) continue;
-      const int64_t b = (int64_t)(r0 + g) * vs + n_obs * NS + j;
-      const double xo = x[b];
-      if (cb[g]) xbest[b] = xo;
       if (!act[g]) continue;
-      x[b] = xo + alpha[g] * p[b];
+      const int64_t b = (int64_t)(r0 + g) * vs + n_obs * NS + j;
       const double rr = rv[b] - alpha[g] * (double)q[b];
       rv[b] = rr;
       const double zz = mt * rr;
@@ -201,20 +194,11 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
     for (int k = 0; k < NM; ++k) m[k] = minv[o * NM + k];
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
-      if (!act[g] && !cb[g]) continue;
-      const int64_t b = (int64_t)(r0 + g) * vs + o * NS;
-      double xo[NS];
-#pragma unroll
-      for (int c = 0; c < NS; ++c) xo[c] = x[b + c];
-      if (cb[g]) {
-#pragma unroll
-        for (int c = 0; c < NS; ++c) xbest[b + c] = xo[c];
-      }
       if (!act[g]) continue;
+      const int64_t b = (int64_t)(r0 + g) * vs + o * NS;
       double rr[NS], zz[NS];
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
-        x[b + c] = xo[c] + alpha[g] * p[b + c];
         rr[c] = rv[b + c] - alpha[g] * (double)q[b + c];
         rv[b + c] = rr[c];
       }
@@ -239,14 +223,14 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_update(
   }
 }
 
-hipError_t launch_cg_update(int ns, double* x, double* xbest, const double* p, double* r, const void* q, void* z,
+hipError_t launch_cg_update(int ns, double* r, const void* q, void* z,
                             bool qz_f32, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s) {
   const dim3 b(kDotThreads);
 #define MM_UPD(NS, RG, TV)                                                                                \
-  hipLaunchKernelGGL((k_cg_update<NS, RG, TV>), dim3(kDotBlocks, (n_rhs + RG - 1) / RG), b, 0, s, x, xbest, p, r, \
+  hipLaunchKernelGGL((k_cg_update<NS, RG, TV>), dim3(kDotBlocks, (n_rhs + RG - 1) / RG), b, 0, s, r, \
                      (const TV*)q, (TV*)z, minv, st, st_prev, n_obs, vs, minv_t, n_tail, n_rhs, pq_part, n_pq,   \
                      partial_rz, partial_rr)
 #define MM_UPD_T(TV)                                     \
@@ -285,14 +269,15 @@ __device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr)
   return true;
 }
 
-// Scalar step, then p = z + beta p (RHS that stepped), in one launch: every block
-// folds the partial sums in the same fixed order and derives the same new state
-// from st_prev (written by the update, read-only here); block 0 of each RHS stores
-// it in st, which no block of this kernel reads.  An iterate that became the best
-// is copied by the next update (or by the host after the last one).
+// Scalar step, then x += alpha p, x_best = x (RHS whose iterate became the best) and
+// p = z + beta p (RHS that stepped), in one launch: every block folds the partial sums
+// in the same fixed order and derives the same new state from st_prev (written by the
+// update, read-only here); block 0 of each RHS stores it in st, which no block of this
+// kernel reads.
 template <typename Tz>
-__global__ void k_cg_step_next(double* __restrict__ p, const Tz* __restrict__ z,
-                               CgState* __restrict__ st, const CgState* __restrict__ st_prev,
+__global__ void k_cg_step_next(double* __restrict__ x, double* __restrict__ xbest, double* __restrict__ p,
+                               const Tz* __restrict__ z, CgState* __restrict__ st,
+                               const CgState* __restrict__ st_prev,
                                const double* __restrict__ prz, const double* __restrict__ prr,
                                double* __restrict__ history, int hist_stride, int64_t nu,
                                float* __restrict__ p32, int64_t n32, int64_t vs32) {
@@ -308,27 +293,32 @@ __global__ void k_cg_step_next(double* __restrict__ p, const Tz* __restrict__ z,
   // p advances on every step taken, also the one on which an RHS stops: a later
   // residual replacement that finds it above tol continues it along this direction
   if (!stepped) return;
-  const double beta = s.beta;
+  const double alpha = s.alpha, beta = s.beta;
+  const bool best = s.copy_best != 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
     const int64_t j = (int64_t)r * nu + i;
-    const double pn = (double)z[j] + beta * p[j];
+    const double pj = p[j];
+    const double xn = x[j] + alpha * pj;
+    x[j] = xn;
+    if (best) xbest[j] = xn;
+    const double pn = (double)z[j] + beta * pj;
     p[j] = pn;
     if (p32 && i < n32) p32[(int64_t)r * vs32 + i] = (float)pn;
   }
 }
 
-hipError_t launch_cg_step_next(double* p, const void* z, bool z_f32, CgState* st,
+hipError_t launch_cg_step_next(double* x, double* xbest, double* p, const void* z, bool z_f32, CgState* st,
                                const CgState* st_prev, const double* partial_rz, const double* partial_rr,
                                double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
                                float* p32, int64_t n32, int64_t vs32) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
   if (z_f32)
-    hipLaunchKernelGGL(k_cg_step_next<float>, g, dim3(256), 0, s, p, (const float*)z, st, st_prev,
+    hipLaunchKernelGGL(k_cg_step_next<float>, g, dim3(256), 0, s, x, xbest, p, (const float*)z, st, st_prev,
                        partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
   else
-    hipLaunchKernelGGL(k_cg_step_next<double>, g, dim3(256), 0, s, p, (const double*)z, st, st_prev,
+    hipLaunchKernelGGL(k_cg_step_next<double>, g, dim3(256), 0, s, x, xbest, p, (const double*)z, st, st_prev,
                        partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
   return hipGetLastError();
 }

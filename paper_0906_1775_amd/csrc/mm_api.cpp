@@ -1472,10 +1472,10 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
            "scatter");
   else
     scatter_all(P, P->fs_main.fp64, P->y2, P->vq, R, s, P->vp, P->st);
-  hipchk(launch_cg_update(P->ns, P->vx, P->vxb, P->vp, P->vr, P->vq, P->vz, v32, P->minv, P->st, P->st_prev, P->n_obs,
+  hipchk(launch_cg_update(P->ns, P->vr, P->vq, P->vz, v32, P->minv, P->st, P->st_prev, P->n_obs,
                           P->nu(), P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
-  hipchk(launch_cg_step_next(P->vp, P->vz, v32, P->st, P->st_prev, P->part2, P->part3, P->hist,
+  hipchk(launch_cg_step_next(P->vx, P->vxb, P->vp, P->vz, v32, P->st, P->st_prev, P->part2, P->part3, P->hist,
                              kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
          "scalar step and next direction");
 }
@@ -1652,17 +1652,6 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
     done += step;
     finished = all_done();
   }
-  // an iterate that the last step made the best has not been copied by an update yet
-  bool pending = false;
-  for (int r = 0; r < R; ++r) {
-    if (!P->st_host[r].copy_best) continue;
-    hipchk(hipMemcpyAsync(P->vxb + (int64_t)r * nu, P->vx + (int64_t)r * nu, sizeof(double) * nu,
-                          hipMemcpyDeviceToDevice, s), "best iterate copy");
-    P->st_host[r].copy_best = 0;
-    pending = true;
-  }
-  if (pending)
-    hipchk(hipMemcpyAsync(P->st, P->st_host, sizeof(CgState) * R, hipMemcpyHostToDevice, s), "state copy");
 }
 
 // out_r = b64_r - H64 x_r for RHS r, in float64 (through the float64 filter)

@@ -222,25 +222,23 @@ hipError_t launch_dot(const double* x, const double* y, int64_t nu, int n_rhs, d
 hipError_t launch_cg_init(CgState* st, const double* partial_bb, const double* partial_rr,
                           const double* partial_rz, double tol, int fixed, int n_rhs,
                           double* history, int hist_stride, hipStream_t s);
-// x += alpha p, r -= alpha q, z = M r with alpha = rho / (p.q) folded from the
-// n_pq partial sums of p.q; writes the r.z and r.r partial sums
+// r -= alpha q, z = M r with alpha = rho / (p.q) folded from the n_pq partial sums of
+// p.q (x += alpha p is left to launch_cg_step_next); writes the r.z and r.r partial sums
 // Vectors are rows of stride vs: n_obs pixel blocks, then n_tail template
 // amplitudes preconditioned by the diagonal minv_t.
 // (also copies the state before the step, alpha and breakdown included, to st_prev)
-// q and z: float64, or float32 when qz_f32 (z rounded after r.z is formed).  RHS whose
-// state has copy_best set get their x (before the step) copied to xbest.
-hipError_t launch_cg_update(int ns, double* x, double* xbest, const double* p, double* r, const void* q, void* z,
+// q and z: float64, or float32 when qz_f32 (z rounded after r.z is formed).
+hipError_t launch_cg_update(int ns, double* r, const void* q, void* z,
                             bool qz_f32, const double* minv, CgState* st, CgState* st_prev, int64_t n_obs,
                             int64_t vs, const double* minv_t, int64_t n_tail,
                             int n_rhs, const double* pq_part, int n_pq, double* partial_rz,
                             double* partial_rr, hipStream_t s);
 // The scalar step (new rho, beta, residual, best iterate, convergence; st from
 // st_prev and the update's partial sums; history[r * hist_stride + iter] = rel),
-// then p = z + beta p (active RHS; the copy of an iterate that became the best is
-// left to the next update, copy_best); p32 (optional): also a float32 copy of the
-// first n32 entries of each row of p (rows of stride vs32); z: float64, or float32
-// when z_f32
-hipError_t launch_cg_step_next(double* p, const void* z, bool z_f32, CgState* st,
+// then x += alpha p, x_best = x (RHS whose iterate became the best) and p = z + beta p
+// (RHS that stepped); p32 (optional): also a float32 copy of the first n32 entries of
+// each row of p (rows of stride vs32); z: float64, or float32 when z_f32
+hipError_t launch_cg_step_next(double* x, double* xbest, double* p, const void* z, bool z_f32, CgState* st,
                                const CgState* st_prev, const double* partial_rz, const double* partial_rr,
                                double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
                                float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
