@@ -274,8 +274,8 @@ __device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr)
 // in the same fixed order and derives the same new state from st_prev (written by the
 // update, read-only here); block 0 of each RHS stores it in st, which no block of this
 // kernel reads.
-template <typename Tz>
-__global__ void k_cg_step_next(double* __restrict__ x, double* __restrict__ xbest, double* __restrict__ p,
+template <typename Tp, typename Tz>
+__global__ void k_cg_step_next(double* __restrict__ x, double* __restrict__ xbest, Tp* __restrict__ p,
                                const Tz* __restrict__ z, CgState* __restrict__ st,
                                const CgState* __restrict__ st_prev,
                                const double* __restrict__ prz, const double* __restrict__ prr,
@@ -298,28 +298,34 @@ __global__ void k_cg_step_next(double* __restrict__ x, double* __restrict__ xbes
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
     const int64_t j = (int64_t)r * nu + i;
-    const double pj = p[j];
+    const double pj = (double)p[j];
     const double xn = x[j] + alpha * pj;
     x[j] = xn;
     if (best) xbest[j] = xn;
     const double pn = (double)z[j] + beta * pj;
-    p[j] = pn;
+    p[j] = (Tp)pn;
     if (p32 && i < n32) p32[(int64_t)r * vs32 + i] = (float)pn;
   }
 }
 
-hipError_t launch_cg_step_next(double* x, double* xbest, double* p, const void* z, bool z_f32, CgState* st,
+hipError_t launch_cg_step_next(double* x, double* xbest, void* p, bool p_f32, const void* z, bool z_f32, CgState* st,
                                const CgState* st_prev, const double* partial_rz, const double* partial_rr,
                                double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
                                float* p32, int64_t n32, int64_t vs32) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
-  if (z_f32)
-    hipLaunchKernelGGL(k_cg_step_next<float>, g, dim3(256), 0, s, x, xbest, p, (const float*)z, st, st_prev,
-                       partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+  if (p_f32 && z_f32)
+    hipLaunchKernelGGL((k_cg_step_next<float, float>), g, dim3(256), 0, s, x, xbest, (float*)p, (const float*)z, st,
+                       st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+  else if (z_f32)
+    hipLaunchKernelGGL((k_cg_step_next<double, float>), g, dim3(256), 0, s, x, xbest, (double*)p, (const float*)z,
+                       st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+  else if (!p_f32)
+    hipLaunchKernelGGL((k_cg_step_next<double, double>), g, dim3(256), 0, s, x, xbest, (double*)p,
+                       (const double*)z, st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32,
+                       vs32);
   else
-    hipLaunchKernelGGL(k_cg_step_next<double>, g, dim3(256), 0, s, x, xbest, p, (const double*)z, st, st_prev,
-                       partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

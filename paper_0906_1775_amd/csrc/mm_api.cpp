@@ -1462,9 +1462,10 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   // the host only every check_every iterations)
   gather_all(P, P->fs_main.fp64, P->vp, P->y1, R, s, P->st, P->vp32);
   weight(P, P->fs_main, P->y1, P->fs_main.fp64, P->y2, R, s, P->st);
-  // the mixed-precision iteration without templates keeps q and z in float32 (in the
-  // first half of their float64 buffers): q is a float32 operator's output, and z only
-  // builds the next direction, whose float32 copy the gather reads
+  // the mixed-precision iteration without templates keeps q, z and p in float32 (q and z
+  // in the first half of their float64 buffers, p in vp32): q is a float32 operator's
+  // output, z only builds the next direction, and p is the direction the operator is
+  // applied to, which x also moves along (x, r and the dots stay float64)
   const bool v32 = P->iter_f32();
   if (v32)
     hipchk(launch_scatter_q32(P->ns, P->px.sell, (const float*)P->y2, (float*)P->vq, P->nu(), P->n_obs, P->n_t, R,
@@ -1475,9 +1476,14 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   hipchk(launch_cg_update(P->ns, P->vr, P->vq, P->vz, v32, P->minv, P->st, P->st_prev, P->n_obs,
                           P->nu(), P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
-  hipchk(launch_cg_step_next(P->vx, P->vxb, P->vp, P->vz, v32, P->st, P->st_prev, P->part2, P->part3, P->hist,
-                             kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
-         "scalar step and next direction");
+  if (v32)
+    hipchk(launch_cg_step_next(P->vx, P->vxb, P->vp32, true, P->vz, true, P->st, P->st_prev, P->part2, P->part3,
+                               P->hist, kHistRing, P->nu(), R, s),
+           "scalar step and next direction");
+  else
+    hipchk(launch_cg_step_next(P->vx, P->vxb, P->vp, false, P->vz, false, P->st, P->st_prev, P->part2, P->part3,
+                               P->hist, kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
+           "scalar step and next direction");
 }
 
 // per-RHS sums of x.y over [R][nu] vectors (float64, fixed order)
@@ -1769,14 +1775,14 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       for (int r : rows) residual64_row(P, P->vx, P->vr, r, s);
       hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
              "precondition");
-      bool any_restart = false;
       for (int r : rows)
         if (P->st_host[r].breakdown) {
           hipchk(hipMemcpyAsync(P->vp + (int64_t)r * nu, P->vz + (int64_t)r * nu, sizeof(double) * nu,
                                 hipMemcpyDeviceToDevice, s), "restart");
-          any_restart = true;
+          if (P->vp32)   // the iteration's direction (the only one in a float32 iteration)
+            hipchk(launch_rows_to_f32(P->vz + (int64_t)r * nu, nu, P->vp32 + (int64_t)r * P->vs32(), P->vs32(),
+                                      P->nmap(), 1, s), "restart");
         }
-      if (any_restart) sync_p32(P, s);
       std::vector<double> rr, rz;
       dots2(P, P->vr, P->vr, P->vz, R, s, rr, rz);
       for (int r : rows) {

@@ -237,8 +237,9 @@ hipError_t launch_cg_update(int ns, double* r, const void* q, void* z,
 // st_prev and the update's partial sums; history[r * hist_stride + iter] = rel),
 // then x += alpha p, x_best = x (RHS whose iterate became the best) and p = z + beta p
 // (RHS that stepped); p32 (optional): also a float32 copy of the first n32 entries of
-// each row of p (rows of stride vs32); z: float64, or float32 when z_f32
-hipError_t launch_cg_step_next(double* x, double* xbest, double* p, const void* z, bool z_f32, CgState* st,
+// each row of p (rows of stride vs32); p and z: float64, or float32 when p_f32 / z_f32
+// (a float32 p, rows of stride nu, is the iteration's only direction: no p32 copy)
+hipError_t launch_cg_step_next(double* x, double* xbest, void* p, bool p_f32, const void* z, bool z_f32, CgState* st,
                                const CgState* st_prev, const double* partial_rz, const double* partial_rr,
                                double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
                                float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
