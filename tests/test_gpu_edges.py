@@ -175,3 +175,28 @@ def test_scatter_widths_match_the_oracle(grid, wps, n_rhs):
     m, _ = mm.solve(tod_tensor(p), fixed_iters=5)
     x, _ = o.pcg(o.rhs(p.tod[n_rhs - 1]), fixed_iters=5)
     assert rel_err(m.cpu().numpy()[n_rhs - 1], o.to_global(x)) <= 1e-10
+
+
+@pytest.mark.parametrize("n_f", [1 << 15, 1 << 16])
+def test_wavefront_private_transforms_on_odd_lengths_and_starts(n_f):
+    """The wavefront-private transforms (fft_shape 10: 16 x 1024 points at n_f = 2^15,
+    32 x 1024 at 2^16) with an odd n_c = 4097 (each window's outputs start at an odd
+    position: element stores), on intervals of odd lengths and odd starts, shorter than a
+    window down to one sample, and one spanning several windows: N^-1 of a mixed plan
+    against the oracle's convolution, for float32 and float64 TOD."""
+    lens = [70001, 3, 1, 40000, 131073, 12345]
+    p = synth.make_custom(3, grid=(16, 16), det_lens=(sum(lens),), interval_lens=[lens], n_c=4097,
+                          f_samp=20.0, seed=21)
+    o = oracle_for(p, 1 << 15)
+    from paper_0906_1775_amd import MapMaker
+    dev = torch.device("cuda:0")
+    mm = MapMaker(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.w).to(dev), p.n_pix, 3, p.iv_start,
+                  p.iv_filter, filter_lags=o.lag_tab, n_c=p.n_c, n_f=n_f, fft_shape=10, precision="mixed")
+    assert mm.info()["n_f"] == n_f and mm.info()["fft_shape"] == 10
+    y = np.random.default_rng(4).standard_normal(p.pix.size)
+    ref = o.apply_ninv(y)
+    for dt in (torch.float32, torch.float64):
+        yt = torch.from_numpy(y).to(dev, dt).reshape(1, -1)
+        want = o.apply_ninv(yt.double().cpu().numpy()[0]) if dt == torch.float32 else ref
+        got = mm.weight(yt).double().cpu().numpy()[0]
+        assert max_rel(got, want) <= 1e-5
