@@ -1660,14 +1660,33 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
   }
 }
 
-// out_r = b64_r - H64 x_r for RHS r, in float64 (through the float64 filter)
-void residual64_row(mm_plan_s* P, const double* x, double* out, int r, hipStream_t s) {
+// Float64 TOD rows one float64 pass can take at once: the TOD work buffers hold R rows
+// of the plan's own precision, so R / 2 float64 rows in a mixed plan
+int rows64(const mm_plan_s* P) { return P->main_fp64() ? P->R : std::max(1, P->R / 2); }
+
+// out_r = b64_r - H64 x_r for the RHS r0 .. r0 + nr - 1, in float64 (through the float64
+// filter), rows64 of them per pass so that the pointing is read once per group
+void residual64_rows(mm_plan_s* P, const double* x, double* out, int r0, int nr, hipStream_t s) {
   const int64_t nu = P->nu();
   const FilterSetup& f64 = P->main_fp64() ? P->fs_main : P->fs64;
   void* ya = P->main_fp64() ? P->y1 : (void*)P->y64a;
   void* yb = P->main_fp64() ? P->y2 : (void*)P->y64b;
-  apply_H_obs(P, f64, x + (int64_t)r * nu, P->vq, ya, yb, 1, s);
-  hipchk(launch_sub(out + (int64_t)r * nu, P->vb64 + (int64_t)r * nu, P->vq, nu, s), "residual");
+  const int B = rows64(P);
+  for (int a = r0; a < r0 + nr; a += B) {
+    const int k = std::min(B, r0 + nr - a);
+    apply_H_obs(P, f64, x + (int64_t)a * nu, P->vq, ya, yb, k, s);
+    hipchk(launch_sub(out + (int64_t)a * nu, P->vb64 + (int64_t)a * nu, P->vq, (int64_t)k * nu, s), "residual");
+  }
+}
+
+// the same for the RHS listed in rows (ascending), consecutive ones together
+void residual64_list(mm_plan_s* P, const double* x, double* out, const std::vector<int>& rows, hipStream_t s) {
+  for (size_t i = 0; i < rows.size();) {
+    size_t j = i + 1;
+    while (j < rows.size() && rows[j] == rows[j - 1] + 1) ++j;
+    residual64_rows(P, x, out, rows[i], (int)(j - i), s);
+    i = j;
+  }
 }
 
 // Right-hand side of a solve: b = P^T N^-1 d from a TOD, or a map given directly.
@@ -1677,6 +1696,9 @@ struct RhsSource {
   const double* map = nullptr;   // global layout [R][n_pix][ns]
 };
 
+// b64 of every RHS through the float64 filter, rows64 per pass
+void make_rhs64(mm_plan_s* P, const RhsSource& src, hipStream_t s);
+
 // b (observed layout) of RHS rows [r0, r0 + nr) with the filter fs into dst
 void make_rhs(mm_plan_s* P, const RhsSource& src, const FilterSetup& fs, int r0, int nr, double* dst,
               void* yb, hipStream_t s) {
@@ -1685,6 +1707,15 @@ void make_rhs(mm_plan_s* P, const RhsSource& src, const FilterSetup& fs, int r0,
   } else {
     const int esz = src.tod64 ? 8 : 4;
     rhs_obs(P, fs, (const char*)src.tod + (size_t)r0 * P->n_t * esz, src.tod64, dst, yb, nr, s);
+  }
+}
+
+void make_rhs64(mm_plan_s* P, const RhsSource& src, hipStream_t s) {
+  const int64_t nu = P->nu();
+  const int B = rows64(P);
+  for (int a = 0; a < P->R; a += B) {
+    const int k = std::min(B, P->R - a);
+    make_rhs(P, src, P->fs64, a, k, P->vb64 + (int64_t)a * nu, P->y64b, s);
   }
 }
 
@@ -1737,11 +1768,11 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     // between checks are sized (BlockSizer) so that the recurrence residual is not
     // predicted to fall more than kMixedMaxDrop decades below the last float64 one.
     // The iterate with the lowest true residual is returned.
-    for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
+    make_rhs64(P, src, s);
     hipchk(hipMemcpyAsync(P->vb, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     if (o.d_x0) {
       to_obs(P, o.d_x0, P->vx, R, s);
-      for (int r = 0; r < R; ++r) residual64_row(P, P->vx, P->vr, r, s);
+      residual64_rows(P, P->vx, P->vr, 0, R, s);
     } else {
       hipchk(launch_fill_f64(P->vx, 0.0, (int64_t)R * nu, s), "fill");
       hipchk(hipMemcpyAsync(P->vr, P->vb, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
@@ -1772,7 +1803,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     // those that broke down); returns after updating the device states
     std::vector<int> restarted(R, -1);
     auto replace = [&](const std::vector<int>& rows) {
-      for (int r : rows) residual64_row(P, P->vx, P->vr, r, s);
+      residual64_list(P, P->vx, P->vr, rows, s);
       hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
              "precondition");
       for (int r : rows)
@@ -1857,10 +1888,10 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     // reliable updates, drifts along directions the float64 H nearly annihilates:
     // invisible in the residual, not in the fitted TOD.)
     double* const vr64 = P->vb;   // the true residual is the correction equation's right-hand side
-    for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
+    make_rhs64(P, src, s);
     if (o.d_x0) {
       to_obs(P, o.d_x0, P->vxacc, R, s);
-      for (int r = 0; r < R; ++r) residual64_row(P, P->vxacc, vr64, r, s);
+      residual64_rows(P, P->vxacc, vr64, 0, R, s);
     } else {
       hipchk(launch_fill_f64(P->vxacc, 0.0, (int64_t)R * nu, s), "fill");
       hipchk(hipMemcpyAsync(vr64, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
@@ -1901,7 +1932,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       run_pcg(P, s, tau, budget, false, o.check_every, o.use_graph != 0, false, inner);
       // x += d (rows of converged RHS add 0)
       hipchk(launch_axpby(P->vxacc, P->vxb, 1.0, 1.0, (int64_t)R * nu, s), "accumulate");
-      for (int r = 0; r < R; ++r) residual64_row(P, P->vxacc, vr64, r, s);
+      residual64_rows(P, P->vxacc, vr64, 0, R, s);
       const std::vector<double> rr = dots(P, vr64, vr64, R, s);
       for (int r = 0; r < R; ++r) {
         const CgState& c = P->st_host[r];
@@ -1957,8 +1988,8 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       }
     } else {
       if (!refine)
-        for (int r = 0; r < R; ++r) make_rhs(P, src, P->fs64, r, 1, P->vb64 + (int64_t)r * nu, P->y64b, s);
-      for (int r = 0; r < R; ++r) residual64_row(P, xs, P->vr, r, s);
+        make_rhs64(P, src, s);
+      residual64_rows(P, xs, P->vr, 0, R, s);
     }
     hipchk(hipMemcpyAsync(P->vb, P->vr, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     std::vector<double> inner;
