@@ -355,7 +355,7 @@ struct mm_plan_s {
 
   int64_t nmap() const { return n_obs * ns; }            // map unknowns per RHS
   int64_t vs32() const { return n_obs * ns; }             // row of the float32 copy of p
-  // float32 q and z in the iteration: mixed precision, no template amplitudes
+  // float32 q, z and p in the iteration: mixed precision, no template amplitudes
   bool iter_f32() const { return vp32 != nullptr && !fs_main.fp64 && tmpl.empty(); }
   int64_t nu() const { return n_obs * ns + n_tunk; }     // iteration vector row
   int64_t ng() const { return n_pix * ns + n_tglob; }    // API map-shaped row
@@ -486,17 +486,16 @@ int64_t count_chunks(const std::vector<int64_t>& iv_start, int64_t m);
 
 // Compute units of the current device (256 when there is none to ask)
 int compute_units() {
-  static thread_local int cached = 0;
-  if (cached == 0) {
-    int dev = 0, cu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
-      cached = cu;
-    else
-      cached = 256;
-    (void)hipGetLastError();
+  static thread_local int cached_dev = -2, cached_cu = 256;
+  int dev = -1, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  if (dev != cached_dev) {
+    cached_dev = dev;
+    cached_cu = (dev >= 0 && hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                 cu > 0) ? cu : 256;
   }
-  return cached;
+  (void)hipGetLastError();
+  return cached_cu;
 }
 
 // Workgroup time of one 2^15-point wavefront-private transform over one 2^14-point one
