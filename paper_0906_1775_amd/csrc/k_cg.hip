@@ -273,9 +273,10 @@ __device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr)
 // p = z + beta p (RHS that stepped), in one launch: every block folds the partial sums
 // in the same fixed order and derives the same new state from st_prev (written by the
 // update, read-only here); block 0 of each RHS stores it in st, which no block of this
-// kernel reads.
-template <typename Tp, typename Tz>
-__global__ void k_cg_step_next(double* __restrict__ x, double* __restrict__ xbest, Tp* __restrict__ p,
+// kernel reads.  Tx = float: x holds the float32 increment of the iterate since its
+// last float64 fold (reliable updates), and no best iterate is copied.
+template <typename Tx, typename Tp, typename Tz>
+__global__ void k_cg_step_next(Tx* __restrict__ x, double* __restrict__ xbest, Tp* __restrict__ p,
                                const Tz* __restrict__ z, CgState* __restrict__ st,
                                const CgState* __restrict__ st_prev,
                                const double* __restrict__ prz, const double* __restrict__ prr,
@@ -299,29 +300,38 @@ __global__ void k_cg_step_next(double* __restrict__ x, double* __restrict__ xbes
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
     const int64_t j = (int64_t)r * nu + i;
     const double pj = (double)p[j];
-    const double xn = x[j] + alpha * pj;
-    x[j] = xn;
-    if (best) xbest[j] = xn;
+    const double xn = (double)x[j] + alpha * pj;
+    x[j] = (Tx)xn;
+    if constexpr (sizeof(Tx) == sizeof(double))
+      if (best) xbest[j] = xn;
     const double pn = (double)z[j] + beta * pj;
     p[j] = (Tp)pn;
     if (p32 && i < n32) p32[(int64_t)r * vs32 + i] = (float)pn;
   }
 }
 
-hipError_t launch_cg_step_next(double* x, double* xbest, void* p, bool p_f32, const void* z, bool z_f32, CgState* st,
-                               const CgState* st_prev, const double* partial_rz, const double* partial_rr,
-                               double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
-                               float* p32, int64_t n32, int64_t vs32) {
+hipError_t launch_cg_step_next(void* x, bool x_f32, double* xbest, void* p, bool p_f32, const void* z, bool z_f32,
+                               CgState* st, const CgState* st_prev, const double* partial_rz,
+                               const double* partial_rr, double* history, int hist_stride, int64_t nu, int n_rhs,
+                               hipStream_t s, float* p32, int64_t n32, int64_t vs32) {
   dim3 g = grid_for(nu);
   g.y = n_rhs;
-  if (p_f32 && z_f32)
-    hipLaunchKernelGGL((k_cg_step_next<float, float>), g, dim3(256), 0, s, x, xbest, (float*)p, (const float*)z, st,
-                       st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+  if (x_f32 && p_f32 && z_f32)
+    hipLaunchKernelGGL((k_cg_step_next<float, float, float>), g, dim3(256), 0, s, (float*)x, xbest, (float*)p,
+                       (const float*)z, st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32,
+                       vs32);
+  else if (x_f32)
+    return hipErrorInvalidValue;
+  else if (p_f32 && z_f32)
+    hipLaunchKernelGGL((k_cg_step_next<double, float, float>), g, dim3(256), 0, s, (double*)x, xbest, (float*)p,
+                       (const float*)z, st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32,
+                       vs32);
   else if (z_f32)
-    hipLaunchKernelGGL((k_cg_step_next<double, float>), g, dim3(256), 0, s, x, xbest, (double*)p, (const float*)z,
-                       st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32, vs32);
+    hipLaunchKernelGGL((k_cg_step_next<double, double, float>), g, dim3(256), 0, s, (double*)x, xbest, (double*)p,
+                       (const float*)z, st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32,
+                       vs32);
   else if (!p_f32)
-    hipLaunchKernelGGL((k_cg_step_next<double, double>), g, dim3(256), 0, s, x, xbest, (double*)p,
+    hipLaunchKernelGGL((k_cg_step_next<double, double, double>), g, dim3(256), 0, s, (double*)x, xbest, (double*)p,
                        (const double*)z, st, st_prev, partial_rz, partial_rr, history, hist_stride, nu, p32, n32,
                        vs32);
   else
@@ -386,6 +396,21 @@ __global__ void k_sub(double* __restrict__ out, const double* __restrict__ a,
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sub, grid_for(n), dim3(256), 0, s, out, a, b, n);
+  return hipGetLastError();
+}
+
+// x += d, then d = 0
+__global__ void k_fold_f32(double* __restrict__ x, float* __restrict__ d, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    x[i] += (double)d[i];
+    d[i] = 0.0f;
+  }
+}
+
+hipError_t launch_fold_f32(double* x, float* d, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_f32, grid_for(n), dim3(256), 0, s, x, d, n);
   return hipGetLastError();
 }
 

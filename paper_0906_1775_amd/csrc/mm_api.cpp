@@ -265,6 +265,11 @@ struct mm_plan_s {
   float* vp32 = nullptr;         // [R][n_obs * ns] float32 copy of p's map part (mixed plans)
   double *vb64 = nullptr, *vxbest = nullptr;   // mixed refinement: b and the best iterate in float64
   double* vxacc = nullptr;                      // accumulated map of the restarted correction
+  // set while a reliable-update solve runs float32 iterations: x then moves by a float32
+  // increment held in the first half of vxb (which that solve does not otherwise use),
+  // folded into the float64 vx for the RHS of each residual replacement
+  bool x_inc32 = false;
+  float* vdx32() const { return reinterpret_cast<float*>(vxb); }
   CgState* st = nullptr;
   CgState* st_prev = nullptr;    // state before the current step (written by the update)
   CgState* st_host = nullptr;     // pinned: the CG states, then the staging slots below
@@ -278,6 +283,7 @@ struct mm_plan_s {
   // cached graph of check_every iterations
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
+  bool graph_x32 = false;        // captured with x_inc32
 
   hipEvent_t ev_ready = nullptr;  // recorded on the build stream when the plan's build work is queued
 
@@ -1475,13 +1481,17 @@ void enqueue_iteration(mm_plan_s* P, hipStream_t s) {
   hipchk(launch_cg_update(P->ns, P->vr, P->vq, P->vz, v32, P->minv, P->st, P->st_prev, P->n_obs,
                           P->nu(), P->minv_t, P->n_tunk, R, P->part_pq, P->n_pq, P->part2, P->part3, s),
          "update");
-  if (v32)
-    hipchk(launch_cg_step_next(P->vx, P->vxb, P->vp32, true, P->vz, true, P->st, P->st_prev, P->part2, P->part3,
-                               P->hist, kHistRing, P->nu(), R, s),
+  if (v32 && P->x_inc32)
+    hipchk(launch_cg_step_next(P->vdx32(), true, nullptr, P->vp32, true, P->vz, true, P->st, P->st_prev, P->part2,
+                               P->part3, P->hist, kHistRing, P->nu(), R, s),
+           "scalar step and next direction");
+  else if (v32)
+    hipchk(launch_cg_step_next(P->vx, false, P->vxb, P->vp32, true, P->vz, true, P->st, P->st_prev, P->part2,
+                               P->part3, P->hist, kHistRing, P->nu(), R, s),
            "scalar step and next direction");
   else
-    hipchk(launch_cg_step_next(P->vx, P->vxb, P->vp, false, P->vz, false, P->st, P->st_prev, P->part2, P->part3,
-                               P->hist, kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
+    hipchk(launch_cg_step_next(P->vx, false, P->vxb, P->vp, false, P->vz, false, P->st, P->st_prev, P->part2,
+                               P->part3, P->hist, kHistRing, P->nu(), R, s, P->vp32, P->nmap(), P->vs32()),
            "scalar step and next direction");
 }
 
@@ -1525,7 +1535,7 @@ void dots2(mm_plan_s* P, const double* x, const double* y, const double* z, int 
 // than the kernels the capture is paid back by the second solve
 void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph) {
   if (use_graph && step == k && k > 0 && P->solves > 0) {
-    if (!P->graph || P->graph_k != k) {
+    if (!P->graph || P->graph_k != k || P->graph_x32 != P->x_inc32) {
       if (P->graph) {
         hipchk(hipGraphExecDestroy(P->graph), "graph destroy");
         P->graph = nullptr;
@@ -1543,6 +1553,7 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
       hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
       hipchk(hipGraphDestroy(g), "graph destroy");
       P->graph_k = k;
+      P->graph_x32 = P->x_inc32;
     }
     hipchk(hipGraphLaunch(P->graph, s), "graph launch");
   } else {
@@ -1758,9 +1769,10 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     }
     to_glob(P, P->vxb, d_x, R, s);
   } else if (P->tmpl.empty()) {
-    // Mixed precision with reliable updates (float64 residual replacement): the
-    // iterate and every CG vector are float64 and H is applied in float32; at the
-    // host's check points, for each RHS whose recurrence residual fell a thousandfold
+    // Mixed precision with reliable updates (float64 residual replacement): H is
+    // applied in float32, r, b and the dots are float64, and in the float32 iteration
+    // (no templates) q, z and p are float32 and x moves by a float32 increment that is
+    // folded into the float64 x at each replacement; at the host's check points, for each RHS whose recurrence residual fell a thousandfold
     // since its last replacement (or reached tol, or stopped), the residual is
     // replaced by the float64 true residual b - H64 x, z = M r and rho = r.z are
     // recomputed, and CG continues along the same direction p (no restart).  Blocks
@@ -1781,6 +1793,16 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
            "precondition");
     hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     sync_p32(P, s);
+    // float32 iterations move x by a float32 increment (half the bytes of the float64
+    // read and write), folded into the float64 x for the RHS of each replacement
+    struct IncrementMode {
+      mm_plan_s* P;
+      ~IncrementMode() { P->x_inc32 = false; }
+    } increment_mode{P};
+    if (P->iter_f32()) {
+      hipchk(launch_fill_i32(reinterpret_cast<int32_t*>(P->vdx32()), 0, (int64_t)R * nu, s), "fill");
+      P->x_inc32 = true;
+    }
     hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
     hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
     hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
@@ -1802,6 +1824,9 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
     // those that broke down); returns after updating the device states
     std::vector<int> restarted(R, -1);
     auto replace = [&](const std::vector<int>& rows) {
+      if (P->x_inc32)
+        for (int r : rows)
+          hipchk(launch_fold_f32(P->vx + (int64_t)r * nu, P->vdx32() + (int64_t)r * nu, nu, s), "fold");
       residual64_list(P, P->vx, P->vr, rows, s);
       hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
              "precondition");

@@ -238,16 +238,20 @@ hipError_t launch_cg_update(int ns, double* r, const void* q, void* z,
 // then x += alpha p, x_best = x (RHS whose iterate became the best) and p = z + beta p
 // (RHS that stepped); p32 (optional): also a float32 copy of the first n32 entries of
 // each row of p (rows of stride vs32); p and z: float64, or float32 when p_f32 / z_f32
-// (a float32 p, rows of stride nu, is the iteration's only direction: no p32 copy)
-hipError_t launch_cg_step_next(double* x, double* xbest, void* p, bool p_f32, const void* z, bool z_f32, CgState* st,
-                               const CgState* st_prev, const double* partial_rz, const double* partial_rr,
-                               double* history, int hist_stride, int64_t nu, int n_rhs, hipStream_t s,
-                               float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
+// (a float32 p, rows of stride nu, is the iteration's only direction: no p32 copy);
+// x: float64, or with x_f32 (float32 p and z only) the float32 increment of the
+// iterate since its last fold (launch_fold_f32), and then no best iterate is copied
+hipError_t launch_cg_step_next(void* x, bool x_f32, double* xbest, void* p, bool p_f32, const void* z, bool z_f32,
+                               CgState* st, const CgState* st_prev, const double* partial_rz,
+                               const double* partial_rr, double* history, int hist_stride, int64_t nu, int n_rhs,
+                               hipStream_t s, float* p32 = nullptr, int64_t n32 = 0, int64_t vs32 = 0);
 hipError_t launch_apply_precond(int ns, const double* minv, const double* r, double* z,
                                 int64_t n_obs, int64_t vs, const double* minv_t, int64_t n_tail,
                                 int n_rhs, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+// x[i] += d[i], then d[i] = 0, i < n (the float64 fold of a float32 increment)
+hipError_t launch_fold_f32(double* x, float* d, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- templates (k_template.hip)
 // y[r][t] += p[r * vs + off + obs_idx[t]] where obs_idx[t] >= 0

@@ -178,6 +178,36 @@ def test_graph_and_plain_launches_agree_bitwise(TQU):
     assert np.array_equal(ia["history"], ib["history"])
 
 
+def test_mixed_solves_of_both_kinds_share_a_plan(T):
+    """Tolerance-driven mixed solves move x by a float32 increment that is folded into the
+    float64 x at each residual replacement; fixed-iteration solves keep a float64 x.  On one
+    plan, alternating the two kinds with graphs captured from the plan's second solve on,
+    each solve returns what a fresh plan returns, bit for bit, and the tolerance-driven maps
+    lie within 1e-7 of the converged float64 oracle map."""
+    p, o = T
+    d = torch.from_numpy(p.tod.astype(np.float32)).cuda()
+    kw = dict(check_every=4, use_graph=True)
+
+    def tol_solve(mm):
+        m, info = mm.solve(d, tol=1e-9, max_iter=400, **kw)
+        assert info["status"] == "MM_OK"
+        return m.clone(), list(info["iters"])
+
+    def fixed_solve(mm):
+        return mm.solve(d, fixed_iters=9, **kw)[0].clone()
+
+    fresh_tol, fresh_iters = tol_solve(plan_for(p, n_rhs=3, precision="mixed", lag_dft_len=L_K))
+    fresh_fixed = fixed_solve(plan_for(p, n_rhs=3, precision="mixed", lag_dft_len=L_K))
+    mm = plan_for(p, n_rhs=3, precision="mixed", lag_dft_len=L_K)
+    for _ in range(2):
+        a, iters = tol_solve(mm)
+        assert torch.equal(a, fresh_tol) and iters == fresh_iters
+        assert torch.equal(fixed_solve(mm), fresh_fixed)
+    for r in range(3):
+        ref, _ = _oracle_map(o, p.tod[r].astype(np.float32).astype(np.float64), tol=1e-13, max_iter=1000)
+        assert rel_err(a.cpu().numpy()[r], ref) <= 1e-7
+
+
 def test_warm_start(T):
     p, o = T
     mm = plan_for(p, n_rhs=1, lag_dft_len=L_K)
