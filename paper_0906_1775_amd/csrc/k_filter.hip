@@ -482,10 +482,14 @@ __global__ __launch_bounds__(Shape<LOGN>::NT) void k_spectrum_fft(
 // cos(2 pi (N - k) tau / n_f) = (-1)^tau cos(2 pi k tau / n_f), F_k = f(0) + 2 (E + O)
 // and F_(N-k) = f(0) + 2 (E - O), E and O the sums over even and odd tau >= 1.  The
 // cosines are the real parts of z_tau = exp(2 pi i k tau / n_f), advanced by one
-// complex rotation per tau and restarted every kDirectRun steps from a float64 table
-// of cos(2 pi j / n_f), j < n_f (indexed by (k tau) mod n_f; the sine is the entry a
-// quarter period earlier), so rounding grows over at most kDirectRun rotations.
+// complex rotation per tau.  A run of kDirectRun steps starts from z at its first tau,
+// which advances by one rotation by w^kDirectRun per run and is restarted every
+// kDirectRestart runs from a float64 table of cos(2 pi j / n_f), j < n_f (indexed by
+// (k tau) mod n_f; the sine is the entry a quarter period earlier): rounding grows over
+// at most kDirectRun + kDirectRestart rotations, and a lane reads the table once per
+// kDirectRun * kDirectRestart steps (its reads scatter over the table, one cache line each).
 constexpr int kDirectRun = 16;
+constexpr int kDirectRestart = 16;
 
 __global__ void k_cos_table(double* ctab, int nf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -504,9 +508,13 @@ __global__ void k_spectrum_direct(const double* __restrict__ lags, int n_c, int 
     return {ctab[j], ctab[(j - quarter) & mask]};
   };
   const cx<double> w = unit(k);
+  const cx<double> w_run = unit((int64_t)k * kDirectRun);
   double ev = 0.0, od = 0.0;
-  for (int t0 = 0; t0 < n_c; t0 += kDirectRun) {
-    cx<double> z = unit((int64_t)k * t0);
+  cx<double> z0 = {1.0, 0.0};
+  for (int t0 = 0, run = 0; t0 < n_c; t0 += kDirectRun, ++run) {
+    if (run % kDirectRestart == 0) z0 = unit((int64_t)k * t0);
+    cx<double> z = z0;
+    z0 = cmul(z0, w_run);
 #pragma unroll
     for (int i = 0; i < kDirectRun; i += 2) {
       const int tau = t0 + i;   // even
