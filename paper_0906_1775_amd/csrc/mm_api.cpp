@@ -63,6 +63,12 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 constexpr double kMixedReplaceFall = 1e-3;
 constexpr double kMixedMaxDrop = 4.5;
 constexpr int kMixedFirstBlock = 8;
+// float64 residual below which (for every RHS) the float32 iteration moves x by a
+// float32 increment: earlier increments are large enough that their rounding stays
+// visible in the map (2^30-sample workload, increments from the first replacement
+// on: map error at tol 1e-8 up by 4e-4 relative, one more tolerance step to reach
+// the float64 solve's map error)
+constexpr double kIncrementFrom = 1e-5;
 
 // pinned staging slots of a plan (8 bytes each) and its dot-partial buffer
 constexpr int kPinSlots = 8;
@@ -280,10 +286,9 @@ struct mm_plan_s {
   double* hist = nullptr;         // [R][kHistRing] residual per iteration (ring, index iter % kHistRing)
   double* hist_host = nullptr;    // pinned copy target of hist
 
-  // cached graph of check_every iterations
-  hipGraphExec_t graph = nullptr;
-  int graph_k = 0;
-  bool graph_x32 = false;        // captured with x_inc32
+  // cached graphs of check_every iterations, one per x mode (index x_inc32)
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_k[2] = {0, 0};
 
   hipEvent_t ev_ready = nullptr;  // recorded on the build stream when the plan's build work is queued
 
@@ -345,7 +350,8 @@ struct mm_plan_s {
   int64_t bytes() const { return (int64_t)(std::max(work_top, tmp_peak)); }
 
   ~mm_plan_s() {
-    if (graph) (void)hipGraphExecDestroy(graph);   // destructor: statuses are discarded
+    for (hipGraphExec_t g : graph)
+      if (g) (void)hipGraphExecDestroy(g);   // destructor: statuses are discarded
     // work the caller queued on its own streams may still read the workspace: drain
     // the device before the caller may reuse it
     (void)hipDeviceSynchronize();
@@ -1535,10 +1541,11 @@ void dots2(mm_plan_s* P, const double* x, const double* y, const double* z, int 
 // than the kernels the capture is paid back by the second solve
 void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph) {
   if (use_graph && step == k && k > 0 && P->solves > 0) {
-    if (!P->graph || P->graph_k != k || P->graph_x32 != P->x_inc32) {
-      if (P->graph) {
-        hipchk(hipGraphExecDestroy(P->graph), "graph destroy");
-        P->graph = nullptr;
+    const int m = P->x_inc32 ? 1 : 0;
+    if (!P->graph[m] || P->graph_k[m] != k) {
+      if (P->graph[m]) {
+        hipchk(hipGraphExecDestroy(P->graph[m]), "graph destroy");
+        P->graph[m] = nullptr;
       }
       hipGraph_t g = nullptr;
       hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -1550,12 +1557,11 @@ void iterate_block(mm_plan_s* P, hipStream_t s, int step, int k, bool use_graph)
         throw;
       }
       hipchk(hipStreamEndCapture(s, &g), "end capture");
-      hipchk(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0), "graph instantiate");
+      hipchk(hipGraphInstantiate(&P->graph[m], g, nullptr, nullptr, 0), "graph instantiate");
       hipchk(hipGraphDestroy(g), "graph destroy");
-      P->graph_k = k;
-      P->graph_x32 = P->x_inc32;
+      P->graph_k[m] = k;
     }
-    hipchk(hipGraphLaunch(P->graph, s), "graph launch");
+    hipchk(hipGraphLaunch(P->graph[m], s), "graph launch");
   } else {
     for (int i = 0; i < step; ++i) enqueue_iteration(P, s);
   }
@@ -1793,16 +1799,13 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
            "precondition");
     hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     sync_p32(P, s);
-    // float32 iterations move x by a float32 increment (half the bytes of the float64
-    // read and write), folded into the float64 x for the RHS of each replacement
+    // Once every RHS's float64 residual is below kIncrementFrom, float32 iterations move
+    // x by a float32 increment (half the bytes of the float64 read and write), folded
+    // into the float64 x for the RHS of each replacement.
     struct IncrementMode {
       mm_plan_s* P;
       ~IncrementMode() { P->x_inc32 = false; }
     } increment_mode{P};
-    if (P->iter_f32()) {
-      hipchk(launch_fill_i32(reinterpret_cast<int32_t*>(P->vdx32()), 0, (int64_t)R * nu, s), "fill");
-      P->x_inc32 = true;
-    }
     hipchk(launch_dot(P->vb, P->vb, nu, R, P->part1, s), "dot");
     hipchk(launch_dot(P->vr, P->vr, nu, R, P->part2, s), "dot");
     hipchk(launch_dot(P->vr, P->vz, nu, R, P->part3, s), "dot");
@@ -1894,6 +1897,17 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
           rows.push_back(r);
       }
       if (!rows.empty()) replace(rows);
+      if (P->iter_f32() && !P->x_inc32) {
+        bool all = true;
+        for (int r = 0; r < R; ++r) {
+          const CgState& c = P->st_host[r];
+          all = all && (c.bnorm <= 0 || !c.active || (rep_iter[r] > 0 && last_true[r] <= kIncrementFrom));
+        }
+        if (all) {
+          hipchk(launch_fill_i32(reinterpret_cast<int32_t*>(P->vdx32()), 0, (int64_t)R * nu, s), "fill");
+          P->x_inc32 = true;
+        }
+      }
     }
     for (int r = 0; r < R; ++r) {
       const CgState& c = P->st_host[r];
