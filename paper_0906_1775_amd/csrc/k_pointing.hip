@@ -326,18 +326,15 @@ constexpr int kBlockWaves = 8;   // wavefronts per scatter block
 constexpr int kBatch = 4;
 
 // RG right-hand sides share one pass over the sliced pointing: the entries are
-// loaded once per group and each RHS keeps its own accumulators.  A slice runs NG
-// such groups one after the other, so the pointing comes from HBM once per NG * RG
-// RHS and the later groups re-read the slice's entries through the caches (with
-// NG = 1 the loads are nontemporal: nothing reads them again soon).  WPS wavefronts
+// loaded once per group and each RHS keeps its own accumulators, so the
+// pointing is streamed ceil(R / RG) times instead of R times.  WPS wavefronts
 // split a slice's entries (the plan picks 8 for pixels with hundreds of hits, 1
 // for a few tens, where the cross-wave combine would dominate); a block of 8
 // wavefronts works on 8 / WPS slices at a time.  Every (pixel, RHS) sum has a
-// fixed order for a given WPS, and so does every block's p.q partial sum (its
-// slices in order), whatever NG.  Tq: the element type q is stored in (the float64
-// sum is rounded to it); p (element type Tp, rows of stride ps) times the stored q
-// gives the p.q partial sums.
-template <typename Ty, typename Tq, typename Tp, int NS, int RG, int WPS, int NG>
+// fixed order for a given WPS.  Tq: the element type q is stored in (the float64 sum is
+// rounded to it); p (element type Tp, rows of stride ps) times the stored q gives the p.q
+// partial sums.
+template <typename Ty, typename Tq, typename Tp, int NS, int RG, int WPS>
 __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
     const uint32_t* __restrict__ slice_end, const uint32_t* __restrict__ slice_len,
     const int32_t* __restrict__ sell_t, const float2* __restrict__ sell_w, const Ty* __restrict__ y,
@@ -346,130 +343,113 @@ __global__ __launch_bounds__(64 * kBlockWaves) void k_scatter(
   constexpr int NW = kBlockWaves, SPB = NW / WPS;
   __shared__ double part[WPS > 1 ? NW : 1][RG * NS][64];
   __shared__ double sh[NW][RG];
-  // with NG > 1 each lane keeps its running p.q sums in its own LDS column (no
-  // other lane reads it), which holds the kernel to the registers of NG = 1
-  __shared__ double pq_lds[NG > 1 ? NG * RG : 1][NG > 1 ? 64 * NW : 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int sg = wv / WPS, wi = wv % WPS;
   const int64_t n_sl = (n_obs + 63) / 64;
-  for (int rs = 0; rs < n_rhs; rs += RG * NG) {
-    // bit h * RG + g: RHS rs + h * RG + g iterates (RHS that stopped are skipped)
-    uint32_t act = 0;
+  for (int r0 = 0; r0 < n_rhs; r0 += RG) {
+    bool act[RG];
+    bool any = false;
 #pragma unroll
-    for (int i = 0; i < NG * RG; ++i) {
-      const int r = rs + i;
-      if (r < n_rhs && !(st && !st[r].active)) act |= 1u << i;
+    for (int g = 0; g < RG; ++g) {
+      act[g] = r0 + g < n_rhs && !(st && !st[r0 + g].active);   // RHS that stopped iterating are skipped
+      any = any || act[g];
     }
-    constexpr uint32_t kGroupMask = (1u << RG) - 1;
-    if (!act) continue;                    // uniform over the block
-    double pq_reg[NG > 1 ? 1 : RG];
-    auto pq = [&](int h, int g) -> double& { return NG > 1 ? pq_lds[h * RG + g][tid] : pq_reg[g]; };
+    if (!any) continue;                    // uniform over the block
+    double pq[RG];
 #pragma unroll
-    for (int h = 0; h < NG; ++h)
-#pragma unroll
-      for (int g = 0; g < RG; ++g) pq(h, g) = 0.0;
+    for (int g = 0; g < RG; ++g) pq[g] = 0.0;
     for (int64_t s0 = (int64_t)blockIdx.x * SPB; s0 < n_sl; s0 += (int64_t)gridDim.x * SPB) {
       const int64_t s = s0 + sg;
       const bool sv = s < n_sl;
       const int64_t base = sv ? (int64_t)slice_end[s] - slice_len[s] + lane : 0;
       const int width = sv ? (int)(slice_len[s] >> 6) : 0;
-#pragma nounroll
-      for (int h = 0; h < NG; ++h) {
-        const uint32_t ag = (act >> (h * RG)) & kGroupMask;
-        if (!ag) continue;                 // uniform over the block
-        const int r0 = rs + h * RG;
-        Acc<Ty> a[RG][NS];
-        for (int j0 = wi; j0 < width; j0 += WPS * kBatch) {
-          // every load is issued unconditionally (a batch slot past the row re-reads the
-          // row's last entry, a padding entry reads sample 0) and masked afterwards, so
-          // that no load waits behind a branch
-          int32_t tt[kBatch];
-          float2 ww[kBatch];
+      Acc<Ty> a[RG][NS];
+      for (int j0 = wi; j0 < width; j0 += WPS * kBatch) {
+        // every load is issued unconditionally (a batch slot past the row re-reads the
+        // row's last entry, a padding entry reads sample 0) and masked afterwards, so
+        // that no load waits behind a branch
+        int32_t tt[kBatch];
+        float2 ww[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int j = j0 + b * WPS;
+          const int64_t e = base + (int64_t)(j < width ? j : width - 1) * 64;
+          const int32_t tv = __builtin_nontemporal_load(sell_t + e);
+          tt[b] = j < width ? tv : -1;
+          if (NS == 3) ww[b] = load_nt(sell_w + e);
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          if (!act[g]) continue;
+          const Ty* __restrict__ yr = y + (int64_t)(r0 + g) * n_t;
+          Ty vv[kBatch];
 #pragma unroll
           for (int b = 0; b < kBatch; ++b) {
-            const int j = j0 + b * WPS;
-            const int64_t e = base + (int64_t)(j < width ? j : width - 1) * 64;
-            const int32_t tv = NG == 1 ? __builtin_nontemporal_load(sell_t + e) : sell_t[e];
-            tt[b] = j < width ? tv : -1;
-            if (NS == 3) ww[b] = NG == 1 ? load_nt(sell_w + e) : sell_w[e];
+            const Ty yv = yr[tt[b] >= 0 ? tt[b] : 0];
+            vv[b] = tt[b] >= 0 ? yv : (Ty)0;
           }
 #pragma unroll
-          for (int g = 0; g < RG; ++g) {
-            if (!((ag >> g) & 1)) continue;
-            const Ty* __restrict__ yr = y + (int64_t)(r0 + g) * n_t;
-            Ty vv[kBatch];
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-              const Ty yv = yr[tt[b] >= 0 ? tt[b] : 0];
-              vv[b] = tt[b] >= 0 ? yv : (Ty)0;
-            }
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-              if (tt[b] < 0) continue;
-              if (NS == 1) {
-                a[g][0].add(vv[b]);
-              } else {
-                const Ty hv = (Ty)0.5 * vv[b];
-                a[g][0].add(hv);
-                a[g][1].add(hv * (Ty)ww[b].x);
-                a[g][2].add(hv * (Ty)ww[b].y);
-              }
+          for (int b = 0; b < kBatch; ++b) {
+            if (tt[b] < 0) continue;
+            if (NS == 1) {
+              a[g][0].add(vv[b]);
+            } else {
+              const Ty h = (Ty)0.5 * vv[b];
+              a[g][0].add(h);
+              a[g][1].add(h * (Ty)ww[b].x);
+              a[g][2].add(h * (Ty)ww[b].y);
             }
           }
         }
-        const int64_t o = s * 64 + lane;
-        if constexpr (WPS > 1) {
-#pragma unroll
-          for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int c = 0; c < NS; ++c) part[wv][g * NS + c][lane] = a[g][c].value();
-          __syncthreads();
-        }
-        if (wi == 0 && sv && o < n_obs) {
-#pragma unroll
-          for (int g = 0; g < RG; ++g) {
-            if (!((ag >> g) & 1)) continue;
-            const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
-            const int64_t ip = (int64_t)(r0 + g) * ps + o * NS;
-#pragma unroll
-            for (int c = 0; c < NS; ++c) {
-              double v;
-              if constexpr (WPS > 1) {
-                v = part[sg * WPS][g * NS + c][lane];
-#pragma unroll
-                for (int w = 1; w < WPS; ++w) v += part[sg * WPS + w][g * NS + c][lane];
-              } else {
-                v = a[g][c].value();
-              }
-              const Tq vq = (Tq)v;
-              q[i + c] = vq;
-              if (p) pq(h, g) += (double)p[ip + c] * (double)vq;
-            }
-          }
-        }
-        if constexpr (WPS > 1) __syncthreads();
       }
+      const int64_t o = s * 64 + lane;
+      if constexpr (WPS > 1) {
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+          for (int c = 0; c < NS; ++c) part[wv][g * NS + c][lane] = a[g][c].value();
+        __syncthreads();
+      }
+      if (wi == 0 && sv && o < n_obs) {
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          if (!act[g]) continue;
+          const int64_t i = (int64_t)(r0 + g) * vs + o * NS;
+          const int64_t ip = (int64_t)(r0 + g) * ps + o * NS;
+#pragma unroll
+          for (int c = 0; c < NS; ++c) {
+            double v;
+            if constexpr (WPS > 1) {
+              v = part[sg * WPS][g * NS + c][lane];
+#pragma unroll
+              for (int w = 1; w < WPS; ++w) v += part[sg * WPS + w][g * NS + c][lane];
+            } else {
+              v = a[g][c].value();
+            }
+            const Tq vq = (Tq)v;
+            q[i + c] = vq;
+            if (p) pq[g] += (double)p[ip + c] * (double)vq;
+          }
+        }
+      }
+      if constexpr (WPS > 1) __syncthreads();
     }
     if (p) {   // block sums of the p.q contributions, fixed order
 #pragma unroll
-      for (int h = 0; h < NG; ++h) {
-        if (!((act >> (h * RG)) & kGroupMask)) continue;   // uniform over the block
+      for (int g = 0; g < RG; ++g) {
+        double v = pq[g];
 #pragma unroll
-        for (int g = 0; g < RG; ++g) {
-          double v = pq(h, g);
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-          if ((tid & 63) == 0) sh[tid >> 6][g] = v;
-        }
-        __syncthreads();
-        if (tid < RG && ((act >> (h * RG + tid)) & 1)) {
-          double sum = 0.0;
-          for (int w = 0; w < NW; ++w) sum += sh[w][tid];
-          pq_part[(int64_t)(rs + h * RG + tid) * pq_stride + pq_slot + blockIdx.x] = sum;
-        }
-        __syncthreads();
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) sh[tid >> 6][g] = v;
       }
+      __syncthreads();
+      if (tid < RG && act[tid]) {
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += sh[w][tid];
+        pq_part[(int64_t)(r0 + tid) * pq_stride + pq_slot + blockIdx.x] = sum;
+      }
+      __syncthreads();
     }
   }
 }
@@ -620,24 +600,18 @@ static hipError_t scatter_typed(int ns, const SellLayout& L, const Ty* y, Tq* q,
     return hipGetLastError();
   }
   const float2* w = (const float2*)L.w;
-#define MM_SC(NS, RG, WPS, NG) hipLaunchKernelGGL((k_scatter<Ty, Tq, Tp, NS, RG, WPS, NG>), g, b, 0, s, L.end, L.len, \
-                                                  L.t, w, y, q, vs, n_obs, n_t, n_rhs, p, ps, pq_part, pq_stride,  \
-                                                  pq_slot, st)
-#define MM_SC_W(NS, RG, NG)                    \
+#define MM_SC(NS, RG, WPS) hipLaunchKernelGGL((k_scatter<Ty, Tq, Tp, NS, RG, WPS>), g, b, 0, s, L.end, L.len, L.t, \
+                                              w, y, q, vs, n_obs, n_t, n_rhs, p, ps, pq_part, pq_stride, pq_slot, st)
+#define MM_SC_W(NS, RG)                        \
   switch (L.wps) {                             \
-    case 1: MM_SC(NS, RG, 1, NG); break;       \
-    case 2: MM_SC(NS, RG, 2, 1); break;        \
-    case 4: MM_SC(NS, RG, 4, 1); break;        \
-    default: MM_SC(NS, RG, 8, 1); break;       \
+    case 1: MM_SC(NS, RG, 1); break;           \
+    case 2: MM_SC(NS, RG, 2); break;           \
+    case 4: MM_SC(NS, RG, 4); break;           \
+    default: MM_SC(NS, RG, 8); break;          \
   }
-  // one accumulator set for a single RHS; groups of 4 otherwise, two groups per slice
-  // pass beyond 4 RHS where one wavefront takes a slice (with WPS > 1 the LDS of the
-  // cross-wave combine and the p.q columns would leave one block per CU)
-  if (ns == 1) {
-    if (n_rhs == 1) { MM_SC_W(1, 1, 1) } else if (n_rhs <= 4) { MM_SC_W(1, 4, 1) } else { MM_SC_W(1, 4, 2) }
-  } else {
-    if (n_rhs == 1) { MM_SC_W(3, 1, 1) } else if (n_rhs <= 4) { MM_SC_W(3, 4, 1) } else { MM_SC_W(3, 4, 2) }
-  }
+  // one accumulator set for a single RHS; groups of 4 otherwise
+  if (ns == 1) { if (n_rhs == 1) { MM_SC_W(1, 1) } else { MM_SC_W(1, 4) } }
+  else { if (n_rhs == 1) { MM_SC_W(3, 1) } else { MM_SC_W(3, 4) } }
 #undef MM_SC_W
 #undef MM_SC
   return hipGetLastError();
