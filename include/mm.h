@@ -294,12 +294,17 @@ typedef struct {
                                    is shortened when every active RHS is predicted (from its
                                    residual rate since the last check) to reach tol sooner */
   int32_t use_graph;            /* replay each full block of check_every iterations as a hipGraph,
-                                   captured once per plan at its second solve (a plan's first
-                                   solve launches directly: capture costs more than it saves then) */
+                                   captured once per plan from its second solve on (a plan's first
+                                   solve launches directly: capture costs more than it saves then);
+                                   a reliable-update solve keeps a second graph for its iterations
+                                   with the float32 increment of x (see refine) */
   int32_t true_residual;        /* recompute ||b - H x_best|| / ||b|| in float64 at exit */
   const double* d_x0;           /* optional initial map [n_rhs][n_pix][n_stokes]; NULL = 0 */
-  int32_t refine;               /* MM_MIXED only: 1 = reliable updates: the iterate and the CG
-                                   vectors are float64 and H is applied in float32; at the host's
+  int32_t refine;               /* MM_MIXED only: 1 = reliable updates: H is applied in float32,
+                                   the iterate, r, b and the dots are float64 (without templates
+                                   q, z and p are float32, and once every RHS's float64 residual
+                                   is below 1e-5 x moves by a float32 increment folded into the
+                                   float64 iterate at each replacement); at the host's
                                    check points each RHS whose recurrence residual fell a
                                    thousandfold since its last replacement (or reached tol) gets
                                    its residual replaced by the float64 true residual b - H x
