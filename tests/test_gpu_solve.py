@@ -208,6 +208,28 @@ def test_mixed_solves_of_both_kinds_share_a_plan(T):
         assert rel_err(a.cpu().numpy()[r], ref) <= 1e-7
 
 
+def test_reliable_updates_with_a_zero_rhs_and_a_warm_start(T):
+    """Reliable updates (float32 increment of x late in the solve) on three RHS, one of
+    them zero: the zero RHS never iterates and returns its x0 (zero here, as the oracle
+    does), the others start from a random map, stop independently, and reach the
+    converged float64 oracle map with true residuals under tol."""
+    p, o = T
+    d = p.tod.astype(np.float32).copy()
+    d[1] = 0.0
+    x0 = np.random.default_rng(5).standard_normal((3, p.n_pix, 1)) * (o.hits > 0)[None, :, None]
+    x0[1] = 0.0
+    mm = plan_for(p, n_rhs=3, precision="mixed", lag_dft_len=L_K)
+    for _ in range(2):   # the second solve replays the plan's graphs
+        m, info = mm.solve(torch.from_numpy(d).cuda(), tol=1e-10, max_iter=500, check_every=4,
+                           x0=torch.from_numpy(x0).cuda())
+        assert info["status"] == "MM_OK"
+        assert info["iters"][1] == 0 and np.all(m.cpu().numpy()[1] == 0)
+        for r in (0, 2):
+            ref, _ = _oracle_map(o, d[r].astype(np.float64), tol=1e-13, max_iter=1000)
+            assert rel_err(m.cpu().numpy()[r], ref) <= 1e-8
+            assert info["true_rel_res"][r] <= 1e-10
+
+
 def test_warm_start(T):
     p, o = T
     mm = plan_for(p, n_rhs=1, lag_dft_len=L_K)
