@@ -1777,14 +1777,15 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
   } else if (P->tmpl.empty()) {
     // Mixed precision with reliable updates (float64 residual replacement): H is
     // applied in float32, r, b and the dots are float64, and in the float32 iteration
-    // (no templates) q, z and p are float32 and x moves by a float32 increment that is
-    // folded into the float64 x at each replacement; at the host's check points, for each RHS whose recurrence residual fell a thousandfold
-    // since its last replacement (or reached tol, or stopped), the residual is
-    // replaced by the float64 true residual b - H64 x, z = M r and rho = r.z are
-    // recomputed, and CG continues along the same direction p (no restart).  Blocks
-    // between checks are sized (BlockSizer) so that the recurrence residual is not
-    // predicted to fall more than kMixedMaxDrop decades below the last float64 one.
-    // The iterate with the lowest true residual is returned.
+    // (no templates) q, z and p are float32 and, late in the solve, x moves by a float32
+    // increment folded into the float64 x at each replacement.  At the host's check
+    // points, for each RHS whose recurrence residual fell a thousandfold since its last
+    // replacement (or reached tol, or stopped), the residual is replaced by the float64
+    // true residual b - H64 x, z = M r and rho = r.z are recomputed, and CG continues
+    // along the same direction p (no restart).  Blocks between checks are sized
+    // (BlockSizer) so that the recurrence residual is not predicted to fall more than
+    // kMixedMaxDrop decades below the last float64 one.  The iterate with the lowest true
+    // residual is returned.
     make_rhs64(P, src, s);
     hipchk(hipMemcpyAsync(P->vb, P->vb64, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
     if (o.d_x0) {
