@@ -92,6 +92,8 @@ __global__ void k_cg_init(CgState* st, const double* __restrict__ pbb, const dou
   s.active = (s.bnorm > 0.0) && (fixed || !(s.rel <= tol)) ? 1 : 0;
   s.copy_best = 0;
   s.breakdown = 0;
+  s.xcur = 0;
+  s.xbest = 0;
   st[r] = s;
   if (history) history[(int64_t)r * hist_stride] = s.rel;
 }
@@ -269,12 +271,15 @@ __device__ __forceinline__ bool cg_scalar_step(CgState& s, double rz, double rr)
   return true;
 }
 
-// Scalar step, then x += alpha p, x_best = x (RHS whose iterate became the best) and
-// p = z + beta p (RHS that stepped), in one launch: every block folds the partial sums
-// in the same fixed order and derives the same new state from st_prev (written by the
-// update, read-only here); block 0 of each RHS stores it in st, which no block of this
-// kernel reads.  Tx = float: x holds the float32 increment of the iterate since its
-// last float64 fold (reliable updates), and no best iterate is copied.
+// Scalar step, then x += alpha p and p = z + beta p (RHS that stepped), in one launch:
+// every block folds the partial sums in the same fixed order and derives the same new
+// state from st_prev (written by the update, read-only here); block 0 of each RHS
+// stores it in st, which no block of this kernel reads.  Tx = double: the iterate lives
+// in one of two buffers, x and xbest (CgState.xcur); while it is also the
+// lowest-residual one (CgState.xbest) the step writes the new iterate to the other
+// buffer, else in place, so the best iterate is kept without a copy.  Tx = float: x
+// holds the float32 increment of the iterate since its last float64 fold (reliable
+// updates), and no best iterate is kept.
 template <typename Tx, typename Tp, typename Tz>
 __global__ void k_cg_step_next(Tx* __restrict__ x, double* __restrict__ xbest, Tp* __restrict__ p,
                                const Tz* __restrict__ z, CgState* __restrict__ st,
@@ -287,6 +292,15 @@ __global__ void k_cg_step_next(Tx* __restrict__ x, double* __restrict__ xbest, T
   const double rr = fold_partials(prr, r);
   CgState s = st_prev[r];
   const bool stepped = cg_scalar_step(s, rz, rr);
+  int src = 0, dst = 0;
+  if constexpr (sizeof(Tx) == sizeof(double)) {
+    if (stepped) {
+      src = s.xcur;
+      dst = s.xcur == s.xbest ? 1 - s.xcur : s.xcur;
+      s.xcur = dst;
+      if (s.copy_best) s.xbest = dst;
+    }
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st[r] = s;
     if (stepped && history) history[(int64_t)r * hist_stride + s.iter % hist_stride] = s.rel;
@@ -295,15 +309,14 @@ __global__ void k_cg_step_next(Tx* __restrict__ x, double* __restrict__ xbest, T
   // residual replacement that finds it above tol continues it along this direction
   if (!stepped) return;
   const double alpha = s.alpha, beta = s.beta;
-  const bool best = s.copy_best != 0;
+  // source and destination rows of the iterate (the same buffer, or x and xbest)
+  const Tx* xs = src ? reinterpret_cast<const Tx*>(xbest) : x;
+  Tx* xd = dst ? reinterpret_cast<Tx*>(xbest) : x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += stride) {
     const int64_t j = (int64_t)r * nu + i;
     const double pj = (double)p[j];
-    const double xn = (double)x[j] + alpha * pj;
-    x[j] = (Tx)xn;
-    if constexpr (sizeof(Tx) == sizeof(double))
-      if (best) xbest[j] = xn;
+    xd[j] = (Tx)((double)xs[j] + alpha * pj);
     const double pn = (double)z[j] + beta * pj;
     p[j] = (Tp)pn;
     if (p32 && i < n32) p32[(int64_t)r * vs32 + i] = (float)pn;

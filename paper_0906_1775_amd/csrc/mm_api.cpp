@@ -1627,7 +1627,8 @@ void read_history(mm_plan_s* P, int n_max, std::vector<int>& seen, std::vector<d
 
 // PCG on H x = vb (observed layout) in the iteration precision of fs_main.
 // vb must hold the right-hand sides; x0 is read from vx when have_x0.  On
-// exit vxb holds the lowest-residual iterate and st_host the final states;
+// exit vxb holds the lowest-residual iterate (vx is then undefined) and st_host
+// the final states;
 // hseq [R][n_max + 1] the relative residual per iteration (entry 0 = start).
 void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int check_every,
              bool use_graph, bool have_x0, std::vector<double>& hseq) {
@@ -1640,7 +1641,6 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
     hipchk(launch_fill_f64(P->vx, 0.0, (int64_t)R * nu, s), "fill");
     hipchk(hipMemcpyAsync(P->vr, P->vb, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
   }
-  hipchk(hipMemcpyAsync(P->vxb, P->vx, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
   hipchk(launch_apply_precond(P->ns, P->minv, P->vr, P->vz, P->n_obs, nu, P->minv_t, P->n_tunk, R, s),
          "precondition");
   hipchk(hipMemcpyAsync(P->vp, P->vz, sizeof(double) * R * nu, hipMemcpyDeviceToDevice, s), "copy");
@@ -1674,6 +1674,12 @@ void run_pcg(mm_plan_s* P, hipStream_t s, double tol, int n_max, bool fixed, int
     done += step;
     finished = all_done();
   }
+  // the iterations keep each RHS's lowest-residual iterate in vx or vxb (CgState.xbest):
+  // gather them in vxb
+  for (int r = 0; r < R; ++r)
+    if (P->st_host[r].xbest == 0)
+      hipchk(hipMemcpyAsync(P->vxb + (int64_t)r * nu, P->vx + (int64_t)r * nu, sizeof(double) * nu,
+                            hipMemcpyDeviceToDevice, s), "copy");
 }
 
 // Float64 TOD rows one float64 pass can take at once: the TOD work buffers hold R rows
@@ -1821,6 +1827,7 @@ void solve_impl(mm_plan_s* P, const RhsSource& src, double* d_x, const mm_solve_
       best_rel[r] = c.rel;
       hist_out[(size_t)r * (n_max + 1)] = c.rel;
       c.best_rel = -1.0;            // the device keeps no best copy: the host tracks true residuals
+      c.xbest = -1;                 // and x stays in vx (replacements read it there)
     }
     hipchk(hipMemcpyAsync(P->st, P->st_host, sizeof(CgState) * R, hipMemcpyHostToDevice, s), "state copy");
 

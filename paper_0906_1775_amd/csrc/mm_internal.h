@@ -31,6 +31,8 @@ struct CgState {
   int32_t copy_best; // set when the current iterate became the best
   int32_t fixed;     // 1 = ignore tol
   int32_t breakdown; // set when p.q <= 0 (H not positive definite on p)
+  int32_t xcur;      // buffer of the current iterate: 0 = x, 1 = x_best (float64 x only)
+  int32_t xbest;     // buffer of the lowest-residual iterate; -1 = none kept (reliable updates)
 };
 
 // A run of samples [t0, t1) inside one HWP-template segment or one stationary
